@@ -1,0 +1,229 @@
+/*
+ * SparkCL map -> reduce oracle (see oracle.h).
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark, never by the GPU product path.
+ *
+ * Written for clarity, not speed: one element at a time, in index order, with
+ * no blocking, fusion or reordering beyond what the definitions state.
+ * Build: gcc -std=c11 -O2 -ffp-contract=off -fno-fast-math -fPIC -shared.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+
+/* ------------------------------------------------------------------------ */
+/* O1  POLY: the MapCL elementwise kernel (sec. 3.1.3; the Fig 3 kernel body
+ * applies one expression per global id).  Horner's rule, highest coefficient
+ * first; each step is fl(fl(t * x) + coef[k]).                               */
+static float poly_one(float x, uint32_t degree, const float *coef)
+{
+    float t = coef[degree];
+    for (uint32_t k = degree; k-- > 0;) {
+        float prod = t * x;   /* one binary32 multiply */
+        t = prod + coef[k];   /* one binary32 add      */
+    }
+    return t;
+}
+
+void oracle_poly_map(const float *x, uint64_t n, uint32_t degree,
+                     const float *coef, float *y)
+{
+    for (uint64_t i = 0; i < n; ++i)
+        y[i] = poly_one(x[i], degree, coef);
+}
+
+/* O2  FMUL: the two-input kernel of Fig 3 (SparkKernel2, elementwise over
+ * data1 and data2), generalised from a + b to x*y + c*x.                     */
+static float fmul_one(float x, float y, float c)
+{
+    float xy = x * y;
+    float cx = c * x;
+    return xy + cx;
+}
+
+void oracle_fmul_map(const float *x, const float *y, uint64_t n, float c,
+                     float *z)
+{
+    for (uint64_t i = 0; i < n; ++i)
+        z[i] = fmul_one(x[i], y[i], c);
+}
+
+/* O3  ReduceCL sum (sec. 3.1.3): Neumaier's compensated summation in FP64,
+ * index order.  s holds the running sum, comp the accumulated rounding error
+ * of every s + v step; the result is s + comp.                               */
+typedef struct {
+    double s, comp;
+} neumaier;
+
+static void neumaier_add(neumaier *a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v))
+        a->comp += (a->s - t) + v;
+    else
+        a->comp += (v - t) + a->s;
+    a->s = t;
+}
+
+static double neumaier_value(const neumaier *a) { return a->s + a->comp; }
+
+double oracle_sum(const float *v, uint64_t n)
+{
+    neumaier a = {0.0, 0.0};
+    for (uint64_t i = 0; i < n; ++i)
+        neumaier_add(&a, (double)v[i]);
+    return neumaier_value(&a);
+}
+
+double oracle_sum_f64(const double *v, uint64_t n)
+{
+    neumaier a = {0.0, 0.0};
+    for (uint64_t i = 0; i < n; ++i)
+        neumaier_add(&a, v[i]);
+    return neumaier_value(&a);
+}
+
+/* O4  ReduceCL max: m starts at -inf; m = v if v > m, index order.           */
+float oracle_max(const float *v, uint64_t n)
+{
+    float m = -INFINITY;
+    for (uint64_t i = 0; i < n; ++i)
+        if (v[i] > m)
+            m = v[i];
+    return m;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O5  Philox4x32-10, from Salmon, Moraes, Dror and Shaw, "Parallel random
+ * numbers: as easy as 1, 2, 3" (SC'11).  Not part of the SparkCL paper: the
+ * Pi demo (sec. 3.2.1) needs a counter-based generator and this is the one
+ * chosen.  A round multiplies counter words 0 and 2 by two odd constants
+ * (32x32 -> 64 bit), then forms the new counter from the high halves xor the
+ * other counter words xor the round key, and the low halves.  The two key
+ * words are bumped by two Weyl constants between rounds.                    */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
+                          uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
+        c3 = n3;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+/* O6  MapCLPartition Monte-Carlo count (SparkCLPi, sec. 3.2.1).
+ * Sample s of partition pid uses the Philox block for pair j = s / 2 with
+ * key = (seed low, seed high) and counter = (j low, j high, pid, 0).  An even
+ * sample takes words (0, 1), an odd sample words (2, 3).  The point is
+ * (a, b) * 2^-24 with a, b the top 24 bits of the two words; it is a hit iff
+ * a^2 + b^2 <= 2^48, i.e. iff the point lies in the closed unit quarter-disc,
+ * decided exactly in 64-bit integers.                                        */
+uint64_t oracle_mc_count(uint64_t seed, uint32_t pid, uint64_t lo, uint64_t hi)
+{
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint64_t hits = 0;
+    for (uint64_t s = lo; s < hi; ++s) {
+        uint64_t j = s / 2;
+        uint32_t ctr[4] = {(uint32_t)j, (uint32_t)(j >> 32), pid, 0u};
+        uint32_t r[4];
+        oracle_philox4x32_10(ctr, key, r);
+        uint32_t wa = (s % 2 == 0) ? r[0] : r[2];
+        uint32_t wb = (s % 2 == 0) ? r[1] : r[3];
+        uint64_t a = wa >> 8, b = wb >> 8;
+        if (a * a + b * b <= (1ull << 48))
+            ++hits;
+    }
+    return hits;
+}
+
+/* ------------------------------------------------------------------------ */
+/* A whole partition task: the map (O1/O2) evaluated element by element and
+ * folded straight into the requested reductions (O3/O4), or the partition
+ * kernel (O6).  Spark pipelines a map into the reduce that consumes it, so
+ * the oracle does not store the mapped values.                               */
+int oracle_task_run(const oracle_task *t, oracle_result *r)
+{
+    r->sum = 0.0;
+    r->max = -INFINITY;
+    r->pad = 0;
+    r->count = 0;
+    r->n = t->n;
+
+    if (t->kernel_id == ORACLE_MC_PI) {
+        if (t->reduce_ops != ORACLE_COUNT)
+            return -1;
+        r->count = oracle_mc_count(t->seed, t->partition_id, 0, t->n);
+        return 0;
+    }
+    if (t->kernel_id != ORACLE_POLY && t->kernel_id != ORACLE_FMUL)
+        return -1;
+    if (t->reduce_ops == 0 || (t->reduce_ops & ~(uint32_t)(ORACLE_SUM | ORACLE_MAX)))
+        return -1;
+    if (t->kernel_id == ORACLE_POLY && t->degree > 7)
+        return -1;
+
+    neumaier acc = {0.0, 0.0};
+    float m = -INFINITY;
+    for (uint64_t i = 0; i < t->n; ++i) {
+        float v = (t->kernel_id == ORACLE_POLY)
+                      ? poly_one(t->in0[i], t->degree, t->coef)
+                      : fmul_one(t->in0[i], t->in1[i], t->c);
+        neumaier_add(&acc, (double)v);
+        if (v > m)
+            m = v;
+    }
+    if (t->reduce_ops & ORACLE_SUM)
+        r->sum = neumaier_value(&acc);
+    if (t->reduce_ops & ORACLE_MAX)
+        r->max = m;
+    return 0;
+}
+
+/* O7  RDD-level ReduceCL combine (sec. 3.1.3 tree-reduce, sec. 3.2.2): the
+ * partition sums folded in FP64 Neumaier in partition order, the max of the
+ * maxima, the integer sum of the counts and of the element counts.          */
+void oracle_rdd_total(const oracle_result *r, uint64_t ntasks,
+                      uint32_t reduce_ops, oracle_result *total)
+{
+    neumaier acc = {0.0, 0.0};
+    float m = -INFINITY;
+    uint64_t count = 0, n = 0;
+    for (uint64_t i = 0; i < ntasks; ++i) {
+        neumaier_add(&acc, r[i].sum);
+        if (r[i].max > m)
+            m = r[i].max;
+        count += r[i].count;
+        n += r[i].n;
+    }
+    total->sum = (reduce_ops & ORACLE_SUM) ? neumaier_value(&acc) : 0.0;
+    total->max = (reduce_ops & ORACLE_MAX) ? m : -INFINITY;
+    total->pad = 0;
+    total->count = (reduce_ops & ORACLE_COUNT) ? count : 0;
+    total->n = n;
+}
