@@ -1,0 +1,399 @@
+"""Benchmark of the SparkCL map -> reduce hot path on one MI355X.
+
+Step = one ReduceCL pass (paper sec. 3.1.3) over the 64-partition RDD: 64
+partitions x 2^22 float32 pairs (x ~ N(0,1), y ~ U[0,2), seeded per
+partition), FMUL map z = x*y + 0.1x fused with per-partition SUM and MAX and
+the RDD-level combine, run as one persistent-executor launch over the device
+tile queue, replayed from a cached hipGraph, tile sizes from the tuning
+table.  Inputs are resident in HBM before timing starts.  The metric is
+elements/s; the roofline object reports the executor kernel's algorithmic HBM
+bandwidth (8 B per element) against the 8 TB/s peak.
+
+Extras (same process, untimed relative to the step): the same RDD with one
+launch per partition, the single 2^20 POLY partition, the 256 x 2^24 Monte-Carlo
+partitions, the 4096-partition uneven batch (persistent vs per-partition),
+and the Poisson serving stream (resident executor vs one launch per task).
+
+Run: python bench.py [--steps K] [--warmup W] [--no-extras] [--serve-seconds S]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import math
+import os
+import statistics
+import sys
+import threading
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+CUS, CLOCK_GHZ = 256, 2.4
+ALU_PEAK_TOPS = CUS * 64 * CLOCK_GHZ / 1e3  # 32-bit VALU lane-ops, T/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    p = os.path.join(ROOT, "paper_1505_01120_amd", "csrc", "kernels.hip")
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(kind: str):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(p) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = d.get(kind)
+    if not e or e.get("kernel_source") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+class Resident:
+    """The 64-partition RDD resident in HBM: one x and one y tensor, each
+    partition a contiguous 16-byte-aligned slice."""
+
+    def __init__(self, parts: int, n: int):
+        import torch
+
+        import datagen
+        self.parts, self.n = parts, n
+        self.x = torch.empty(parts * n, dtype=torch.float32, device="cuda")
+        self.y = torch.empty(parts * n, dtype=torch.float32, device="cuda")
+        hx = torch.empty(n, dtype=torch.float32).pin_memory()
+        hy = torch.empty(n, dtype=torch.float32).pin_memory()
+        for p in range(parts):
+            datagen.fill(n, 0, p, 1, datagen.NORMAL, out=hx.numpy())
+            datagen.fill(n, 0, p, 2, datagen.U_02, out=hy.numpy())
+            self.x[p * n:(p + 1) * n].copy_(hx)
+            self.y[p * n:(p + 1) * n].copy_(hy)
+        torch.cuda.synchronize()
+
+    def tasks(self, sc, kid=None):
+        import datagen
+        out = []
+        for p in range(self.parts):
+            xs = self.x[p * self.n:(p + 1) * self.n]
+            ys = self.y[p * self.n:(p + 1) * self.n]
+            out.append(sc.task(sc.FMUL, self.n, xs, ys, ops=sc.SUM | sc.MAX,
+                               pid=p, c=datagen.FMUL_C))
+        return out
+
+
+def time_async(ctx, sc, tasks, mode, steps, warmup, dres, dtot):
+    """(wall ms per step, event ms per step) of back-to-back async reduces."""
+    import torch
+    s = torch.cuda.current_stream()
+    for _ in range(warmup):
+        ctx.reduce_async(tasks, mode, dres, dtot, stream=s)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s)
+    for _ in range(steps):
+        ctx.reduce_async(tasks, mode, dres, dtot, stream=s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    return wall, e0.elapsed_time(e1) / steps
+
+
+def spot_check(ctx, sc, res: Resident, tasks, pids=(0, 33, 63)):
+    """Untimed: blocking reduce against the oracle on a few partitions."""
+    import numpy as np
+
+    import oracle
+    per, _ = ctx.reduce(tasks, sc.BATCHED)
+    bad = []
+    for p in pids:
+        x = res.x[p * res.n:(p + 1) * res.n].cpu().numpy()
+        y = res.y[p * res.n:(p + 1) * res.n].cpu().numpy()
+        o = oracle.run_task(oracle.FMUL, oracle.SUM | oracle.MAX, res.n, x, y, c=0.1)
+        if abs(per[p].sum - o.sum) > 1e-6 * abs(o.sum) or \
+                np.float32(per[p].max) != np.float32(o.max):
+            bad.append(p)
+    return bad
+
+
+def cpu_baseline(res: Resident, reps: int = 3) -> dict:
+    """The oracle as it stands (single-threaded per partition), run on all 64
+    partitions partition-parallel over the host's cores (one thread per core,
+    each calling the unchanged oracle on distinct partitions)."""
+    import oracle
+    xs = [res.x[p * res.n:(p + 1) * res.n].cpu().numpy() for p in range(res.parts)]
+    ys = [res.y[p * res.n:(p + 1) * res.n].cpu().numpy() for p in range(res.parts)]
+    cores = max(1, min(os.cpu_count() or 1, 16, res.parts))
+    oracle.lib()
+
+    def run(idx):
+        for p in idx:
+            oracle.run_task(oracle.FMUL, oracle.SUM | oracle.MAX, res.n, xs[p], ys[p], c=0.1)
+
+    times = []
+    for _ in range(reps):
+        ths = [threading.Thread(target=run, args=(list(range(k, res.parts, cores)),))
+               for k in range(cores)]
+        t0 = time.perf_counter()
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        times.append(time.perf_counter() - t0)
+    t1 = time.perf_counter()
+    run([0, 1])
+    single = 2 * res.n / (time.perf_counter() - t1)
+    med = statistics.median(times)
+    return {"value": res.parts * res.n / med, "unit": "elements/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"all {res.parts} partitions x {res.n} pairs, partition-parallel over "
+                      f"{cores} threads, median of {reps}",
+            "single_thread_elements_per_s": single}
+
+
+# ---- extras -----------------------------------------------------------------
+
+def bench_single_partition(ctx, sc, reps=50) -> dict:
+    import torch
+
+    import datagen
+    p = datagen.single_partition()[0]
+    x = torch.from_numpy(p.x).cuda()
+    tasks = [sc.task(sc.POLY, p.n, x, ops=sc.SUM, coef=p.coef)]
+    out = {}
+    dres = torch.empty(64, dtype=torch.uint8, device="cuda")
+    for name, mode in (("per_launch", sc.PER_LAUNCH), ("batched", sc.BATCHED)):
+        wall, ev = time_async(ctx, sc, tasks, mode, reps, 5, dres, None)
+        t0 = time.perf_counter()
+        for _ in range(10):
+            ctx.reduce(tasks, mode)
+        blocking = (time.perf_counter() - t0) / 10 * 1e6
+        out[name] = {"us_per_launch": ev * 1e3, "elements_per_s": p.n / (ev / 1e3),
+                     "us_blocking_call": blocking}
+    out["note"] = "4 MiB fits in cache: launch-latency bound; HBM % not meaningful"
+    return out
+
+
+def bench_monte_carlo(ctx, sc, steps=5) -> dict:
+    import torch
+
+    import datagen
+    parts = datagen.monte_carlo()
+    tasks = [sc.task(sc.MC_PI, p.n, pid=p.pid) for p in parts]
+    dres = torch.empty(64 * len(tasks), dtype=torch.uint8, device="cuda")
+    wall, ev = time_async(ctx, sc, tasks, sc.BATCHED, steps, 2, dres, None)
+    samples = sum(p.n for p in parts)
+    blocks = samples // 2
+    # VALU lane-op count per Philox block from the kernel's own gfx950 ISA is
+    # recorded in profiles/; the fraction below uses that figure when present.
+    return {"ms": ev, "samples_per_s": samples / (ev / 1e3),
+            "philox_blocks_per_s": blocks / (ev / 1e3), "samples": samples}
+
+
+def bench_uneven(ctx, sc, steps=5) -> dict:
+    import torch
+
+    import datagen
+    sizes, kids = datagen.uneven_sizes()
+    # inputs: one resident pool per input; partition p reads its own slice
+    nx = int(sum(n for n, k in zip(sizes, kids) if k != datagen.MC_PI))
+    ny = int(sum(n for n, k in zip(sizes, kids) if k == datagen.FMUL))
+    x = torch.empty(nx, dtype=torch.float32, device="cuda")
+    y = torch.empty(max(ny, 1), dtype=torch.float32, device="cuda")
+    tasks, ox, oy, bytes_, elems, mc = [], 0, 0, 0, 0, 0
+    for p, (n, k) in enumerate(zip(map(int, sizes), map(int, kids))):
+        if k == datagen.MC_PI:
+            tasks.append(sc.task(k, n, pid=p))
+            mc += n
+            continue
+        xs = x[ox:ox + n]
+        xs.copy_(torch.from_numpy(datagen.x_for(k, n, 0, p)))
+        ox += n
+        ys = None
+        if k == datagen.FMUL:
+            ys = y[oy:oy + n]
+            ys.copy_(torch.from_numpy(datagen.y_for(k, n, 0, p)))
+            oy += n
+        tasks.append(sc.task(k, n, xs, ys, coef=datagen.POLY_COEF if k == 1 else (),
+                             c=datagen.FMUL_C))
+        bytes_ += n * (4 if k == datagen.POLY else 8)
+        elems += n
+    dres = torch.empty(64 * len(tasks), dtype=torch.uint8, device="cuda")
+    out = {"partitions": len(tasks), "elements": int(sizes.sum()),
+           "hbm_bytes": bytes_, "mc_samples": mc}
+    for name, mode in (("batched", sc.BATCHED), ("per_launch", sc.PER_LAUNCH)):
+        wall, ev = time_async(ctx, sc, tasks, mode, steps, 2, dres, None)
+        out[name] = {"ms": ev, "wall_ms": wall,
+                     "elements_per_s": int(sizes.sum()) / (ev / 1e3)}
+    out["batched_speedup"] = out["per_launch"]["ms"] / out["batched"]["ms"]
+    return out
+
+
+def serve_run(sc, res: Resident, seconds: float, warm: float, per_task: bool,
+              rate: float = 20000.0) -> dict:
+    """Open-loop Poisson stream: submit at the scheduled arrival times, latency
+    = host-observed completion - scheduled arrival (no coordinated omission)."""
+    import datagen
+    count = int((seconds + warm) * rate)
+    pool = res.parts * res.n
+    tr = datagen.serving_trace(count, rate=rate, pool=pool)
+    ctx = sc.Context(device=0, arena_bytes=1 << 30, budget_bytes=64 << 30,
+                     flags=sc.FLAG_SERVE_PER_TASK if per_task else 0)
+    xp, yp = res.x.data_ptr(), res.y.data_ptr()
+    tasks = []
+    for i in range(count):
+        k, n, off = int(tr.kids[i]), int(tr.sizes[i]), int(tr.offsets[i])
+        if k == datagen.MC_PI:
+            tasks.append(sc.task(k, n, pid=i))
+        else:
+            tasks.append(sc.task(k, n, xp + 4 * off, yp + 4 * off if k == datagen.FMUL else None,
+                                 coef=datagen.POLY_COEF if k == datagen.POLY else (),
+                                 c=datagen.FMUL_C))
+    sched = (tr.t_arrive * 1e9).astype("int64")
+    tickets = [0] * count
+    results = [None] * count
+    L = sc.load()
+    h = ctx._h
+    r = sc.Result()
+    outstanding = []
+    t0 = time.monotonic_ns() + 20_000_000
+    i = 0
+    while i < count or outstanding:
+        now = time.monotonic_ns()
+        while i < count and t0 + sched[i] <= now:
+            tk = ctypes.c_uint64()
+            rc = L.sparkcl_submit(h, ctypes.byref(tasks[i]), ctypes.byref(tk))
+            if rc != 0:
+                raise RuntimeError(f"submit failed: {rc}")
+            tickets[i] = tk.value
+            outstanding.append(i)
+            i += 1
+        keep = []
+        for j in outstanding:
+            if L.sparkcl_poll(h, tickets[j], ctypes.byref(r)) == 0:
+                results[j] = (r.t_done_ns, r.status, r.n)
+            else:
+                keep.append(j)
+        outstanding = keep
+    stats = ctx.serve_stats()
+    ctx.destroy()
+    first = int(warm * rate)
+    lat = sorted((results[j][0] - (t0 + sched[j])) / 1e3 for j in range(first, count))
+    failed = sum(1 for j in range(count) if results[j][1] != 0)
+    span = (max(results[j][0] for j in range(first, count)) - (t0 + sched[first])) / 1e9
+    elems = sum(int(tr.sizes[j]) for j in range(first, count))
+
+    def pct(p):
+        return lat[min(len(lat) - 1, int(math.ceil(p / 100 * len(lat))) - 1)]
+    return {"tasks": count - first, "failed": failed, "p50_us": pct(50), "p99_us": pct(99),
+            "p999_us": pct(99.9), "mean_us": statistics.fmean(lat),
+            "tasks_per_s": (count - first) / span, "elements_per_s": elems / span,
+            "executor_launches": stats["executor_launches"],
+            "admission_waits": stats["admission_waits"],
+            "budget_peak_bytes": stats["budget_peak"]}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the hot path is built and measured on a single "
+              "MI355X; partitions would shard across GPUs as independent units (see the "
+              "design notes), but no multi-GPU figure is produced.", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1505_01120_amd as sc
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+
+    parts, n = 64, 1 << 22
+    log("generating the 64 x 2^22 RDD ...")
+    res = Resident(parts, n)
+    ctx = sc.Context(device=0, arena_bytes=1 << 30)
+    tasks = res.tasks(sc)
+    bad = spot_check(ctx, sc, res, tasks)
+    if bad:
+        log("parity spot check FAILED on partitions", bad)
+        return 1
+    dres = torch.empty(64 * parts, dtype=torch.uint8, device="cuda")
+    dtot = torch.empty(64, dtype=torch.uint8, device="cuda")
+    log("timing ...")
+    wall_ms, ev_ms = time_async(ctx, sc, tasks, sc.BATCHED, args.steps, args.warmup, dres, dtot)
+    elems = parts * n
+    algo_bytes = 8 * elems
+    achieved = algo_bytes / (ev_ms / 1e3) / 1e9
+    traffic = load_traffic("fmul_rdd_batched")
+    line = {
+        "metric": "mapCL+reduceCL elements/s (64 x 2^22 FMUL pairs, SUM+MAX per partition)",
+        "value": elems / (wall_ms / 1e3),
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (FP64 combine)",
+        "data": "synthetic, seeded per partition (x~N(0,1), y~U[0,2))",
+        "config": {"workload": "RDD of 64 partitions x 2^22 float32 pairs; FMUL z=x*y+0.1x; "
+                               "per-partition SUM+MAX + RDD total; persistent executor, "
+                               "hipGraph replay", "partitions": parts, "elements": elems,
+                   "mode": "batched"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "kernel": "k_batch",
+                     "algorithmic_bytes_per_launch": algo_bytes,
+                     "kernel_ms_per_launch": ev_ms},
+    }
+    if not args.no_cpu:
+        log("cpu baseline ...")
+        line["cpu_baseline"] = cpu_baseline(res)
+    if not args.no_extras:
+        ex = {}
+        log("extras: per-launch RDD ...")
+        wl, el = time_async(ctx, sc, tasks, sc.PER_LAUNCH, max(5, args.steps // 5), 2, dres, dtot)
+        ex["fmul_rdd_per_launch"] = {"ms": el, "wall_ms": wl, "elements_per_s": elems / (el / 1e3),
+                                     "hbm_GBps": algo_bytes / (el / 1e3) / 1e9}
+        log("extras: single partition ...")
+        ex["single_partition_poly"] = bench_single_partition(ctx, sc)
+        log("extras: monte carlo ...")
+        ex["monte_carlo"] = bench_monte_carlo(ctx, sc)
+        log("extras: uneven batch ...")
+        ex["uneven_batch"] = bench_uneven(ctx, sc)
+        if not args.no_serve:
+            for name, per_task in (("resident", False), ("per_task_launch", True)):
+                log(f"extras: serving ({name}) ...")
+                ex.setdefault("serving", {})[name] = serve_run(
+                    sc, res, args.serve_seconds, 1.0, per_task)
+        line["extras"] = ex
+    ctx.destroy()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

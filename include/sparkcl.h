@@ -1,0 +1,258 @@
+/*
+ * sparkcl.h -- C ABI of the SparkCL map -> reduce offload hot path on MI355X.
+ *
+ * The paper's model (SparkCL, sec. 3.1): a user kernel is applied to the data of
+ * RDD partitions through three constructs (sec. 3.1.3):
+ *   MapCL          -- elementwise kernel over a partition        -> sparkcl_map
+ *   MapCLPartition -- kernel over a whole partition              -> sparkcl_map_partition
+ *   ReduceCL       -- kernel-driven reduction, tree-combined      -> sparkcl_reduce
+ * The paper's SparkKernel (Fig 2) bundles a data-preparation hook, the kernel
+ * body and a result hook; here a task descriptor (sparkcl_task) carries what
+ * mapParameters prepares (data, range, parameters), a registry kernel id names
+ * the body, and sparkcl_result is what mapReturnValue hands back.  Java kernels
+ * cannot be compiled here, so a registry of three built-in kernels stands in
+ * for user kernels:
+ *   SPARKCL_POLY  -- y = sum_k coef[k] x^k (Horner, degree <= 7), one input
+ *   SPARKCL_FMUL  -- z = x*y + c*x, two inputs (the SparkKernel2 arity of Fig 3)
+ *   SPARKCL_MC_PI -- Philox4x32-10 Monte-Carlo quarter-disc hit count
+ *                    (the SparkCLPi demo, sec. 3.2.1)
+ *
+ * Conventions for every entry point:
+ *   - Returns SPARKCL_OK (0) or a negative SPARKCL_E* code; nothing throws
+ *     across the ABI.  sparkcl_last_error() gives this thread's detail text.
+ *   - Input/output arrays named "device" are device pointers owned by the
+ *     caller; they must stay valid until the call returns (blocking calls),
+ *     until the stream reaches the work (async calls), or until sparkcl_poll
+ *     reports the task done (serving).
+ *   - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *   - Floating point: maps evaluate each multiply and add as one binary32
+ *     operation in the order written (no contraction), so materialised map
+ *     outputs are bit-exact.  Sums are accumulated per thread in binary32 with
+ *     Neumaier compensation, folded to FP64, combined in FP64 across the wave,
+ *     the block and the partition's tiles, and returned as double.  For a
+ *     given context and inputs every result is run-to-run identical.
+ *   - An empty partition (n == 0) gives sum +0.0, max -inf, count 0.
+ */
+#ifndef SPARKCL_H
+#define SPARKCL_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define SPARKCL_API __attribute__((visibility("default")))
+#else
+#define SPARKCL_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define SPARKCL_OK 0
+#define SPARKCL_EINVAL (-1)    /* bad argument: NULL with n > 0, bad op mask,
+                                  degree > 7, wrong kernel for the call ...  */
+#define SPARKCL_ENOKERNEL (-2) /* kernel id not in the registry               */
+#define SPARKCL_ETOOBIG (-3)   /* task bytes exceed the serving budget, or a
+                                  size beyond the library's limits            */
+#define SPARKCL_EAGAIN (-4)    /* serving: not done yet / queue full          */
+#define SPARKCL_EHIP (-5)      /* a HIP runtime call failed (see last_error)  */
+#define SPARKCL_ETIMEDOUT (-6) /* a bounded wait expired                      */
+#define SPARKCL_ESTOPPED (-7)  /* serving stopped / context being destroyed   */
+#define SPARKCL_ENOMEM (-8)    /* arena exhausted for library workspaces      */
+#define SPARKCL_ENOTFOUND (-9) /* unknown serving ticket                      */
+
+/* ---- registry ---------------------------------------------------------- */
+#define SPARKCL_POLY 1
+#define SPARKCL_FMUL 2
+#define SPARKCL_MC_PI 3
+
+/* reduce-op bits: POLY/FMUL accept a non-empty subset of SUM|MAX; MC_PI
+   accepts COUNT only. */
+#define SPARKCL_SUM 1u
+#define SPARKCL_MAX 2u
+#define SPARKCL_COUNT 4u
+
+/* execution modes of sparkcl_reduce / sparkcl_map_partition */
+#define SPARKCL_PER_LAUNCH 0 /* one kernel launch per partition              */
+#define SPARKCL_BATCHED 1    /* all partitions in one persistent launch over
+                                a device tile queue, replayed from a cached
+                                hipGraph                                     */
+
+typedef struct sparkcl_ctx sparkcl_ctx; /* opaque, library-owned */
+
+/* sparkcl_config.flags bits */
+#define SPARKCL_FLAG_SERVE_PER_TASK 1u /* serving runs one kernel launch per
+                                         task over a pool of 4 streams (the
+                                         one-task-at-a-time baseline) instead
+                                         of the resident executor            */
+
+/* Context configuration.  Zero fields take the defaults shown. */
+typedef struct sparkcl_config {
+    int32_t device;             /* HIP device ordinal                        */
+    uint32_t ring_capacity;     /* serving slots (tasks on the device at
+                                   once), power of two; 0 -> 4096            */
+    void *arena;                /* device memory the library sub-allocates
+                                   for every workspace it needs (tile
+                                   queues, partials, tickets, results);
+                                   caller-owned, valid until destroy.  The
+                                   library calls no hipMalloc after init.    */
+    uint64_t arena_bytes;       /* size of `arena`; at least 16 MiB          */
+    uint64_t budget_bytes;      /* serving admission budget (input + output
+                                   + partial bytes of tasks on the device);
+                                   0 -> arena_bytes                          */
+    uint32_t exec_blocks_per_cu;/* persistent executor blocks per CU; 0 ->
+                                   tuned value                               */
+    uint32_t idle_exit_ms;      /* resident serving executor exits after this
+                                   long with no work (relaunched on demand);
+                                   0 -> 1000                                 */
+    uint32_t watchdog_ms;       /* serving: a task not done this long after
+                                   admission is failed with ETIMEDOUT; 0 ->
+                                   10000                                     */
+    uint32_t flags;             /* SPARKCL_FLAG_* bits                       */
+    const char *tune_cache;     /* JSON tuning cache (tile sizes per kernel
+                                   and size bucket, keyed by gfx arch); NULL
+                                   -> built-in defaults                      */
+} sparkcl_config;
+
+/* One partition task: what mapParameters prepares in the paper (Fig 2, Fig 3):
+   the data arrays, the range (n) and the kernel's parameters. */
+typedef struct sparkcl_task {
+    uint32_t kernel_id;    /* SPARKCL_POLY / SPARKCL_FMUL / SPARKCL_MC_PI   */
+    uint32_t reduce_ops;   /* SPARKCL_SUM | SPARKCL_MAX | SPARKCL_COUNT      */
+    uint64_t n;            /* elements (POLY, FMUL) or samples (MC_PI)       */
+    const float *in0;      /* device x[n] (POLY, FMUL); any 4-byte alignment */
+    const float *in1;      /* device y[n] (FMUL)                             */
+    float *out;            /* device map output [n] or NULL (POLY, FMUL)     */
+    uint64_t seed;         /* MC_PI: Philox key = (seed lo, seed hi)         */
+    uint32_t partition_id; /* MC_PI: Philox counter word 2                   */
+    uint32_t degree;       /* POLY: 0..7                                     */
+    float coef[8];         /* POLY: coef[k] multiplies x^k                   */
+    float c;               /* FMUL constant                                  */
+    uint32_t reserved;     /* 0                                              */
+} sparkcl_task;
+
+/* What mapReturnValue hands back for one partition (or the RDD total). */
+typedef struct sparkcl_result {
+    double sum;            /* SUM requested: FP64 sum, else +0.0              */
+    float max;             /* MAX requested: max, else -inf                   */
+    int32_t status;        /* SPARKCL_OK or the task's error                  */
+    uint64_t count;        /* COUNT: hits (MC_PI), else 0                     */
+    uint64_t n;            /* elements/samples covered by the tiles           */
+    uint64_t t_arrive_ns;  /* serving: submit time (host steady clock)        */
+    uint64_t t_admit_ns;   /* serving: admission time (host steady clock)     */
+    uint64_t t_start_ns;   /* first tile started (device clock, 10 ns steps)  */
+    uint64_t t_done_ns;    /* serving: completion seen (host steady clock);
+                              batch: last tile done (device clock)            */
+} sparkcl_result;
+
+/* Create a context on config->device.  Validates the config, loads tuning,
+   allocates the host-coherent serving ring (pinned host memory) and carves
+   its workspaces out of config->arena.  *out is NULL on error. */
+SPARKCL_API int sparkcl_init(const sparkcl_config *config, sparkcl_ctx **out);
+
+/* Stop serving (waits up to 10 s for the resident executor to drain), release
+   pinned memory and cached graphs.  The arena itself stays the caller's. */
+SPARKCL_API int sparkcl_destroy(sparkcl_ctx *ctx);
+
+/* MapCL (sec. 3.1.3): out[i] = kernel(in0[i] [, in1[i]]) for each task
+   (POLY or FMUL, out != NULL).  Asynchronous on `stream`; bit-exact against
+   the binary32 definition.  reduce_ops is ignored. */
+SPARKCL_API int sparkcl_map(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t ntasks,
+                void *stream);
+
+/* MapCLPartition (sec. 3.1.3): run a partition kernel (MC_PI, ops COUNT) on
+   each task and write one partition-level result per task into results[]
+   (host memory, ntasks entries).  mode: SPARKCL_PER_LAUNCH or
+   SPARKCL_BATCHED.  Blocking. */
+SPARKCL_API int sparkcl_map_partition(sparkcl_ctx *ctx, const sparkcl_task *tasks,
+                          uint32_t ntasks, int mode, sparkcl_result *results,
+                          void *stream);
+
+/* ReduceCL (sec. 3.1.3, tree-reduce; sec. 3.2.2): for each task, the map fused
+   with the requested reductions (no intermediate array unless task.out is
+   set, in which case the map output is also written), then the RDD-level
+   combine of all partition results in task order.  per_task (ntasks entries)
+   and total are host memory; either may be NULL.  Blocking. */
+SPARKCL_API int sparkcl_reduce(sparkcl_ctx *ctx, const sparkcl_task *tasks,
+                   uint32_t ntasks, int mode, sparkcl_result *per_task,
+                   sparkcl_result *total, void *stream);
+
+/* The same as sparkcl_reduce without the host synchronisation: results are
+   written by the GPU to dev_per_task[ntasks] and *dev_total (device memory,
+   caller-owned; either may be NULL) in stream order.  Calls that share a
+   context must not overlap in time on different streams. */
+SPARKCL_API int sparkcl_reduce_async(sparkcl_ctx *ctx, const sparkcl_task *tasks,
+                         uint32_t ntasks, int mode,
+                         sparkcl_result *dev_per_task,
+                         sparkcl_result *dev_total, void *stream);
+
+/* Serving (continuous batching): enqueue one task, stamping its arrival.
+   Non-blocking.  The task is admitted to the resident executor once a slot is
+   free and its bytes fit the budget; tasks admitted while others run share
+   the GPU with them.  *ticket identifies it for sparkcl_poll.  ETOOBIG if the
+   task alone exceeds the budget; EAGAIN if the pending queue is full. */
+SPARKCL_API int sparkcl_submit(sparkcl_ctx *ctx, const sparkcl_task *task,
+                   uint64_t *ticket);
+
+/* Serving: SPARKCL_OK and *result when the task is done (the ticket is then
+   retired), SPARKCL_EAGAIN while pending, ENOTFOUND for an unknown ticket.
+   A failed task returns OK with result->status holding its error. */
+SPARKCL_API int sparkcl_poll(sparkcl_ctx *ctx, uint64_t ticket, sparkcl_result *result);
+
+typedef struct sparkcl_serve_stats {
+    uint64_t submitted, admitted, completed, failed;
+    uint64_t pending;          /* submitted, not yet admitted               */
+    uint64_t in_flight;        /* admitted, not yet complete                */
+    uint64_t budget_in_use;    /* bytes charged against the budget          */
+    uint64_t budget_peak;
+    uint64_t admission_waits;  /* times the queue head waited for budget or
+                                  a slot                                    */
+    uint64_t executor_launches;/* resident executor (re)launches            */
+} sparkcl_serve_stats;
+
+SPARKCL_API int sparkcl_serve_stats_get(sparkcl_ctx *ctx, sparkcl_serve_stats *stats);
+
+/* Wait until every submitted task is complete, up to timeout_ms. */
+SPARKCL_API int sparkcl_serve_drain(sparkcl_ctx *ctx, uint32_t timeout_ms);
+
+/* ---- tuning ------------------------------------------------------------ */
+#define SPARKCL_TUNE_BUCKETS 32  /* log2(n) buckets 0..31 */
+#define SPARKCL_TUNE_MODES 3     /* PER_LAUNCH, BATCHED, serving */
+
+typedef struct sparkcl_tuning {
+    uint32_t blocks_per_cu;      /* persistent executor occupancy             */
+    uint32_t reserved;
+    /* tile size in elements (samples for MC_PI) for [mode][kernel-1][log2 n];
+       powers of two from 2^10 to 2^22. */
+    uint32_t tile[SPARKCL_TUNE_MODES][3][SPARKCL_TUNE_BUCKETS];
+} sparkcl_tuning;
+
+SPARKCL_API int sparkcl_get_tuning(sparkcl_ctx *ctx, sparkcl_tuning *out);
+/* Replace the tuning table (validated: tiles must be powers of two in range).
+   Cached graphs are dropped. */
+SPARKCL_API int sparkcl_set_tuning(sparkcl_ctx *ctx, const sparkcl_tuning *in);
+
+/* Autotuner: for each kernel and size bucket in [lo_log2, hi_log2], time the
+   candidate tile sizes on synthetic device data and keep the fastest by
+   median HIP-event time; writes the table into the context and, if `path` is
+   non-NULL, into that JSON file under the device's gfx arch name. */
+SPARKCL_API int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_log2,
+                     const char *path);
+
+/* ---- diagnostics ------------------------------------------------------- */
+SPARKCL_API const char *sparkcl_strerror(int code);
+SPARKCL_API const char *sparkcl_last_error(void);
+
+/* Device kernel time (ms) of the last reduce/map_partition launch sequence on
+   this context, measured with HIP events on the launch stream. */
+SPARKCL_API int sparkcl_last_kernel_ms(sparkcl_ctx *ctx, float *ms);
+
+/* Library version string. */
+SPARKCL_API const char *sparkcl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPARKCL_H */

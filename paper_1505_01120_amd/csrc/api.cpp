@@ -1,0 +1,713 @@
+// C ABI of the SparkCL map -> reduce hot path (include/sparkcl.h).
+//
+// Execution model: a call's tasks are validated, decomposed into tiles by the
+// tuning table, and uploaded once into arena memory as a Plan (device task
+// table, tile queue, partial slots, sync words, results).  Plans are cached by
+// the content of the call, so a repeated batch skips validation and upload;
+// in batched mode the cached plan also holds an instantiated hipGraph of the
+// persistent executor, which is simply replayed (the kernel leaves its
+// queue and tickets at zero, so nothing is cleared between replays).  This is
+// the paper's point that a kernel should be instantiated once per worker and
+// cached (sec. 3.1.1.2), and that enough data must be gathered per offload
+// (sec. 3, issue 2).
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <string>
+
+#include "runtime.h"
+#include "serve.h"
+
+using namespace sparkcl;
+
+namespace sparkcl {
+
+namespace {
+thread_local std::string t_last_error;
+constexpr uint32_t kMaxPlans = 32;
+constexpr uint64_t kMaxN = 1ull << 40;
+} // namespace
+
+int fail(int code, const std::string &msg)
+{
+    t_last_error = msg;
+    return code;
+}
+
+int fail_hip(hipError_t e, const char *what)
+{
+    return fail(SPARKCL_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+uint64_t host_ns()
+{
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+int check_task(const sparkcl_task &t, uint32_t *variant)
+{
+    if (t.kernel_id < SPARKCL_POLY || t.kernel_id > SPARKCL_MC_PI)
+        return fail(SPARKCL_ENOKERNEL, "kernel id " + std::to_string(t.kernel_id) +
+                                           " is not in the registry");
+    if (t.n > kMaxN)
+        return fail(SPARKCL_ETOOBIG, "partition of " + std::to_string(t.n) +
+                                         " elements exceeds 2^40");
+    if (t.kernel_id == SPARKCL_MC_PI) {
+        if (t.reduce_ops != SPARKCL_COUNT)
+            return fail(SPARKCL_EINVAL, "MC_PI takes reduce_ops == SPARKCL_COUNT");
+        *variant = V_MC;
+        return SPARKCL_OK;
+    }
+    if (t.reduce_ops == 0 || (t.reduce_ops & ~(SPARKCL_SUM | SPARKCL_MAX)))
+        return fail(SPARKCL_EINVAL, "POLY/FMUL take a non-empty subset of SUM|MAX");
+    if (t.n > 0 && !t.in0)
+        return fail(SPARKCL_EINVAL, "in0 is NULL with n > 0");
+    if (t.kernel_id == SPARKCL_FMUL && t.n > 0 && !t.in1)
+        return fail(SPARKCL_EINVAL, "FMUL needs in1");
+    if (((uintptr_t)t.in0 | (uintptr_t)t.in1 | (uintptr_t)t.out) & 3u)
+        return fail(SPARKCL_EINVAL, "arrays must be 4-byte aligned");
+    if (t.kernel_id == SPARKCL_POLY) {
+        if (t.degree > 7)
+            return fail(SPARKCL_EINVAL, "POLY degree above 7");
+        *variant = (t.out ? V_POLYW : V_POLY) + t.degree;
+    } else {
+        *variant = t.out ? V_FMULW : V_FMUL;
+    }
+    return SPARKCL_OK;
+}
+
+} // namespace sparkcl
+
+namespace {
+
+uint64_t fnv1a(uint64_t h, const void *p, size_t n)
+{
+    const unsigned char *b = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 0x100000001B3ull;
+    }
+    return h;
+}
+
+uint64_t plan_hash(int kind, int mode, const sparkcl_task *tasks, uint32_t ntasks,
+                   const void *ures, const void *utot)
+{
+    uint64_t h = 0xCBF29CE484222325ull;
+    h = fnv1a(h, &kind, sizeof(kind));
+    h = fnv1a(h, &mode, sizeof(mode));
+    h = fnv1a(h, &ntasks, sizeof(ntasks));
+    h = fnv1a(h, &ures, sizeof(ures));
+    h = fnv1a(h, &utot, sizeof(utot));
+    return fnv1a(h, tasks, sizeof(sparkcl_task) * ntasks);
+}
+
+void free_plan(sparkcl_ctx *ctx, Plan *p)
+{
+    if (p->gexec)
+        (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph)
+        (void)hipGraphDestroy(p->graph);
+    for (uint64_t off : p->blocks)
+        ctx->arena.release(off);
+    delete p;
+}
+
+// Evicts the least recently used plan; waits for the device first so no
+// in-flight launch still uses its memory.  False if nothing is left.
+bool evict_one(sparkcl_ctx *ctx)
+{
+    if (ctx->plans.empty())
+        return false;
+    (void)hipDeviceSynchronize();
+    Plan *p = ctx->plans.back();
+    ctx->plans.pop_back();
+    free_plan(ctx, p);
+    return true;
+}
+
+int arena_alloc(sparkcl_ctx *ctx, Plan *p, uint64_t bytes, void **out)
+{
+    for (;;) {
+        uint64_t off = ctx->arena.alloc(bytes);
+        if (off != Arena::kFail) {
+            p->blocks.push_back(off);
+            *out = ctx->dev(off);
+            return SPARKCL_OK;
+        }
+        if (!evict_one(ctx))
+            return fail(SPARKCL_ENOMEM, "arena exhausted: need " + std::to_string(bytes) +
+                                            " bytes, largest free block " +
+                                            std::to_string(ctx->arena.largest_free()));
+    }
+}
+
+} // namespace
+
+uint32_t sparkcl::exec_grid(const sparkcl_ctx *ctx)
+{
+    uint32_t per_cu = (uint32_t)ctx->occ_batch;
+    if (ctx->config.exec_blocks_per_cu)
+        per_cu = std::min(per_cu, ctx->config.exec_blocks_per_cu);
+    else if (ctx->tuning.blocks_per_cu)
+        per_cu = std::min(per_cu, ctx->tuning.blocks_per_cu);
+    return std::max(1u, per_cu) * (uint32_t)ctx->cus;
+}
+
+namespace {
+
+int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
+               uint32_t ntasks, sparkcl_result *ures, sparkcl_result *utot,
+               hipStream_t stream, Plan **out)
+{
+    std::unique_ptr<Plan> p(new Plan);
+    p->kind = kind;
+    p->mode = mode;
+    p->tasks.assign(tasks, tasks + ntasks);
+    p->user_results = ures;
+    p->user_total = utot;
+    p->ntasks = ntasks;
+    p->ntiles.resize(ntasks);
+    p->variants.resize(ntasks);
+
+    const int tm = mode == SPARKCL_BATCHED ? TM_BATCHED : TM_PER_LAUNCH;
+    std::vector<uint64_t> first(ntasks);
+    uint64_t total_tiles = 0;
+    for (uint32_t i = 0; i < ntasks; ++i) {
+        uint32_t v = 0;
+        int rc = check_task(tasks[i], &v);
+        if (rc != SPARKCL_OK)
+            return fail(rc, "task " + std::to_string(i) + ": " + sparkcl_last_error());
+        p->variants[i] = v;
+        const uint32_t T = tile_for(ctx->tuning, tm, tasks[i].kernel_id, tasks[i].n);
+        const uint64_t nt = std::max<uint64_t>(1, (tasks[i].n + T - 1) / T);
+        if (nt > 0xFFFFFFFFull)
+            return fail(SPARKCL_ETOOBIG, "too many tiles in task " + std::to_string(i));
+        p->ntiles[i] = (uint32_t)nt;
+        first[i] = total_tiles;
+        total_tiles += nt;
+    }
+    if (total_tiles > 0xFFFFFFF0ull)
+        return fail(SPARKCL_ETOOBIG, "too many tiles in one call");
+    p->ntiles_total = (uint32_t)total_tiles;
+
+    void *m = nullptr;
+    int rc;
+#define ALLOC(field, bytes)                                                    \
+    do {                                                                       \
+        if ((rc = arena_alloc(ctx, p.get(), (bytes), &m)) != SPARKCL_OK) {    \
+            for (uint64_t off : p->blocks)                                     \
+                ctx->arena.release(off);                                       \
+            return rc;                                                         \
+        }                                                                      \
+        p->field = reinterpret_cast<decltype(p->field)>(m);                    \
+    } while (0)
+    ALLOC(dtasks, sizeof(TaskDev) * ntasks);
+    if (kind == 0) {
+        ALLOC(dparts, sizeof(Partial) * total_tiles);
+        ALLOC(dsync, sizeof(TaskSync) * ntasks);
+        ALLOC(dctl, sizeof(BatchCtl));
+        ALLOC(dresults, sizeof(sparkcl_result) * ntasks);
+        ALLOC(dtotal, sizeof(sparkcl_result));
+        if (mode == SPARKCL_BATCHED)
+            ALLOC(dtiles, sizeof(TileRef) * total_tiles);
+    }
+#undef ALLOC
+
+    std::vector<TaskDev> host(ntasks);
+    for (uint32_t i = 0; i < ntasks; ++i) {
+        const sparkcl_task &t = tasks[i];
+        TaskDev &d = host[i];
+        std::memset(&d, 0, sizeof(d));
+        d.kid = t.kernel_id;
+        d.ops = t.reduce_ops;
+        d.n = t.n;
+        d.in0 = t.in0;
+        d.in1 = t.in1;
+        d.out = t.out;
+        d.seed = t.seed;
+        d.pid = t.partition_id;
+        d.variant = p->variants[i];
+        std::memcpy(d.coef, t.coef, sizeof(d.coef));
+        d.c = t.c;
+        d.tile_elems = tile_for(ctx->tuning, tm, t.kernel_id, t.n);
+        d.ntiles = p->ntiles[i];
+        d.index = i;
+        d.partials = p->dparts ? p->dparts + first[i] : nullptr;
+    }
+    hipError_t e = hipMemcpyAsync(p->dtasks, host.data(), sizeof(TaskDev) * ntasks,
+                                  hipMemcpyHostToDevice, stream);
+    std::vector<TileRef> tiles;
+    if (e == hipSuccess && p->dtiles) {
+        // Tile queue: tasks in order, each task's tiles in order.
+        tiles.reserve(total_tiles);
+        for (uint32_t i = 0; i < ntasks; ++i)
+            for (uint32_t j = 0; j < p->ntiles[i]; ++j)
+                tiles.push_back(TileRef{i, j});
+        e = hipMemcpyAsync(p->dtiles, tiles.data(), sizeof(TileRef) * total_tiles,
+                           hipMemcpyHostToDevice, stream);
+    }
+    if (e == hipSuccess && kind == 0) {
+        if ((rc = launch_zero(p->dsync, sizeof(TaskSync) * ntasks, stream)) != SPARKCL_OK ||
+            (rc = launch_zero(p->dctl, sizeof(BatchCtl), stream)) != SPARKCL_OK)
+            e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        for (uint64_t off : p->blocks)
+            ctx->arena.release(off);
+        return fail_hip(e, "plan upload");
+    }
+
+    if (kind == 0) {
+        p->out.sync = p->dsync;
+        p->out.ctl = p->dctl;
+        p->out.results = ures ? ures : p->dresults;
+        p->out.total = utot ? utot : p->dtotal;
+        p->out.ntasks = ntasks;
+        p->out.ns_per_tick = ctx->ns_per_tick;
+        p->grid = std::min(exec_grid(ctx), p->ntiles_total);
+        if (mode == SPARKCL_BATCHED) {
+            hipStream_t cs = ctx->capture_stream;
+            e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                rc = launch_batch(p->dtasks, p->dtiles, p->ntiles_total, p->grid, p->out, cs);
+                hipError_t e2 = hipStreamEndCapture(cs, &p->graph);
+                if (rc != SPARKCL_OK)
+                    e = hipErrorLaunchFailure;
+                else
+                    e = e2;
+            }
+            if (e == hipSuccess)
+                e = hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                Plan *raw = p.release();
+                free_plan(ctx, raw);
+                return fail_hip(e, "graph capture of the persistent executor");
+            }
+        }
+    }
+    p->hash = plan_hash(kind, mode, tasks, ntasks, ures, utot);
+    *out = p.release();
+    return SPARKCL_OK;
+}
+
+} // namespace
+
+int sparkcl::get_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
+                      uint32_t ntasks, sparkcl_result *ures, sparkcl_result *utot,
+                      hipStream_t stream, Plan **out)
+{
+    const uint64_t h = plan_hash(kind, mode, tasks, ntasks, ures, utot);
+    for (auto it = ctx->plans.begin(); it != ctx->plans.end(); ++it) {
+        Plan *p = *it;
+        if (p->hash == h && p->kind == kind && p->mode == mode && p->ntasks == ntasks &&
+            p->user_results == ures && p->user_total == utot &&
+            std::memcmp(p->tasks.data(), tasks, sizeof(sparkcl_task) * ntasks) == 0) {
+            ctx->plans.splice(ctx->plans.begin(), ctx->plans, it);
+            *out = p;
+            return SPARKCL_OK;
+        }
+    }
+    while (ctx->plans.size() >= kMaxPlans)
+        evict_one(ctx);
+    Plan *p = nullptr;
+    int rc = build_plan(ctx, kind, mode, tasks, ntasks, ures, utot, stream, &p);
+    if (rc != SPARKCL_OK)
+        return rc;
+    ctx->plans.push_front(p);
+    *out = p;
+    return SPARKCL_OK;
+}
+
+void sparkcl::drop_plans(sparkcl_ctx *ctx)
+{
+    (void)hipDeviceSynchronize();
+    for (Plan *p : ctx->plans)
+        free_plan(ctx, p);
+    ctx->plans.clear();
+}
+
+namespace {
+
+int ensure_pinned(sparkcl_ctx *ctx, uint32_t count)
+{
+    if (count <= ctx->pinned_cap)
+        return SPARKCL_OK;
+    uint32_t cap = std::max(count, ctx->pinned_cap * 2);
+    if (ctx->pinned)
+        (void)hipHostFree(ctx->pinned);
+    ctx->pinned = nullptr;
+    ctx->pinned_cap = 0;
+    SPARKCL_HIP(hipHostMalloc((void **)&ctx->pinned, sizeof(sparkcl_result) * cap,
+                              hipHostMallocDefault));
+    ctx->pinned_cap = cap;
+    return SPARKCL_OK;
+}
+
+} // namespace
+
+// Enqueue the launches of a reduce-kind plan on `stream`, bracketed by the
+// context's timing events.
+int sparkcl::enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream)
+{
+    SPARKCL_HIP(hipEventRecord(ctx->ev0, stream));
+    if (p->mode == SPARKCL_BATCHED) {
+        SPARKCL_HIP(hipGraphLaunch(p->gexec, stream));
+    } else {
+        const uint32_t cap = exec_grid(ctx);
+        for (uint32_t i = 0; i < p->ntasks; ++i) {
+            int rc = launch_task(p->dtasks + i, p->ntiles[i], std::min(cap, p->ntiles[i]),
+                                 p->out, stream);
+            if (rc != SPARKCL_OK)
+                return fail(rc, "kernel launch failed: " +
+                                    std::string(hipGetErrorString(hipGetLastError())));
+        }
+    }
+    SPARKCL_HIP(hipEventRecord(ctx->ev1, stream));
+    ctx->have_ms = true;
+    return SPARKCL_OK;
+}
+
+namespace {
+
+int run_blocking(sparkcl_ctx *ctx, int mode, const sparkcl_task *tasks,
+                 uint32_t ntasks, sparkcl_result *per_task, sparkcl_result *total,
+                 hipStream_t stream)
+{
+    std::lock_guard<std::mutex> g(ctx->mu);
+    Plan *p = nullptr;
+    int rc = get_plan(ctx, 0, mode, tasks, ntasks, nullptr, nullptr, stream, &p);
+    if (rc != SPARKCL_OK)
+        return rc;
+    if ((rc = ensure_pinned(ctx, ntasks + 1)) != SPARKCL_OK)
+        return rc;
+    if ((rc = enqueue(ctx, p, stream)) != SPARKCL_OK)
+        return rc;
+    SPARKCL_HIP(hipMemcpyAsync(ctx->pinned, p->dresults, sizeof(sparkcl_result) * ntasks,
+                               hipMemcpyDeviceToHost, stream));
+    SPARKCL_HIP(hipMemcpyAsync(ctx->pinned + ntasks, p->dtotal, sizeof(sparkcl_result),
+                               hipMemcpyDeviceToHost, stream));
+    SPARKCL_HIP(hipStreamSynchronize(stream));
+    if (per_task)
+        std::memcpy(per_task, ctx->pinned, sizeof(sparkcl_result) * ntasks);
+    if (total) {
+        *total = ctx->pinned[ntasks];
+        uint32_t ops = 0;
+        for (uint32_t i = 0; i < ntasks; ++i)
+            ops |= tasks[i].reduce_ops;
+        if (!(ops & SPARKCL_SUM))
+            total->sum = 0.0;
+        if (!(ops & SPARKCL_MAX))
+            total->max = -__builtin_huge_valf();
+        if (!(ops & SPARKCL_COUNT))
+            total->count = 0;
+    }
+    return SPARKCL_OK;
+}
+
+int check_ctx(sparkcl_ctx *ctx)
+{
+    if (!ctx)
+        return fail(SPARKCL_EINVAL, "null context");
+    SPARKCL_HIP(hipSetDevice(ctx->device));
+    return SPARKCL_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *sparkcl_version(void) { return "sparkcl-mi355x 0.1"; }
+
+const char *sparkcl_strerror(int code)
+{
+    switch (code) {
+    case SPARKCL_OK: return "ok";
+    case SPARKCL_EINVAL: return "invalid argument";
+    case SPARKCL_ENOKERNEL: return "kernel id not in the registry";
+    case SPARKCL_ETOOBIG: return "task too big";
+    case SPARKCL_EAGAIN: return "not ready";
+    case SPARKCL_EHIP: return "HIP runtime error";
+    case SPARKCL_ETIMEDOUT: return "timed out";
+    case SPARKCL_ESTOPPED: return "stopped";
+    case SPARKCL_ENOMEM: return "arena exhausted";
+    case SPARKCL_ENOTFOUND: return "unknown ticket";
+    default: return "unknown status";
+    }
+}
+
+const char *sparkcl_last_error(void) { return t_last_error.c_str(); }
+
+int sparkcl_init(const sparkcl_config *config, sparkcl_ctx **out)
+{
+    if (!out)
+        return fail(SPARKCL_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!config)
+        return fail(SPARKCL_EINVAL, "config is NULL");
+    int ndev = 0;
+    SPARKCL_HIP(hipGetDeviceCount(&ndev));
+    if (config->device < 0 || config->device >= ndev)
+        return fail(SPARKCL_EINVAL, "device " + std::to_string(config->device) +
+                                        " out of range (" + std::to_string(ndev) + ")");
+    uint32_t cap = config->ring_capacity ? config->ring_capacity : 4096;
+    if (cap & (cap - 1) || cap > (1u << 20))
+        return fail(SPARKCL_EINVAL, "ring_capacity must be a power of two <= 2^20");
+    uint64_t arena_bytes = config->arena_bytes ? config->arena_bytes : (256ull << 20);
+    if (arena_bytes < (16ull << 20))
+        return fail(SPARKCL_EINVAL, "arena_bytes below 16 MiB");
+    if (config->arena && ((uintptr_t)config->arena & 255u))
+        return fail(SPARKCL_EINVAL, "arena must be 256-byte aligned");
+
+    std::unique_ptr<sparkcl_ctx> ctx(new sparkcl_ctx);
+    ctx->config = *config;
+    ctx->config.ring_capacity = cap;
+    ctx->config.arena_bytes = arena_bytes;
+    if (!ctx->config.budget_bytes)
+        ctx->config.budget_bytes = arena_bytes;
+    if (!ctx->config.idle_exit_ms)
+        ctx->config.idle_exit_ms = 1000;
+    if (!ctx->config.watchdog_ms)
+        ctx->config.watchdog_ms = 10000;
+    ctx->device = config->device;
+    SPARKCL_HIP(hipSetDevice(ctx->device));
+    hipDeviceProp_t prop;
+    SPARKCL_HIP(hipGetDeviceProperties(&prop, ctx->device));
+    ctx->arch = prop.gcnArchName;
+    ctx->cus = prop.multiProcessorCount;
+    int rate_khz = 0;
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ctx->device) ==
+            hipSuccess &&
+        rate_khz > 0)
+        ctx->ns_per_tick = std::max(1, 1000000 / rate_khz);
+    int occ = 0;
+    int rc = batch_blocks_per_cu(&occ);
+    if (rc != SPARKCL_OK)
+        return fail(rc, "occupancy query failed");
+    ctx->occ_batch = std::max(1, occ);
+
+    tuning_defaults(&ctx->tuning);
+    if (config->tune_cache) {
+        std::string err;
+        sparkcl_tuning t;
+        if (tuning_load_file(config->tune_cache, ctx->arch, &t, &err))
+            ctx->tuning = t;
+        // a missing or foreign cache keeps the defaults
+    }
+
+    if (config->arena) {
+        ctx->arena_base = static_cast<char *>(config->arena);
+    } else {
+        SPARKCL_HIP(hipMalloc((void **)&ctx->arena_base, arena_bytes));
+        ctx->own_arena = true;
+    }
+    ctx->arena.reset(arena_bytes);
+    SPARKCL_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+    SPARKCL_HIP(hipEventCreate(&ctx->ev0));
+    SPARKCL_HIP(hipEventCreate(&ctx->ev1));
+    if ((rc = ensure_pinned(ctx.get(), 1024)) != SPARKCL_OK)
+        return rc;
+    rc = Server::create(ctx.get(), &ctx->server);
+    if (rc != SPARKCL_OK)
+        return rc;
+    *out = ctx.release();
+    return SPARKCL_OK;
+}
+
+int sparkcl_destroy(sparkcl_ctx *ctx)
+{
+    if (!ctx)
+        return fail(SPARKCL_EINVAL, "null context");
+    (void)hipSetDevice(ctx->device);
+    int rc = SPARKCL_OK;
+    if (ctx->server)
+        rc = ctx->server->shutdown();
+    ctx->server.reset();
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        drop_plans(ctx);
+    }
+    if (ctx->pinned)
+        (void)hipHostFree(ctx->pinned);
+    if (ctx->ev0)
+        (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1)
+        (void)hipEventDestroy(ctx->ev1);
+    if (ctx->capture_stream)
+        (void)hipStreamDestroy(ctx->capture_stream);
+    if (ctx->own_arena)
+        (void)hipFree(ctx->arena_base);
+    delete ctx;
+    return rc;
+}
+
+int sparkcl_map(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t ntasks, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc != SPARKCL_OK)
+        return rc;
+    if (ntasks && !tasks)
+        return fail(SPARKCL_EINVAL, "tasks is NULL");
+    for (uint32_t i = 0; i < ntasks; ++i) {
+        if (tasks[i].kernel_id == SPARKCL_MC_PI)
+            return fail(SPARKCL_EINVAL, "MC_PI is a partition kernel, not a map");
+        if (tasks[i].n && !tasks[i].out)
+            return fail(SPARKCL_EINVAL, "map needs an output array");
+    }
+    if (ntasks == 0)
+        return SPARKCL_OK;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Plan *p = nullptr;
+    if ((rc = get_plan(ctx, 1, 0, tasks, ntasks, nullptr, nullptr, s, &p)) != SPARKCL_OK)
+        return rc;
+    const uint32_t cap = exec_grid(ctx);
+    for (uint32_t i = 0; i < ntasks; ++i) {
+        const uint64_t n = tasks[i].n;
+        if (n == 0)
+            continue;
+        const uint64_t want = (n / 4 + kBlock - 1) / kBlock;
+        const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, cap));
+        if ((rc = launch_map(p->dtasks + i, n, p->variants[i], grid, s)) != SPARKCL_OK)
+            return fail(rc, "map launch failed");
+    }
+    return SPARKCL_OK;
+}
+
+int sparkcl_map_partition(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t ntasks,
+                          int mode, sparkcl_result *results, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc != SPARKCL_OK)
+        return rc;
+    if (ntasks && (!tasks || !results))
+        return fail(SPARKCL_EINVAL, "tasks/results is NULL");
+    if (mode != SPARKCL_PER_LAUNCH && mode != SPARKCL_BATCHED)
+        return fail(SPARKCL_EINVAL, "unknown mode");
+    for (uint32_t i = 0; i < ntasks; ++i)
+        if (tasks[i].kernel_id != SPARKCL_MC_PI)
+            return fail(tasks[i].kernel_id >= 1 && tasks[i].kernel_id <= 3 ? SPARKCL_EINVAL
+                                                                            : SPARKCL_ENOKERNEL,
+                        "map_partition runs partition kernels (MC_PI)");
+    if (ntasks == 0)
+        return SPARKCL_OK;
+    return run_blocking(ctx, mode, tasks, ntasks, results, nullptr,
+                        static_cast<hipStream_t>(stream));
+}
+
+int sparkcl_reduce(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t ntasks, int mode,
+                   sparkcl_result *per_task, sparkcl_result *total, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc != SPARKCL_OK)
+        return rc;
+    if (ntasks && !tasks)
+        return fail(SPARKCL_EINVAL, "tasks is NULL");
+    if (mode != SPARKCL_PER_LAUNCH && mode != SPARKCL_BATCHED)
+        return fail(SPARKCL_EINVAL, "unknown mode");
+    if (ntasks == 0) {
+        if (total) {
+            std::memset(total, 0, sizeof(*total));
+            total->max = -__builtin_huge_valf();
+        }
+        return SPARKCL_OK;
+    }
+    return run_blocking(ctx, mode, tasks, ntasks, per_task, total,
+                        static_cast<hipStream_t>(stream));
+}
+
+int sparkcl_reduce_async(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t ntasks,
+                         int mode, sparkcl_result *dev_per_task, sparkcl_result *dev_total,
+                         void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc != SPARKCL_OK)
+        return rc;
+    if (ntasks == 0)
+        return SPARKCL_OK;
+    if (!tasks)
+        return fail(SPARKCL_EINVAL, "tasks is NULL");
+    if (mode != SPARKCL_PER_LAUNCH && mode != SPARKCL_BATCHED)
+        return fail(SPARKCL_EINVAL, "unknown mode");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Plan *p = nullptr;
+    if ((rc = get_plan(ctx, 0, mode, tasks, ntasks, dev_per_task, dev_total, s, &p)) !=
+        SPARKCL_OK)
+        return rc;
+    return enqueue(ctx, p, s);
+}
+
+int sparkcl_submit(sparkcl_ctx *ctx, const sparkcl_task *task, uint64_t *ticket)
+{
+    if (!ctx || !ctx->server)
+        return fail(SPARKCL_EINVAL, "null context");
+    if (!task || !ticket)
+        return fail(SPARKCL_EINVAL, "task/ticket is NULL");
+    return ctx->server->submit(*task, ticket);
+}
+
+int sparkcl_poll(sparkcl_ctx *ctx, uint64_t ticket, sparkcl_result *result)
+{
+    if (!ctx || !ctx->server)
+        return fail(SPARKCL_EINVAL, "null context");
+    if (!result)
+        return fail(SPARKCL_EINVAL, "result is NULL");
+    return ctx->server->poll(ticket, result);
+}
+
+int sparkcl_serve_stats_get(sparkcl_ctx *ctx, sparkcl_serve_stats *stats)
+{
+    if (!ctx || !ctx->server || !stats)
+        return fail(SPARKCL_EINVAL, "null argument");
+    ctx->server->stats(stats);
+    return SPARKCL_OK;
+}
+
+int sparkcl_serve_drain(sparkcl_ctx *ctx, uint32_t timeout_ms)
+{
+    if (!ctx || !ctx->server)
+        return fail(SPARKCL_EINVAL, "null context");
+    return ctx->server->drain(timeout_ms);
+}
+
+int sparkcl_get_tuning(sparkcl_ctx *ctx, sparkcl_tuning *out)
+{
+    if (!ctx || !out)
+        return fail(SPARKCL_EINVAL, "null argument");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    *out = ctx->tuning;
+    return SPARKCL_OK;
+}
+
+int sparkcl_set_tuning(sparkcl_ctx *ctx, const sparkcl_tuning *in)
+{
+    int rc = check_ctx(ctx);
+    if (rc != SPARKCL_OK)
+        return rc;
+    std::string why;
+    if (tuning_validate(in, &why) != SPARKCL_OK)
+        return fail(SPARKCL_EINVAL, why);
+    std::lock_guard<std::mutex> g(ctx->mu);
+    drop_plans(ctx);
+    ctx->tuning = *in;
+    return SPARKCL_OK;
+}
+
+int sparkcl_last_kernel_ms(sparkcl_ctx *ctx, float *ms)
+{
+    if (!ctx || !ms)
+        return fail(SPARKCL_EINVAL, "null argument");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    if (!ctx->have_ms)
+        return fail(SPARKCL_EAGAIN, "no launch timed yet");
+    SPARKCL_HIP(hipEventSynchronize(ctx->ev1));
+    SPARKCL_HIP(hipEventElapsedTime(ms, ctx->ev0, ctx->ev1));
+    return SPARKCL_OK;
+}
+
+} // extern "C"

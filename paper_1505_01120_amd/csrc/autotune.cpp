@@ -1,0 +1,186 @@
+// Autotuner: picks, per execution mode, registry kernel and log2(n) bucket, the
+// tile size with the lowest median HIP-event time on synthetic device data,
+// then the persistent executor's blocks per CU.  The result is a tuning table
+// that is written to a JSON cache keyed by the device's gfx arch, so a given
+// machine always decomposes a task the same way (results stay run-to-run
+// identical).  The paper leaves optimisation open (sec. 6); this is ours.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "runtime.h"
+
+using namespace sparkcl;
+
+namespace {
+
+constexpr uint64_t kPoolElems = 1ull << 24; // synthetic input per array
+constexpr uint64_t kWorkElems = 1ull << 25; // elements per timed batch
+constexpr int kWarm = 2, kReps = 7;
+
+struct Bench {
+    sparkcl_ctx *ctx;
+    float *x = nullptr, *y = nullptr;
+    hipStream_t s = nullptr;
+};
+
+// Median time (ms) of one reduce of `tasks` in `mode` under the context's
+// current tuning table.
+int time_reduce(Bench &b, int mode, const std::vector<sparkcl_task> &tasks, float *ms)
+{
+    Plan *p = nullptr;
+    int rc = get_plan(b.ctx, 0, mode, tasks.data(), (uint32_t)tasks.size(), nullptr,
+                      nullptr, b.s, &p);
+    if (rc != SPARKCL_OK)
+        return rc;
+    std::vector<float> t;
+    for (int r = 0; r < kWarm + kReps; ++r) {
+        if ((rc = enqueue(b.ctx, p, b.s)) != SPARKCL_OK)
+            return rc;
+        SPARKCL_HIP(hipEventSynchronize(b.ctx->ev1));
+        float v = 0;
+        SPARKCL_HIP(hipEventElapsedTime(&v, b.ctx->ev0, b.ctx->ev1));
+        if (r >= kWarm)
+            t.push_back(v);
+    }
+    std::sort(t.begin(), t.end());
+    *ms = t[t.size() / 2];
+    return SPARKCL_OK;
+}
+
+std::vector<sparkcl_task> make_tasks(const Bench &b, uint32_t kid, uint64_t n, int mode)
+{
+    const uint64_t count = mode == SPARKCL_BATCHED ? std::max<uint64_t>(1, kWorkElems / n) : 1;
+    std::vector<sparkcl_task> v;
+    for (uint64_t i = 0; i < std::min<uint64_t>(count, 4096); ++i) {
+        sparkcl_task t;
+        std::memset(&t, 0, sizeof(t));
+        t.kernel_id = kid;
+        t.n = n;
+        const uint64_t off = (i * n) % (kPoolElems - n + 1);
+        if (kid == SPARKCL_MC_PI) {
+            t.reduce_ops = SPARKCL_COUNT;
+            t.partition_id = (uint32_t)i;
+        } else {
+            t.reduce_ops = SPARKCL_SUM | SPARKCL_MAX;
+            t.in0 = b.x + off;
+            t.in1 = kid == SPARKCL_FMUL ? b.y + off : nullptr;
+            t.degree = 2;
+            t.coef[0] = 3.0f;
+            t.coef[1] = -1.25f;
+            t.coef[2] = 0.5f;
+            t.c = 0.1f;
+        }
+        v.push_back(t);
+    }
+    return v;
+}
+
+} // namespace
+
+extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_log2,
+                                const char *path)
+{
+    if (!ctx)
+        return fail(SPARKCL_EINVAL, "null context");
+    if (lo_log2 > hi_log2 || hi_log2 > 24)
+        return fail(SPARKCL_EINVAL, "bucket range must satisfy lo <= hi <= 24");
+    SPARKCL_HIP(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> g(ctx->mu);
+
+    Bench b;
+    b.ctx = ctx;
+    const uint64_t xoff = ctx->arena.alloc(kPoolElems * 4);
+    const uint64_t yoff = ctx->arena.alloc(kPoolElems * 4);
+    auto cleanup = [&]() {
+        drop_plans(ctx);
+        if (xoff != Arena::kFail)
+            ctx->arena.release(xoff);
+        if (yoff != Arena::kFail)
+            ctx->arena.release(yoff);
+        if (b.s)
+            (void)hipStreamDestroy(b.s);
+    };
+    if (xoff == Arena::kFail || yoff == Arena::kFail) {
+        cleanup();
+        return fail(SPARKCL_ENOMEM, "autotune needs 128 MiB of free arena");
+    }
+    b.x = static_cast<float *>(ctx->dev(xoff));
+    b.y = static_cast<float *>(ctx->dev(yoff));
+    int rc;
+    if (hipStreamCreateWithFlags(&b.s, hipStreamNonBlocking) != hipSuccess ||
+        (rc = launch_fill_pattern(b.x, kPoolElems, 0x1234u, b.s)) != SPARKCL_OK ||
+        (rc = launch_fill_pattern(b.y, kPoolElems, 0xBEEFu, b.s)) != SPARKCL_OK ||
+        hipStreamSynchronize(b.s) != hipSuccess) {
+        cleanup();
+        return fail(SPARKCL_EHIP, "autotune setup failed");
+    }
+
+    sparkcl_tuning best = ctx->tuning;
+    const int modes[2] = {SPARKCL_PER_LAUNCH, SPARKCL_BATCHED};
+    for (int mode : modes) {
+        const int tm = mode == SPARKCL_BATCHED ? TM_BATCHED : TM_PER_LAUNCH;
+        for (uint32_t kid = SPARKCL_POLY; kid <= SPARKCL_MC_PI; ++kid) {
+            for (uint32_t bk = lo_log2; bk <= hi_log2; ++bk) {
+                const uint64_t n = 1ull << bk;
+                const std::vector<sparkcl_task> tasks = make_tasks(b, kid, n, mode);
+                float best_ms = 1e30f;
+                uint32_t best_tile = best.tile[tm][kid - 1][bk];
+                for (uint32_t tl = kMinTileLog2; tl <= kMaxTileLog2; ++tl) {
+                    const uint32_t T = 1u << tl;
+                    if (T > std::max<uint64_t>(n, 1u << kMinTileLog2))
+                        break;
+                    if (n / T > (1u << 20))
+                        continue;
+                    drop_plans(ctx);
+                    ctx->tuning = best;
+                    ctx->tuning.tile[tm][kid - 1][bk] = T;
+                    float ms = 0;
+                    if ((rc = time_reduce(b, mode, tasks, &ms)) != SPARKCL_OK) {
+                        ctx->tuning = best;
+                        cleanup();
+                        return rc;
+                    }
+                    if (ms < best_ms * 0.98f) { // prefer the earlier (smaller) on ties
+                        best_ms = ms;
+                        best_tile = T;
+                    }
+                }
+                best.tile[tm][kid - 1][bk] = best_tile;
+            }
+        }
+    }
+
+    // Executor occupancy on a large bandwidth-bound batch.
+    {
+        const std::vector<sparkcl_task> tasks =
+            make_tasks(b, SPARKCL_FMUL, 1ull << std::min<uint32_t>(hi_log2, 22), SPARKCL_BATCHED);
+        float best_ms = 1e30f;
+        uint32_t best_bpc = best.blocks_per_cu;
+        for (uint32_t bpc = 1; bpc <= (uint32_t)ctx->occ_batch; ++bpc) {
+            drop_plans(ctx);
+            ctx->tuning = best;
+            ctx->tuning.blocks_per_cu = bpc;
+            float ms = 0;
+            if ((rc = time_reduce(b, SPARKCL_BATCHED, tasks, &ms)) != SPARKCL_OK) {
+                ctx->tuning = best;
+                cleanup();
+                return rc;
+            }
+            if (ms < best_ms * 0.98f) {
+                best_ms = ms;
+                best_bpc = bpc;
+            }
+        }
+        best.blocks_per_cu = best_bpc;
+    }
+
+    ctx->tuning = best;
+    cleanup();
+    if (path) {
+        std::string err;
+        if (!tuning_save_file(path, ctx->arch, best, &err))
+            return fail(SPARKCL_EINVAL, err);
+    }
+    return SPARKCL_OK;
+}

@@ -1,0 +1,894 @@
+// HIP kernels of the SparkCL map -> reduce hot path, written for gfx950.
+//
+// A partition task (a MapCL / MapCLPartition / ReduceCL application, paper
+// sec. 3.1.3) is cut into tiles of `tile_elems` elements.  One 256-thread
+// block turns one tile into one partial:
+//   1. streaming loop: coalesced 128-bit loads (float4), kUnroll quads in
+//      flight per thread, the registry kernel's map applied per element, each
+//      value folded into a per-thread binary32 Neumaier pair (s, c), a running
+//      max, or a hit counter;
+//   2. (s, c) folded to FP64 as (double)s + (double)c, then combined across
+//      the wave with cross-lane shuffles and across the block's waves through
+//      LDS in a fixed tree;
+//   3. the partial is published and an arrival ticket taken; the block that
+//      takes the last ticket combines the task's partials in FP64 in a fixed
+//      order and writes the partition result (the tree-reduce of ReduceCL,
+//      sec. 3.1.3 and 3.2.2).  The block that finishes the last task of a
+//      launch folds the partition results into the RDD-level total.
+// Every element's owner thread and every combine order depend only on the
+// tile size, the block size and the inputs' 16-byte alignment, so results
+// are identical run to run and across execution modes with the same tiles.
+//
+// Compiled with -ffp-contract=off: the maps are the binary32 definition
+// operation by operation.  No MFMA: nothing on this path is a contraction.
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "sparkcl_dev.h"
+
+namespace sparkcl {
+
+namespace {
+
+constexpr float kNegInf = -__builtin_huge_valf();
+
+__device__ __forceinline__ uint32_t uni(uint32_t v)
+{
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ uint64_t uni64(uint64_t v)
+{
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// ---- agent-scope atomics used by the last-block combine -----------------
+__device__ __forceinline__ void st_agent(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_agent(const uint64_t *p)
+{
+    return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_partial(Partial *p, double s, float m,
+                                              uint64_t h, uint64_t n)
+{
+    uint64_t *w = reinterpret_cast<uint64_t *>(p);
+    st_agent(w + 0, __double_as_longlong(s));
+    st_agent(w + 1, (uint64_t)__float_as_uint(m));
+    st_agent(w + 2, h);
+    st_agent(w + 3, n);
+}
+
+__device__ __forceinline__ void load_partial(const Partial *p, double &s,
+                                             float &m, uint64_t &h, uint64_t &n)
+{
+    const uint64_t *w = reinterpret_cast<const uint64_t *>(p);
+    s = __longlong_as_double(ld_agent(w + 0));
+    m = __uint_as_float((uint32_t)ld_agent(w + 1));
+    h = ld_agent(w + 2);
+    n = ld_agent(w + 3);
+}
+
+__device__ __forceinline__ uint64_t device_ns(uint32_t ns_per_tick)
+{
+    return (uint64_t)wall_clock64() * ns_per_tick;
+}
+
+// ---- binary32 Neumaier step ---------------------------------------------
+// t = s + v; the rounding error of that add is (big - t) + small, where big
+// is the operand of larger magnitude; it accumulates in c.
+__device__ __forceinline__ void neumaier(float &s, float &c, float v)
+{
+    float t = s + v;
+    bool sbig = fabsf(s) >= fabsf(v);
+    float big = sbig ? s : v;
+    float small = sbig ? v : s;
+    c += (big - t) + small;
+    s = t;
+}
+
+// ---- registry maps (one binary32 operation per step, in order) -----------
+template <int D> struct PolyMap {
+    static constexpr bool kTwo = false;
+    float k[8];
+    __device__ __forceinline__ float operator()(float x, float) const
+    {
+        float t = k[D];
+#pragma unroll
+        for (int i = D - 1; i >= 0; --i) {
+            float p = t * x;
+            t = p + k[i];
+        }
+        return t;
+    }
+};
+
+struct FmulMap {
+    static constexpr bool kTwo = true;
+    float c;
+    __device__ __forceinline__ float operator()(float x, float y) const
+    {
+        float xy = x * y;
+        float cx = c * x;
+        return xy + cx;
+    }
+};
+
+// Per-thread accumulator of one tile.
+struct Acc {
+    float s = 0.0f, c = 0.0f, m = kNegInf;
+    uint32_t hits = 0;
+    __device__ __forceinline__ void add(float v)
+    {
+        neumaier(s, c, v);
+        m = fmaxf(m, v);
+    }
+};
+
+// Elementwise tile [begin, end): the aligned middle in float4 quads (thread t
+// owns quads t, t+B, t+2B, ...), the unaligned head and the ragged tail as
+// single elements owned by threads 0..2.  If the inputs (and the output) do
+// not share one 16-byte misalignment, every element goes through the scalar
+// strided loop instead.
+template <class M, bool W>
+__device__ __forceinline__ void tile_elementwise(const M &f,
+                                                 const float *__restrict__ x,
+                                                 const float *__restrict__ y,
+                                                 float *__restrict__ out,
+                                                 uint64_t begin, uint64_t end,
+                                                 Acc &a)
+{
+    const uint32_t tid = threadIdx.x;
+    const uint32_t len = (uint32_t)(end - begin);
+    const float *xb = x + begin;
+    const float *yb = M::kTwo ? y + begin : nullptr;
+    float *ob = W ? out + begin : nullptr;
+
+    const uintptr_t ax = (uintptr_t)xb;
+    bool vec = true;
+    if (M::kTwo && ((ax ^ (uintptr_t)yb) & 15u))
+        vec = false;
+    if (W && ((ax ^ (uintptr_t)ob) & 15u))
+        vec = false;
+    const uint32_t mis = (uint32_t)((ax & 15u) >> 2);
+    const uint32_t head = vec ? min((4u - mis) & 3u, len) : len;
+
+    for (uint32_t i = tid; i < head; i += kBlock) {
+        float v = f(xb[i], M::kTwo ? yb[i] : 0.0f);
+        if (W)
+            ob[i] = v;
+        a.add(v);
+    }
+    if (!vec)
+        return;
+
+    const uint32_t nq = (len - head) >> 2;
+    const float4 *x4 = reinterpret_cast<const float4 *>(xb + head);
+    const float4 *y4 = M::kTwo ? reinterpret_cast<const float4 *>(yb + head) : nullptr;
+    float4 *o4 = W ? reinterpret_cast<float4 *>(ob + head) : nullptr;
+
+    auto quad = [&](const float4 &xv, const float4 &yv, uint32_t q) {
+        float4 v;
+        v.x = f(xv.x, yv.x);
+        v.y = f(xv.y, yv.y);
+        v.z = f(xv.z, yv.z);
+        v.w = f(xv.w, yv.w);
+        if (W)
+            o4[q] = v;
+        a.add(v.x);
+        a.add(v.y);
+        a.add(v.z);
+        a.add(v.w);
+    };
+
+    uint32_t q = tid;
+    for (; q + (kUnroll - 1) * kBlock < nq; q += kUnroll * kBlock) {
+        float4 xv[kUnroll], yv[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            xv[u] = x4[q + u * kBlock];
+            if (M::kTwo)
+                yv[u] = y4[q + u * kBlock];
+            else
+                yv[u] = xv[u];
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            quad(xv[u], yv[u], q + u * kBlock);
+    }
+    for (; q < nq; q += kBlock) {
+        float4 xv = x4[q];
+        float4 yv = M::kTwo ? y4[q] : xv;
+        quad(xv, yv, q);
+    }
+
+    const uint32_t t0 = head + 4u * nq;
+    if (tid < len - t0) {
+        uint32_t i = t0 + tid;
+        float v = f(xb[i], M::kTwo ? yb[i] : 0.0f);
+        if (W)
+            ob[i] = v;
+        a.add(v);
+    }
+}
+
+// ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) --------------------
+// The key words are wave-uniform and stay in scalar registers; each round is
+// two 32x32->64 products and two three-way xors per lane.
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        U4 n;
+        n.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+        n.y = (uint32_t)p1;
+        n.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+        n.w = (uint32_t)p0;
+        c = n;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Point (a, b) * 2^-24 from the top 24 bits of two words; a hit iff
+// a^2 + b^2 <= 2^48.  Both squares and their sum are below 2^49, so the FP64
+// multiply and fused add are exact and the test is the integer test.
+__device__ __forceinline__ uint32_t disc_hit(uint32_t wa, uint32_t wb)
+{
+    const double a = (double)(wa >> 8);
+    const double b = (double)(wb >> 8);
+    return __fma_rn(a, a, b * b) <= 281474976710656.0 ? 1u : 0u;
+}
+
+// MapCLPartition Monte-Carlo tile: samples [begin, end), begin even.  Pair p
+// is the Philox block with counter (p lo, p hi, partition id, 0); sample 2p
+// takes words (0, 1), sample 2p+1 words (2, 3).
+__device__ __forceinline__ void tile_mc(uint64_t seed, uint32_t pid,
+                                        uint64_t begin, uint64_t end, Acc &a)
+{
+    const uint64_t p0 = begin >> 1;
+    const uint32_t npairs = (uint32_t)(((end + 1) >> 1) - p0);
+    const bool odd_tail = (end & 1u) != 0;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    uint32_t hits = 0;
+    for (uint32_t i = threadIdx.x; i < npairs; i += kBlock) {
+        const uint64_t p = p0 + i;
+        const U4 r = philox10(U4{(uint32_t)p, (uint32_t)(p >> 32), pid, 0u}, k0, k1);
+        hits += disc_hit(r.x, r.y);
+        if (!(odd_tail && i == npairs - 1))
+            hits += disc_hit(r.z, r.w);
+    }
+    a.hits += hits;
+}
+
+// ---- wave and block combines --------------------------------------------
+struct Red {
+    double s;
+    float m;
+    uint64_t h, n;
+};
+
+__device__ __forceinline__ void wave_reduce(Red &r)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        r.s += __shfl_xor(r.s, o);
+        r.m = fmaxf(r.m, __shfl_xor(r.m, o));
+        r.h += __shfl_xor(r.h, o);
+        r.n += __shfl_xor(r.n, o);
+    }
+}
+
+// Block-wide combine; the result is valid in thread 0.  Waves are combined
+// as a fixed pairwise tree ((w0 + w1) + (w2 + w3)).
+__device__ __forceinline__ Red block_reduce(Red r)
+{
+    __shared__ double sh_s[kWaves];
+    __shared__ float sh_m[kWaves];
+    __shared__ uint64_t sh_h[kWaves], sh_n[kWaves];
+    wave_reduce(r);
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh_s[w] = r.s;
+        sh_m[w] = r.m;
+        sh_h[w] = r.h;
+        sh_n[w] = r.n;
+    }
+    __syncthreads();
+    Red out = r;
+    if (threadIdx.x == 0) {
+        double s[kWaves];
+        float m[kWaves];
+        uint64_t h[kWaves], n[kWaves];
+#pragma unroll
+        for (int i = 0; i < kWaves; ++i) {
+            s[i] = sh_s[i];
+            m[i] = sh_m[i];
+            h[i] = sh_h[i];
+            n[i] = sh_n[i];
+        }
+#pragma unroll
+        for (int step = 1; step < kWaves; step <<= 1)
+#pragma unroll
+            for (int i = 0; i + step < kWaves; i += 2 * step) {
+                s[i] = s[i] + s[i + step];
+                m[i] = fmaxf(m[i], m[i + step]);
+                h[i] += h[i + step];
+                n[i] += n[i + step];
+            }
+        out = Red{s[0], m[0], h[0], n[0]};
+    }
+    __syncthreads();
+    return out;
+}
+
+// Fold the strided slice of `count` partials owned by this thread (in index
+// order), then combine across the block.  Thread 0 holds the result.
+template <class Load>
+__device__ __forceinline__ Red combine_ordered(uint32_t count, Load load)
+{
+    Red r{0.0, kNegInf, 0, 0};
+    for (uint32_t k = threadIdx.x; k < count; k += kBlock) {
+        double s;
+        float m;
+        uint64_t h, n;
+        load(k, s, m, h, n);
+        r.s += s;
+        r.m = fmaxf(r.m, m);
+        r.h += h;
+        r.n += n;
+    }
+    return block_reduce(r);
+}
+
+__device__ __forceinline__ void write_result(sparkcl_result *dst, uint32_t ops,
+                                             const Red &r, uint64_t t_start,
+                                             uint64_t t_done)
+{
+    sparkcl_result v;
+    v.sum = (ops & SPARKCL_SUM) ? r.s : 0.0;
+    v.max = (ops & SPARKCL_MAX) ? r.m : kNegInf;
+    v.status = SPARKCL_OK;
+    v.count = (ops & SPARKCL_COUNT) ? r.h : 0;
+    v.n = r.n;
+    v.t_arrive_ns = 0;
+    v.t_admit_ns = 0;
+    v.t_start_ns = t_start;
+    v.t_done_ns = t_done;
+    const uint64_t *src = reinterpret_cast<const uint64_t *>(&v);
+    uint64_t *d = reinterpret_cast<uint64_t *>(dst);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(v) / 8); ++i)
+        st_agent(d + i, src[i]);
+}
+
+__device__ __forceinline__ void read_result(const sparkcl_result *p, double &s,
+                                            float &m, uint64_t &h, uint64_t &n)
+{
+    const uint64_t *w = reinterpret_cast<const uint64_t *>(p);
+    s = __longlong_as_double(ld_agent(w + 0));
+    m = __uint_as_float((uint32_t)ld_agent(w + 1));
+    h = ld_agent(w + 2);
+    n = ld_agent(w + 3);
+}
+
+// ---- one tile, start to finish ------------------------------------------
+// Returns true in the block that completed the task (after writing its
+// result); callers use it only for the RDD-level step.
+__device__ bool run_tile(const TaskDev *__restrict__ tp, uint32_t j,
+                         const LaunchOut &L)
+{
+    __shared__ uint32_t sh_last;
+    TaskSync *__restrict__ sync = L.sync;
+    const uint64_t t0 = device_ns(L.ns_per_tick);
+
+    const uint32_t variant = uni(tp->variant);
+    const uint32_t T = uni(tp->tile_elems);
+    const uint64_t n = uni64(tp->n);
+    const uint64_t begin = (uint64_t)j * T;
+    const uint64_t end = min(n, begin + T);
+
+    Acc a;
+    if (begin < end) {
+        const float *x = tp->in0;
+        const float *y = tp->in1;
+        float *o = tp->out;
+        if (variant < V_FMUL) {
+            const bool w = variant >= V_POLYW;
+            const uint32_t d = variant & 7u;
+            float k[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                k[i] = tp->coef[i];
+#define SPARKCL_POLY_CASE(D)                                                   \
+    case D: {                                                                  \
+        PolyMap<D> f;                                                          \
+        for (int i = 0; i < 8; ++i)                                            \
+            f.k[i] = k[i];                                                     \
+        if (w)                                                                 \
+            tile_elementwise<PolyMap<D>, true>(f, x, y, o, begin, end, a);     \
+        else                                                                   \
+            tile_elementwise<PolyMap<D>, false>(f, x, y, o, begin, end, a);    \
+    } break;
+            switch (d) {
+                SPARKCL_POLY_CASE(0)
+                SPARKCL_POLY_CASE(1)
+                SPARKCL_POLY_CASE(2)
+                SPARKCL_POLY_CASE(3)
+                SPARKCL_POLY_CASE(4)
+                SPARKCL_POLY_CASE(5)
+                SPARKCL_POLY_CASE(6)
+                SPARKCL_POLY_CASE(7)
+            }
+#undef SPARKCL_POLY_CASE
+        } else if (variant == V_FMUL || variant == V_FMULW) {
+            FmulMap f{tp->c};
+            if (variant == V_FMULW)
+                tile_elementwise<FmulMap, true>(f, x, y, o, begin, end, a);
+            else
+                tile_elementwise<FmulMap, false>(f, x, y, o, begin, end, a);
+        } else {
+            tile_mc(uni64(tp->seed), uni(tp->pid), begin, end, a);
+        }
+    }
+
+    Red r{(double)a.s + (double)a.c, a.m, a.hits, 0};
+    r = block_reduce(r);
+
+    const uint32_t idx = uni(tp->index);
+    const uint32_t ntiles = uni(tp->ntiles);
+    if (threadIdx.x == 0) {
+        store_partial(tp->partials + j, r.s, r.m, r.h, end > begin ? end - begin : 0);
+        // t_start keeps the bitwise complement of the earliest tile start, so
+        // its cleared state (0) is the identity of the max below.
+        __hip_atomic_fetch_max(&sync[idx].t_start, ~t0, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        const uint32_t prev = atomicAdd(&sync[idx].ticket, 1u);
+        sh_last = (prev == ntiles - 1) ? 1u : 0u;
+    }
+    __syncthreads();
+    const bool last = sh_last != 0;
+    __syncthreads();
+    if (!last)
+        return false;
+
+    // Last tile of the task: combine its partials in index order.
+    __threadfence();
+    const Partial *parts = tp->partials;
+    Red t = combine_ordered(ntiles, [&](uint32_t k, double &s, float &m,
+                                        uint64_t &h, uint64_t &nn) {
+        load_partial(parts + k, s, m, h, nn);
+    });
+    if (threadIdx.x == 0) {
+        const uint64_t t_start = ~ld_agent(&sync[idx].t_start);
+        write_result(L.results + idx, uni(tp->ops), t, t_start,
+                     device_ns(L.ns_per_tick));
+        __hip_atomic_store(&sync[idx].t_start, 0ull, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&sync[idx].ticket, 0u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        if (L.done) {
+            // Serving: the result lives in host memory; publish it with a
+            // system-scope release so the host sees the result before the word.
+            __threadfence_system();
+            __hip_atomic_store(L.done + idx, uni64(tp->seq) + 1, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+        } else {
+            __threadfence();
+        }
+    }
+    return true;
+}
+
+// RDD-level step, run by the block that completed a task: the block that
+// completes the launch's last task folds all partition results in task order.
+__device__ void rdd_step(const LaunchOut &L)
+{
+    __shared__ uint32_t sh_last;
+    if (L.ntasks == 0)
+        return;
+    if (threadIdx.x == 0) {
+        const uint32_t prev = atomicAdd(&L.ctl->rdd_ticket, 1u);
+        sh_last = (prev == L.ntasks - 1) ? 1u : 0u;
+    }
+    __syncthreads();
+    const bool last = sh_last != 0;
+    __syncthreads();
+    if (!last)
+        return;
+    __threadfence();
+    const sparkcl_result *res = L.results;
+    Red t = combine_ordered(L.ntasks, [&](uint32_t k, double &s, float &m,
+                                          uint64_t &h, uint64_t &n) {
+        read_result(res + k, s, m, h, n);
+    });
+    if (threadIdx.x == 0) {
+        if (L.total)
+            write_result(L.total, SPARKCL_SUM | SPARKCL_MAX | SPARKCL_COUNT, t,
+                         0, device_ns(L.ns_per_tick));
+        __hip_atomic_store(&L.ctl->rdd_ticket, 0u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+    }
+}
+
+// ---- kernels --------------------------------------------------------------
+
+// One partition per launch: blocks stride over the task's tiles.
+__global__ __launch_bounds__(kBlock) void k_task(const TaskDev *__restrict__ task,
+                                                 LaunchOut L)
+{
+    const uint32_t ntiles = uni(task->ntiles);
+    for (uint32_t j = blockIdx.x; j < ntiles; j += gridDim.x)
+        if (run_tile(task, j, L))
+            rdd_step(L);
+}
+
+// Persistent executor: a fixed grid of blocks takes tiles from the queue with
+// one atomic each until the queue is empty.  The last block to leave resets
+// the queue head, so the launch can be replayed from a graph as is.
+__global__ __launch_bounds__(kBlock) void k_batch(const TaskDev *__restrict__ tasks,
+                                                  const TileRef *__restrict__ tiles,
+                                                  uint32_t ntiles, LaunchOut L)
+{
+    __shared__ uint32_t sh_tile;
+    for (;;) {
+        if (threadIdx.x == 0)
+            sh_tile = atomicAdd(&L.ctl->head, 1u);
+        __syncthreads();
+        const uint32_t t = uni(sh_tile);
+        __syncthreads();
+        if (t >= ntiles)
+            break;
+        const TileRef tr = tiles[t];
+        const TaskDev *tp = tasks + uni(tr.task);
+        if (run_tile(tp, uni(tr.tile), L))
+            rdd_step(L);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&L.ctl->exited, 1u) == gridDim.x - 1) {
+            __hip_atomic_store(&L.ctl->head, 0u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&L.ctl->exited, 0u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+        }
+    }
+}
+
+// MapCL materialisation only (no reduction): out[i] = map(x[i] [, y[i]]),
+// grid-stride over float4 quads when the arrays share their alignment.
+template <class M>
+__device__ __forceinline__ void map_only(const M &f, const float *__restrict__ x,
+                                         const float *__restrict__ y,
+                                         float *__restrict__ out, uint64_t n)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    const uint64_t gtid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uintptr_t ax = (uintptr_t)x;
+    bool vec = ((ax ^ (uintptr_t)out) & 15u) == 0;
+    if (M::kTwo && ((ax ^ (uintptr_t)y) & 15u))
+        vec = false;
+    const uint64_t head = vec ? min((uint64_t)((4u - ((ax & 15u) >> 2)) & 3u), n) : n;
+    for (uint64_t i = gtid; i < head; i += stride)
+        out[i] = f(x[i], M::kTwo ? y[i] : 0.0f);
+    if (!vec)
+        return;
+    const uint64_t nq = (n - head) >> 2;
+    const float4 *x4 = reinterpret_cast<const float4 *>(x + head);
+    const float4 *y4 = M::kTwo ? reinterpret_cast<const float4 *>(y + head) : nullptr;
+    float4 *o4 = reinterpret_cast<float4 *>(out + head);
+    for (uint64_t q = gtid; q < nq; q += stride) {
+        const float4 xv = x4[q];
+        const float4 yv = M::kTwo ? y4[q] : xv;
+        float4 v;
+        v.x = f(xv.x, yv.x);
+        v.y = f(xv.y, yv.y);
+        v.z = f(xv.z, yv.z);
+        v.w = f(xv.w, yv.w);
+        o4[q] = v;
+    }
+    const uint64_t t0 = head + 4 * nq;
+    if (gtid < n - t0)
+        out[t0 + gtid] = f(x[t0 + gtid], M::kTwo ? y[t0 + gtid] : 0.0f);
+}
+
+__global__ __launch_bounds__(kBlock) void k_map(const TaskDev *__restrict__ tp,
+                                                uint64_t n, uint32_t variant)
+{
+    const float *x = tp->in0;
+    const float *y = tp->in1;
+    float *o = tp->out;
+    if (variant < V_FMUL) {
+        float k[8];
+        for (int i = 0; i < 8; ++i)
+            k[i] = tp->coef[i];
+#define SPARKCL_MAP_CASE(D)                                                    \
+    case D: {                                                                  \
+        PolyMap<D> f;                                                          \
+        for (int i = 0; i < 8; ++i)                                            \
+            f.k[i] = k[i];                                                     \
+        map_only(f, x, y, o, n);                                               \
+    } break;
+        switch (variant & 7u) {
+            SPARKCL_MAP_CASE(0)
+            SPARKCL_MAP_CASE(1)
+            SPARKCL_MAP_CASE(2)
+            SPARKCL_MAP_CASE(3)
+            SPARKCL_MAP_CASE(4)
+            SPARKCL_MAP_CASE(5)
+            SPARKCL_MAP_CASE(6)
+            SPARKCL_MAP_CASE(7)
+        }
+#undef SPARKCL_MAP_CASE
+    } else {
+        FmulMap f{tp->c};
+        map_only(f, x, y, o, n);
+    }
+}
+
+// Clears library workspaces with a kernel (no memset nodes in captured work).
+__global__ __launch_bounds__(kBlock) void k_zero(uint32_t *p, uint64_t words)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < words; i += stride)
+        p[i] = 0u;
+}
+
+// Synthetic data for the autotuner: a cheap hash pattern in [-1, 1).
+__global__ __launch_bounds__(kBlock) void k_fill_pattern(float *p, uint64_t n,
+                                                         uint32_t salt)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        uint32_t h = (uint32_t)i * 0x9E3779B1u ^ salt;
+        h ^= h >> 15;
+        h *= 0x85EBCA6Bu;
+        h ^= h >> 13;
+        p[i] = (float)((int32_t)(h >> 8) - (1 << 23)) * (1.0f / 8388608.0f);
+    }
+}
+
+// ---- resident serving executor -------------------------------------------
+// Block 0 is the dispatcher: it polls the host ring's tail word (system
+// scope), copies each new descriptor into the device table, writes the task's
+// tiles into the tile map and publishes the new tile count.  Every other block
+// is a worker: it claims published tiles one at a time with a compare-and-swap
+// (never claiming a tile that is not yet published) and runs each exactly as
+// the batch executor does; a task's last tile writes its result to host
+// memory and then its completion word.  Every wait is bounded: the dispatcher
+// leaves on the host's stop word, or after idle_ticks without new work once
+// every published tile is claimed; a worker leaves when the dispatcher says so
+// (checked before each claim) or after four idle periods without a tile.
+
+static_assert(offsetof(TaskDev, ntiles) == 96, "word 24 of a descriptor");
+static_assert(offsetof(TaskDev, tile_first) == 120, "words 30-31 of a descriptor");
+
+__device__ void serve_dispatch(const ServeArgs &a)
+{
+    __shared__ uint64_t sh_tail, sh_stop;
+    __shared__ uint32_t sh_nt, sh_first_lo, sh_first_hi;
+    uint64_t taken = uni64(ld_agent(&a.dev->taken));
+    uint64_t last = wall_clock64();
+    for (;;) {
+        if (threadIdx.x == 0) {
+            sh_tail = __hip_atomic_load(&a.host->tail, __ATOMIC_ACQUIRE,
+                                        __HIP_MEMORY_SCOPE_SYSTEM);
+            sh_stop = __hip_atomic_load(&a.host->stop, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        __syncthreads();
+        const uint64_t tail = uni64(sh_tail);
+        const bool stop = sh_stop != 0;
+        __syncthreads();
+        if (stop)
+            break;
+        if (tail > taken) {
+            uint64_t pub = 0;
+            for (uint64_t s = taken; s < tail; ++s) {
+                const uint32_t slot = (uint32_t)(s & (a.cap - 1));
+                if (threadIdx.x < 32) {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+                    uint32_t *src = reinterpret_cast<uint32_t *>(
+                                        const_cast<TaskDev *>(a.ring + slot)) + threadIdx.x;
+                    uint32_t *dst = reinterpret_cast<uint32_t *>(a.table + slot) + threadIdx.x;
+                    const uint32_t w = __hip_atomic_load(src, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_SYSTEM);
+                    __hip_atomic_store(dst, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (threadIdx.x == 24)
+                        sh_nt = w;
+                    if (threadIdx.x == 30)
+                        sh_first_lo = w;
+                    if (threadIdx.x == 31)
+                        sh_first_hi = w;
+                }
+                __syncthreads();
+                const uint64_t first = ((uint64_t)sh_first_hi << 32) | sh_first_lo;
+                const uint32_t nt = sh_nt;
+                for (uint32_t k = threadIdx.x; k < nt; k += kBlock)
+                    __hip_atomic_store(a.tilemap + ((first + k) & (a.tile_cap - 1)), slot,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                pub = first + nt;
+                __syncthreads();
+            }
+            __threadfence();
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                st_agent(&a.dev->taken, tail);
+                __hip_atomic_store(&a.dev->tiles_pub, pub, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+            taken = tail;
+            last = wall_clock64();
+            continue;
+        }
+        if (wall_clock64() - last > a.idle_ticks &&
+            ld_agent(&a.dev->claim) >= ld_agent(&a.dev->tiles_pub))
+            break;
+        __builtin_amdgcn_s_sleep(8);
+    }
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&a.dev->stop, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ void serve_work(const ServeArgs &a)
+{
+    __shared__ uint64_t sh_tile;
+    __shared__ TaskDev sh_task;
+    constexpr uint64_t kNone = ~0ull;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            uint64_t got = kNone;
+            const uint64_t wait0 = wall_clock64();
+            for (;;) {
+                // the stop word is checked before every claim, so a stop from
+                // the host takes effect after the tiles already running
+                const uint32_t stop = __hip_atomic_load(&a.dev->stop, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t p = __hip_atomic_load(&a.dev->tiles_pub, __ATOMIC_ACQUIRE,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                if (stop)
+                    break;
+                uint64_t c = __hip_atomic_load(&a.dev->claim, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                if (c < p) {
+                    if (__hip_atomic_compare_exchange_strong(&a.dev->claim, &c, c + 1,
+                                                             __ATOMIC_ACQ_REL,
+                                                             __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT)) {
+                        got = c;
+                        break;
+                    }
+                    continue;
+                }
+                if (wall_clock64() - wait0 > 4 * a.idle_ticks)
+                    break;
+                __builtin_amdgcn_s_sleep(2);
+            }
+            sh_tile = got;
+        }
+        __syncthreads();
+        const uint64_t t = uni64(sh_tile);
+        if (t == kNone)
+            break;
+        if (threadIdx.x < 32) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const uint32_t slot = __hip_atomic_load(a.tilemap + (t & (a.tile_cap - 1)),
+                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint32_t *src = reinterpret_cast<uint32_t *>(a.table + slot) + threadIdx.x;
+            reinterpret_cast<uint32_t *>(&sh_task)[threadIdx.x] =
+                __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        const uint32_t j = (uint32_t)(t - sh_task.tile_first);
+        run_tile(&sh_task, j, a.out);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_serve(ServeArgs a)
+{
+    if (blockIdx.x == 0)
+        serve_dispatch(a);
+    else
+        serve_work(a);
+}
+
+int hip_status(hipError_t e)
+{
+    return e == hipSuccess ? SPARKCL_OK : SPARKCL_EHIP;
+}
+
+} // namespace
+
+int launch_task(const TaskDev *dtask, uint32_t ntiles, uint32_t grid,
+                const LaunchOut &out, void *stream)
+{
+    if (ntiles == 0 || grid == 0)
+        return SPARKCL_EINVAL;
+    grid = grid < ntiles ? grid : ntiles;
+    hipLaunchKernelGGL(k_task, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
+                       dtask, out);
+    return hip_status(hipGetLastError());
+}
+
+int launch_batch(const TaskDev *dtasks, const TileRef *tiles, uint32_t ntiles,
+                 uint32_t grid, const LaunchOut &out, void *stream)
+{
+    if (ntiles == 0 || grid == 0)
+        return SPARKCL_EINVAL;
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
+                       dtasks, tiles, ntiles, out);
+    return hip_status(hipGetLastError());
+}
+
+int launch_map(const TaskDev *dtask, uint64_t n, uint32_t variant, uint32_t grid,
+               void *stream)
+{
+    if (grid == 0)
+        return SPARKCL_EINVAL;
+    hipLaunchKernelGGL(k_map, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
+                       dtask, n, variant);
+    return hip_status(hipGetLastError());
+}
+
+int launch_zero(void *p, uint64_t bytes, void *stream)
+{
+    if (bytes % 4 != 0 || ((uintptr_t)p & 3u))
+        return SPARKCL_EINVAL;
+    const uint64_t words = bytes / 4;
+    if (words == 0)
+        return SPARKCL_OK;
+    uint64_t grid = (words + kBlock - 1) / kBlock;
+    if (grid > 4096)
+        grid = 4096;
+    hipLaunchKernelGGL(k_zero, dim3((uint32_t)grid), dim3(kBlock), 0,
+                       (hipStream_t)stream, (uint32_t *)p, words);
+    return hip_status(hipGetLastError());
+}
+
+int launch_fill_pattern(float *p, uint64_t n, uint32_t salt, void *stream)
+{
+    if (n == 0)
+        return SPARKCL_OK;
+    uint64_t grid = (n + kBlock - 1) / kBlock;
+    if (grid > 8192)
+        grid = 8192;
+    hipLaunchKernelGGL(k_fill_pattern, dim3((uint32_t)grid), dim3(kBlock), 0,
+                       (hipStream_t)stream, p, n, salt);
+    return hip_status(hipGetLastError());
+}
+
+int launch_serve(const ServeArgs &a, uint32_t workers, void *stream)
+{
+    if (workers == 0 || a.cap == 0 || (a.cap & (a.cap - 1)) || a.tile_cap == 0 ||
+        (a.tile_cap & (a.tile_cap - 1)))
+        return SPARKCL_EINVAL;
+    hipLaunchKernelGGL(k_serve, dim3(workers + 1), dim3(kBlock), 0, (hipStream_t)stream, a);
+    return hip_status(hipGetLastError());
+}
+
+int batch_blocks_per_cu(int *out)
+{
+    return hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        out, reinterpret_cast<const void *>(k_batch), kBlock, 0));
+}
+
+} // namespace sparkcl

@@ -1,0 +1,103 @@
+// Internal runtime types shared by the C ABI (api.cpp) and the serving loop
+// (serve.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <list>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "arena.h"
+#include "sparkcl.h"
+#include "sparkcl_dev.h"
+#include "tuning.h"
+
+namespace sparkcl {
+
+// Sets this thread's sparkcl_last_error() text and returns `code`.
+int fail(int code, const std::string &msg);
+int fail_hip(hipError_t e, const char *what);
+
+#define SPARKCL_HIP(expr)                                                      \
+    do {                                                                       \
+        hipError_t e_ = (expr);                                                \
+        if (e_ != hipSuccess)                                                  \
+            return ::sparkcl::fail_hip(e_, #expr);                             \
+    } while (0)
+
+// Validates one task and derives its kernel body selector.
+int check_task(const sparkcl_task &t, uint32_t *variant);
+
+// Host steady-clock time in ns.
+uint64_t host_ns();
+
+class Server;
+
+// A cached, uploaded launch: device task table, tile queue, partials, sync
+// words and results, plus (batched mode) an instantiated graph.
+struct Plan {
+    uint64_t hash = 0;
+    int kind = 0; // 0 reduce/map_partition, 1 map
+    int mode = 0;
+    std::vector<sparkcl_task> tasks;
+    sparkcl_result *user_results = nullptr;
+    sparkcl_result *user_total = nullptr;
+
+    std::vector<uint64_t> blocks; // arena offsets owned
+    TaskDev *dtasks = nullptr;
+    TileRef *dtiles = nullptr;
+    Partial *dparts = nullptr;
+    TaskSync *dsync = nullptr;
+    BatchCtl *dctl = nullptr;
+    sparkcl_result *dresults = nullptr;
+    sparkcl_result *dtotal = nullptr;
+    uint32_t ntasks = 0;
+    uint32_t ntiles_total = 0;
+    std::vector<uint32_t> ntiles;
+    std::vector<uint32_t> variants;
+    uint32_t grid = 0;
+    LaunchOut out{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+};
+
+// Plan cache and launch helpers (api.cpp); the caller holds ctx->mu.
+int get_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
+             uint32_t ntasks, sparkcl_result *ures, sparkcl_result *utot,
+             hipStream_t stream, Plan **out);
+int enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream);
+void drop_plans(sparkcl_ctx *ctx);
+uint32_t exec_grid(const sparkcl_ctx *ctx);
+
+} // namespace sparkcl
+
+struct sparkcl_ctx {
+    int device = 0;
+    std::string arch;
+    int cus = 0;
+    uint32_t ns_per_tick = 10;
+    int occ_batch = 1; // batch-executor blocks per CU that fit
+
+    char *arena_base = nullptr;
+    bool own_arena = false;
+    sparkcl::Arena arena;
+
+    sparkcl_tuning tuning{};
+    sparkcl_config config{};
+
+    std::mutex mu; // plans, events, pinned buffers
+    std::list<sparkcl::Plan *> plans; // most recently used first
+    hipStream_t capture_stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool have_ms = false;
+    sparkcl_result *pinned = nullptr;
+    uint32_t pinned_cap = 0;
+
+    std::unique_ptr<sparkcl::Server> server;
+
+    void *dev(uint64_t off) const { return arena_base + off; }
+};

@@ -1,0 +1,557 @@
+// Serving loop: continuous batching of partition tasks onto one GPU.
+//
+// Callers submit tasks at any time (sparkcl_submit stamps the arrival).  A
+// host thread admits them in FIFO order as ring slots, HBM budget and tile-map
+// room free up (admission.h), writes each admitted task's descriptor into a
+// ring of host-coherent pinned memory and release-stores the ring's tail.  The
+// resident executor (k_serve: one dispatcher block plus worker blocks) picks
+// the new descriptors up without any launch, spreads each task's tiles over
+// the workers while earlier tasks are still running, and each task's last
+// tile writes the result and a completion word into host memory.  The thread
+// reaps completions, frees the task's budget, slot and partials, and keeps the
+// result until sparkcl_poll collects it.  An idle executor exits on its own
+// and is relaunched when work arrives.
+//
+// The same machinery also runs the baseline the paper's workers use: one
+// kernel launch per task (SPARKCL_FLAG_SERVE_PER_TASK), spread over a pool of
+// streams, with the same admission, descriptors and completion words.
+//
+// Where the paper serialises accelerator tasks per worker to avoid contention
+// (`--cores 1`, sec. 3.1.5), this loop shares the GPU between tasks and keeps
+// them within the memory budget instead; memory management and data layout
+// are the framework's job (sec. 3, issue 3).
+#include "serve.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+
+namespace sparkcl {
+
+namespace {
+
+constexpr uint32_t kTileCap = 1u << 20;     // tile map entries
+constexpr uint32_t kPoolStreams = 4;        // per-task launch baseline
+constexpr uint64_t kMaxPending = 1u << 22;  // queued tasks before EAGAIN
+constexpr uint64_t kSpinNs = 2000000;       // busy-poll this long after activity
+
+uint64_t task_bytes(const sparkcl_task &t, uint32_t ntiles)
+{
+    uint64_t in = 0;
+    if (t.kernel_id == SPARKCL_POLY)
+        in = 4 * t.n;
+    else if (t.kernel_id == SPARKCL_FMUL)
+        in = 8 * t.n;
+    const uint64_t out = (t.out && t.kernel_id != SPARKCL_MC_PI) ? 4 * t.n : 0;
+    return in + out + sizeof(Partial) * (uint64_t)ntiles;
+}
+
+sparkcl_result failed_result(int code)
+{
+    sparkcl_result r;
+    std::memset(&r, 0, sizeof(r));
+    r.max = -__builtin_huge_valf();
+    r.status = code;
+    return r;
+}
+
+} // namespace
+
+Server::Server(sparkcl_ctx *ctx)
+    : ctx_(ctx), adm_(ctx->config.budget_bytes, ctx->config.ring_capacity, kTileCap)
+{
+}
+
+int Server::create(sparkcl_ctx *ctx, std::unique_ptr<Server> *out)
+{
+    std::unique_ptr<Server> s(new Server(ctx));
+    int rc = s->init();
+    if (rc != SPARKCL_OK)
+        return rc;
+    *out = std::move(s);
+    return SPARKCL_OK;
+}
+
+int Server::init()
+{
+    cap_ = ctx_->config.ring_capacity;
+    tile_cap_ = kTileCap;
+    per_task_launch_ = (ctx_->config.flags & SPARKCL_FLAG_SERVE_PER_TASK) != 0;
+    workers_ = 2u * (uint32_t)ctx_->cus;
+
+    const size_t bytes = sizeof(ServeHost) + (size_t)cap_ * sizeof(TaskDev) +
+                         (size_t)cap_ * sizeof(sparkcl_result) + (size_t)cap_ * sizeof(uint64_t);
+    SPARKCL_HIP(hipHostMalloc((void **)&pinned_, bytes,
+                              hipHostMallocCoherent | hipHostMallocMapped));
+    std::memset(pinned_, 0, bytes);
+    char *p = pinned_;
+    host_ = reinterpret_cast<ServeHost *>(p);
+    p += sizeof(ServeHost);
+    ring_ = reinterpret_cast<TaskDev *>(p);
+    p += (size_t)cap_ * sizeof(TaskDev);
+    results_ = reinterpret_cast<sparkcl_result *>(p);
+    p += (size_t)cap_ * sizeof(sparkcl_result);
+    done_ = reinterpret_cast<uint64_t *>(p);
+
+    auto take = [&](uint64_t n, void **out) -> int {
+        const uint64_t off = ctx_->arena.alloc(n);
+        if (off == Arena::kFail)
+            return fail(SPARKCL_ENOMEM, "arena too small for the serving tables");
+        blocks_.push_back(off);
+        *out = ctx_->dev(off);
+        return SPARKCL_OK;
+    };
+    int rc;
+    void *m;
+    if ((rc = take(sizeof(ServeDev), &m)) != SPARKCL_OK)
+        return rc;
+    dev_ = static_cast<ServeDev *>(m);
+    if ((rc = take((uint64_t)cap_ * sizeof(TaskDev), &m)) != SPARKCL_OK)
+        return rc;
+    table_ = static_cast<TaskDev *>(m);
+    if ((rc = take((uint64_t)tile_cap_ * sizeof(uint32_t), &m)) != SPARKCL_OK)
+        return rc;
+    tilemap_ = static_cast<uint32_t *>(m);
+    if ((rc = take((uint64_t)cap_ * sizeof(TaskSync), &m)) != SPARKCL_OK)
+        return rc;
+    sync_ = static_cast<TaskSync *>(m);
+
+    SPARKCL_HIP(hipStreamCreateWithFlags(&exec_stream_, hipStreamNonBlocking));
+    if ((rc = launch_zero(dev_, sizeof(ServeDev), exec_stream_)) != SPARKCL_OK ||
+        (rc = launch_zero(sync_, (uint64_t)cap_ * sizeof(TaskSync), exec_stream_)) != SPARKCL_OK)
+        return fail(rc, "clearing the serving tables failed");
+    SPARKCL_HIP(hipStreamSynchronize(exec_stream_));
+    if (per_task_launch_) {
+        pool_.resize(kPoolStreams);
+        for (auto &s : pool_)
+            SPARKCL_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    }
+    return SPARKCL_OK;
+}
+
+Server::~Server()
+{
+    shutdown();
+}
+
+int Server::start_thread_locked()
+{
+    if (started_)
+        return SPARKCL_OK;
+    started_ = true;
+    thread_ = std::thread([this] { loop(); });
+    return SPARKCL_OK;
+}
+
+int Server::submit(const sparkcl_task &task, uint64_t *ticket)
+{
+    uint32_t variant = 0;
+    int rc = check_task(task, &variant);
+    if (rc != SPARKCL_OK)
+        return rc;
+    const uint32_t tile = tile_for(ctx_->tuning, TM_SERVE, task.kernel_id, task.n);
+    const uint64_t nt64 = std::max<uint64_t>(1, (task.n + tile - 1) / tile);
+    if (nt64 > tile_cap_)
+        return fail(SPARKCL_ETOOBIG, "task needs more tiles than the tile map holds");
+    const uint32_t ntiles = (uint32_t)nt64;
+    const uint64_t bytes = task_bytes(task, ntiles);
+    if (!adm_.fits_at_all(bytes, ntiles))
+        return fail(SPARKCL_ETOOBIG, "task needs " + std::to_string(bytes) +
+                                         " bytes, budget is " + std::to_string(adm_.budget()));
+    std::lock_guard<std::mutex> g(mu_);
+    if (quit_)
+        return fail(SPARKCL_ESTOPPED, "serving is shutting down");
+    if (adm_.pending() >= kMaxPending)
+        return fail(SPARKCL_EAGAIN, "pending queue full");
+    Pending p;
+    p.ticket = next_ticket_++;
+    p.bytes = bytes;
+    p.ntiles = ntiles;
+    p.t_arrive = host_ns();
+    adm_.push(p);
+    Waiting w;
+    w.task = task;
+    w.ntiles = ntiles;
+    w.tile = tile;
+    w.variant = variant;
+    waiting_[p.ticket] = w;
+    ++submitted_;
+    *ticket = p.ticket;
+    start_thread_locked();
+    cv_work_.notify_one();
+    return SPARKCL_OK;
+}
+
+int Server::poll(uint64_t ticket, sparkcl_result *result)
+{
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = done_map_.find(ticket);
+    if (it != done_map_.end()) {
+        *result = it->second;
+        done_map_.erase(it);
+        return SPARKCL_OK;
+    }
+    if (waiting_.count(ticket))
+        return SPARKCL_EAGAIN;
+    return fail(SPARKCL_ENOTFOUND, "unknown or already collected ticket");
+}
+
+void Server::stats(sparkcl_serve_stats *s)
+{
+    std::lock_guard<std::mutex> g(mu_);
+    s->submitted = submitted_;
+    s->admitted = admitted_;
+    s->completed = completed_;
+    s->failed = failed_;
+    s->pending = adm_.pending();
+    s->in_flight = adm_.in_flight();
+    s->budget_in_use = adm_.in_use();
+    s->budget_peak = adm_.peak();
+    s->admission_waits = waits_;
+    s->executor_launches = launches_;
+}
+
+int Server::drain(uint32_t timeout_ms)
+{
+    std::unique_lock<std::mutex> lk(mu_);
+    const bool ok = cv_done_.wait_for(lk, std::chrono::milliseconds(timeout_ms),
+                                      [this] { return waiting_.empty(); });
+    return ok ? SPARKCL_OK : fail(SPARKCL_ETIMEDOUT, "drain timed out");
+}
+
+// Admit queued tasks while the head fits; the admitted ones are appended to
+// the in-flight list and copied to *out.
+void Server::admit_some(std::vector<Flight> *out)
+{
+    std::lock_guard<std::mutex> g(mu_);
+    for (;;) {
+        const AdmitBlock b = adm_.head_block();
+        if (b == AdmitBlock::EMPTY)
+            break;
+        if (b != AdmitBlock::NONE) {
+            ++waits_;
+            break;
+        }
+        Admitted a = adm_.admit_head();
+        const Waiting &w = waiting_[a.p.ticket];
+        const uint64_t off = ctx_->arena.alloc(sizeof(Partial) * (uint64_t)w.ntiles);
+        if (off == Arena::kFail) {
+            adm_.unadmit(a);
+            ++waits_;
+            break;
+        }
+        Flight f;
+        f.a = a;
+        f.task = w.task;
+        f.variant = w.variant;
+        f.part_off = off;
+        f.t_admit = host_ns();
+        flight_.push_back(f);
+        out->push_back(f);
+        ++admitted_;
+    }
+}
+
+// Write the descriptors of newly admitted tasks and hand them to the GPU.
+int Server::publish(const std::vector<Flight> &fl)
+{
+    if (fl.empty())
+        return SPARKCL_OK;
+    for (const Flight &f : fl) {
+        const sparkcl_task &t = f.task;
+        TaskDev d;
+        std::memset(&d, 0, sizeof(d));
+        d.kid = t.kernel_id;
+        d.ops = t.reduce_ops;
+        d.n = t.n;
+        d.in0 = t.in0;
+        d.in1 = t.in1;
+        d.out = t.out;
+        d.seed = t.seed;
+        d.pid = t.partition_id;
+        d.variant = f.variant;
+        std::memcpy(d.coef, t.coef, sizeof(d.coef));
+        d.c = t.c;
+        d.tile_elems = tile_for(ctx_->tuning, TM_SERVE, t.kernel_id, t.n);
+        d.ntiles = f.a.p.ntiles;
+        d.index = f.a.slot;
+        d.partials = static_cast<Partial *>(ctx_->dev(f.part_off));
+        d.seq = f.a.seq;
+        d.tile_first = tiles_pub_host_;
+        tiles_pub_host_ += d.ntiles;
+        std::memcpy(ring_ + f.a.slot, &d, sizeof(d));
+    }
+    if (per_task_launch_) {
+        LaunchOut L{};
+        L.sync = sync_;
+        L.results = results_;
+        L.done = done_;
+        L.ntasks = 0;
+        L.ns_per_tick = ctx_->ns_per_tick;
+        const uint32_t cap = (uint32_t)ctx_->cus * (uint32_t)ctx_->occ_batch;
+        for (const Flight &f : fl) {
+            hipStream_t s = pool_[pool_next_++ % pool_.size()];
+            const uint32_t slot = f.a.slot;
+            SPARKCL_HIP(hipMemcpyAsync(table_ + slot, ring_ + slot, sizeof(TaskDev),
+                                       hipMemcpyHostToDevice, s));
+            const uint32_t nt = f.a.p.ntiles;
+            int rc = launch_task(table_ + slot, nt, std::min(nt, cap), L, s);
+            if (rc != SPARKCL_OK)
+                return fail(rc, "per-task launch failed");
+        }
+        std::lock_guard<std::mutex> g(mu_);
+        launches_ += fl.size();
+        return SPARKCL_OK;
+    }
+    __atomic_store_n(&host_->tail, fl.back().a.seq + 1, __ATOMIC_RELEASE);
+    return SPARKCL_OK;
+}
+
+bool Server::executor_running()
+{
+    if (!exec_launched_)
+        return false;
+    if (hipStreamQuery(exec_stream_) == hipSuccess)
+        exec_launched_ = false;
+    return exec_launched_;
+}
+
+int Server::launch_executor()
+{
+    ServeArgs a{};
+    a.host = host_;
+    a.ring = ring_;
+    a.dev = dev_;
+    a.table = table_;
+    a.tilemap = tilemap_;
+    a.out.sync = sync_;
+    a.out.results = results_;
+    a.out.done = done_;
+    a.out.ntasks = 0;
+    a.out.ns_per_tick = ctx_->ns_per_tick;
+    a.cap = cap_;
+    a.tile_cap = tile_cap_;
+    a.idle_ticks = (uint64_t)ctx_->config.idle_exit_ms * 1000000ull / ctx_->ns_per_tick;
+    int rc = launch_zero(&dev_->stop, 8, exec_stream_);
+    if (rc == SPARKCL_OK)
+        rc = launch_serve(a, workers_, exec_stream_);
+    if (rc != SPARKCL_OK)
+        return fail(rc, "resident executor launch failed");
+    exec_launched_ = true;
+    std::lock_guard<std::mutex> g(mu_);
+    ++launches_;
+    return SPARKCL_OK;
+}
+
+int Server::stop_executor(uint32_t timeout_ms)
+{
+    int rc = SPARKCL_OK;
+    const uint64_t t0 = host_ns();
+    auto wait_stream = [&](hipStream_t s) {
+        while (hipStreamQuery(s) == hipErrorNotReady) {
+            if (host_ns() - t0 > (uint64_t)timeout_ms * 1000000ull) {
+                rc = fail(SPARKCL_ETIMEDOUT, "executor did not stop");
+                return;
+            }
+            std::this_thread::sleep_for(std::chrono::microseconds(100));
+        }
+    };
+    __atomic_store_n(&host_->stop, 1ull, __ATOMIC_RELEASE);
+    wait_stream(exec_stream_);
+    for (hipStream_t s : pool_)
+        wait_stream(s);
+    if (rc == SPARKCL_OK) {
+        __atomic_store_n(&host_->stop, 0ull, __ATOMIC_RELEASE);
+        exec_launched_ = false;
+    }
+    return rc;
+}
+
+// Completes every in-flight task whose completion word is set.
+bool Server::reap()
+{
+    bool any = false;
+    std::lock_guard<std::mutex> g(mu_);
+    for (size_t i = 0; i < flight_.size();) {
+        Flight &f = flight_[i];
+        const uint64_t d = __atomic_load_n(done_ + f.a.slot, __ATOMIC_ACQUIRE);
+        if (d != f.a.seq + 1) {
+            ++i;
+            continue;
+        }
+        sparkcl_result r = results_[f.a.slot];
+        r.t_arrive_ns = f.a.p.t_arrive;
+        r.t_admit_ns = f.t_admit;
+        r.t_done_ns = host_ns();
+        ctx_->arena.release(f.part_off);
+        adm_.complete(f.a);
+        done_map_[f.a.p.ticket] = r;
+        waiting_.erase(f.a.p.ticket);
+        ++completed_;
+        flight_[i] = flight_.back();
+        flight_.pop_back();
+        any = true;
+    }
+    if (any)
+        cv_done_.notify_all();
+    return any;
+}
+
+void Server::fail_in_flight(int code)
+{
+    std::lock_guard<std::mutex> g(mu_);
+    for (Flight &f : flight_) {
+        sparkcl_result r = failed_result(code);
+        r.n = f.task.n;
+        r.t_arrive_ns = f.a.p.t_arrive;
+        r.t_admit_ns = f.t_admit;
+        r.t_done_ns = host_ns();
+        ctx_->arena.release(f.part_off);
+        adm_.complete(f.a);
+        done_map_[f.a.p.ticket] = r;
+        waiting_.erase(f.a.p.ticket);
+        ++failed_;
+    }
+    flight_.clear();
+    cv_done_.notify_all();
+}
+
+// After a stop: bring the device control block in line with the host so the
+// next launch starts from a clean state (nothing claimable, tickets cleared).
+int Server::reset_device_state()
+{
+    ServeDev d;
+    std::memset(&d, 0, sizeof(d));
+    d.taken = __atomic_load_n(&host_->tail, __ATOMIC_ACQUIRE);
+    d.tiles_pub = tiles_pub_host_;
+    d.claim = tiles_pub_host_;
+    SPARKCL_HIP(hipMemcpyAsync(dev_, &d, sizeof(d), hipMemcpyHostToDevice, exec_stream_));
+    int rc = launch_zero(sync_, (uint64_t)cap_ * sizeof(TaskSync), exec_stream_);
+    if (rc != SPARKCL_OK)
+        return fail(rc, "clearing serving tickets failed");
+    SPARKCL_HIP(hipStreamSynchronize(exec_stream_));
+    return SPARKCL_OK;
+}
+
+void Server::loop()
+{
+    (void)hipSetDevice(ctx_->device);
+    const uint64_t watchdog_ns = (uint64_t)ctx_->config.watchdog_ms * 1000000ull;
+    uint64_t last_activity = host_ns();
+    uint64_t last_exec_check = 0;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(mu_);
+            if (quit_)
+                break;
+            if (flight_.empty() && adm_.pending() == 0 &&
+                host_ns() - last_activity > kSpinNs) {
+                cv_work_.wait_for(lk, std::chrono::milliseconds(20));
+                continue;
+            }
+        }
+        std::vector<Flight> adm;
+        admit_some(&adm);
+        bool progress = !adm.empty();
+        if (publish(adm) != SPARKCL_OK) {
+            fail_in_flight(SPARKCL_EHIP);
+            continue;
+        }
+        bool have_flight;
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            have_flight = !flight_.empty();
+        }
+        if (have_flight && !per_task_launch_) {
+            const uint64_t now = host_ns();
+            if (!adm.empty() || now - last_exec_check > 50000) {
+                last_exec_check = now;
+                if (!executor_running() && launch_executor() != SPARKCL_OK)
+                    fail_in_flight(SPARKCL_EHIP);
+            }
+        }
+        if (reap())
+            progress = true;
+        // Watchdog: a task stuck past the limit fails every in-flight task
+        // after the executor has been stopped and the device state reset.
+        uint64_t oldest = ~0ull;
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            for (const Flight &f : flight_)
+                oldest = std::min(oldest, f.t_admit);
+        }
+        if (oldest != ~0ull && host_ns() - oldest > watchdog_ns) {
+            if (stop_executor(2000) == SPARKCL_OK) {
+                reap();
+                fail_in_flight(SPARKCL_ETIMEDOUT);
+                reset_device_state();
+            } else {
+                fail_in_flight(SPARKCL_ETIMEDOUT);
+            }
+        }
+        if (progress)
+            last_activity = host_ns();
+        else
+            std::this_thread::yield();
+    }
+    // Shutdown: let in-flight work finish (bounded), then stop the executor.
+    const uint64_t t0 = host_ns();
+    for (;;) {
+        reap();
+        bool empty;
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            empty = flight_.empty();
+        }
+        if (empty || host_ns() - t0 > 10000000000ull)
+            break;
+        if (!per_task_launch_ && !executor_running())
+            launch_executor();
+        std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+    const int rc = stop_executor(10000);
+    reap();
+    fail_in_flight(rc == SPARKCL_OK ? SPARKCL_ESTOPPED : SPARKCL_ETIMEDOUT);
+}
+
+int Server::shutdown()
+{
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        if (quit_ && !thread_.joinable() && !pinned_)
+            return SPARKCL_OK;
+        quit_ = true;
+        // tasks never admitted fail with ESTOPPED
+        for (const Pending &p : adm_.take_queue()) {
+            sparkcl_result r = failed_result(SPARKCL_ESTOPPED);
+            r.t_arrive_ns = p.t_arrive;
+            done_map_[p.ticket] = r;
+            waiting_.erase(p.ticket);
+            ++failed_;
+        }
+    }
+    cv_work_.notify_all();
+    if (thread_.joinable())
+        thread_.join();
+    const int rc = stop_executor(10000);
+    if (rc == SPARKCL_OK) {
+        for (hipStream_t s : pool_)
+            (void)hipStreamDestroy(s);
+        pool_.clear();
+        if (exec_stream_)
+            (void)hipStreamDestroy(exec_stream_);
+        exec_stream_ = nullptr;
+        for (uint64_t off : blocks_)
+            ctx_->arena.release(off);
+        blocks_.clear();
+        if (pinned_)
+            (void)hipHostFree(pinned_);
+        pinned_ = nullptr;
+    }
+    // On a timeout the pinned memory is left allocated: a kernel may still
+    // be reading it.
+    cv_done_.notify_all();
+    return rc;
+}
+
+} // namespace sparkcl

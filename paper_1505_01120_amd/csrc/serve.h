@@ -1,0 +1,95 @@
+// Serving loop of the SparkCL hot path: continuous batching of partition tasks
+// onto one GPU (see serve.cpp).
+#pragma once
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "admission.h"
+#include "runtime.h"
+
+namespace sparkcl {
+
+class Server {
+  public:
+    static int create(sparkcl_ctx *ctx, std::unique_ptr<Server> *out);
+    ~Server();
+
+    int submit(const sparkcl_task &task, uint64_t *ticket);
+    int poll(uint64_t ticket, sparkcl_result *result);
+    void stats(sparkcl_serve_stats *s);
+    int drain(uint32_t timeout_ms);
+    int shutdown();
+
+  private:
+    explicit Server(sparkcl_ctx *ctx);
+    int init();
+    void loop();
+    int start_thread_locked();
+    // serving-thread helpers (called without mu_ held unless noted)
+    struct Flight;
+    void admit_some(std::vector<Flight> *out);
+    int publish(const std::vector<Flight> &fl);
+    bool reap();
+    bool executor_running();
+    int launch_executor();
+    int stop_executor(uint32_t timeout_ms);
+    void fail_in_flight(int code);
+    int reset_device_state();
+
+    struct Flight {
+        Admitted a;
+        sparkcl_task task;
+        uint32_t variant = 0;
+        uint64_t part_off = 0; // arena block for the partials
+        uint64_t t_admit = 0;
+    };
+    struct Waiting {
+        sparkcl_task task;
+        uint32_t ntiles = 0, tile = 0, variant = 0;
+    };
+
+    sparkcl_ctx *ctx_;
+    bool per_task_launch_ = false;
+    uint32_t cap_ = 0, tile_cap_ = 0;
+    uint32_t workers_ = 0;
+
+    // host-coherent (pinned) memory shared with the device
+    char *pinned_ = nullptr;
+    ServeHost *host_ = nullptr;
+    TaskDev *ring_ = nullptr;
+    sparkcl_result *results_ = nullptr;
+    uint64_t *done_ = nullptr;
+    // device memory (arena)
+    std::vector<uint64_t> blocks_;
+    ServeDev *dev_ = nullptr;
+    TaskDev *table_ = nullptr;
+    uint32_t *tilemap_ = nullptr;
+    TaskSync *sync_ = nullptr;
+
+    hipStream_t exec_stream_ = nullptr;
+    std::vector<hipStream_t> pool_; // per-task launch mode
+    uint32_t pool_next_ = 0;
+    bool exec_launched_ = false;
+    uint64_t tiles_pub_host_ = 0; // tiles handed out so far (global index)
+
+    std::mutex mu_; // queue, tables, counters below
+    std::condition_variable cv_work_, cv_done_;
+    Admission adm_;
+    std::unordered_map<uint64_t, Waiting> waiting_;     // ticket -> task (queued)
+    std::unordered_map<uint64_t, sparkcl_result> done_map_;
+    std::vector<Flight> flight_; // admitted, not complete (serving thread)
+    uint64_t next_ticket_ = 1;
+    uint64_t submitted_ = 0, admitted_ = 0, completed_ = 0, failed_ = 0, waits_ = 0;
+    uint64_t launches_ = 0;
+    bool quit_ = false, started_ = false;
+    std::thread thread_;
+};
+
+} // namespace sparkcl

@@ -1,0 +1,139 @@
+// Device-format descriptors shared by the host runtime and the HIP kernels of
+// the SparkCL hot path.  Not part of the public ABI (include/sparkcl.h).
+#pragma once
+
+#include <stdint.h>
+
+#include "sparkcl.h"
+
+namespace sparkcl {
+
+// Threads per block of every tile kernel.  The per-thread element order inside
+// a tile, and so the rounding of its sum, depends on this constant and on the
+// tile size only.
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+// Loads in flight per thread in the streaming loops (float4 per input).
+constexpr int kUnroll = 4;
+
+// Kernel body selector, derived on the host from (kernel id, degree, output).
+enum Variant : uint32_t {
+    V_POLY = 0,   // V_POLY + d: POLY of degree d, reduce only
+    V_POLYW = 8,  // V_POLYW + d: POLY of degree d, reduce and write map output
+    V_FMUL = 16,  // FMUL, reduce only
+    V_FMULW = 17, // FMUL, reduce and write map output
+    V_MC = 18,    // MC_PI hit count
+    V_COUNT = 19
+};
+
+// One tile's block-combined partial result.
+struct Partial {
+    double sum;
+    float max;
+    uint32_t pad;
+    uint64_t count;
+    uint64_t n;
+};
+static_assert(sizeof(Partial) == 32, "Partial layout");
+
+// A partition task as the kernels read it (128 B, one cache line pair).
+struct TaskDev {
+    uint32_t kid;
+    uint32_t ops;
+    uint64_t n;
+    const float *in0;
+    const float *in1;
+    float *out;
+    uint64_t seed;
+    uint32_t pid;
+    uint32_t variant;
+    float coef[8];
+    float c;
+    uint32_t tile_elems; // tile size in elements (samples for MC_PI); even
+    uint32_t ntiles;     // >= 1 (an empty task has one empty tile)
+    uint32_t index;      // result / sync slot of this task
+    Partial *partials;   // ntiles entries
+    uint64_t seq;        // serving sequence number (0 in batch launches)
+    uint64_t tile_first; // serving: global index of the task's first tile
+};
+static_assert(sizeof(TaskDev) == 128, "TaskDev layout");
+
+// Per-task arrival ticket of the last-block combine; self-resetting.
+struct TaskSync {
+    uint32_t ticket;
+    uint32_t pad;
+    uint64_t t_start; // min device time over the task's tiles; reset to ~0
+};
+static_assert(sizeof(TaskSync) == 16, "TaskSync layout");
+
+// Persistent-executor queue state; every field returns to zero at kernel end
+// so a captured graph can be replayed without clearing it.
+struct BatchCtl {
+    uint32_t head;       // next tile to hand out
+    uint32_t exited;     // blocks that have left the loop
+    uint32_t rdd_ticket; // tasks finished (RDD-level combine)
+    uint32_t pad;
+};
+
+struct TileRef {
+    uint32_t task;
+    uint32_t tile;
+};
+
+// Where a launch writes its results.
+struct LaunchOut {
+    TaskSync *sync;          // per task index
+    BatchCtl *ctl;
+    sparkcl_result *results; // per task index, contiguous
+    sparkcl_result *total;   // RDD-level total, or nullptr
+    uint64_t *done;          // serving: completion words (seq + 1), or nullptr
+    uint32_t ntasks;         // tasks in the RDD-level combine (0: none)
+    uint32_t ns_per_tick;    // device wall clock period
+};
+
+// Serving: host-visible control words of the resident executor (pinned,
+// host-coherent memory).
+struct ServeHost {
+    uint64_t tail;  // tasks published by the host (release-stored)
+    uint64_t stop;  // nonzero: the executor should exit
+    uint64_t pad[6];
+};
+
+// Serving: device-side state of the resident executor.  It persists across
+// relaunches (an idle executor exits and is started again on demand).
+struct ServeDev {
+    uint64_t taken;     // host-ring tasks copied into the device table
+    uint64_t tiles_pub; // tiles published to the workers
+    uint64_t claim;     // next tile to claim
+    uint32_t stop;      // dispatcher tells the workers to exit (reset per launch)
+    uint32_t pad0;
+    uint64_t pad[4];
+};
+
+struct ServeArgs {
+    ServeHost *host;     // host-coherent control words
+    const TaskDev *ring; // host-coherent descriptor ring [cap]
+    ServeDev *dev;       // device control block
+    TaskDev *table;      // device copy of the descriptors [cap]
+    uint32_t *tilemap;   // device tile -> slot map [tile_cap]
+    LaunchOut out;       // sync per slot, host results, host done words
+    uint32_t cap;        // ring capacity (power of two)
+    uint32_t tile_cap;   // tile map capacity (power of two)
+    uint64_t idle_ticks; // executor exits after this many idle clock ticks
+};
+
+// ---- launchers (kernels.hip) ---------------------------------------------
+int launch_task(const TaskDev *dtask, uint32_t ntiles, uint32_t grid,
+                const LaunchOut &out, void *stream);
+int launch_batch(const TaskDev *dtasks, const TileRef *tiles, uint32_t ntiles,
+                 uint32_t grid, const LaunchOut &out, void *stream);
+int launch_map(const TaskDev *dtask, uint64_t n, uint32_t variant,
+               uint32_t grid, void *stream);
+int launch_zero(void *p, uint64_t bytes, void *stream);
+// Resident serving executor: block 0 dispatches, the rest run tiles.
+int launch_serve(const ServeArgs &a, uint32_t workers, void *stream);
+int launch_fill_pattern(float *p, uint64_t n, uint32_t salt, void *stream);
+// Blocks of the batch executor that fit on one CU at once.
+int batch_blocks_per_cu(int *out);
+
+} // namespace sparkcl

@@ -1,0 +1,224 @@
+"""GPU parity: the HIP path through the C ABI against the oracle, element by
+element on the same seeded inputs (MapCL, MapCLPartition, ReduceCL; paper
+sec. 3.1.3).  Sizes span several tiles with ragged tails; the full-size
+workloads are checked on sampled partitions plus size-independent properties.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+import paper_1505_01120_amd as sc
+from gpu_helpers import DevParts, check_result, check_total, dev, oracle_result
+
+pytestmark = pytest.mark.gpu
+
+MODES = [sc.PER_LAUNCH, sc.BATCHED]
+EDGE_N = [0, 1, 3, 4, 5, 63, 64, 65, 255, 257, 1023, 1025, 4095, 4097, 65535,
+          65537, 131073, 1 << 20, (1 << 20) + 3]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = sc.Context(device=0, arena_bytes=2 << 30)
+    yield c
+    c.destroy()
+
+
+def run_and_check(ctx, parts, mode, xoff=0, yoff=0):
+    d = DevParts(parts, xoff, yoff)
+    per, tot = ctx.reduce(d.tasks, mode)
+    want = [oracle_result(p) for p in parts]
+    for p, g, o in zip(parts, per, want):
+        check_result(g, o, p.kid, p.ops, f"kid={p.kid} n={p.n} pid={p.pid} mode={mode}")
+    ops = 0
+    for p in parts:
+        ops |= p.ops
+    check_total(tot, want, ops)
+    return per, tot
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_single_partition_poly_sum(ctx, mode):
+    # 2^20 floats U[-1,1) from seed 0, y = 0.5x^2 - 1.25x + 3, SUM
+    run_and_check(ctx, datagen.single_partition(), mode)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("kid", [datagen.POLY, datagen.FMUL])
+def test_edge_sizes(ctx, mode, kid):
+    parts = [datagen.make_part(kid, n, pid) for pid, n in enumerate(EDGE_N)]
+    run_and_check(ctx, parts, mode)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_mc_counts_bit_exact(ctx, mode):
+    sizes = [0, 1, 2, 3, 4, 5, 1023, 4097, 65536, 65537, 1 << 20, (1 << 20) + 1]
+    parts = [datagen.make_part(datagen.MC_PI, n, pid, with_data=False)
+             for pid, n in enumerate(sizes)]
+    parts.append(datagen.Part(kid=datagen.MC_PI, ops=datagen.COUNT, n=99_999, pid=7,
+                              seed=0xDEADBEEF12345678))
+    run_and_check(ctx, parts, mode)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_map_partition_mc(ctx, mode):
+    parts = [datagen.make_part(datagen.MC_PI, 300_001 + p, p, with_data=False)
+             for p in range(6)]
+    d = DevParts(parts)
+    res = ctx.map_partition(d.tasks, mode)
+    for p, g in zip(parts, res):
+        check_result(g, oracle_result(p), p.kid, p.ops, f"pid={p.pid}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_ops_subsets(ctx, mode):
+    parts = [datagen.make_part(datagen.FMUL, 70_001, 0, ops=datagen.SUM),
+             datagen.make_part(datagen.FMUL, 70_002, 1, ops=datagen.MAX),
+             datagen.make_part(datagen.POLY, 70_003, 2, ops=datagen.MAX),
+             datagen.make_part(datagen.POLY, 70_004, 3, ops=datagen.SUM | datagen.MAX)]
+    run_and_check(ctx, parts, mode)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("xoff,yoff", [(1, 1), (2, 2), (3, 3), (1, 2), (0, 3)])
+def test_unaligned_inputs(ctx, mode, xoff, yoff):
+    # equal misalignment takes the float4 path with a scalar head; unequal
+    # misalignment takes the scalar path
+    parts = [datagen.make_part(datagen.FMUL, n, pid) for pid, n in
+             enumerate([5, 1000, 65537, 300_000])]
+    parts += [datagen.make_part(datagen.POLY, 65539, 9)]
+    run_and_check(ctx, parts, mode, xoff, yoff)
+
+
+@pytest.mark.parametrize("degree", range(8))
+def test_poly_degrees(ctx, degree):
+    coef = tuple(float(np.float32(0.5 - 0.125 * k)) for k in range(degree + 1))
+    x = datagen.fill(40_001, 0, degree, 1, datagen.U_PM1)
+    p = datagen.Part(kid=datagen.POLY, ops=datagen.SUM | datagen.MAX, n=x.size,
+                     pid=degree, x=x, coef=coef)
+    run_and_check(ctx, [p], sc.BATCHED)
+
+
+@pytest.mark.parametrize("kid", [datagen.POLY, datagen.FMUL])
+@pytest.mark.parametrize("xoff,ooff", [(0, 0), (1, 1), (1, 0), (3, 2)])
+def test_map_materialised_bit_exact(ctx, kid, xoff, ooff):
+    n = 100_003
+    p = datagen.make_part(kid, n, 5)
+    x, y = dev(p.x, xoff), dev(p.y, xoff)
+    buf = torch.full((n + 8,), float("nan"), dtype=torch.float32, device="cuda")
+    out = buf[ooff:ooff + n]
+    ctx.map([sc.task(kid, n, x, y, out, coef=p.coef, c=p.c)])
+    torch.cuda.synchronize()
+    want = oracle.poly_map(p.x, p.coef) if kid == datagen.POLY else oracle.fmul_map(p.x, p.y)
+    got = out.cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    # nothing written outside [0, n)
+    assert torch.isnan(buf[:ooff]).all() and torch.isnan(buf[ooff + n:]).all()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_reduce_with_materialised_output(ctx, mode):
+    parts = [datagen.make_part(datagen.FMUL, 123_457, 0),
+             datagen.make_part(datagen.POLY, 65_541, 1)]
+    d = DevParts(parts, out=True)
+    per, _ = ctx.reduce(d.tasks, mode)
+    torch.cuda.synchronize()
+    for p, g, o in zip(parts, per, d.outs):
+        check_result(g, oracle_result(p), p.kid, p.ops, f"kid={p.kid}")
+        want = oracle.poly_map(p.x, p.coef) if p.kid == datagen.POLY else \
+            oracle.fmul_map(p.x, p.y)
+        assert np.array_equal(o.cpu().numpy().view(np.uint32), want.view(np.uint32))
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_repeat_is_bit_identical_and_async_matches(ctx, mode):
+    parts = [datagen.make_part(k, 200_000 + 17 * i, i)
+             for i, k in enumerate([1, 2, 3, 2, 1, 3, 2])]
+    d = DevParts(parts)
+    first, tot1 = ctx.reduce(d.tasks, mode)
+    for _ in range(3):  # cached plan / graph replay
+        again, tot2 = ctx.reduce(d.tasks, mode)
+        assert [r.as_dict() | {"t_start_ns": 0, "t_done_ns": 0} for r in again] == \
+               [r.as_dict() | {"t_start_ns": 0, "t_done_ns": 0} for r in first]
+        assert (tot2.sum, tot2.max, tot2.count, tot2.n) == (tot1.sum, tot1.max,
+                                                            tot1.count, tot1.n)
+    dres = torch.zeros(64 * len(parts), dtype=torch.uint8, device="cuda")
+    dtot = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    for _ in range(2):
+        ctx.reduce_async(d.tasks, mode, dres, dtot)
+    torch.cuda.synchronize()
+    raw = dres.cpu().numpy()
+    for i, r in enumerate(first):
+        g = sc.Result.from_buffer_copy(raw[64 * i:64 * (i + 1)].tobytes())
+        assert (g.sum, g.max, g.count, g.n, g.status) == (r.sum, r.max, r.count, r.n, 0)
+    gt = sc.Result.from_buffer_copy(dtot.cpu().numpy().tobytes())
+    assert (gt.sum, gt.count, gt.n) == (tot1.sum, tot1.count, tot1.n)
+    assert ctx.last_kernel_ms() > 0
+
+
+def test_errors(ctx):
+    x = torch.zeros(16, dtype=torch.float32, device="cuda")
+    with pytest.raises(sc.SparkclError) as e:
+        ctx.reduce([sc.task(9, 16, x)], sc.BATCHED)
+    assert e.value.code == sc.ENOKERNEL
+    with pytest.raises(sc.SparkclError) as e:
+        ctx.reduce([sc.task(sc.POLY, 16, x, ops=sc.COUNT)], sc.BATCHED)
+    assert e.value.code == sc.EINVAL
+    with pytest.raises(sc.SparkclError) as e:
+        ctx.reduce([sc.task(sc.FMUL, 16, x, None)], sc.PER_LAUNCH)
+    assert e.value.code == sc.EINVAL
+    with pytest.raises(sc.SparkclError) as e:
+        ctx.map([sc.task(sc.MC_PI, 16)])
+    assert e.value.code == sc.EINVAL
+    with pytest.raises(sc.SparkclError) as e:
+        ctx.map_partition([sc.task(sc.POLY, 16, x, coef=(1.0,))])
+    assert e.value.code == sc.EINVAL
+    bad = sc.task(sc.POLY, 16, x, coef=(1.0,))
+    bad.degree = 8
+    with pytest.raises(sc.SparkclError) as e:
+        ctx.reduce([bad], sc.BATCHED)
+    assert e.value.code == sc.EINVAL
+    # the context still works after errors
+    per, tot = ctx.reduce([sc.task(sc.POLY, 16, x, coef=(2.0,))], sc.BATCHED)
+    assert per[0].sum == 32.0 and tot.sum == 32.0
+
+
+def test_fmul_rdd_full_size(ctx):
+    # 64 partitions x 2^22 pairs (x~N(0,1), y~U[0,2)); every partition checked
+    parts = datagen.fmul_rdd()
+    d = DevParts(parts)
+    for mode in MODES:
+        per, tot = ctx.reduce(d.tasks, mode)
+        want = [oracle_result(p) for p in parts]
+        for p, g, o in zip(parts, per, want):
+            check_result(g, o, p.kid, p.ops, f"pid={p.pid} mode={mode}")
+        check_total(tot, want, datagen.SUM | datagen.MAX)
+
+
+def test_monte_carlo_full_size(ctx):
+    # 256 partitions x 2^24 samples: 8 partitions against the oracle, all
+    # against pi/4 within 5 sigma, and the RDD count equal to the sum
+    parts = datagen.monte_carlo()
+    d = DevParts(parts)
+    per, tot = ctx.reduce(d.tasks, sc.BATCHED)
+    n = 1 << 24
+    p4 = math.pi / 4
+    sigma = math.sqrt(p4 * (1 - p4) / n)
+    for r in per:
+        assert r.n == n and abs(r.count / n - p4) < 5 * sigma
+    assert tot.count == sum(r.count for r in per) and tot.n == 256 * n
+    for pid in (0, 1, 77, 128, 200, 255):
+        assert per[pid].count == oracle.mc_count(0, pid, n), f"pid {pid}"
+
+
+def test_uneven_batch_reduced(ctx):
+    # log-normal sizes (median 4K, clipped 16..256K) with mixed kernels
+    sizes = datagen.lognormal_sizes(300, 5, 3, 4096, math.log(4.0), 16, 262144)
+    kids = datagen.uniform_kernel_ids(300, 5, 4)
+    parts = [datagen.make_part(int(k), int(n), i) for i, (n, k) in enumerate(zip(sizes, kids))]
+    for mode in MODES:
+        run_and_check(ctx, parts, mode)

@@ -1,0 +1,187 @@
+"""GPU serving: continuous batching through sparkcl_submit / sparkcl_poll.
+
+Each task's result must match the oracle, and must be bit-identical whether it
+ran alone or in a mix with other tasks sharing the GPU.  Admission against a
+small budget, oversize and invalid requests, executor relaunch after an idle
+exit, the per-task-launch baseline mode, and the watchdog are covered too.
+The watchdog case ends a long task from the host (stop word); every kernel
+still exits normally.
+"""
+import math
+import threading
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import paper_1505_01120_amd as sc
+from gpu_helpers import DevParts, check_result, oracle_result
+
+pytestmark = pytest.mark.gpu
+
+
+def mixed_parts(count, seed, median=16384, lo=1024, hi=262144):
+    sizes = datagen.lognormal_sizes(count, seed, 6, median, math.log(4.0), lo, hi)
+    kids = datagen.uniform_kernel_ids(count, seed, 7)
+    return [datagen.make_part(int(k), int(n), i, seed=0)
+            for i, (n, k) in enumerate(zip(sizes, kids))]
+
+
+def wait_all(ctx, tickets, timeout=60.0):
+    out = {}
+    t0 = time.time()
+    pending = list(tickets)
+    while pending:
+        rest = []
+        for t in pending:
+            r = ctx.poll(t)
+            if r is None:
+                rest.append(t)
+            else:
+                out[t] = r
+        pending = rest
+        if pending:
+            assert time.time() - t0 < timeout, f"{len(pending)} tasks not done"
+            time.sleep(0.0002)
+    return [out[t] for t in tickets]
+
+
+def key(r):
+    return (r.sum, float(r.max), r.count, r.n, r.status)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = sc.Context(device=0, arena_bytes=1 << 30)
+    yield c
+    c.destroy()
+
+
+def test_serve_matches_oracle(ctx):
+    parts = mixed_parts(200, 11)
+    d = DevParts(parts)
+    tickets = [ctx.submit(t) for t in d.tasks]
+    res = wait_all(ctx, tickets)
+    for p, r in zip(parts, res):
+        check_result(r, oracle_result(p), p.kid, p.ops, f"kid={p.kid} n={p.n}")
+        assert r.t_arrive_ns <= r.t_admit_ns <= r.t_done_ns
+    st = ctx.serve_stats()
+    assert st["completed"] >= 200 and st["in_flight"] == 0 and st["pending"] == 0
+
+
+def test_serve_alone_vs_mix_bit_identical(ctx):
+    parts = mixed_parts(64, 12, median=65536, hi=1 << 20)
+    d = DevParts(parts)
+    alone = []
+    for t in d.tasks[:16]:
+        alone.append(wait_all(ctx, [ctx.submit(t)])[0])
+    mix = wait_all(ctx, [ctx.submit(t) for t in d.tasks])
+    for a, m in zip(alone, mix[:16]):
+        assert key(a) == key(m)
+    for p, m in zip(parts, mix):
+        check_result(m, oracle_result(p), p.kid, p.ops, f"kid={p.kid} n={p.n}")
+
+
+def test_serve_concurrent_submitters(ctx):
+    parts = mixed_parts(120, 13)
+    d = DevParts(parts)
+    results = [None] * len(parts)
+
+    def worker(idx):
+        tk = [(i, ctx.submit(d.tasks[i])) for i in idx]
+        for (i, t), r in zip(tk, wait_all(ctx, [t for _, t in tk])):
+            results[i] = r
+
+    ths = [threading.Thread(target=worker, args=(list(range(k, len(parts), 4)),))
+           for k in range(4)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    for p, r in zip(parts, results):
+        check_result(r, oracle_result(p), p.kid, p.ops, f"kid={p.kid} n={p.n}")
+
+
+def test_serve_small_budget_waits():
+    # a 6 MiB budget with ~1 MiB tasks: admission must queue and still finish
+    c = sc.Context(device=0, arena_bytes=256 << 20, budget_bytes=6 << 20)
+    try:
+        parts = [datagen.make_part(datagen.FMUL, 131072 + i, i) for i in range(40)]
+        d = DevParts(parts)
+        res = wait_all(c, [c.submit(t) for t in d.tasks])
+        for p, r in zip(parts, res):
+            check_result(r, oracle_result(p), p.kid, p.ops, f"n={p.n}")
+        st = c.serve_stats()
+        assert st["budget_peak"] <= 6 << 20
+        assert st["admission_waits"] > 0
+        with pytest.raises(sc.SparkclError) as e:
+            big = datagen.make_part(datagen.FMUL, 1 << 20, 99, with_data=False)
+            x = torch.zeros(1 << 20, dtype=torch.float32, device="cuda")
+            c.submit(sc.task(sc.FMUL, 1 << 20, x, x))
+        assert e.value.code == sc.ETOOBIG
+        del big
+    finally:
+        c.destroy()
+
+
+def test_serve_rejects_invalid(ctx):
+    x = torch.zeros(64, dtype=torch.float32, device="cuda")
+    with pytest.raises(sc.SparkclError) as e:
+        ctx.submit(sc.task(7, 64, x))
+    assert e.value.code == sc.ENOKERNEL
+    with pytest.raises(sc.SparkclError) as e:
+        ctx.submit(sc.task(sc.MC_PI, 64, ops=sc.SUM))
+    assert e.value.code == sc.EINVAL
+    with pytest.raises(sc.SparkclError) as e:
+        ctx.poll(1 << 60)
+    assert e.value.code == sc.ENOTFOUND
+
+
+def test_serve_per_task_launch_matches_resident(ctx):
+    parts = mixed_parts(48, 14)
+    d = DevParts(parts)
+    resident = wait_all(ctx, [ctx.submit(t) for t in d.tasks])
+    c = sc.Context(device=0, arena_bytes=256 << 20, flags=sc.FLAG_SERVE_PER_TASK)
+    try:
+        launched = wait_all(c, [c.submit(t) for t in d.tasks])
+        assert c.serve_stats()["executor_launches"] >= len(parts)
+    finally:
+        c.destroy()
+    for a, b in zip(resident, launched):
+        assert key(a) == key(b)
+
+
+def test_serve_relaunch_after_idle_exit():
+    c = sc.Context(device=0, arena_bytes=256 << 20, idle_exit_ms=20)
+    try:
+        parts = mixed_parts(10, 15)
+        d = DevParts(parts)
+        first = wait_all(c, [c.submit(t) for t in d.tasks[:5]])
+        time.sleep(0.3)  # the resident executor idles out
+        second = wait_all(c, [c.submit(t) for t in d.tasks[5:]])
+        assert c.serve_stats()["executor_launches"] >= 2
+        for p, r in zip(parts, first + second):
+            check_result(r, oracle_result(p), p.kid, p.ops, f"n={p.n}")
+    finally:
+        c.destroy()
+
+
+def test_serve_watchdog_fails_long_task_then_recovers():
+    # a 2^34-sample Monte-Carlo task (2^20 tiles) cannot finish within a 5 ms
+    # watchdog; the host stops the executor (workers exit after their current
+    # tile), fails the task with ETIMEDOUT, resets the device state and keeps
+    # serving
+    c = sc.Context(device=0, arena_bytes=256 << 20, watchdog_ms=5)
+    try:
+        t = c.submit(sc.task(sc.MC_PI, 1 << 34, pid=1))
+        r = wait_all(c, [t], timeout=30)[0]
+        assert r.status == sc.ETIMEDOUT
+        parts = mixed_parts(8, 16, hi=65536)
+        d = DevParts(parts)
+        res = wait_all(c, [c.submit(x) for x in d.tasks])
+        for p, q in zip(parts, res):
+            check_result(q, oracle_result(p), p.kid, p.ops, f"n={p.n}")
+    finally:
+        c.destroy()

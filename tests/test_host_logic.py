@@ -1,0 +1,288 @@
+"""CPU tests of the library's host side: the C ABI surface (every declared
+symbol exported, struct layouts as the header defines them, clean failure
+without a GPU) and the pure host logic behind it: the arena sub-allocator,
+serving admission control and the tuning table with its JSON cache."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1505_01120_amd as sc
+from paper_1505_01120_amd import build as libbuild
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sparkcl.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(libbuild.LIB):
+        libbuild.build()
+    return sc.load()
+
+
+@pytest.fixture(scope="module")
+def host():
+    if not os.path.exists(libbuild.HOST_LIB):
+        libbuild.build()
+    H = ctypes.CDLL(libbuild.HOST_LIB)
+    U64, U32, P = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p
+    for name, args, res in [
+        ("hl_arena_new", [U64], P), ("hl_arena_free", [P], None),
+        ("hl_arena_alloc", [P, U64], U64), ("hl_arena_release", [P, U64], ctypes.c_int),
+        ("hl_arena_in_use", [P], U64), ("hl_arena_peak", [P], U64),
+        ("hl_arena_largest_free", [P], U64), ("hl_arena_free_blocks", [P], U64),
+        ("hl_arena_live_blocks", [P], U64), ("hl_arena_size", [P], U64),
+        ("hl_adm_new", [U64, U32, U64], P), ("hl_adm_free", [P], None),
+        ("hl_adm_fits", [P, U64, U32], ctypes.c_int),
+        ("hl_adm_push", [P, U64, U64, U32, U64], None),
+        ("hl_adm_head_block", [P], ctypes.c_int),
+        ("hl_adm_admit", [P, ctypes.POINTER(U64), ctypes.POINTER(U32), ctypes.POINTER(U64)],
+         ctypes.c_int),
+        ("hl_adm_unadmit", [P, U64], ctypes.c_int), ("hl_adm_complete", [P, U64], ctypes.c_int),
+        ("hl_adm_in_use", [P], U64), ("hl_adm_peak", [P], U64), ("hl_adm_pending", [P], U64),
+        ("hl_adm_in_flight", [P], U64), ("hl_adm_tiles", [P], U64),
+        ("hl_tuning_defaults", [ctypes.POINTER(sc.Tuning)], None),
+        ("hl_tuning_validate", [ctypes.POINTER(sc.Tuning)], ctypes.c_int),
+        ("hl_tile_for", [ctypes.POINTER(sc.Tuning), ctypes.c_int, U32, U64], U32),
+        ("hl_size_bucket", [U64], U32),
+        ("hl_tuning_save", [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(sc.Tuning)],
+         ctypes.c_int),
+        ("hl_tuning_load", [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(sc.Tuning)],
+         ctypes.c_int),
+        ("hl_tuning_parse", [ctypes.c_char_p, ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
+    ]:
+        f = getattr(H, name)
+        f.argtypes, f.restype = args, res
+    return H
+
+
+# ---- the C ABI ---------------------------------------------------------------
+
+def header_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"SPARKCL_API\s+[\w\s\*]+?\b(sparkcl_\w+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(sc.EXPORTS) == names
+    out = subprocess.run(["nm", "-D", "--defined-only", libbuild.LIB], capture_output=True,
+                         text=True, check=True).stdout
+    exported = sorted(set(re.findall(r" T (sparkcl_\w+)", out)))
+    assert exported == names  # nothing else leaks from the library
+
+
+def test_struct_layouts_match_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text('#include "sparkcl.h"\n#include <stdio.h>\n#include <stddef.h>\n'
+                   "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\","
+                   "sizeof(sparkcl_task), sizeof(sparkcl_result), sizeof(sparkcl_config),"
+                   "sizeof(sparkcl_tuning), sizeof(sparkcl_serve_stats),"
+                   "offsetof(sparkcl_task, coef), offsetof(sparkcl_result, t_done_ns),"
+                   "offsetof(sparkcl_config, tune_cache));return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src),
+                           "-o", str(exe)])
+    got = list(map(int, subprocess.check_output([str(exe)]).split()))
+    want = [ctypes.sizeof(sc.Task), ctypes.sizeof(sc.Result), ctypes.sizeof(sc.Config),
+            ctypes.sizeof(sc.Tuning), ctypes.sizeof(sc.ServeStats), sc.Task.coef.offset,
+            sc.Result.t_done_ns.offset, sc.Config.tune_cache.offset]
+    assert got == want
+
+
+def test_strerror_and_version(lib):
+    assert sc.strerror(sc.ETOOBIG) == "task too big"
+    assert sc.strerror(sc.OK) == "ok"
+    assert sc.version().startswith("sparkcl")
+
+
+def test_init_fails_cleanly_without_gpu(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p(123)
+    cfg = sc.Config()
+    rc = lib.sparkcl_init(ctypes.byref(cfg), ctypes.byref(h))
+    assert rc == sc.EHIP and h.value is None
+    assert b"device" in lib.sparkcl_last_error()
+    assert lib.sparkcl_init(None, ctypes.byref(h)) == sc.EINVAL
+    # calls on a null context are rejected, not crashed
+    assert lib.sparkcl_reduce(None, None, 0, 0, None, None, None) == sc.EINVAL
+    assert lib.sparkcl_poll(None, 1, None) == sc.EINVAL
+
+
+def test_binding_fails_loudly_when_library_missing(monkeypatch, tmp_path):
+    import paper_1505_01120_amd.sparkcl as mod
+    monkeypatch.setattr(mod, "_lib", None)
+    monkeypatch.setattr(mod, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="no fallback"):
+        mod.load()
+
+
+# ---- arena -------------------------------------------------------------------
+
+def test_arena_alignment_and_coalescing(host):
+    a = host.hl_arena_new(1 << 20)
+    try:
+        offs = [host.hl_arena_alloc(a, n) for n in (1, 255, 256, 257, 1000)]
+        assert all(o % 256 == 0 for o in offs)
+        assert offs == [0, 256, 512, 768, 1280]
+        assert host.hl_arena_in_use(a) == 256 * 3 + 512 + 1024
+        for o in (offs[1], offs[3], offs[2]):  # free the middle run out of order
+            assert host.hl_arena_release(a, o) == 1
+        assert host.hl_arena_release(a, offs[2]) == 0  # double free is refused
+        assert host.hl_arena_alloc(a, 768) == 256      # coalesced hole is reused
+        for o in (offs[0], 256, offs[4]):
+            host.hl_arena_release(a, o)
+        assert host.hl_arena_in_use(a) == 0 and host.hl_arena_free_blocks(a) == 1
+        assert host.hl_arena_largest_free(a) == 1 << 20
+        assert host.hl_arena_alloc(a, (1 << 20) + 1) == 2 ** 64 - 1
+    finally:
+        host.hl_arena_free(a)
+
+
+def test_arena_random_against_model(host, datagen):
+    size = 1 << 24
+    a = host.hl_arena_new(size)
+    w = datagen.fill(4000, 3, 0, 1, datagen.WORDS)
+    live = {}
+    try:
+        for v in map(int, w):
+            if live and v % 3 == 0:
+                off = sorted(live)[v % len(live)]
+                assert host.hl_arena_release(a, off) == 1
+                del live[off]
+            else:
+                n = 1 + (v >> 8) % 200_000
+                off = host.hl_arena_alloc(a, n)
+                if off == 2 ** 64 - 1:
+                    assert sum(live.values()) + n > 0  # failure only when fragmented/full
+                    continue
+                rounded = (n + 255) // 256 * 256
+                for o, l in live.items():  # no overlap with any live block
+                    assert off + rounded <= o or o + l <= off
+                assert off + rounded <= size
+                live[off] = rounded
+            assert host.hl_arena_in_use(a) == sum(live.values())
+        for off in list(live):
+            host.hl_arena_release(a, off)
+        assert host.hl_arena_free_blocks(a) == 1 and host.hl_arena_in_use(a) == 0
+    finally:
+        host.hl_arena_free(a)
+
+
+# ---- admission ---------------------------------------------------------------
+
+def admit(host, b):
+    seq, slot, tk = ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint64()
+    if not host.hl_adm_admit(b, ctypes.byref(seq), ctypes.byref(slot), ctypes.byref(tk)):
+        return None
+    return seq.value, slot.value, tk.value
+
+
+def test_admission_budget_fifo_and_peak(host):
+    b = host.hl_adm_new(1000, 8, 1 << 20)
+    try:
+        assert host.hl_adm_fits(b, 1000, 1) and not host.hl_adm_fits(b, 1001, 1)
+        for t, nbytes in enumerate([400, 400, 300, 100], start=1):
+            host.hl_adm_push(b, t, nbytes, 1, 0)
+        assert admit(host, b) == (0, 0, 1)
+        assert admit(host, b) == (1, 1, 2)
+        assert host.hl_adm_head_block(b) == 3      # 300 more exceeds 1000
+        assert admit(host, b) is None              # FIFO: the 100 behind it waits too
+        assert host.hl_adm_complete(b, 0) == 1
+        assert admit(host, b) == (2, 2, 3) and admit(host, b) == (3, 3, 4)
+        assert host.hl_adm_peak(b) <= 1000 and host.hl_adm_in_use(b) == 800
+        assert host.hl_adm_head_block(b) == 1      # empty
+    finally:
+        host.hl_adm_free(b)
+
+
+def test_admission_slots_wrap(host):
+    b = host.hl_adm_new(1 << 40, 4, 1 << 20)
+    try:
+        for t in range(6):
+            host.hl_adm_push(b, t + 1, 1, 1, 0)
+        got = [admit(host, b) for _ in range(4)]
+        assert [g[1] for g in got] == [0, 1, 2, 3]
+        assert host.hl_adm_head_block(b) == 2      # seq 4 maps to busy slot 0
+        host.hl_adm_complete(b, 1)                 # slot 1 frees, but seq 4 needs 0
+        assert admit(host, b) is None
+        host.hl_adm_complete(b, 0)
+        assert admit(host, b) == (4, 0, 5)
+        assert host.hl_adm_head_block(b) == 0 and admit(host, b) == (5, 1, 6)
+    finally:
+        host.hl_adm_free(b)
+
+
+def test_admission_tiles_and_unadmit(host):
+    b = host.hl_adm_new(1 << 40, 64, 100)
+    try:
+        assert not host.hl_adm_fits(b, 1, 101)
+        host.hl_adm_push(b, 1, 10, 60, 0)
+        host.hl_adm_push(b, 2, 10, 60, 0)
+        a1 = admit(host, b)
+        assert host.hl_adm_head_block(b) == 4      # tile map full
+        host.hl_adm_complete(b, a1[0])
+        a2 = admit(host, b)
+        assert a2 == (1, 1, 2) and host.hl_adm_tiles(b) == 60
+        assert host.hl_adm_unadmit(b, a2[0]) == 1  # resources unavailable: back to queue
+        assert host.hl_adm_pending(b) == 1 and host.hl_adm_in_flight(b) == 0
+        assert admit(host, b) == (1, 1, 2)         # same sequence number again
+    finally:
+        host.hl_adm_free(b)
+
+
+# ---- tuning table ---------------------------------------------------------------
+
+def test_tuning_defaults_valid_and_lookup(host):
+    t = sc.Tuning()
+    host.hl_tuning_defaults(ctypes.byref(t))
+    assert host.hl_tuning_validate(ctypes.byref(t)) == 0
+    assert [host.hl_size_bucket(n) for n in (0, 1, 2, 3, 1023, 1024, 1 << 22, (1 << 22) + 5)] == \
+        [0, 0, 1, 1, 9, 10, 22, 22]
+    assert host.hl_size_bucket(1 << 40) == 31
+    for mode in range(3):
+        for kid in (1, 2, 3):
+            for n in (1, 1000, 1 << 16, 1 << 22, 1 << 30):
+                T = host.hl_tile_for(ctypes.byref(t), mode, kid, n)
+                assert T & (T - 1) == 0 and 1 << 10 <= T <= 1 << 22
+    t.tile[1][0][5] = 3000
+    assert host.hl_tuning_validate(ctypes.byref(t)) == sc.EINVAL
+
+
+def test_tuning_json_roundtrip(host, tmp_path):
+    t = sc.Tuning()
+    host.hl_tuning_defaults(ctypes.byref(t))
+    t.blocks_per_cu = 5
+    t.tile[1][1][22] = 1 << 16
+    path = str(tmp_path / "tune.json").encode()
+    assert host.hl_tuning_save(path, b"gfx950:sramecc+:xnack-", ctypes.byref(t)) == 1
+    other = sc.Tuning()
+    host.hl_tuning_defaults(ctypes.byref(other))
+    assert host.hl_tuning_save(path, b"gfx942", ctypes.byref(other)) == 1  # kept side by side
+    back = sc.Tuning()
+    assert host.hl_tuning_load(path, b"gfx950:sramecc+:xnack-", ctypes.byref(back)) == 1
+    assert bytes(back) == bytes(t)
+    assert host.hl_tuning_load(path, b"gfx942", ctypes.byref(back)) == 1
+    assert bytes(back) == bytes(other)
+    assert host.hl_tuning_load(path, b"gfx1100", ctypes.byref(back)) == 0
+    err = ctypes.create_string_buffer(256)
+    assert host.hl_tuning_parse(open(path).read().encode(), err, 256) == 2
+    bad = b'{"gfx950": {"tile": {"batched": {"poly": [1, 2]}}}}'
+    assert host.hl_tuning_parse(bad, err, 256) == -1 and b"32 sizes" in err.value
+    assert host.hl_tuning_parse(b'{"gfx950": [}', err, 256) == -1
+
+
+def test_committed_tuning_cache_is_valid(host):
+    path = sc.TUNING_PATH
+    if not os.path.exists(path):
+        pytest.skip("no tuning cache committed yet")
+    err = ctypes.create_string_buffer(256)
+    assert host.hl_tuning_parse(open(path).read().encode(), err, 256) >= 1, err.value
