@@ -463,7 +463,11 @@ __device__ bool run_tile(const TaskDev *__restrict__ tp, uint32_t j,
         sh_last = (prev == ntiles - 1) ? 1u : 0u;
     }
     __syncthreads();
-    const bool last = sh_last != 0;
+    // Every branch that guards a barrier must be provably uniform (a scalar
+    // value): a condition read from LDS looks divergent to the compiler, and
+    // its control-flow structurizer may then send some threads around a loop
+    // latch without the others.
+    const bool last = uni(sh_last) != 0;
     __syncthreads();
     if (!last)
         return false;
@@ -493,6 +497,10 @@ __device__ bool run_tile(const TaskDev *__restrict__ tp, uint32_t j,
             __threadfence();
         }
     }
+    // A barrier closes every thread-0 region that ends a loop iteration of the
+    // callers: without it the compiler may sink the region past the loop
+    // latch and let the other threads start the next iteration early.
+    __syncthreads();
     return true;
 }
 
@@ -508,7 +516,7 @@ __device__ void rdd_step(const LaunchOut &L)
         sh_last = (prev == L.ntasks - 1) ? 1u : 0u;
     }
     __syncthreads();
-    const bool last = sh_last != 0;
+    const bool last = uni(sh_last) != 0;
     __syncthreads();
     if (!last)
         return;
@@ -526,6 +534,7 @@ __device__ void rdd_step(const LaunchOut &L)
                            __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();
     }
+    __syncthreads();
 }
 
 // ---- kernels --------------------------------------------------------------
@@ -684,7 +693,7 @@ static_assert(offsetof(TaskDev, tile_first) == 120, "words 30-31 of a descriptor
 __device__ void serve_dispatch(const ServeArgs &a)
 {
     __shared__ uint64_t sh_tail, sh_stop;
-    __shared__ uint32_t sh_nt, sh_first_lo, sh_first_hi;
+    __shared__ uint32_t sh_nt, sh_first_lo, sh_first_hi, sh_idle_exit;
     uint64_t taken = uni64(ld_agent(&a.dev->taken));
     uint64_t last = wall_clock64();
     for (;;) {
@@ -696,7 +705,7 @@ __device__ void serve_dispatch(const ServeArgs &a)
         }
         __syncthreads();
         const uint64_t tail = uni64(sh_tail);
-        const bool stop = sh_stop != 0;
+        const bool stop = uni((uint32_t)(sh_stop != 0)) != 0;
         __syncthreads();
         if (stop)
             break;
@@ -720,8 +729,8 @@ __device__ void serve_dispatch(const ServeArgs &a)
                         sh_first_hi = w;
                 }
                 __syncthreads();
-                const uint64_t first = ((uint64_t)sh_first_hi << 32) | sh_first_lo;
-                const uint32_t nt = sh_nt;
+                const uint64_t first = ((uint64_t)uni(sh_first_hi) << 32) | uni(sh_first_lo);
+                const uint32_t nt = uni(sh_nt);
                 for (uint32_t k = threadIdx.x; k < nt; k += kBlock)
                     __hip_atomic_store(a.tilemap + ((first + k) & (a.tile_cap - 1)), slot,
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -739,8 +748,17 @@ __device__ void serve_dispatch(const ServeArgs &a)
             last = wall_clock64();
             continue;
         }
-        if (wall_clock64() - last > a.idle_ticks &&
-            ld_agent(&a.dev->claim) >= ld_agent(&a.dev->tiles_pub))
+        // idle exit: decided by thread 0 alone (different waves could read
+        // different counter values) and broadcast, so all waves agree
+        if (threadIdx.x == 0)
+            sh_idle_exit = (wall_clock64() - last > a.idle_ticks &&
+                            ld_agent(&a.dev->claim) >= ld_agent(&a.dev->tiles_pub))
+                               ? 1u
+                               : 0u;
+        __syncthreads();
+        const bool idle_exit = uni(sh_idle_exit) != 0;
+        __syncthreads();
+        if (idle_exit)
             break;
         __builtin_amdgcn_s_sleep(8);
     }
@@ -797,7 +815,7 @@ __device__ void serve_work(const ServeArgs &a)
                 __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
-        const uint32_t j = (uint32_t)(t - sh_task.tile_first);
+        const uint32_t j = uni((uint32_t)(t - sh_task.tile_first));
         run_tile(&sh_task, j, a.out);
         __syncthreads();
     }
