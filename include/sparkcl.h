@@ -221,7 +221,10 @@ SPARKCL_API int sparkcl_serve_drain(sparkcl_ctx *ctx, uint32_t timeout_ms);
 #define SPARKCL_TUNE_MODES 3     /* PER_LAUNCH, BATCHED, serving */
 
 typedef struct sparkcl_tuning {
-    uint32_t blocks_per_cu;      /* persistent executor occupancy             */
+    uint32_t blocks_per_cu[3];   /* persistent-executor blocks per CU for each
+                                    registry kernel (index kernel id - 1); a
+                                    batch uses the largest among the kernels
+                                    it holds; 0 = as many as fit              */
     uint32_t reserved;
     /* tile size in elements (samples for MC_PI) for [mode][kernel-1][log2 n];
        powers of two from 2^10 to 2^22. */
@@ -235,8 +238,9 @@ SPARKCL_API int sparkcl_set_tuning(sparkcl_ctx *ctx, const sparkcl_tuning *in);
 
 /* Autotuner: for each kernel and size bucket in [lo_log2, hi_log2], time the
    candidate tile sizes on synthetic device data and keep the fastest by
-   median HIP-event time; writes the table into the context and, if `path` is
-   non-NULL, into that JSON file under the device's gfx arch name. */
+   median HIP-event time, then each kernel's executor blocks per CU; writes
+   the table into the context and, if `path` is non-NULL, into that JSON file
+   under the device's gfx arch name.  Needs 2 GiB of free arena. */
 SPARKCL_API int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_log2,
                      const char *path);
 

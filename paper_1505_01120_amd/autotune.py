@@ -1,0 +1,45 @@
+"""Run the library's autotuner on GPU 0 and write the tuning cache.
+
+The autotuner (sparkcl_autotune) times candidate tile sizes for every
+execution mode, registry kernel and log2(n) bucket on synthetic device data,
+then the persistent executor's blocks per CU, and stores the table in a JSON
+file keyed by the device's gfx arch.  Contexts load that file by default
+(paper_1505_01120_amd/tuning.json), so one machine always cuts a task into the
+same tiles and results stay run-to-run identical.
+
+Usage: python -m paper_1505_01120_amd.autotune [--lo 10] [--hi 24] [--out PATH]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+from . import sparkcl as sc
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--lo", type=int, default=10, help="smallest log2(n) bucket")
+    ap.add_argument("--hi", type=int, default=24, help="largest log2(n) bucket")
+    ap.add_argument("--out", default=sc.TUNING_PATH)
+    args = ap.parse_args(argv)
+    t0 = time.time()
+    # start from the built-in defaults, not from an existing cache
+    with sc.Context(device=0, arena_bytes=2 << 30, tune_cache=None) as ctx:
+        ctx.autotune(args.lo, args.hi, args.out)
+        t = ctx.get_tuning()
+    names = ["per_launch", "batched", "serve"]
+    kern = ["poly", "fmul", "mc_pi"]
+    summary = {"blocks_per_cu": list(t.blocks_per_cu),
+               "tiles": {m: {k: list(t.tile[i][j][args.lo:args.hi + 1])
+                             for j, k in enumerate(kern)} for i, m in enumerate(names[:2])}}
+    print(json.dumps(summary), flush=True)
+    print(f"wrote {args.out} in {time.time() - t0:.1f} s", file=sys.stderr)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

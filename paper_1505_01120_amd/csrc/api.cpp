@@ -146,14 +146,25 @@ int arena_alloc(sparkcl_ctx *ctx, Plan *p, uint64_t bytes, void **out)
 
 } // namespace
 
-uint32_t sparkcl::exec_grid(const sparkcl_ctx *ctx)
+uint32_t sparkcl::exec_grid(const sparkcl_ctx *ctx, uint32_t kid_mask)
 {
-    uint32_t per_cu = (uint32_t)ctx->occ_batch;
-    if (ctx->config.exec_blocks_per_cu)
-        per_cu = std::min(per_cu, ctx->config.exec_blocks_per_cu);
-    else if (ctx->tuning.blocks_per_cu)
-        per_cu = std::min(per_cu, ctx->tuning.blocks_per_cu);
-    return std::max(1u, per_cu) * (uint32_t)ctx->cus;
+    const uint32_t occ = (uint32_t)ctx->occ_batch;
+    uint32_t per_cu = 0;
+    if (ctx->config.exec_blocks_per_cu) {
+        per_cu = ctx->config.exec_blocks_per_cu;
+    } else {
+        // the largest tuned value among the kernels in the batch: a
+        // compute-bound kernel needs waves to hide instruction latency, a
+        // streaming one does best with a few deep streams per CU
+        for (uint32_t k = 0; k < 3; ++k)
+            if (kid_mask & (1u << k)) {
+                const uint32_t v = ctx->tuning.blocks_per_cu[k];
+                per_cu = std::max(per_cu, v ? v : occ);
+            }
+        if (per_cu == 0)
+            per_cu = occ;
+    }
+    return std::max(1u, std::min(per_cu, occ)) * (uint32_t)ctx->cus;
 }
 
 namespace {
@@ -175,6 +186,7 @@ int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
     const int tm = mode == SPARKCL_BATCHED ? TM_BATCHED : TM_PER_LAUNCH;
     std::vector<uint64_t> first(ntasks);
     uint64_t total_tiles = 0;
+    uint32_t kid_mask = 0;
     for (uint32_t i = 0; i < ntasks; ++i) {
         uint32_t v = 0;
         int rc = check_task(tasks[i], &v);
@@ -186,6 +198,7 @@ int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
         if (nt > 0xFFFFFFFFull)
             return fail(SPARKCL_ETOOBIG, "too many tiles in task " + std::to_string(i));
         p->ntiles[i] = (uint32_t)nt;
+        kid_mask |= 1u << (tasks[i].kernel_id - 1);
         first[i] = total_tiles;
         total_tiles += nt;
     }
@@ -269,7 +282,7 @@ int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
         p->out.total = utot ? utot : p->dtotal;
         p->out.ntasks = ntasks;
         p->out.ns_per_tick = ctx->ns_per_tick;
-        p->grid = std::min(exec_grid(ctx), p->ntiles_total);
+        p->grid = std::min(exec_grid(ctx, kid_mask), p->ntiles_total);
         if (mode == SPARKCL_BATCHED) {
             hipStream_t cs = ctx->capture_stream;
             e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
@@ -358,8 +371,8 @@ int sparkcl::enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream)
     if (p->mode == SPARKCL_BATCHED) {
         SPARKCL_HIP(hipGraphLaunch(p->gexec, stream));
     } else {
-        const uint32_t cap = exec_grid(ctx);
         for (uint32_t i = 0; i < p->ntasks; ++i) {
+            const uint32_t cap = exec_grid(ctx, 1u << (p->tasks[i].kernel_id - 1));
             int rc = launch_task(p->dtasks + i, p->ntiles[i], std::min(cap, p->ntiles[i]),
                                  p->out, stream);
             if (rc != SPARKCL_OK)
@@ -565,7 +578,7 @@ int sparkcl_map(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t ntasks, vo
     Plan *p = nullptr;
     if ((rc = get_plan(ctx, 1, 0, tasks, ntasks, nullptr, nullptr, s, &p)) != SPARKCL_OK)
         return rc;
-    const uint32_t cap = exec_grid(ctx);
+    const uint32_t cap = (uint32_t)ctx->occ_batch * (uint32_t)ctx->cus;
     for (uint32_t i = 0; i < ntasks; ++i) {
         const uint64_t n = tasks[i].n;
         if (n == 0)

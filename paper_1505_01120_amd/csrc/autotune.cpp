@@ -14,9 +14,17 @@ using namespace sparkcl;
 
 namespace {
 
-constexpr uint64_t kPoolElems = 1ull << 24; // synthetic input per array
-constexpr uint64_t kWorkElems = 1ull << 25; // elements per timed batch
+// Synthetic input per array (512 MiB): batches stream from HBM, not from the
+// 256 MB last-level cache.
+constexpr uint64_t kPoolElems = 1ull << 27;
 constexpr int kWarm = 2, kReps = 7;
+
+// Elements per timed batch: at least 512 MiB of input for the streaming
+// kernels; 2^26 samples for the Monte-Carlo kernel.
+uint64_t work_elems(uint32_t kid)
+{
+    return kid == SPARKCL_POLY ? (1ull << 27) : (1ull << 26);
+}
 
 struct Bench {
     sparkcl_ctx *ctx;
@@ -50,7 +58,8 @@ int time_reduce(Bench &b, int mode, const std::vector<sparkcl_task> &tasks, floa
 
 std::vector<sparkcl_task> make_tasks(const Bench &b, uint32_t kid, uint64_t n, int mode)
 {
-    const uint64_t count = mode == SPARKCL_BATCHED ? std::max<uint64_t>(1, kWorkElems / n) : 1;
+    const uint64_t count =
+        mode == SPARKCL_BATCHED ? std::max<uint64_t>(1, work_elems(kid) / n) : 1;
     std::vector<sparkcl_task> v;
     for (uint64_t i = 0; i < std::min<uint64_t>(count, 4096); ++i) {
         sparkcl_task t;
@@ -103,7 +112,7 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
     };
     if (xoff == Arena::kFail || yoff == Arena::kFail) {
         cleanup();
-        return fail(SPARKCL_ENOMEM, "autotune needs 128 MiB of free arena");
+        return fail(SPARKCL_ENOMEM, "autotune needs 1 GiB of free arena");
     }
     b.x = static_cast<float *>(ctx->dev(xoff));
     b.y = static_cast<float *>(ctx->dev(yoff));
@@ -151,16 +160,15 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
         }
     }
 
-    // Executor occupancy on a large bandwidth-bound batch.
-    {
-        const std::vector<sparkcl_task> tasks =
-            make_tasks(b, SPARKCL_FMUL, 1ull << std::min<uint32_t>(hi_log2, 22), SPARKCL_BATCHED);
+    // Executor occupancy per kernel, on a large batch of that kernel alone.
+    for (uint32_t kid = SPARKCL_POLY; kid <= SPARKCL_MC_PI; ++kid) {
+        const std::vector<sparkcl_task> tasks = make_tasks(b, kid, 1ull << 22, SPARKCL_BATCHED);
         float best_ms = 1e30f;
-        uint32_t best_bpc = best.blocks_per_cu;
+        uint32_t best_bpc = best.blocks_per_cu[kid - 1];
         for (uint32_t bpc = 1; bpc <= (uint32_t)ctx->occ_batch; ++bpc) {
             drop_plans(ctx);
             ctx->tuning = best;
-            ctx->tuning.blocks_per_cu = bpc;
+            ctx->tuning.blocks_per_cu[kid - 1] = bpc;
             float ms = 0;
             if ((rc = time_reduce(b, SPARKCL_BATCHED, tasks, &ms)) != SPARKCL_OK) {
                 ctx->tuning = best;
@@ -172,7 +180,7 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
                 best_bpc = bpc;
             }
         }
-        best.blocks_per_cu = best_bpc;
+        best.blocks_per_cu[kid - 1] = best_bpc;
     }
 
     ctx->tuning = best;

@@ -82,6 +82,49 @@ __device__ __forceinline__ uint64_t device_ns(uint32_t ns_per_tick)
     return (uint64_t)wall_clock64() * ns_per_tick;
 }
 
+// ---- streaming loads and stores -------------------------------------------
+// The task's arrays arrive as generic pointers read from the task table; the
+// casts below tell the compiler they are global memory, so it emits
+// global_load/global_store instead of flat ones (flat accesses also count
+// against the LDS/scalar counter and stall behind unrelated waits).  Every
+// element is touched once, so the loads and stores are nontemporal.
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const f4v gf4;
+typedef __attribute__((address_space(1))) f4v gf4w;
+typedef __attribute__((address_space(1))) const float gf1;
+typedef __attribute__((address_space(1))) float gf1w;
+
+__device__ __forceinline__ float4 ld4(const float *p)
+{
+    const f4v v = __builtin_nontemporal_load((gf4 *)p);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float ld1(const float *p)
+{
+    return __builtin_nontemporal_load((gf1 *)p);
+}
+__device__ __forceinline__ void st4(float *p, const float4 &v)
+{
+    const f4v w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, (gf4w *)p);
+}
+__device__ __forceinline__ void st1(float *p, float v)
+{
+    __builtin_nontemporal_store(v, (gf1w *)p);
+}
+
+// Publication order without cache maintenance: the partials and results are
+// written with agent-scope atomic stores, which write through the per-XCD L2
+// to the device coherence point, and read back with agent-scope atomic loads,
+// which bypass it.  Waiting for this thread's stores to complete before the
+// arrival ticket is taken therefore makes them visible to the block that
+// takes the last ticket, without the L2 write-back of a release fence (which
+// costs half the streaming bandwidth when paid once per tile).
+__device__ __forceinline__ void own_stores_complete()
+{
+    __builtin_amdgcn_s_waitcnt(0);
+}
+
 // ---- binary32 Neumaier step ---------------------------------------------
 // t = s + v; the rounding error of that add is (big - t) + small, where big
 // is the operand of larger magnitude; it accumulates in c.
@@ -162,18 +205,22 @@ __device__ __forceinline__ void tile_elementwise(const M &f,
     const uint32_t head = vec ? min((4u - mis) & 3u, len) : len;
 
     for (uint32_t i = tid; i < head; i += kBlock) {
-        float v = f(xb[i], M::kTwo ? yb[i] : 0.0f);
+        float v = f(ld1(xb + i), M::kTwo ? ld1(yb + i) : 0.0f);
         if (W)
-            ob[i] = v;
+            st1(ob + i, v);
         a.add(v);
     }
     if (!vec)
         return;
 
+    // kUnroll quads per input in flight per thread.  (Doubling it for the
+    // one-input map triples the register count of the high-degree POLY
+    // bodies and spills.)
+    constexpr int U = kUnroll;
     const uint32_t nq = (len - head) >> 2;
-    const float4 *x4 = reinterpret_cast<const float4 *>(xb + head);
-    const float4 *y4 = M::kTwo ? reinterpret_cast<const float4 *>(yb + head) : nullptr;
-    float4 *o4 = W ? reinterpret_cast<float4 *>(ob + head) : nullptr;
+    const float *x4 = xb + head;
+    const float *y4 = M::kTwo ? yb + head : nullptr;
+    float *o4 = W ? ob + head : nullptr;
 
     auto quad = [&](const float4 &xv, const float4 &yv, uint32_t q) {
         float4 v;
@@ -182,7 +229,7 @@ __device__ __forceinline__ void tile_elementwise(const M &f,
         v.z = f(xv.z, yv.z);
         v.w = f(xv.w, yv.w);
         if (W)
-            o4[q] = v;
+            st4(o4 + 4u * q, v);
         a.add(v.x);
         a.add(v.y);
         a.add(v.z);
@@ -190,32 +237,32 @@ __device__ __forceinline__ void tile_elementwise(const M &f,
     };
 
     uint32_t q = tid;
-    for (; q + (kUnroll - 1) * kBlock < nq; q += kUnroll * kBlock) {
-        float4 xv[kUnroll], yv[kUnroll];
+    for (; q + (U - 1) * kBlock < nq; q += U * kBlock) {
+        float4 xv[U], yv[U];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            xv[u] = x4[q + u * kBlock];
+        for (int u = 0; u < U; ++u) {
+            xv[u] = ld4(x4 + 4u * (q + u * kBlock));
             if (M::kTwo)
-                yv[u] = y4[q + u * kBlock];
+                yv[u] = ld4(y4 + 4u * (q + u * kBlock));
             else
                 yv[u] = xv[u];
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
+        for (int u = 0; u < U; ++u)
             quad(xv[u], yv[u], q + u * kBlock);
     }
     for (; q < nq; q += kBlock) {
-        float4 xv = x4[q];
-        float4 yv = M::kTwo ? y4[q] : xv;
+        float4 xv = ld4(x4 + 4u * q);
+        float4 yv = M::kTwo ? ld4(y4 + 4u * q) : xv;
         quad(xv, yv, q);
     }
 
     const uint32_t t0 = head + 4u * nq;
     if (tid < len - t0) {
         uint32_t i = t0 + tid;
-        float v = f(xb[i], M::kTwo ? yb[i] : 0.0f);
+        float v = f(ld1(xb + i), M::kTwo ? ld1(yb + i) : 0.0f);
         if (W)
-            ob[i] = v;
+            st1(ob + i, v);
         a.add(v);
     }
 }
@@ -227,6 +274,12 @@ struct U4 {
     uint32_t x, y, z, w;
 };
 
+// Three-way xor as one gfx950 v_bitop3_b32 (truth table 0x96 = a ^ b ^ c).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
@@ -234,9 +287,9 @@ __device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1)
         const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
         U4 n;
-        n.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+        n.x = xor3((uint32_t)(p1 >> 32), c.y, k0);
         n.y = (uint32_t)p1;
-        n.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+        n.z = xor3((uint32_t)(p0 >> 32), c.w, k1);
         n.w = (uint32_t)p0;
         c = n;
         k0 += 0x9E3779B9u;
@@ -246,13 +299,13 @@ __device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1)
 }
 
 // Point (a, b) * 2^-24 from the top 24 bits of two words; a hit iff
-// a^2 + b^2 <= 2^48.  Both squares and their sum are below 2^49, so the FP64
-// multiply and fused add are exact and the test is the integer test.
+// a^2 + b^2 <= 2^48, decided exactly in 64-bit integers (two 32x32->64
+// multiply-adds).
 __device__ __forceinline__ uint32_t disc_hit(uint32_t wa, uint32_t wb)
 {
-    const double a = (double)(wa >> 8);
-    const double b = (double)(wb >> 8);
-    return __fma_rn(a, a, b * b) <= 281474976710656.0 ? 1u : 0u;
+    const uint32_t a = wa >> 8, b = wb >> 8;
+    const uint64_t r2 = (uint64_t)a * a + (uint64_t)b * b;
+    return r2 <= (1ull << 48) ? 1u : 0u;
 }
 
 // MapCLPartition Monte-Carlo tile: samples [begin, end), begin even.  Pair p
@@ -269,9 +322,8 @@ __device__ __forceinline__ void tile_mc(uint64_t seed, uint32_t pid,
     for (uint32_t i = threadIdx.x; i < npairs; i += kBlock) {
         const uint64_t p = p0 + i;
         const U4 r = philox10(U4{(uint32_t)p, (uint32_t)(p >> 32), pid, 0u}, k0, k1);
-        hits += disc_hit(r.x, r.y);
-        if (!(odd_tail && i == npairs - 1))
-            hits += disc_hit(r.z, r.w);
+        const uint32_t second = (odd_tail && i == npairs - 1) ? 0u : 1u;
+        hits += disc_hit(r.x, r.y) + (disc_hit(r.z, r.w) & second);
     }
     a.hits += hits;
 }
@@ -458,8 +510,9 @@ __device__ bool run_tile(const TaskDev *__restrict__ tp, uint32_t j,
         // its cleared state (0) is the identity of the max below.
         __hip_atomic_fetch_max(&sync[idx].t_start, ~t0, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const uint32_t prev = atomicAdd(&sync[idx].ticket, 1u);
+        own_stores_complete();
+        const uint32_t prev = __hip_atomic_fetch_add(&sync[idx].ticket, 1u, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
         sh_last = (prev == ntiles - 1) ? 1u : 0u;
     }
     __syncthreads();
@@ -472,8 +525,8 @@ __device__ bool run_tile(const TaskDev *__restrict__ tp, uint32_t j,
     if (!last)
         return false;
 
-    // Last tile of the task: combine its partials in index order.
-    __threadfence();
+    // Last tile of the task: combine its partials in index order (agent-scope
+    // atomic loads, issued only after the last ticket was observed).
     const Partial *parts = tp->partials;
     Red t = combine_ordered(ntiles, [&](uint32_t k, double &s, float &m,
                                         uint64_t &h, uint64_t &nn) {
@@ -494,7 +547,7 @@ __device__ bool run_tile(const TaskDev *__restrict__ tp, uint32_t j,
             __hip_atomic_store(L.done + idx, uni64(tp->seq) + 1, __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_SYSTEM);
         } else {
-            __threadfence();
+            own_stores_complete();
         }
     }
     // A barrier closes every thread-0 region that ends a loop iteration of the
@@ -512,7 +565,8 @@ __device__ void rdd_step(const LaunchOut &L)
     if (L.ntasks == 0)
         return;
     if (threadIdx.x == 0) {
-        const uint32_t prev = atomicAdd(&L.ctl->rdd_ticket, 1u);
+        const uint32_t prev = __hip_atomic_fetch_add(&L.ctl->rdd_ticket, 1u, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
         sh_last = (prev == L.ntasks - 1) ? 1u : 0u;
     }
     __syncthreads();
@@ -520,7 +574,6 @@ __device__ void rdd_step(const LaunchOut &L)
     __syncthreads();
     if (!last)
         return;
-    __threadfence();
     const sparkcl_result *res = L.results;
     Red t = combine_ordered(L.ntasks, [&](uint32_t k, double &s, float &m,
                                           uint64_t &h, uint64_t &n) {
@@ -532,7 +585,7 @@ __device__ void rdd_step(const LaunchOut &L)
                          0, device_ns(L.ns_per_tick));
         __hip_atomic_store(&L.ctl->rdd_ticket, 0u, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
+        own_stores_complete();
     }
     __syncthreads();
 }
@@ -550,34 +603,44 @@ __global__ __launch_bounds__(kBlock) void k_task(const TaskDev *__restrict__ tas
 }
 
 // Persistent executor: a fixed grid of blocks takes tiles from the queue with
-// one atomic each until the queue is empty.  The last block to leave resets
-// the queue head, so the launch can be replayed from a graph as is.
+// one atomic each until the queue is empty; thread 0 asks for the next tile
+// while the current one streams, so the queue round trip is hidden.  The last
+// block to leave resets the queue head, so the launch can be replayed from a
+// graph as is.
 __global__ __launch_bounds__(kBlock) void k_batch(const TaskDev *__restrict__ tasks,
                                                   const TileRef *__restrict__ tiles,
                                                   uint32_t ntiles, LaunchOut L)
 {
     __shared__ uint32_t sh_tile;
-    for (;;) {
+    if (threadIdx.x == 0)
+        sh_tile = __hip_atomic_fetch_add(&L.ctl->head, 1u, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    uint32_t t = uni(sh_tile);
+    __syncthreads();
+    while (t < ntiles) {
+        uint32_t next = 0;
         if (threadIdx.x == 0)
-            sh_tile = atomicAdd(&L.ctl->head, 1u);
-        __syncthreads();
-        const uint32_t t = uni(sh_tile);
-        __syncthreads();
-        if (t >= ntiles)
-            break;
+            next = __hip_atomic_fetch_add(&L.ctl->head, 1u, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
         const TileRef tr = tiles[t];
         const TaskDev *tp = tasks + uni(tr.task);
         if (run_tile(tp, uni(tr.tile), L))
             rdd_step(L);
+        if (threadIdx.x == 0)
+            sh_tile = next;
+        __syncthreads();
+        t = uni(sh_tile);
+        __syncthreads();
     }
     if (threadIdx.x == 0) {
-        __threadfence();
-        if (atomicAdd(&L.ctl->exited, 1u) == gridDim.x - 1) {
+        own_stores_complete();
+        if (__hip_atomic_fetch_add(&L.ctl->exited, 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1) {
             __hip_atomic_store(&L.ctl->head, 0u, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&L.ctl->exited, 0u, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();
         }
     }
 }
@@ -597,26 +660,26 @@ __device__ __forceinline__ void map_only(const M &f, const float *__restrict__ x
         vec = false;
     const uint64_t head = vec ? min((uint64_t)((4u - ((ax & 15u) >> 2)) & 3u), n) : n;
     for (uint64_t i = gtid; i < head; i += stride)
-        out[i] = f(x[i], M::kTwo ? y[i] : 0.0f);
+        st1(out + i, f(ld1(x + i), M::kTwo ? ld1(y + i) : 0.0f));
     if (!vec)
         return;
     const uint64_t nq = (n - head) >> 2;
-    const float4 *x4 = reinterpret_cast<const float4 *>(x + head);
-    const float4 *y4 = M::kTwo ? reinterpret_cast<const float4 *>(y + head) : nullptr;
-    float4 *o4 = reinterpret_cast<float4 *>(out + head);
+    const float *x4 = x + head;
+    const float *y4 = M::kTwo ? y + head : nullptr;
+    float *o4 = out + head;
     for (uint64_t q = gtid; q < nq; q += stride) {
-        const float4 xv = x4[q];
-        const float4 yv = M::kTwo ? y4[q] : xv;
+        const float4 xv = ld4(x4 + 4 * q);
+        const float4 yv = M::kTwo ? ld4(y4 + 4 * q) : xv;
         float4 v;
         v.x = f(xv.x, yv.x);
         v.y = f(xv.y, yv.y);
         v.z = f(xv.z, yv.z);
         v.w = f(xv.w, yv.w);
-        o4[q] = v;
+        st4(o4 + 4 * q, v);
     }
     const uint64_t t0 = head + 4 * nq;
     if (gtid < n - t0)
-        out[t0 + gtid] = f(x[t0 + gtid], M::kTwo ? y[t0 + gtid] : 0.0f);
+        st1(out + t0 + gtid, f(ld1(x + t0 + gtid), M::kTwo ? ld1(y + t0 + gtid) : 0.0f));
 }
 
 __global__ __launch_bounds__(kBlock) void k_map(const TaskDev *__restrict__ tp,
@@ -679,13 +742,18 @@ __global__ __launch_bounds__(kBlock) void k_fill_pattern(float *p, uint64_t n,
 // Block 0 is the dispatcher: it polls the host ring's tail word (system
 // scope), copies each new descriptor into the device table, writes the task's
 // tiles into the tile map and publishes the new tile count.  Every other block
-// is a worker: it claims published tiles one at a time with a compare-and-swap
-// (never claiming a tile that is not yet published) and runs each exactly as
-// the batch executor does; a task's last tile writes its result to host
-// memory and then its completion word.  Every wait is bounded: the dispatcher
-// leaves on the host's stop word, or after idle_ticks without new work once
-// every published tile is claimed; a worker leaves when the dispatcher says so
-// (checked before each claim) or after four idle periods without a tile.
+// is a worker.  A worker takes one tile ticket at a time with an atomic add
+// (one round trip, no retries), then polls the published-tile word with
+// exponential backoff until its ticket is published, and runs the tile
+// exactly as the batch executor does; a task's last tile writes its result to
+// host memory and then its completion word.  Every wait is bounded: the
+// dispatcher leaves on the host's stop word, or after idle_ticks without new
+// work, setting the stop bit of the published-tile word (and the abort bit
+// when the host asked to abort); a worker leaves at once on abort, when its
+// ticket is unpublished and the stop bit is set, or after four idle periods.  Tickets are issued in order and a worker never leaves holding a
+// published ticket, so every published tile runs before the grid drains.  A
+// ticket left unpublished at exit is discarded by the next launch's prologue,
+// which restarts the tickets at the published count.
 
 static_assert(offsetof(TaskDev, ntiles) == 96, "word 24 of a descriptor");
 static_assert(offsetof(TaskDev, tile_first) == 120, "words 30-31 of a descriptor");
@@ -693,22 +761,26 @@ static_assert(offsetof(TaskDev, tile_first) == 120, "words 30-31 of a descriptor
 __device__ void serve_dispatch(const ServeArgs &a)
 {
     __shared__ uint64_t sh_tail, sh_stop;
-    __shared__ uint32_t sh_nt, sh_first_lo, sh_first_hi, sh_idle_exit;
+    __shared__ uint32_t sh_nt, sh_first_lo, sh_first_hi;
     uint64_t taken = uni64(ld_agent(&a.dev->taken));
     uint64_t last = wall_clock64();
     for (;;) {
         if (threadIdx.x == 0) {
-            sh_tail = __hip_atomic_load(&a.host->tail, __ATOMIC_ACQUIRE,
+            sh_tail = __hip_atomic_load(&a.host->tail, __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_SYSTEM);
             sh_stop = __hip_atomic_load(&a.host->stop, __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_SYSTEM);
         }
         __syncthreads();
         const uint64_t tail = uni64(sh_tail);
-        const bool stop = uni((uint32_t)(sh_stop != 0)) != 0;
+        const uint32_t stop = uni((uint32_t)sh_stop);
         __syncthreads();
-        if (stop)
+        if (stop) {
+            if (threadIdx.x == 0 && stop >= 2)
+                __hip_atomic_fetch_or(&a.dev->tiles_pub, kServeAbortBit, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
             break;
+        }
         if (tail > taken) {
             uint64_t pub = 0;
             for (uint64_t s = taken; s < tail; ++s) {
@@ -737,33 +809,26 @@ __device__ void serve_dispatch(const ServeArgs &a)
                 pub = first + nt;
                 __syncthreads();
             }
-            __threadfence();
+            // table and tile-map entries were written with agent-scope atomic
+            // stores; once they are complete the new tile count is published
+            own_stores_complete();
             __syncthreads();
             if (threadIdx.x == 0) {
                 st_agent(&a.dev->taken, tail);
-                __hip_atomic_store(&a.dev->tiles_pub, pub, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+                own_stores_complete();
+                st_agent(&a.dev->tiles_pub, pub);
             }
             taken = tail;
             last = wall_clock64();
             continue;
         }
-        // idle exit: decided by thread 0 alone (different waves could read
-        // different counter values) and broadcast, so all waves agree
-        if (threadIdx.x == 0)
-            sh_idle_exit = (wall_clock64() - last > a.idle_ticks &&
-                            ld_agent(&a.dev->claim) >= ld_agent(&a.dev->tiles_pub))
-                               ? 1u
-                               : 0u;
-        __syncthreads();
-        const bool idle_exit = uni(sh_idle_exit) != 0;
-        __syncthreads();
-        if (idle_exit)
+        if (wall_clock64() - last > a.idle_ticks)
             break;
-        __builtin_amdgcn_s_sleep(8);
+        __builtin_amdgcn_s_sleep(16);
     }
     if (threadIdx.x == 0)
-        __hip_atomic_store(&a.dev->stop, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_or(&a.dev->tiles_pub, kServeStopBit, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ void serve_work(const ServeArgs &a)
@@ -773,32 +838,29 @@ __device__ void serve_work(const ServeArgs &a)
     constexpr uint64_t kNone = ~0ull;
     for (;;) {
         if (threadIdx.x == 0) {
+            const uint64_t c = __hip_atomic_fetch_add(&a.dev->claim, 1ull, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
             uint64_t got = kNone;
             const uint64_t wait0 = wall_clock64();
+            uint32_t backoff = 1;
             for (;;) {
-                // the stop word is checked before every claim, so a stop from
-                // the host takes effect after the tiles already running
-                const uint32_t stop = __hip_atomic_load(&a.dev->stop, __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_AGENT);
-                const uint64_t p = __hip_atomic_load(&a.dev->tiles_pub, __ATOMIC_ACQUIRE,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-                if (stop)
+                const uint64_t w = ld_agent(&a.dev->tiles_pub);
+                if (w & kServeAbortBit)
                     break;
-                uint64_t c = __hip_atomic_load(&a.dev->claim, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                if (c < p) {
-                    if (__hip_atomic_compare_exchange_strong(&a.dev->claim, &c, c + 1,
-                                                             __ATOMIC_ACQ_REL,
-                                                             __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_AGENT)) {
-                        got = c;
-                        break;
-                    }
-                    continue;
+                if (c < (w & kServeCountMask)) {
+                    got = c;
+                    break;
                 }
-                if (wall_clock64() - wait0 > 4 * a.idle_ticks)
+                if ((w & kServeStopBit) || wall_clock64() - wait0 > 4 * a.idle_ticks)
                     break;
-                __builtin_amdgcn_s_sleep(2);
+                // s_sleep takes an immediate: a few fixed steps of backoff
+                if (backoff == 1)
+                    __builtin_amdgcn_s_sleep(1);
+                else if (backoff == 2)
+                    __builtin_amdgcn_s_sleep(4);
+                else
+                    __builtin_amdgcn_s_sleep(16);
+                backoff = backoff < 3 ? backoff + 1 : 3;
             }
             sh_tile = got;
         }
@@ -806,8 +868,12 @@ __device__ void serve_work(const ServeArgs &a)
         const uint64_t t = uni64(sh_tile);
         if (t == kNone)
             break;
+        // Acquire before touching the task: the descriptor, and the task's
+        // inputs, which the caller may have rewritten since this resident
+        // kernel last read that memory (its L2 is not invalidated between
+        // tasks the way it is between kernel launches).
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (threadIdx.x < 32) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             const uint32_t slot = __hip_atomic_load(a.tilemap + (t & (a.tile_cap - 1)),
                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             uint32_t *src = reinterpret_cast<uint32_t *>(a.table + slot) + threadIdx.x;
@@ -827,6 +893,17 @@ __global__ __launch_bounds__(kBlock) void k_serve(ServeArgs a)
         serve_dispatch(a);
     else
         serve_work(a);
+}
+
+// Launch prologue: clear the stop bit and restart the tickets at the
+// published count (no worker of the previous launch is alive to hold one).
+__global__ void k_serve_prologue(ServeDev *d)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const uint64_t pub = d->tiles_pub & kServeCountMask;
+        d->tiles_pub = pub;
+        d->claim = pub;
+    }
 }
 
 int hip_status(hipError_t e)
@@ -899,6 +976,10 @@ int launch_serve(const ServeArgs &a, uint32_t workers, void *stream)
     if (workers == 0 || a.cap == 0 || (a.cap & (a.cap - 1)) || a.tile_cap == 0 ||
         (a.tile_cap & (a.tile_cap - 1)))
         return SPARKCL_EINVAL;
+    hipLaunchKernelGGL(k_serve_prologue, dim3(1), dim3(64), 0, (hipStream_t)stream, a.dev);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_status(e);
     hipLaunchKernelGGL(k_serve, dim3(workers + 1), dim3(kBlock), 0, (hipStream_t)stream, a);
     return hip_status(hipGetLastError());
 }

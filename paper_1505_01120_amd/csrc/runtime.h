@@ -71,7 +71,9 @@ int get_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
              hipStream_t stream, Plan **out);
 int enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream);
 void drop_plans(sparkcl_ctx *ctx);
-uint32_t exec_grid(const sparkcl_ctx *ctx);
+// Persistent-executor grid for a batch holding the kernels in kid_mask
+// (bit k-1 for kernel id k).
+uint32_t exec_grid(const sparkcl_ctx *ctx, uint32_t kid_mask);
 
 } // namespace sparkcl
 

@@ -159,8 +159,9 @@ int Server::submit(const sparkcl_task &task, uint64_t *ticket)
         return fail(SPARKCL_ETOOBIG, "task needs " + std::to_string(bytes) +
                                          " bytes, budget is " + std::to_string(adm_.budget()));
     std::lock_guard<std::mutex> g(mu_);
-    if (quit_)
-        return fail(SPARKCL_ESTOPPED, "serving is shutting down");
+    if (quit_ || poisoned_)
+        return fail(SPARKCL_ESTOPPED, poisoned_ ? "serving executor could not be stopped"
+                                                : "serving is shutting down");
     if (adm_.pending() >= kMaxPending)
         return fail(SPARKCL_EAGAIN, "pending queue full");
     Pending p;
@@ -332,9 +333,7 @@ int Server::launch_executor()
     a.cap = cap_;
     a.tile_cap = tile_cap_;
     a.idle_ticks = (uint64_t)ctx_->config.idle_exit_ms * 1000000ull / ctx_->ns_per_tick;
-    int rc = launch_zero(&dev_->stop, 8, exec_stream_);
-    if (rc == SPARKCL_OK)
-        rc = launch_serve(a, workers_, exec_stream_);
+    const int rc = launch_serve(a, workers_, exec_stream_);
     if (rc != SPARKCL_OK)
         return fail(rc, "resident executor launch failed");
     exec_launched_ = true;
@@ -343,7 +342,7 @@ int Server::launch_executor()
     return SPARKCL_OK;
 }
 
-int Server::stop_executor(uint32_t timeout_ms)
+int Server::stop_executor(uint32_t timeout_ms, bool abort)
 {
     int rc = SPARKCL_OK;
     const uint64_t t0 = host_ns();
@@ -356,7 +355,7 @@ int Server::stop_executor(uint32_t timeout_ms)
             std::this_thread::sleep_for(std::chrono::microseconds(100));
         }
     };
-    __atomic_store_n(&host_->stop, 1ull, __ATOMIC_RELEASE);
+    __atomic_store_n(&host_->stop, abort ? 2ull : 1ull, __ATOMIC_RELEASE);
     wait_stream(exec_stream_);
     for (hipStream_t s : pool_)
         wait_stream(s);
@@ -423,7 +422,7 @@ int Server::reset_device_state()
     ServeDev d;
     std::memset(&d, 0, sizeof(d));
     d.taken = __atomic_load_n(&host_->tail, __ATOMIC_ACQUIRE);
-    d.tiles_pub = tiles_pub_host_;
+    d.tiles_pub = tiles_pub_host_; // stop bit clear
     d.claim = tiles_pub_host_;
     SPARKCL_HIP(hipMemcpyAsync(dev_, &d, sizeof(d), hipMemcpyHostToDevice, exec_stream_));
     int rc = launch_zero(sync_, (uint64_t)cap_ * sizeof(TaskSync), exec_stream_);
@@ -481,12 +480,13 @@ void Server::loop()
                 oldest = std::min(oldest, f.t_admit);
         }
         if (oldest != ~0ull && host_ns() - oldest > watchdog_ns) {
-            if (stop_executor(2000) == SPARKCL_OK) {
+            if (stop_executor(2000, true) == SPARKCL_OK) {
                 reap();
                 fail_in_flight(SPARKCL_ETIMEDOUT);
                 reset_device_state();
             } else {
-                fail_in_flight(SPARKCL_ETIMEDOUT);
+                poison(SPARKCL_ETIMEDOUT);
+                break;
             }
         }
         if (progress)
@@ -509,9 +509,34 @@ void Server::loop()
             launch_executor();
         std::this_thread::sleep_for(std::chrono::microseconds(50));
     }
-    const int rc = stop_executor(10000);
+    if (poisoned_)
+        return;
+    const int rc = stop_executor(10000, false);
     reap();
-    fail_in_flight(rc == SPARKCL_OK ? SPARKCL_ESTOPPED : SPARKCL_ETIMEDOUT);
+    if (rc == SPARKCL_OK)
+        fail_in_flight(SPARKCL_ESTOPPED);
+    else
+        poison(SPARKCL_ETIMEDOUT);
+}
+
+// The executor did not stop in time: fail every in-flight task but keep its
+// partials and slot reserved, and refuse further work.
+void Server::poison(int code)
+{
+    std::lock_guard<std::mutex> g(mu_);
+    poisoned_ = true;
+    for (Flight &f : flight_) {
+        sparkcl_result r = failed_result(code);
+        r.n = f.task.n;
+        r.t_arrive_ns = f.a.p.t_arrive;
+        r.t_admit_ns = f.t_admit;
+        r.t_done_ns = host_ns();
+        done_map_[f.a.p.ticket] = r;
+        waiting_.erase(f.a.p.ticket);
+        ++failed_;
+    }
+    flight_.clear();
+    cv_done_.notify_all();
 }
 
 int Server::shutdown()
@@ -533,7 +558,7 @@ int Server::shutdown()
     cv_work_.notify_all();
     if (thread_.joinable())
         thread_.join();
-    const int rc = stop_executor(10000);
+    const int rc = poisoned_ ? SPARKCL_ETIMEDOUT : stop_executor(10000, false);
     if (rc == SPARKCL_OK) {
         for (hipStream_t s : pool_)
             (void)hipStreamDestroy(s);

@@ -39,8 +39,11 @@ class Server {
     bool reap();
     bool executor_running();
     int launch_executor();
-    int stop_executor(uint32_t timeout_ms);
+    // abort: leave without running further tiles (watchdog); otherwise the
+    // executor drains the tiles already published before it exits
+    int stop_executor(uint32_t timeout_ms, bool abort);
     void fail_in_flight(int code);
+    void poison(int code);
     int reset_device_state();
 
     struct Flight {
@@ -89,6 +92,9 @@ class Server {
     uint64_t submitted_ = 0, admitted_ = 0, completed_ = 0, failed_ = 0, waits_ = 0;
     uint64_t launches_ = 0;
     bool quit_ = false, started_ = false;
+    // set when the executor could not be stopped: in-flight memory stays
+    // reserved (the GPU may still write it) and no new work is accepted
+    bool poisoned_ = false;
     std::thread thread_;
 };
 

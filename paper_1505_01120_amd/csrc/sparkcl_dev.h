@@ -95,20 +95,26 @@ struct LaunchOut {
 // host-coherent memory).
 struct ServeHost {
     uint64_t tail;  // tasks published by the host (release-stored)
-    uint64_t stop;  // nonzero: the executor should exit
+    uint64_t stop;  // 1: drain published tiles and exit; 2: abort at once
     uint64_t pad[6];
 };
 
 // Serving: device-side state of the resident executor.  It persists across
-// relaunches (an idle executor exits and is started again on demand).
+// relaunches (an idle executor exits and is started again on demand).  The
+// polled word, the claim counter and the dispatcher's own counter sit on
+// separate 128-byte lines so polling does not contend with claims.
+constexpr uint64_t kServeStopBit = 1ull << 63;  // drain published tiles, then exit
+constexpr uint64_t kServeAbortBit = 1ull << 62; // exit without running more tiles
+constexpr uint64_t kServeCountMask = kServeAbortBit - 1;
 struct ServeDev {
+    uint64_t tiles_pub; // tiles published to the workers; kServeStopBit: exit
+    uint64_t pad0[15];
+    uint64_t claim;     // next tile ticket handed to a worker
+    uint64_t pad1[15];
     uint64_t taken;     // host-ring tasks copied into the device table
-    uint64_t tiles_pub; // tiles published to the workers
-    uint64_t claim;     // next tile to claim
-    uint32_t stop;      // dispatcher tells the workers to exit (reset per launch)
-    uint32_t pad0;
-    uint64_t pad[4];
+    uint64_t pad2[15];
 };
+static_assert(sizeof(ServeDev) == 384, "ServeDev layout");
 
 struct ServeArgs {
     ServeHost *host;     // host-coherent control words
@@ -130,7 +136,8 @@ int launch_batch(const TaskDev *dtasks, const TileRef *tiles, uint32_t ntiles,
 int launch_map(const TaskDev *dtask, uint64_t n, uint32_t variant,
                uint32_t grid, void *stream);
 int launch_zero(void *p, uint64_t bytes, void *stream);
-// Resident serving executor: block 0 dispatches, the rest run tiles.
+// Resident serving executor: block 0 dispatches, the rest run tiles.  Each
+// launch first discards tickets left unpublished by the previous launch.
 int launch_serve(const ServeArgs &a, uint32_t workers, void *stream);
 int launch_fill_pattern(float *p, uint64_t n, uint32_t salt, void *stream);
 // Blocks of the batch executor that fit on one CU at once.

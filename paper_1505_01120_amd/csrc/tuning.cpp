@@ -173,7 +173,7 @@ struct Parser {
 void tuning_defaults(sparkcl_tuning *t)
 {
     std::memset(t, 0, sizeof(*t));
-    t->blocks_per_cu = 0; // 0: as many as fit (occupancy)
+    // blocks_per_cu 0: as many as fit (occupancy)
     for (uint32_t b = 0; b < SPARKCL_TUNE_BUCKETS; ++b) {
         // One launch per partition: aim at ~2048 tiles so the grid fills the
         // chip, without going below 4K elements per 256-thread block.
@@ -203,11 +203,12 @@ int tuning_validate(const sparkcl_tuning *t, std::string *why)
             *why = "null tuning table";
         return SPARKCL_EINVAL;
     }
-    if (t->blocks_per_cu > 32) {
-        if (why)
-            *why = "blocks_per_cu above 32";
-        return SPARKCL_EINVAL;
-    }
+    for (int k = 0; k < 3; ++k)
+        if (t->blocks_per_cu[k] > 32) {
+            if (why)
+                *why = "blocks_per_cu above 32";
+            return SPARKCL_EINVAL;
+        }
     for (int m = 0; m < SPARKCL_TUNE_MODES; ++m)
         for (int k = 0; k < 3; ++k)
             for (int b = 0; b < SPARKCL_TUNE_BUCKETS; ++b) {
@@ -253,8 +254,19 @@ bool tuning_parse_json(const std::string &text,
                 *err = "entry for " + arch.first + " is not an object";
             return false;
         }
-        if (const Json *b = e.get("blocks_per_cu"))
-            t.blocks_per_cu = (uint32_t)b->num;
+        if (const Json *b = e.get("blocks_per_cu")) {
+            if (b->kind == Json::NUM) {
+                for (int k = 0; k < 3; ++k)
+                    t.blocks_per_cu[k] = (uint32_t)b->num;
+            } else if (b->kind == Json::ARR && b->arr.size() == 3) {
+                for (int k = 0; k < 3; ++k)
+                    t.blocks_per_cu[k] = (uint32_t)b->arr[k].num;
+            } else {
+                if (err)
+                    *err = "blocks_per_cu must be a number or an array of 3";
+                return false;
+            }
+        }
         if (const Json *tile = e.get("tile")) {
             for (int m = 0; m < SPARKCL_TUNE_MODES; ++m) {
                 const Json *mj = tile->get(kModeNames[m]);
@@ -293,8 +305,9 @@ std::string tuning_to_json(const std::map<std::string, sparkcl_tuning> &all)
     size_t ai = 0;
     for (auto &kv : all) {
         const sparkcl_tuning &t = kv.second;
-        o << " \"" << kv.first << "\": {\n  \"blocks_per_cu\": " << t.blocks_per_cu
-          << ",\n  \"tile\": {\n";
+        o << " \"" << kv.first << "\": {\n  \"blocks_per_cu\": [" << t.blocks_per_cu[0]
+          << ", " << t.blocks_per_cu[1] << ", " << t.blocks_per_cu[2]
+          << "],\n  \"tile\": {\n";
         for (int m = 0; m < SPARKCL_TUNE_MODES; ++m) {
             o << "   \"" << kModeNames[m] << "\": {\n";
             for (int k = 0; k < 3; ++k) {

@@ -31,7 +31,7 @@ void tuning_defaults(sparkcl_tuning *t);
 int tuning_validate(const sparkcl_tuning *t, std::string *why);
 uint32_t tile_for(const sparkcl_tuning &t, int mode, uint32_t kid, uint64_t n);
 
-// JSON cache: { "<gfx arch>": { "blocks_per_cu": N, "tile": { "<mode>":
+// JSON cache: { "<gfx arch>": { "blocks_per_cu": [P, F, M], "tile": { "<mode>":
 // { "<kernel>": [32 tile sizes] } } }, ... } with modes per_launch, batched,
 // serve and kernels poly, fmul, mc_pi.
 bool tuning_parse_json(const std::string &text,

@@ -260,7 +260,7 @@ def test_tuning_defaults_valid_and_lookup(host):
 def test_tuning_json_roundtrip(host, tmp_path):
     t = sc.Tuning()
     host.hl_tuning_defaults(ctypes.byref(t))
-    t.blocks_per_cu = 5
+    t.blocks_per_cu[0], t.blocks_per_cu[1], t.blocks_per_cu[2] = 1, 2, 7
     t.tile[1][1][22] = 1 << 16
     path = str(tmp_path / "tune.json").encode()
     assert host.hl_tuning_save(path, b"gfx950:sramecc+:xnack-", ctypes.byref(t)) == 1
@@ -277,6 +277,9 @@ def test_tuning_json_roundtrip(host, tmp_path):
     assert host.hl_tuning_parse(open(path).read().encode(), err, 256) == 2
     bad = b'{"gfx950": {"tile": {"batched": {"poly": [1, 2]}}}}'
     assert host.hl_tuning_parse(bad, err, 256) == -1 and b"32 sizes" in err.value
+    # a single number sets every kernel's occupancy
+    assert host.hl_tuning_parse(b'{"gfx950": {"blocks_per_cu": 3}}', err, 256) == 1
+    assert host.hl_tuning_parse(b'{"gfx950": {"blocks_per_cu": 40}}', err, 256) == -1
     assert host.hl_tuning_parse(b'{"gfx950": [}', err, 256) == -1
 
 
