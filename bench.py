@@ -359,7 +359,7 @@ def main() -> int:
     achieved = algo_bytes / (ev_ms / 1e3) / 1e9
     traffic = load_traffic("fmul_rdd_batched")
     line = {
-        "metric": "mapCL+reduceCL elements/s (64 x 2^22 FMUL pairs, SUM+MAX per partition)",
+        "metric": "mapCL+reduceCL elements/s and % peak HBM GB/s; p50/p99 task latency",
         "value": elems / (wall_ms / 1e3),
         "unit": "elements/s",
         "n_gpus": 1,

@@ -225,7 +225,11 @@ typedef struct sparkcl_tuning {
                                     registry kernel (index kernel id - 1); a
                                     batch uses the largest among the kernels
                                     it holds; 0 = as many as fit              */
-    uint32_t reserved;
+    uint32_t blocks_per_cu_many; /* the executor's blocks per CU for a batch of
+                                    many small tasks (under 4 tiles per task
+                                    on average), where per-tile latency
+                                    rather than streaming depth dominates;
+                                    0 = as many as fit                        */
     /* tile size in elements (samples for MC_PI) for [mode][kernel-1][log2 n];
        powers of two from 2^10 to 2^22. */
     uint32_t tile[SPARKCL_TUNE_MODES][3][SPARKCL_TUNE_BUCKETS];

@@ -28,12 +28,13 @@ def main(argv=None) -> int:
     args = ap.parse_args(argv)
     t0 = time.time()
     # start from the built-in defaults, not from an existing cache
-    with sc.Context(device=0, arena_bytes=2 << 30, tune_cache=None) as ctx:
+    with sc.Context(device=0, arena_bytes=3 << 30, tune_cache=None) as ctx:
         ctx.autotune(args.lo, args.hi, args.out)
         t = ctx.get_tuning()
     names = ["per_launch", "batched", "serve"]
     kern = ["poly", "fmul", "mc_pi"]
     summary = {"blocks_per_cu": list(t.blocks_per_cu),
+               "blocks_per_cu_many": t.blocks_per_cu_many,
                "tiles": {m: {k: list(t.tile[i][j][args.lo:args.hi + 1])
                              for j, k in enumerate(kern)} for i, m in enumerate(names[:2])}}
     print(json.dumps(summary), flush=True)

@@ -5,6 +5,7 @@
 // machine always decomposes a task the same way (results stay run-to-run
 // identical).  The paper leaves optimisation open (sec. 6); this is ours.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -14,16 +15,24 @@ using namespace sparkcl;
 
 namespace {
 
-// Synthetic input per array (512 MiB): batches stream from HBM, not from the
+// Synthetic input per array (1 GiB): batches stream from HBM, not from the
 // 256 MB last-level cache.
-constexpr uint64_t kPoolElems = 1ull << 27;
-constexpr int kWarm = 2, kReps = 7;
+constexpr uint64_t kPoolElems = 1ull << 28;
+constexpr int kWarm = 3, kReps = 9;
 
-// Elements per timed batch: at least 512 MiB of input for the streaming
-// kernels; 2^26 samples for the Monte-Carlo kernel.
+// Elements per timed batch: 1 GiB of input for the streaming kernels (a batch
+// large enough that the tile count per block, not the launch, dominates);
+// 2^26 samples for the Monte-Carlo kernel.
 uint64_t work_elems(uint32_t kid)
 {
-    return kid == SPARKCL_POLY ? (1ull << 27) : (1ull << 26);
+    return kid == SPARKCL_POLY ? (1ull << 28) : kid == SPARKCL_FMUL ? (1ull << 27) : (1ull << 26);
+}
+
+uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
 }
 
 struct Bench {
@@ -56,32 +65,60 @@ int time_reduce(Bench &b, int mode, const std::vector<sparkcl_task> &tasks, floa
     return SPARKCL_OK;
 }
 
+sparkcl_task make_task(const Bench &b, uint32_t kid, uint64_t n, uint64_t i)
+{
+    sparkcl_task t;
+    std::memset(&t, 0, sizeof(t));
+    t.kernel_id = kid;
+    t.n = n;
+    const uint64_t off = (i * n) % (kPoolElems - n + 1);
+    if (kid == SPARKCL_MC_PI) {
+        t.reduce_ops = SPARKCL_COUNT;
+        t.partition_id = (uint32_t)i;
+    } else {
+        t.reduce_ops = SPARKCL_SUM | SPARKCL_MAX;
+        t.in0 = b.x + off;
+        t.in1 = kid == SPARKCL_FMUL ? b.y + off : nullptr;
+        t.degree = 2;
+        t.coef[0] = 3.0f;
+        t.coef[1] = -1.25f;
+        t.coef[2] = 0.5f;
+        t.c = 0.1f;
+    }
+    return t;
+}
+
+// Many small tasks of mixed kernels: 2048 tasks, sizes log-uniform in
+// [2^10, 2^20), kernel ids uniform.
+std::vector<sparkcl_task> make_mixed(const Bench &b)
+{
+    std::vector<sparkcl_task> v;
+    uint64_t off = 0;
+    for (uint64_t i = 0; i < 2048; ++i) {
+        const uint64_t h = mix64(0x5eed + i);
+        const double e = 10.0 + 10.0 * (double)(h >> 11) * 0x1p-53;
+        const uint64_t n = (uint64_t)std::exp2(e);
+        const uint32_t kid = 1 + (uint32_t)((mix64(h) >> 32) % 3);
+        sparkcl_task t = make_task(b, kid, n, 0);
+        if (kid != SPARKCL_MC_PI) {
+            if (off + n > kPoolElems)
+                off = 0;
+            t.in0 = b.x + off;
+            t.in1 = kid == SPARKCL_FMUL ? b.y + off : nullptr;
+            off += n;
+        }
+        v.push_back(t);
+    }
+    return v;
+}
+
 std::vector<sparkcl_task> make_tasks(const Bench &b, uint32_t kid, uint64_t n, int mode)
 {
     const uint64_t count =
         mode == SPARKCL_BATCHED ? std::max<uint64_t>(1, work_elems(kid) / n) : 1;
     std::vector<sparkcl_task> v;
-    for (uint64_t i = 0; i < std::min<uint64_t>(count, 4096); ++i) {
-        sparkcl_task t;
-        std::memset(&t, 0, sizeof(t));
-        t.kernel_id = kid;
-        t.n = n;
-        const uint64_t off = (i * n) % (kPoolElems - n + 1);
-        if (kid == SPARKCL_MC_PI) {
-            t.reduce_ops = SPARKCL_COUNT;
-            t.partition_id = (uint32_t)i;
-        } else {
-            t.reduce_ops = SPARKCL_SUM | SPARKCL_MAX;
-            t.in0 = b.x + off;
-            t.in1 = kid == SPARKCL_FMUL ? b.y + off : nullptr;
-            t.degree = 2;
-            t.coef[0] = 3.0f;
-            t.coef[1] = -1.25f;
-            t.coef[2] = 0.5f;
-            t.c = 0.1f;
-        }
-        v.push_back(t);
-    }
+    for (uint64_t i = 0; i < std::min<uint64_t>(count, 4096); ++i)
+        v.push_back(make_task(b, kid, n, i));
     return v;
 }
 
@@ -112,7 +149,7 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
     };
     if (xoff == Arena::kFail || yoff == Arena::kFail) {
         cleanup();
-        return fail(SPARKCL_ENOMEM, "autotune needs 1 GiB of free arena");
+        return fail(SPARKCL_ENOMEM, "autotune needs 2 GiB of free arena");
     }
     b.x = static_cast<float *>(ctx->dev(xoff));
     b.y = static_cast<float *>(ctx->dev(yoff));
@@ -181,6 +218,29 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
             }
         }
         best.blocks_per_cu[kid - 1] = best_bpc;
+    }
+
+    // Occupancy for batches of many small tasks.
+    {
+        const std::vector<sparkcl_task> tasks = make_mixed(b);
+        float best_ms = 1e30f;
+        uint32_t best_bpc = best.blocks_per_cu_many;
+        for (uint32_t bpc = 1; bpc <= (uint32_t)ctx->occ_batch; ++bpc) {
+            drop_plans(ctx);
+            ctx->tuning = best;
+            ctx->tuning.blocks_per_cu_many = bpc;
+            float ms = 0;
+            if ((rc = time_reduce(b, SPARKCL_BATCHED, tasks, &ms)) != SPARKCL_OK) {
+                ctx->tuning = best;
+                cleanup();
+                return rc;
+            }
+            if (ms < best_ms * 0.98f) {
+                best_ms = ms;
+                best_bpc = bpc;
+            }
+        }
+        best.blocks_per_cu_many = best_bpc;
     }
 
     ctx->tuning = best;

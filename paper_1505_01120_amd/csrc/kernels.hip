@@ -236,20 +236,58 @@ __device__ __forceinline__ void tile_elementwise(const M &f,
         a.add(v.w);
     };
 
-    uint32_t q = tid;
-    for (; q + (U - 1) * kBlock < nq; q += U * kBlock) {
-        float4 xv[U], yv[U];
+    // Software-pipelined main loop: the loads of the next group of U quads
+    // are issued before the current group is folded, so a wave keeps loads
+    // in flight while it computes (with one or two waves per SIMD nothing
+    // else would).  Two register buffers alternate; each thread still visits
+    // its quads in increasing order, so the rounding is that of the plain
+    // loop.
+    // (One-input maps carry no y buffer: NY = 0.)
+    constexpr int NY = M::kTwo ? U : 1;
+    auto load = [&](float4 *xv, float4 *yv, uint32_t q0) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            xv[u] = ld4(x4 + 4u * (q + u * kBlock));
+            xv[u] = ld4(x4 + 4u * (q0 + u * kBlock));
             if (M::kTwo)
-                yv[u] = ld4(y4 + 4u * (q + u * kBlock));
-            else
-                yv[u] = xv[u];
+                yv[u] = ld4(y4 + 4u * (q0 + u * kBlock));
         }
+    };
+    auto fold = [&](const float4 *xv, const float4 *yv, uint32_t q0) {
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            quad(xv[u], yv[u], q + u * kBlock);
+            quad(xv[u], M::kTwo ? yv[u] : xv[u], q0 + u * kBlock);
+    };
+    constexpr uint32_t kStep = U * kBlock;
+    uint32_t q = tid;
+    if (!M::kTwo) {
+        // One-input maps keep the plain loop: doubling the buffers of the
+        // high-degree POLY bodies spills registers.
+        for (; q + (U - 1) * kBlock < nq; q += kStep) {
+            float4 xv[U], yv[NY];
+            load(xv, yv, q);
+            fold(xv, yv, q);
+        }
+    } else if (q + (U - 1) * kBlock < nq) {
+        float4 xa[U], ya[NY], xb[U], yb[NY];
+        load(xa, ya, q);
+        for (;;) {
+            const uint32_t qb = q + kStep;
+            const bool has_b = qb + (U - 1) * kBlock < nq;
+            if (has_b)
+                load(xb, yb, qb);
+            fold(xa, ya, q);
+            q = qb;
+            if (!has_b)
+                break;
+            const uint32_t qa = q + kStep;
+            const bool has_a = qa + (U - 1) * kBlock < nq;
+            if (has_a)
+                load(xa, ya, qa);
+            fold(xb, yb, q);
+            q = qa;
+            if (!has_a)
+                break;
+        }
     }
     for (; q < nq; q += kBlock) {
         float4 xv = ld4(x4 + 4u * q);

@@ -72,8 +72,9 @@ int get_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
 int enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream);
 void drop_plans(sparkcl_ctx *ctx);
 // Persistent-executor grid for a batch holding the kernels in kid_mask
-// (bit k-1 for kernel id k).
-uint32_t exec_grid(const sparkcl_ctx *ctx, uint32_t kid_mask);
+// (bit k-1 for kernel id k) and `ntiles` tiles over `ntasks` tasks.
+uint32_t exec_grid(const sparkcl_ctx *ctx, uint32_t kid_mask, uint64_t ntiles = 0,
+                   uint64_t ntasks = 0);
 
 } // namespace sparkcl
 

@@ -203,6 +203,11 @@ int tuning_validate(const sparkcl_tuning *t, std::string *why)
             *why = "null tuning table";
         return SPARKCL_EINVAL;
     }
+    if (t->blocks_per_cu_many > 32) {
+        if (why)
+            *why = "blocks_per_cu_many above 32";
+        return SPARKCL_EINVAL;
+    }
     for (int k = 0; k < 3; ++k)
         if (t->blocks_per_cu[k] > 32) {
             if (why)
@@ -267,6 +272,8 @@ bool tuning_parse_json(const std::string &text,
                 return false;
             }
         }
+        if (const Json *b = e.get("blocks_per_cu_many"))
+            t.blocks_per_cu_many = (uint32_t)b->num;
         if (const Json *tile = e.get("tile")) {
             for (int m = 0; m < SPARKCL_TUNE_MODES; ++m) {
                 const Json *mj = tile->get(kModeNames[m]);
@@ -307,7 +314,8 @@ std::string tuning_to_json(const std::map<std::string, sparkcl_tuning> &all)
         const sparkcl_tuning &t = kv.second;
         o << " \"" << kv.first << "\": {\n  \"blocks_per_cu\": [" << t.blocks_per_cu[0]
           << ", " << t.blocks_per_cu[1] << ", " << t.blocks_per_cu[2]
-          << "],\n  \"tile\": {\n";
+          << "],\n  \"blocks_per_cu_many\": " << t.blocks_per_cu_many
+          << ",\n  \"tile\": {\n";
         for (int m = 0; m < SPARKCL_TUNE_MODES; ++m) {
             o << "   \"" << kModeNames[m] << "\": {\n";
             for (int k = 0; k < 3; ++k) {

@@ -60,7 +60,7 @@ class Result(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("blocks_per_cu", ctypes.c_uint32 * 3), ("reserved", ctypes.c_uint32),
+    _fields_ = [("blocks_per_cu", ctypes.c_uint32 * 3), ("blocks_per_cu_many", ctypes.c_uint32),
                 ("tile", ((ctypes.c_uint32 * TUNE_BUCKETS) * 3) * TUNE_MODES)]
 
 
