@@ -81,6 +81,8 @@ def lib() -> ctypes.CDLL:
             L.oracle_mc_count.restype = U64
             L.oracle_task_run.argtypes = [ctypes.POINTER(Task), ctypes.POINTER(Result)]
             L.oracle_task_run.restype = ctypes.c_int
+            L.oracle_tree_reduce_arrays.argtypes = [U32, P, U32, U64, P]
+            L.oracle_tree_reduce_arrays.restype = ctypes.c_int
             L.oracle_rdd_total.argtypes = [ctypes.POINTER(Result), U64, U32,
                                            ctypes.POINTER(Result)]
             _lib = L
@@ -186,4 +188,24 @@ def rdd_total(results, ops) -> Result:
     arr = (Result * len(results))(*results)
     out = Result()
     lib().oracle_rdd_total(arr, len(results), ops, ctypes.byref(out))
+    return out
+
+
+VADD, VMAX = 1, 2
+
+
+def tree_reduce_arrays(arrays, combiner: int = VADD) -> np.ndarray:
+    """O9: fold the RDD elements (a sequence of equal-length float32 arrays,
+    or the rows of a 2-D array) with the combiner along the fixed tree."""
+    rows = [_f32(a) for a in arrays]
+    if not rows:
+        raise ValueError("tree reduce of an empty RDD")
+    n = rows[0].size
+    if any(r.size != n for r in rows):
+        raise ValueError("RDD elements differ in length")
+    ptrs = (ctypes.c_void_p * len(rows))(*[_ptr(r) for r in rows])
+    out = np.empty(n, dtype=np.float32)
+    rc = lib().oracle_tree_reduce_arrays(combiner, ptrs, len(rows), n, _ptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle_tree_reduce_arrays rejected combiner {combiner}")
     return out

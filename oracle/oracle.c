@@ -227,3 +227,44 @@ void oracle_rdd_total(const oracle_result *r, uint64_t ntasks,
     total->count = (reduce_ops & ORACLE_COUNT) ? count : 0;
     total->n = n;
 }
+
+/* ------------------------------------------------------------------------ */
+/* O9  Array-valued ReduceCL: the Fig 3 combiner (elementwise over two RDD
+ * elements that are arrays) applied along a fixed binary tree (sec. 3.1.3
+ * item 3, sec. 3.2.2).  The tree over elements [k0, k1) splits at k0 plus the
+ * largest power of two strictly below the count, left part first.            */
+static float combine_one(uint32_t combiner, float a, float b)
+{
+    if (combiner == ORACLE_VADD)
+        return a + b;             /* one binary32 add */
+    return (b > a) ? b : a;       /* VMAX */
+}
+
+static uint32_t largest_pow2_below(uint32_t m) /* m >= 2 */
+{
+    uint32_t p = 1;
+    while (2 * p < m)
+        p *= 2;
+    return p;
+}
+
+static float tree_at(uint32_t combiner, const float *const *arrays,
+                     uint32_t k0, uint32_t k1, uint64_t i)
+{
+    if (k1 - k0 == 1)
+        return arrays[k0][i];
+    const uint32_t mid = k0 + largest_pow2_below(k1 - k0);
+    const float left = tree_at(combiner, arrays, k0, mid, i);
+    const float right = tree_at(combiner, arrays, mid, k1, i);
+    return combine_one(combiner, left, right);
+}
+
+int oracle_tree_reduce_arrays(uint32_t combiner, const float *const *arrays,
+                              uint32_t k, uint64_t len, float *out)
+{
+    if ((combiner != ORACLE_VADD && combiner != ORACLE_VMAX) || k == 0)
+        return -1;
+    for (uint64_t i = 0; i < len; ++i)
+        out[i] = tree_at(combiner, arrays, 0, k, i);
+    return 0;
+}

@@ -86,6 +86,19 @@ int oracle_task_run(const oracle_task *t, oracle_result *r);
 void oracle_rdd_total(const oracle_result *r, uint64_t ntasks,
                       uint32_t reduce_ops, oracle_result *total);
 
+/* O9  Array-valued ReduceCL (sec. 3.1.3 item 3; Fig 3; sec. 3.2.2): the RDD's
+ *     elements are float arrays of one length `len`; a two-input combiner
+ *     kernel (Fig 3: c[gid] = a[gid] + b[gid]) is applied pairwise along a tree
+ *     until one array is left.  Tree (a reading: the paper names a Spark
+ *     tree-reduce and fixes no shape): over elements [k0, k1) the split point
+ *     is k0 + the largest power of two strictly below k1 - k0, and the left
+ *     part is the left operand.  Each combine is one binary32 operation per
+ *     position:  VADD: fl(a + b);  VMAX: (b > a) ? b : a.
+ *     Returns 0, or -1 for an unknown combiner or k == 0. */
+enum { ORACLE_VADD = 1, ORACLE_VMAX = 2 };
+int oracle_tree_reduce_arrays(uint32_t combiner, const float *const *arrays,
+                              uint32_t k, uint64_t len, float *out);
+
 #ifdef __cplusplus
 }
 #endif
