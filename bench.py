@@ -47,6 +47,18 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+def load_isa():
+    """Resource figures of this build's device code (written by the build
+    next to the library), if they belong to the current kernel source."""
+    p = os.path.join(ROOT, "paper_1505_01120_amd", "isa.json")
+    try:
+        with open(p) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    return d if d.get("kernels_sha256_16") == kernel_source_hash() else None
+
+
 def load_traffic(kind: str):
     """HBM traffic per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source."""
@@ -196,10 +208,19 @@ def bench_monte_carlo(ctx, sc, steps=5) -> dict:
     wall, ev = time_async(ctx, sc, tasks, sc.BATCHED, steps, 2, dres, None)
     samples = sum(p.n for p in parts)
     blocks = samples // 2
-    # VALU lane-op count per Philox block from the kernel's own gfx950 ISA is
-    # recorded in profiles/; the fraction below uses that figure when present.
-    return {"ms": ev, "samples_per_s": samples / (ev / 1e3),
-            "philox_blocks_per_s": blocks / (ev / 1e3), "samples": samples}
+    out = {"ms": ev, "samples_per_s": samples / (ev / 1e3),
+           "philox_blocks_per_s": blocks / (ev / 1e3), "samples": samples}
+    # ALU roofline: VALU instructions per Philox block (one block = two
+    # samples per lane) counted in this build's own gfx950 assembly, times
+    # blocks/s, against 256 CUs x 64 lanes x 2.4 GHz.
+    isa = load_isa()
+    if isa and "philox_loop" in isa:
+        valu = isa["philox_loop"]["valu"]
+        achieved = blocks * valu / (ev / 1e3) / 1e12
+        out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS,
+                           "unit": "T VALU lane-instr/s", "frac": achieved / ALU_PEAK_TOPS,
+                           "valu_per_philox_block": valu}
+    return out
 
 
 def bench_uneven(ctx, sc, steps=5) -> dict:

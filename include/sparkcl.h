@@ -27,9 +27,9 @@
  *   - `stream` is a hipStream_t passed as void*; NULL is the default stream.
  *   - Floating point: maps evaluate each multiply and add as one binary32
  *     operation in the order written (no contraction), so materialised map
- *     outputs are bit-exact.  Sums are accumulated per thread in binary32 with
- *     Neumaier compensation, folded to FP64, combined in FP64 across the wave,
- *     the block and the partition's tiles, and returned as double.  For a
+ *     outputs are bit-exact.  Sums are accumulated per thread in FP64 and
+ *     combined in FP64 across the wave, the block and the partition's tiles,
+ *     and returned as double.  For a
  *     given context and inputs every result is run-to-run identical.
  *   - An empty partition (n == 0) gives sum +0.0, max -inf, count 0.
  */
@@ -72,6 +72,10 @@ extern "C" {
 #define SPARKCL_SUM 1u
 #define SPARKCL_MAX 2u
 #define SPARKCL_COUNT 4u
+
+/* combiners of the array-valued ReduceCL (sparkcl_reduce_arrays) */
+#define SPARKCL_VADD 1u /* c[i] = a[i] + b[i], one binary32 add (Fig 3)     */
+#define SPARKCL_VMAX 2u /* c[i] = (b[i] > a[i]) ? b[i] : a[i]                 */
 
 /* execution modes of sparkcl_reduce / sparkcl_map_partition */
 #define SPARKCL_PER_LAUNCH 0 /* one kernel launch per partition              */
@@ -186,6 +190,32 @@ SPARKCL_API int sparkcl_reduce_async(sparkcl_ctx *ctx, const sparkcl_task *tasks
                          uint32_t ntasks, int mode,
                          sparkcl_result *dev_per_task,
                          sparkcl_result *dev_total, void *stream);
+
+/* Array-valued ReduceCL (sec. 3.1.3 item 3; the Fig 3 vector add; sec.
+   3.2.2): the RDD's elements are `k` float arrays of `len` elements each, in
+   RDD order; arrays[] is a HOST array of k DEVICE pointers (caller-owned, any
+   4-byte alignment; 16-byte-aligned arrays with len % 4 == 0 take the float4
+   path).  The combiner (SPARKCL_VADD or SPARKCL_VMAX) folds them pairwise
+   along a fixed tree -- over elements [k0, k1) the split is at k0 plus the
+   largest power of two below the count, left part the left operand -- and
+   the result goes to out[0..len) (device memory; it may be one of the
+   inputs).  Bit-exact against that definition.  Asynchronous on `stream`;
+   k may not exceed 2^24; intermediate rows (when the reduction runs in
+   several passes) come from the arena: ENOMEM if it is too small.  EINVAL
+   for k == 0, a NULL pointer, an unknown combiner or a misaligned array. */
+SPARKCL_API int sparkcl_reduce_arrays(sparkcl_ctx *ctx, uint32_t combiner,
+                                      const float *const *arrays, uint32_t k,
+                                      uint64_t len, float *out, void *stream);
+
+/* The same array-valued ReduceCL over RDD elements stored as the rows of one
+   device buffer: element e is base[e * row_stride .. e * row_stride + len)
+   (row_stride in elements, >= len when k > 1).  No pointer table is built or
+   hashed, so very many short elements cost nothing on the host.  Bit-exact
+   against the same tree; same errors and stream semantics. */
+SPARKCL_API int sparkcl_reduce_rows(sparkcl_ctx *ctx, uint32_t combiner,
+                                    const float *base, uint64_t row_stride,
+                                    uint32_t k, uint64_t len, float *out,
+                                    void *stream);
 
 /* Serving (continuous batching): enqueue one task, stamping its arrival.
    Non-blocking.  The task is admitted to the resident executor once a slot is

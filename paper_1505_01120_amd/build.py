@@ -4,7 +4,12 @@ Produces, next to this file:
   libsparkcl.so       -- the C-ABI library (HIP kernels + host runtime), built
                          with hipcc --offload-arch=gfx950;
   libsparkcl_host.so  -- the pure host logic (arena, admission, tuning cache)
-                         behind a small C shim, built with g++, for CPU tests.
+                         behind a small C shim, built with g++, for CPU tests;
+  isa.json            -- resource figures of the kernels' own gfx950 code
+                         (registers, private segment, VALU instructions per
+                         Philox block), read from the device assembly of this
+                         same build: the no-spill guard test and the
+                         Monte-Carlo ALU roofline use them.
 
 Every HIP translation unit is compiled with -ffp-contract=off (the maps are
 the binary32 definition step by step) and with packed-FP32 instructions
@@ -12,7 +17,10 @@ disabled.  Run: python -m paper_1505_01120_amd.build
 """
 from __future__ import annotations
 
+import hashlib
+import json
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -24,6 +32,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsparkcl.so")
 HOST_LIB = os.path.join(HERE, "libsparkcl_host.so")
+ISA_JSON = os.path.join(HERE, "isa.json")
+KERNELS = ("k_task", "k_batch", "k_serve", "k_map")
 ARCH = "gfx950"
 
 HIP_SOURCES = ["kernels.hip", "api.cpp", "serve.cpp", "autotune.cpp", "tuning.cpp"]
@@ -49,6 +59,50 @@ def _run(cmd: list[str]) -> None:
         raise RuntimeError("build step failed: " + os.path.basename(cmd[-1]))
 
 
+def isa_report(asm: str) -> dict:
+    """Per-kernel resources from the AMDGPU metadata, and the VALU count of
+    the Philox loop (the basic block of k_batch holding the most three-way
+    xors) from the device assembly text."""
+    out = {}
+    meta = asm[asm.find("amdhsa.kernels:"):]
+    for k in KERNELS:
+        m = re.search(r"\.name:\s+_ZN7sparkcl12_GLOBAL__N_1\d+" + k + r"E.*?(?=\n  - \.|\Z)",
+                      meta, re.S)
+        if not m:
+            continue
+        block = m.group(0)
+
+        def field(name):
+            f = re.search(r"\." + name + r":\s+(\d+)", block)
+            return int(f.group(1)) if f else None
+        out[k] = {"vgpr": field("vgpr_count"), "sgpr": field("sgpr_count"),
+                  "private_segment_bytes": field("private_segment_fixed_size"),
+                  "vgpr_spills": field("vgpr_spill_count"),
+                  "sgpr_spills": field("sgpr_spill_count")}
+    body = re.search(r"^_ZN7sparkcl12_GLOBAL__N_17k_batch\S*:(.*?)\.end_amdhsa_kernel",
+                     asm, re.S | re.M)
+    if body:
+        best, cur, cur_xor, best_xor = None, [], 0, 0
+        for line in body.group(1).splitlines() + [".LBB_end:"]:
+            t = line.strip()
+            if re.match(r"^\.LBB\d+_\d+:", t) or t.startswith("; %bb."):
+                if cur_xor > best_xor:
+                    best, best_xor = cur, cur_xor
+                cur, cur_xor = [], 0
+                continue
+            if not t or t.startswith(";") or t.startswith("."):
+                continue
+            op = t.split()[0]
+            cur.append(op)
+            if op == "v_bitop3_b32":
+                cur_xor += 1
+        if best:
+            out["philox_loop"] = {"valu": sum(1 for o in best if o.startswith("v_")),
+                                  "xor3": best_xor,
+                                  "mad_u64_u32": best.count("v_mad_u64_u32")}
+    return out
+
+
 def build(verbose: bool = False) -> str:
     """Compile every source and link both libraries (always rebuilds)."""
     out_dir = os.path.join(HERE, "_build")
@@ -61,8 +115,16 @@ def build(verbose: bool = False) -> str:
         _run([cc, *COMMON, *HIP_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj])
         return obj
 
+    def device_asm() -> str:
+        asm = os.path.join(out_dir, "kernels.s")
+        _run([cc, *COMMON, *HIP_FLAGS, "-x", "hip", "--cuda-device-only", "-S",
+              os.path.join(CSRC, "kernels.hip"), "-o", asm])
+        return asm
+
     with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        asm_job = ex.submit(device_asm)
         objs = list(ex.map(compile_hip, HIP_SOURCES))
+        asm = asm_job.result()
     tmp = LIB + ".tmp"
     _run([cc, "-shared", "-fPIC", "--offload-arch=" + ARCH, *objs, "-o", tmp, "-lpthread"])
     os.replace(tmp, LIB)
@@ -71,6 +133,13 @@ def build(verbose: bool = False) -> str:
     _run(["g++", *COMMON, "-shared", *[os.path.join(CSRC, s) for s in HOST_SOURCES],
           "-o", tmp])
     os.replace(tmp, HOST_LIB)
+    with open(asm) as f:
+        report = isa_report(f.read())
+    with open(os.path.join(CSRC, "kernels.hip"), "rb") as f:
+        report["kernels_sha256_16"] = hashlib.sha256(f.read()).hexdigest()[:16]
+    with open(ISA_JSON + ".tmp", "w") as f:
+        json.dump(report, f, indent=1)
+    os.replace(ISA_JSON + ".tmp", ISA_JSON)
     if verbose:
         print("built", LIB, "and", HOST_LIB)
     return LIB

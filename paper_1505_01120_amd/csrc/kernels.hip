@@ -3,21 +3,24 @@
 // A partition task (a MapCL / MapCLPartition / ReduceCL application, paper
 // sec. 3.1.3) is cut into tiles of `tile_elems` elements.  One 256-thread
 // block turns one tile into one partial:
-//   1. streaming loop: coalesced 128-bit loads (float4), kUnroll quads in
-//      flight per thread, the registry kernel's map applied per element, each
-//      value folded into a per-thread binary32 Neumaier pair (s, c), a running
-//      max, or a hit counter;
-//   2. (s, c) folded to FP64 as (double)s + (double)c, then combined across
-//      the wave with cross-lane shuffles and across the block's waves through
-//      LDS in a fixed tree;
+//   1. streaming loop: coalesced 128-bit loads (float4), two register
+//      buffers of kUnroll quads per input so one buffer is in flight while
+//      the other is folded, the registry kernel's map applied per element,
+//      each value added to a per-thread FP64 sum, a running max, or a hit
+//      counter;
+//   2. the per-thread values are combined across the wave with cross-lane
+//      shuffles and across the block's waves through LDS in a fixed tree;
 //   3. the partial is published and an arrival ticket taken; the block that
 //      takes the last ticket combines the task's partials in FP64 in a fixed
 //      order and writes the partition result (the tree-reduce of ReduceCL,
 //      sec. 3.1.3 and 3.2.2).  The block that finishes the last task of a
 //      launch folds the partition results into the RDD-level total.
-// Every element's owner thread and every combine order depend only on the
-// tile size, the block size and the inputs' 16-byte alignment, so results
-// are identical run to run and across execution modes with the same tiles.
+// Tiles of at least one chunk (kBlock x kUnroll quads) deal a task's chunks
+// round-robin to its tiles, so the tiles that run together read one sliding
+// window of the task; smaller tiles are contiguous ranges.  Every element's
+// owner thread and every combine order depend only on the tile size, the
+// block size and the inputs' 16-byte alignment, so results are identical run
+// to run and across execution modes with the same tiles.
 //
 // Compiled with -ffp-contract=off: the maps are the binary32 definition
 // operation by operation.  No MFMA: nothing on this path is a contraction.
@@ -125,19 +128,6 @@ __device__ __forceinline__ void own_stores_complete()
     __builtin_amdgcn_s_waitcnt(0);
 }
 
-// ---- binary32 Neumaier step ---------------------------------------------
-// t = s + v; the rounding error of that add is (big - t) + small, where big
-// is the operand of larger magnitude; it accumulates in c.
-__device__ __forceinline__ void neumaier(float &s, float &c, float v)
-{
-    float t = s + v;
-    bool sbig = fabsf(s) >= fabsf(v);
-    float big = sbig ? s : v;
-    float small = sbig ? v : s;
-    c += (big - t) + small;
-    s = t;
-}
-
 // ---- registry maps (one binary32 operation per step, in order) -----------
 template <int D> struct PolyMap {
     static constexpr bool kTwo = false;
@@ -165,144 +155,237 @@ struct FmulMap {
     }
 };
 
-// Per-thread accumulator of one tile.
+// Per-thread accumulator of one tile.  The sum is carried in FP64: on
+// gfx950 a vector FP64 add issues at the full 32-bit rate, so converting and
+// adding (two instructions) is cheaper than binary32 Neumaier compensation
+// (seven), and a recursive FP64 sum of m terms is within (m-1) 2^-53 of the
+// sum of magnitudes -- far inside the binary32 result's own resolution.
 struct Acc {
-    float s = 0.0f, c = 0.0f, m = kNegInf;
+    double s = 0.0;
+    float m = kNegInf;
     uint32_t hits = 0;
     __device__ __forceinline__ void add(float v)
     {
-        neumaier(s, c, v);
+        s += (double)v;
         m = fmaxf(m, v);
     }
 };
 
-// Elementwise tile [begin, end): the aligned middle in float4 quads (thread t
-// owns quads t, t+B, t+2B, ...), the unaligned head and the ragged tail as
-// single elements owned by threads 0..2.  If the inputs (and the output) do
-// not share one 16-byte misalignment, every element goes through the scalar
-// strided loop instead.
+// ---- elementwise tiles ------------------------------------------------------
+// One quad of the map: four results, optionally stored, folded into the
+// thread's accumulator in element order.
 template <class M, bool W>
-__device__ __forceinline__ void tile_elementwise(const M &f,
-                                                 const float *__restrict__ x,
-                                                 const float *__restrict__ y,
-                                                 float *__restrict__ out,
-                                                 uint64_t begin, uint64_t end,
-                                                 Acc &a)
+__device__ __forceinline__ void map_quad(const M &f, const float4 &xv,
+                                         const float4 &yv, float *o, Acc &a)
+{
+    float4 v;
+    v.x = f(xv.x, yv.x);
+    v.y = f(xv.y, yv.y);
+    v.z = f(xv.z, yv.z);
+    v.w = f(xv.w, yv.w);
+    if (W)
+        st4(o, v);
+    a.add(v.x);
+    a.add(v.y);
+    a.add(v.z);
+    a.add(v.w);
+}
+
+// Stream `ng` groups of the calling thread.  Group g is the kUnroll quads
+// base(g) + u * kBlock (u = 0..kUnroll-1), in quads from x4/y4/o4.  The loads
+// of group g+1 are issued before group g is folded, so a wave keeps loads in
+// flight while it computes (with one or two waves per SIMD nothing else
+// would).  Two register buffers alternate; each thread still folds its quads
+// in group order, so the rounding is that of the plain loop.  The
+// steady-state body is straight-line code (no conditional load between the
+// two folds) and the scheduling barriers keep the machine scheduler from
+// hoisting the second load group above the first fold: the compiler's
+// wait-count placement then waits only for the buffer being folded, with the
+// other one still in flight.
+template <class M, bool W, class Base>
+__device__ __forceinline__ void stream_groups(const M &f, const float *x4,
+                                              const float *y4, float *o4,
+                                              uint64_t ng, Base base, Acc &a)
+{
+    constexpr int U = kUnroll;
+    constexpr int NY = M::kTwo ? U : 1; // one-input maps carry no y buffer
+    auto load = [&](float4 *xv, float4 *yv, uint64_t q0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            xv[u] = ld4(x4 + 4 * (q0 + u * kBlock));
+            if (M::kTwo)
+                yv[u] = ld4(y4 + 4 * (q0 + u * kBlock));
+        }
+    };
+    auto fold = [&](const float4 *xv, const float4 *yv, uint64_t q0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            map_quad<M, W>(f, xv[u], M::kTwo ? yv[u] : xv[u],
+                           W ? o4 + 4 * (q0 + u * kBlock) : nullptr, a);
+    };
+    if (ng == 0)
+        return;
+    float4 xa[U], ya[NY], xb[U], yb[NY];
+    load(xa, ya, base(0));
+    uint64_t g = 0;
+    for (; g + 2 < ng; g += 2) {
+        const uint64_t qa = base(g), qb = base(g + 1), qc = base(g + 2);
+        load(xb, yb, qb);
+        __builtin_amdgcn_sched_barrier(0);
+        fold(xa, ya, qa);
+        __builtin_amdgcn_sched_barrier(0);
+        load(xa, ya, qc);
+        __builtin_amdgcn_sched_barrier(0);
+        fold(xb, yb, qb);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (g + 1 < ng) {
+        load(xb, yb, base(g + 1));
+        fold(xa, ya, base(g));
+        fold(xb, yb, base(g + 1));
+    } else {
+        fold(xa, ya, base(g));
+    }
+}
+
+// Scalar elements [i0, i1) of an elementwise task, strided over the block.
+template <class M, bool W>
+__device__ __forceinline__ void map_scalar(const M &f, const float *x,
+                                           const float *y, float *out,
+                                           uint64_t i0, uint64_t i1, Acc &a)
+{
+    for (uint64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
+        float v = f(ld1(x + i), M::kTwo ? ld1(y + i) : 0.0f);
+        if (W)
+            st1(out + i, v);
+        a.add(v);
+    }
+}
+
+// Whether a task's arrays share one 16-byte misalignment (so the aligned
+// middle can be read as float4 quads), and the length of the scalar head
+// that reaches the first quad boundary.
+template <class M, bool W>
+__device__ __forceinline__ bool quad_aligned(const float *x, const float *y,
+                                             const float *out, uint64_t n,
+                                             uint32_t &head)
+{
+    const uintptr_t ax = (uintptr_t)x;
+    bool vec = true;
+    if (M::kTwo && ((ax ^ (uintptr_t)y) & 15u))
+        vec = false;
+    if (W && ((ax ^ (uintptr_t)out) & 15u))
+        vec = false;
+    const uint32_t mis = (uint32_t)((ax & 15u) >> 2);
+    head = vec ? (uint32_t)min((uint64_t)((4u - mis) & 3u), n) : 0u;
+    return vec;
+}
+
+// Contiguous tile [begin, end): the aligned middle in float4 quads (thread t
+// owns quads t, t+B, t+2B, ...), the unaligned head and the ragged tail as
+// single elements owned by threads 0..2.  If the arrays do not share one
+// 16-byte misalignment, every element goes through the scalar strided loop.
+template <class M, bool W>
+__device__ __forceinline__ void tile_contiguous(const M &f,
+                                                const float *__restrict__ x,
+                                                const float *__restrict__ y,
+                                                float *__restrict__ out,
+                                                uint64_t begin, uint64_t end,
+                                                Acc &a)
 {
     const uint32_t tid = threadIdx.x;
     const uint32_t len = (uint32_t)(end - begin);
     const float *xb = x + begin;
     const float *yb = M::kTwo ? y + begin : nullptr;
     float *ob = W ? out + begin : nullptr;
-
-    const uintptr_t ax = (uintptr_t)xb;
-    bool vec = true;
-    if (M::kTwo && ((ax ^ (uintptr_t)yb) & 15u))
-        vec = false;
-    if (W && ((ax ^ (uintptr_t)ob) & 15u))
-        vec = false;
-    const uint32_t mis = (uint32_t)((ax & 15u) >> 2);
-    const uint32_t head = vec ? min((4u - mis) & 3u, len) : len;
-
-    for (uint32_t i = tid; i < head; i += kBlock) {
-        float v = f(ld1(xb + i), M::kTwo ? ld1(yb + i) : 0.0f);
-        if (W)
-            st1(ob + i, v);
-        a.add(v);
-    }
-    if (!vec)
+    uint32_t head = 0;
+    if (!quad_aligned<M, W>(xb, yb, ob, len, head)) {
+        map_scalar<M, W>(f, xb, yb, ob, 0, len, a);
         return;
+    }
+    map_scalar<M, W>(f, xb, yb, ob, 0, head, a);
 
-    // kUnroll quads per input in flight per thread.  (Doubling it for the
-    // one-input map triples the register count of the high-degree POLY
-    // bodies and spills.)
-    constexpr int U = kUnroll;
+    constexpr uint32_t kStep = kUnroll * kBlock;
     const uint32_t nq = (len - head) >> 2;
     const float *x4 = xb + head;
     const float *y4 = M::kTwo ? yb + head : nullptr;
     float *o4 = W ? ob + head : nullptr;
+    // full groups of kUnroll quads owned by this thread
+    const uint32_t full = (tid + (kUnroll - 1) * kBlock < nq)
+                              ? (nq - tid - (kUnroll - 1) * kBlock + kStep - 1) / kStep
+                              : 0u;
+    stream_groups<M, W>(f, x4, y4, o4, full,
+                        [&](uint64_t g) { return (uint64_t)tid + g * kStep; }, a);
+    for (uint32_t q = tid + full * kStep; q < nq; q += kBlock)
+        map_quad<M, W>(f, ld4(x4 + 4u * q), M::kTwo ? ld4(y4 + 4u * q) : float4{},
+                       W ? o4 + 4u * q : nullptr, a);
+    map_scalar<M, W>(f, xb, yb, ob, head + 4u * nq, len, a);
+}
 
-    auto quad = [&](const float4 &xv, const float4 &yv, uint32_t q) {
-        float4 v;
-        v.x = f(xv.x, yv.x);
-        v.y = f(xv.y, yv.y);
-        v.z = f(xv.z, yv.z);
-        v.w = f(xv.w, yv.w);
-        if (W)
-            st4(o4 + 4u * q, v);
-        a.add(v.x);
-        a.add(v.y);
-        a.add(v.z);
-        a.add(v.w);
-    };
+// Interleaved layout of a whole task (tiles of at least kChunkElems
+// elements, arrays sharing one 16-byte misalignment): the task's aligned
+// middle is cut into chunks of kBlock * kUnroll quads, and tile j of nt owns
+// chunks j, j + nt, j + 2 nt, ...; tile 0 also owns the unaligned head and
+// the ragged tail.  Tiles that run at the same time (the queue hands out a
+// task's tiles in order) then read neighbouring chunks, one sliding window
+// per task instead of one stream per tile, which HBM serves at a higher rate.
+// Returns the number of elements the tile covers.
+constexpr uint32_t kChunkQuads = kUnroll * kBlock;
+constexpr uint32_t kChunkElems = 4 * kChunkQuads;
 
-    // Software-pipelined main loop: the loads of the next group of U quads
-    // are issued before the current group is folded, so a wave keeps loads
-    // in flight while it computes (with one or two waves per SIMD nothing
-    // else would).  Two register buffers alternate; each thread still visits
-    // its quads in increasing order, so the rounding is that of the plain
-    // loop.
-    // (One-input maps carry no y buffer: NY = 0.)
-    constexpr int NY = M::kTwo ? U : 1;
-    auto load = [&](float4 *xv, float4 *yv, uint32_t q0) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            xv[u] = ld4(x4 + 4u * (q0 + u * kBlock));
-            if (M::kTwo)
-                yv[u] = ld4(y4 + 4u * (q0 + u * kBlock));
-        }
-    };
-    auto fold = [&](const float4 *xv, const float4 *yv, uint32_t q0) {
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            quad(xv[u], M::kTwo ? yv[u] : xv[u], q0 + u * kBlock);
-    };
-    constexpr uint32_t kStep = U * kBlock;
-    uint32_t q = tid;
-    if (!M::kTwo) {
-        // One-input maps keep the plain loop: doubling the buffers of the
-        // high-degree POLY bodies spills registers.
-        for (; q + (U - 1) * kBlock < nq; q += kStep) {
-            float4 xv[U], yv[NY];
-            load(xv, yv, q);
-            fold(xv, yv, q);
-        }
-    } else if (q + (U - 1) * kBlock < nq) {
-        float4 xa[U], ya[NY], xb[U], yb[NY];
-        load(xa, ya, q);
-        for (;;) {
-            const uint32_t qb = q + kStep;
-            const bool has_b = qb + (U - 1) * kBlock < nq;
-            if (has_b)
-                load(xb, yb, qb);
-            fold(xa, ya, q);
-            q = qb;
-            if (!has_b)
-                break;
-            const uint32_t qa = q + kStep;
-            const bool has_a = qa + (U - 1) * kBlock < nq;
-            if (has_a)
-                load(xa, ya, qa);
-            fold(xb, yb, q);
-            q = qa;
-            if (!has_a)
-                break;
-        }
+template <class M, bool W>
+__device__ __forceinline__ uint64_t tile_interleaved(const M &f,
+                                                     const float *__restrict__ x,
+                                                     const float *__restrict__ y,
+                                                     float *__restrict__ out,
+                                                     uint64_t n, uint32_t head,
+                                                     uint32_t nt, uint32_t j,
+                                                     Acc &a)
+{
+    const uint32_t tid = threadIdx.x;
+    const uint64_t nq = (n - head) >> 2;
+    const uint64_t nfull = nq / kChunkQuads;
+    const uint32_t rem = (uint32_t)(nq % kChunkQuads);
+    const float *x4 = x + head;
+    const float *y4 = M::kTwo ? y + head : nullptr;
+    float *o4 = W ? out + head : nullptr;
+    const uint64_t ng = nfull > j ? (nfull - j + nt - 1) / nt : 0;
+    stream_groups<M, W>(f, x4, y4, o4, ng,
+                        [&](uint64_t g) { return (j + g * nt) * kChunkQuads + tid; }, a);
+    uint64_t count = 4 * ng * kChunkQuads;
+    if (rem != 0 && nfull % nt == j) {
+        const uint64_t q0 = nfull * kChunkQuads;
+        for (uint32_t q = tid; q < rem; q += kBlock)
+            map_quad<M, W>(f, ld4(x4 + 4 * (q0 + q)),
+                           M::kTwo ? ld4(y4 + 4 * (q0 + q)) : float4{},
+                           W ? o4 + 4 * (q0 + q) : nullptr, a);
+        count += 4 * rem;
     }
-    for (; q < nq; q += kBlock) {
-        float4 xv = ld4(x4 + 4u * q);
-        float4 yv = M::kTwo ? ld4(y4 + 4u * q) : xv;
-        quad(xv, yv, q);
+    if (j == 0) {
+        map_scalar<M, W>(f, x, y, out, 0, head, a);
+        map_scalar<M, W>(f, x, y, out, head + 4 * nq, n, a);
+        count += n - 4 * nq;
     }
+    return count;
+}
 
-    const uint32_t t0 = head + 4u * nq;
-    if (tid < len - t0) {
-        uint32_t i = t0 + tid;
-        float v = f(ld1(xb + i), M::kTwo ? ld1(yb + i) : 0.0f);
-        if (W)
-            st1(ob + i, v);
-        a.add(v);
-    }
+// Tile j of an elementwise task: interleaved when the tile size allows and
+// the arrays are quad-compatible, else the contiguous range [jT, jT + T).
+// Returns the number of elements covered.
+template <class M, bool W>
+__device__ __forceinline__ uint64_t tile_map(const M &f, const float *x,
+                                             const float *y, float *out,
+                                             uint64_t n, uint32_t T, uint32_t nt,
+                                             uint32_t j, Acc &a)
+{
+    uint32_t head = 0;
+    if (T >= kChunkElems && quad_aligned<M, W>(x, y, out, n, head))
+        return tile_interleaved<M, W>(f, x, y, out, n, head, nt, j, a);
+    const uint64_t begin = (uint64_t)j * T;
+    const uint64_t end = min(n, begin + T);
+    if (begin < end)
+        tile_contiguous<M, W>(f, x, y, out, begin, end, a);
+    return begin < end ? end - begin : 0;
 }
 
 // ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) --------------------
@@ -480,7 +563,7 @@ __device__ __forceinline__ void read_result(const sparkcl_result *p, double &s,
 // ---- one tile, start to finish ------------------------------------------
 // Returns true in the block that completed the task (after writing its
 // result); callers use it only for the RDD-level step.
-__device__ bool run_tile(const TaskDev *__restrict__ tp, uint32_t j,
+__device__ __forceinline__ bool run_tile(const TaskDev *__restrict__ tp, uint32_t j,
                          const LaunchOut &L)
 {
     __shared__ uint32_t sh_last;
@@ -489,61 +572,59 @@ __device__ bool run_tile(const TaskDev *__restrict__ tp, uint32_t j,
 
     const uint32_t variant = uni(tp->variant);
     const uint32_t T = uni(tp->tile_elems);
+    const uint32_t ntiles = uni(tp->ntiles);
     const uint64_t n = uni64(tp->n);
-    const uint64_t begin = (uint64_t)j * T;
-    const uint64_t end = min(n, begin + T);
 
     Acc a;
-    if (begin < end) {
-        const float *x = tp->in0;
-        const float *y = tp->in1;
-        float *o = tp->out;
-        if (variant < V_FMUL) {
-            const bool w = variant >= V_POLYW;
-            const uint32_t d = variant & 7u;
-            float k[8];
+    uint64_t count = 0;
+    const float *x = tp->in0;
+    const float *y = tp->in1;
+    float *o = tp->out;
+    if (variant < V_FMUL) {
+        const bool w = variant >= V_POLYW;
+        const uint32_t d = variant & 7u;
+        float k[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                k[i] = tp->coef[i];
+        for (int i = 0; i < 8; ++i)
+            k[i] = tp->coef[i];
 #define SPARKCL_POLY_CASE(D)                                                   \
     case D: {                                                                  \
         PolyMap<D> f;                                                          \
         for (int i = 0; i < 8; ++i)                                            \
             f.k[i] = k[i];                                                     \
-        if (w)                                                                 \
-            tile_elementwise<PolyMap<D>, true>(f, x, y, o, begin, end, a);     \
-        else                                                                   \
-            tile_elementwise<PolyMap<D>, false>(f, x, y, o, begin, end, a);    \
+        count = w ? tile_map<PolyMap<D>, true>(f, x, y, o, n, T, ntiles, j, a)  \
+                  : tile_map<PolyMap<D>, false>(f, x, y, o, n, T, ntiles, j, a); \
     } break;
-            switch (d) {
-                SPARKCL_POLY_CASE(0)
-                SPARKCL_POLY_CASE(1)
-                SPARKCL_POLY_CASE(2)
-                SPARKCL_POLY_CASE(3)
-                SPARKCL_POLY_CASE(4)
-                SPARKCL_POLY_CASE(5)
-                SPARKCL_POLY_CASE(6)
-                SPARKCL_POLY_CASE(7)
-            }
+        switch (d) {
+            SPARKCL_POLY_CASE(0)
+            SPARKCL_POLY_CASE(1)
+            SPARKCL_POLY_CASE(2)
+            SPARKCL_POLY_CASE(3)
+            SPARKCL_POLY_CASE(4)
+            SPARKCL_POLY_CASE(5)
+            SPARKCL_POLY_CASE(6)
+            SPARKCL_POLY_CASE(7)
+        }
 #undef SPARKCL_POLY_CASE
-        } else if (variant == V_FMUL || variant == V_FMULW) {
-            FmulMap f{tp->c};
-            if (variant == V_FMULW)
-                tile_elementwise<FmulMap, true>(f, x, y, o, begin, end, a);
-            else
-                tile_elementwise<FmulMap, false>(f, x, y, o, begin, end, a);
-        } else {
+    } else if (variant == V_FMUL || variant == V_FMULW) {
+        FmulMap f{tp->c};
+        count = variant == V_FMULW ? tile_map<FmulMap, true>(f, x, y, o, n, T, ntiles, j, a)
+                                   : tile_map<FmulMap, false>(f, x, y, o, n, T, ntiles, j, a);
+    } else {
+        const uint64_t begin = (uint64_t)j * T;
+        const uint64_t end = min(n, begin + T);
+        if (begin < end) {
             tile_mc(uni64(tp->seed), uni(tp->pid), begin, end, a);
+            count = end - begin;
         }
     }
 
-    Red r{(double)a.s + (double)a.c, a.m, a.hits, 0};
+    Red r{a.s, a.m, a.hits, 0};
     r = block_reduce(r);
 
     const uint32_t idx = uni(tp->index);
-    const uint32_t ntiles = uni(tp->ntiles);
     if (threadIdx.x == 0) {
-        store_partial(tp->partials + j, r.s, r.m, r.h, end > begin ? end - begin : 0);
+        store_partial(tp->partials + j, r.s, r.m, r.h, count);
         // t_start keeps the bitwise complement of the earliest tile start, so
         // its cleared state (0) is the identity of the max below.
         __hip_atomic_fetch_max(&sync[idx].t_start, ~t0, __ATOMIC_RELAXED,
@@ -597,7 +678,7 @@ __device__ bool run_tile(const TaskDev *__restrict__ tp, uint32_t j,
 
 // RDD-level step, run by the block that completed a task: the block that
 // completes the launch's last task folds all partition results in task order.
-__device__ void rdd_step(const LaunchOut &L)
+__device__ __forceinline__ void rdd_step(const LaunchOut &L)
 {
     __shared__ uint32_t sh_last;
     if (L.ntasks == 0)
@@ -755,6 +836,115 @@ __global__ __launch_bounds__(kBlock) void k_map(const TaskDev *__restrict__ tp,
 }
 
 // Clears library workspaces with a kernel (no memset nodes in captured work).
+// ---- array-valued ReduceCL ----------------------------------------------------
+// The RDD's elements are float arrays of one length; the two-input combiner
+// (Fig 3 adds two arrays elementwise) folds them pairwise along a fixed
+// tree: over elements [k0, k1) the tree splits at k0 + the largest power of
+// two below the count, left part first.  Each thread owns V columns and
+// walks the leaves in order with a binary counter of partial results: slot j
+// holds the finished perfect subtree of 2^j leaves, a new leaf merges with
+// the full slots of the counter's carry chain, and at the end the occupied
+// slots are merged from the smallest (rightmost) up.  That is exactly the
+// tree above, so every position sees the same sequence of binary32
+// combines as the definition.  Eight aligned leaves are combined as a perfect
+// tree first and enter the counter at level 3.
+//
+// A pass reduces chunks of S leaves (S a power of two unless the pass has a
+// single chunk); chunk c writes its tree to row c of the output.  Full chunks
+// are aligned perfect subtrees and the last chunk is the tree of the
+// remaining suffix, so a later pass over the chunk rows, with the same rule,
+// rebuilds the tree over all elements.
+constexpr int kTreeSlots = 13; // up to 2^12 leaves per chunk
+
+template <int V> struct TreeVec;
+template <> struct TreeVec<1> {
+    typedef float T;
+    static __device__ __forceinline__ T ld(const float *p) { return ld1(p); }
+    static __device__ __forceinline__ void st(float *p, T v) { st1(p, v); }
+};
+template <> struct TreeVec<4> {
+    typedef float4 T;
+    static __device__ __forceinline__ T ld(const float *p) { return ld4(p); }
+    static __device__ __forceinline__ void st(float *p, T v) { st4(p, v); }
+};
+
+template <uint32_t COMB>
+__device__ __forceinline__ float comb1(float a, float b)
+{
+    if (COMB == SPARKCL_VADD)
+        return a + b;
+    return (b > a) ? b : a;
+}
+template <uint32_t COMB>
+__device__ __forceinline__ float comb(float a, float b)
+{
+    return comb1<COMB>(a, b);
+}
+template <uint32_t COMB>
+__device__ __forceinline__ float4 comb(const float4 &a, const float4 &b)
+{
+    return make_float4(comb1<COMB>(a.x, b.x), comb1<COMB>(a.y, b.y),
+                       comb1<COMB>(a.z, b.z), comb1<COMB>(a.w, b.w));
+}
+
+// Insert a perfect subtree of 2^L leaves that starts at leaf `pos` (a
+// multiple of 2^L) into the counter.  `pos` is wave-uniform, so every branch
+// here is a scalar branch and every slot index is a compile-time constant.
+template <int L, uint32_t COMB, class T>
+__device__ __forceinline__ void tree_insert(T (&slot)[kTreeSlots], uint32_t pos, T v)
+{
+    // the carry chain: the full slots L, L+1, ... below the first empty one
+    const uint32_t full = (uint32_t)__builtin_ctz(~(pos >> L));
+#pragma unroll
+    for (int j = L; j < kTreeSlots; ++j) {
+        if ((uint32_t)j < L + full)
+            v = comb<COMB>(slot[j], v);
+        else if ((uint32_t)j == L + full)
+            slot[j] = v;
+    }
+}
+
+template <int V, uint32_t COMB>
+__global__ __launch_bounds__(kBlock) void k_tree(TreeArgs a)
+{
+    typedef TreeVec<V> TV;
+    typedef typename TV::T T;
+    const uint64_t col = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * V;
+    if (col >= a.len)
+        return; // no barriers below
+    const uint32_t c = blockIdx.y;
+    const uint32_t k0 = c * a.chunk;
+    const uint32_t m = min(a.count - k0, a.chunk);
+    auto leaf = [&](uint32_t i) -> const float * {
+        const uint32_t kk = k0 + i;
+        return (a.ptrs ? a.ptrs[kk] : a.base + (uint64_t)kk * a.stride) + col;
+    };
+    T slot[kTreeSlots];
+    uint32_t i = 0;
+    for (; i + 8 <= m; i += 8) {
+        T v[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+            v[b] = TV::ld(leaf(i + b));
+        const T l = comb<COMB>(comb<COMB>(v[0], v[1]), comb<COMB>(v[2], v[3]));
+        const T r = comb<COMB>(comb<COMB>(v[4], v[5]), comb<COMB>(v[6], v[7]));
+        tree_insert<3, COMB>(slot, i, comb<COMB>(l, r));
+    }
+    for (; i < m; ++i)
+        tree_insert<0, COMB>(slot, i, TV::ld(leaf(i)));
+    // merge the occupied slots, smallest (rightmost) first
+    T acc{};
+    bool have = false;
+#pragma unroll
+    for (int j = 0; j < kTreeSlots; ++j) {
+        if (m & (1u << j)) {
+            acc = have ? comb<COMB>(slot[j], acc) : slot[j];
+            have = true;
+        }
+    }
+    TV::st(a.out + (uint64_t)c * a.len + col, acc);
+}
+
 __global__ __launch_bounds__(kBlock) void k_zero(uint32_t *p, uint64_t words)
 {
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
@@ -796,7 +986,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_pattern(float *p, uint64_t n,
 static_assert(offsetof(TaskDev, ntiles) == 96, "word 24 of a descriptor");
 static_assert(offsetof(TaskDev, tile_first) == 120, "words 30-31 of a descriptor");
 
-__device__ void serve_dispatch(const ServeArgs &a)
+__device__ __forceinline__ void serve_dispatch(const ServeArgs &a)
 {
     __shared__ uint64_t sh_tail, sh_stop;
     __shared__ uint32_t sh_nt, sh_first_lo, sh_first_hi;
@@ -869,7 +1059,7 @@ __device__ void serve_dispatch(const ServeArgs &a)
                               __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ void serve_work(const ServeArgs &a)
+__device__ __forceinline__ void serve_work(const ServeArgs &a)
 {
     __shared__ uint64_t sh_tile;
     __shared__ TaskDev sh_task;
@@ -979,6 +1169,39 @@ int launch_map(const TaskDev *dtask, uint64_t n, uint32_t variant, uint32_t grid
         return SPARKCL_EINVAL;
     hipLaunchKernelGGL(k_map, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
                        dtask, n, variant);
+    return hip_status(hipGetLastError());
+}
+
+int launch_tree(const TreeArgs &a, uint32_t combiner, bool vec4, void *stream)
+{
+    if (a.len == 0 || a.count == 0 || a.chunk == 0)
+        return SPARKCL_EINVAL;
+    const uint32_t nchunks = (a.count + a.chunk - 1) / a.chunk;
+    if (nchunks > 1 && (a.chunk & (a.chunk - 1)))
+        return SPARKCL_EINVAL;
+    if (a.chunk > (1u << (kTreeSlots - 1)) || nchunks > 65535)
+        return SPARKCL_EINVAL;
+    if (vec4 && (a.len & 3u))
+        return SPARKCL_EINVAL;
+    const uint32_t V = vec4 ? 4 : 1;
+    const uint64_t colblocks = (a.len + (uint64_t)kBlock * V - 1) / ((uint64_t)kBlock * V);
+    if (colblocks > 0x7fffffffull)
+        return SPARKCL_EINVAL;
+    const dim3 grid((uint32_t)colblocks, nchunks);
+    hipStream_t s = (hipStream_t)stream;
+    if (combiner == SPARKCL_VADD) {
+        if (vec4)
+            hipLaunchKernelGGL((k_tree<4, SPARKCL_VADD>), grid, dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_tree<1, SPARKCL_VADD>), grid, dim3(kBlock), 0, s, a);
+    } else if (combiner == SPARKCL_VMAX) {
+        if (vec4)
+            hipLaunchKernelGGL((k_tree<4, SPARKCL_VMAX>), grid, dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_tree<1, SPARKCL_VMAX>), grid, dim3(kBlock), 0, s, a);
+    } else {
+        return SPARKCL_EINVAL;
+    }
     return hip_status(hipGetLastError());
 }
 

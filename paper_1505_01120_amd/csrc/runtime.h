@@ -41,7 +41,7 @@ class Server;
 // words and results, plus (batched mode) an instantiated graph.
 struct Plan {
     uint64_t hash = 0;
-    int kind = 0; // 0 reduce/map_partition, 1 map
+    int kind = 0; // 0 reduce/map_partition, 1 map, 2/3 array reduce (table/rows)
     int mode = 0;
     std::vector<sparkcl_task> tasks;
     sparkcl_result *user_results = nullptr;
@@ -63,6 +63,18 @@ struct Plan {
     LaunchOut out{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+
+    // kinds 2 and 3, array-valued ReduceCL: the leaves (a pointer table, or
+    // rows of one buffer) and the passes
+    uint32_t combiner = 0;
+    uint64_t len = 0;
+    float *user_out = nullptr;
+    bool vec4 = false;
+    uint32_t nleaves = 0;
+    const float *leaf_base = nullptr;
+    uint64_t leaf_stride = 0;
+    std::vector<const float *> leaves;
+    std::vector<TreeArgs> passes;
 };
 
 // Plan cache and launch helpers (api.cpp); the caller holds ctx->mu.

@@ -136,6 +136,20 @@ int launch_batch(const TaskDev *dtasks, const TileRef *tiles, uint32_t ntiles,
 int launch_map(const TaskDev *dtask, uint64_t n, uint32_t variant,
                uint32_t grid, void *stream);
 int launch_zero(void *p, uint64_t bytes, void *stream);
+// Array-valued ReduceCL, one pass: reduces `count` leaves of `len` floats
+// (from the device pointer table `ptrs`, or, when ptrs is null, the rows
+// base + i * stride) in chunks of `chunk` leaves; chunk c's tree goes to
+// out + c * len.
+struct TreeArgs {
+    const float *const *ptrs;
+    const float *base;
+    uint64_t stride;
+    float *out;
+    uint64_t len;
+    uint32_t count;
+    uint32_t chunk;
+};
+int launch_tree(const TreeArgs &a, uint32_t combiner, bool vec4, void *stream);
 // Resident serving executor: block 0 dispatches, the rest run tiles.  Each
 // launch first discards tickets left unpublished by the previous launch.
 int launch_serve(const ServeArgs &a, uint32_t workers, void *stream);

@@ -7,7 +7,8 @@ no fallback path.
 
 Names mirror the C entry points: ``Context.map`` is sparkcl_map (MapCL),
 ``Context.map_partition`` is sparkcl_map_partition (MapCLPartition),
-``Context.reduce`` is sparkcl_reduce (ReduceCL), ``Context.submit`` /
+``Context.reduce`` is sparkcl_reduce (ReduceCL), ``Context.reduce_arrays``
+is sparkcl_reduce_arrays (ReduceCL over array-valued elements), ``Context.submit`` /
 ``Context.poll`` are the serving calls.
 """
 from __future__ import annotations
@@ -26,6 +27,7 @@ OK, EINVAL, ENOKERNEL, ETOOBIG, EAGAIN, EHIP, ETIMEDOUT, ESTOPPED, ENOMEM, ENOTF
 POLY, FMUL, MC_PI = 1, 2, 3
 SUM, MAX, COUNT = 1, 2, 4
 PER_LAUNCH, BATCHED = 0, 1
+VADD, VMAX = 1, 2
 FLAG_SERVE_PER_TASK = 1
 TUNE_BUCKETS, TUNE_MODES = 32, 3
 
@@ -77,7 +79,9 @@ assert ctypes.sizeof(Task) == 96 and ctypes.sizeof(Result) == 64
 
 # Every symbol declared in include/sparkcl.h.
 EXPORTS = ("sparkcl_init", "sparkcl_destroy", "sparkcl_map", "sparkcl_map_partition",
-           "sparkcl_reduce", "sparkcl_reduce_async", "sparkcl_submit", "sparkcl_poll",
+           "sparkcl_reduce", "sparkcl_reduce_async", "sparkcl_reduce_arrays",
+           "sparkcl_reduce_rows",
+           "sparkcl_submit", "sparkcl_poll",
            "sparkcl_serve_stats_get", "sparkcl_serve_drain", "sparkcl_get_tuning",
            "sparkcl_set_tuning", "sparkcl_autotune", "sparkcl_strerror",
            "sparkcl_last_error", "sparkcl_last_kernel_ms", "sparkcl_version")
@@ -113,6 +117,8 @@ def load() -> ctypes.CDLL:
             "sparkcl_map_partition": ([P, TP, U32, I32, RP, P], I32),
             "sparkcl_reduce": ([P, TP, U32, I32, RP, RP, P], I32),
             "sparkcl_reduce_async": ([P, TP, U32, I32, P, P, P], I32),
+            "sparkcl_reduce_arrays": ([P, U32, ctypes.POINTER(P), U32, U64, P, P], I32),
+            "sparkcl_reduce_rows": ([P, U32, P, U64, U32, U64, P, P], I32),
             "sparkcl_submit": ([P, TP, ctypes.POINTER(U64)], I32),
             "sparkcl_poll": ([P, U64, RP], I32),
             "sparkcl_serve_stats_get": ([P, ctypes.POINTER(ServeStats)], I32),
@@ -255,6 +261,29 @@ class Context:
         _check(load().sparkcl_reduce_async(self._h, arr, n, mode, _ptr(dev_results),
                                            _ptr(dev_total), _stream(stream, self.device)),
                "sparkcl_reduce_async")
+
+    def reduce_arrays(self, arrays: Sequence, out, combiner: int = VADD,
+                      stream=None) -> None:
+        """Array-valued ReduceCL: fold the RDD elements (device float32
+        arrays of one length, in RDD order) with the combiner along the
+        library's fixed tree into `out`.  Asynchronous on `stream`."""
+        ptrs = [_ptr(a) for a in arrays]
+        n = len(ptrs)
+        table = (ctypes.c_void_p * max(n, 1))(*ptrs)
+        length = int(out.numel()) if out is not None else 0
+        _check(load().sparkcl_reduce_arrays(self._h, combiner, table, n, length, _ptr(out),
+                                            _stream(stream, self.device)),
+               "sparkcl_reduce_arrays")
+
+    def reduce_rows(self, rows, out, combiner: int = VADD, stream=None) -> None:
+        """Array-valued ReduceCL over the rows of a 2-D device tensor (each
+        row one RDD element, unit inner stride) into `out`."""
+        if rows.dim() != 2 or (rows.size(1) > 1 and rows.stride(1) != 1):
+            raise ValueError("rows must be a 2-D tensor with contiguous rows")
+        k, length = rows.shape
+        _check(load().sparkcl_reduce_rows(self._h, combiner, rows.data_ptr(), rows.stride(0),
+                                          k, length, _ptr(out), _stream(stream, self.device)),
+               "sparkcl_reduce_rows")
 
     # -- serving ------------------------------------------------------------
     def submit(self, t: Task) -> int:

@@ -134,6 +134,53 @@ def test_reduce_with_materialised_output(ctx, mode):
         assert np.array_equal(o.cpu().numpy().view(np.uint32), want.view(np.uint32))
 
 
+# Sizes around the chunk-interleaved tile layout (chunks of 4096 elements
+# dealt round-robin to a task's tiles): fewer chunks than tiles, a partial
+# last chunk owned by a tile other than 0, ragged tails and unaligned heads.
+FORCED_N = [1, 4095, 4096, 4097, 4099, 8191, 3 * 4096 + 5, 5 * 4096 + 1030,
+            17 * 4096 + 3, 100_003, 262_147]
+
+
+@pytest.fixture
+def forced_tiles(ctx):
+    """Set every tile size of every mode to one value for the test's duration."""
+    saved = ctx.get_tuning()
+
+    def force(log2: int):
+        t = sc.Tuning.from_buffer_copy(saved)
+        for m in range(len(t.tile)):
+            for k in range(len(t.tile[m])):
+                for b in range(len(t.tile[m][k])):
+                    t.tile[m][k][b] = 1 << log2
+        ctx.set_tuning(t)
+
+    yield force
+    ctx.set_tuning(saved)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("tile_log2", [10, 12, 13, 16])
+@pytest.mark.parametrize("off", [0, 1, 3])
+def test_forced_tile_sizes(ctx, forced_tiles, mode, tile_log2, off):
+    forced_tiles(tile_log2)
+    parts = [datagen.make_part(kid, n, 8 * i + kid)
+             for i, n in enumerate(FORCED_N) for kid in (datagen.POLY, datagen.FMUL)]
+    d = DevParts(parts, off, off, out=True)
+    per, tot = ctx.reduce(d.tasks, mode)
+    torch.cuda.synchronize()
+    want = [oracle_result(p) for p in parts]
+    for p, g, o, buf in zip(parts, per, want, d.outs):
+        where = f"kid={p.kid} n={p.n} T=2^{tile_log2} off={off} mode={mode}"
+        check_result(g, o, p.kid, p.ops, where)
+        m = oracle.poly_map(p.x, p.coef) if p.kid == datagen.POLY else \
+            oracle.fmul_map(p.x, p.y)
+        assert np.array_equal(buf.cpu().numpy().view(np.uint32), m.view(np.uint32)), where
+    ops = 0
+    for p in parts:
+        ops |= p.ops
+    check_total(tot, want, ops)
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_repeat_is_bit_identical_and_async_matches(ctx, mode):
     parts = [datagen.make_part(k, 200_000 + 17 * i, i)

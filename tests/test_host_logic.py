@@ -3,6 +3,8 @@ symbol exported, struct layouts as the header defines them, clean failure
 without a GPU) and the pure host logic behind it: the arena sub-allocator,
 serving admission control and the tuning table with its JSON cache."""
 import ctypes
+import hashlib
+import json
 import os
 import re
 import subprocess
@@ -289,3 +291,28 @@ def test_committed_tuning_cache_is_valid(host):
         pytest.skip("no tuning cache committed yet")
     err = ctypes.create_string_buffer(256)
     assert host.hl_tuning_parse(open(path).read().encode(), err, 256) >= 1, err.value
+
+
+def test_hot_kernels_keep_registers_and_no_scratch():
+    """The hot kernels stay inlined and in registers: no private segment (a
+    non-inlined call or a spill puts state in scratch), at most 128 VGPRs
+    (four waves per SIMD), and the Philox loop at its expected size.  Figures
+    come from the device assembly of the current build."""
+    if not os.path.exists(libbuild.ISA_JSON):
+        libbuild.build()
+    with open(libbuild.ISA_JSON) as f:
+        isa = json.load(f)
+    with open(os.path.join(libbuild.CSRC, "kernels.hip"), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    if isa.get("kernels_sha256_16") != sha:
+        libbuild.build()
+        with open(libbuild.ISA_JSON) as f:
+            isa = json.load(f)
+    for k in ("k_task", "k_batch", "k_serve", "k_map"):
+        assert isa[k]["private_segment_bytes"] == 0, (k, isa[k])
+        assert isa[k]["vgpr_spills"] == 0, (k, isa[k])
+        assert isa[k]["vgpr"] <= 128, (k, isa[k])
+    loop = isa["philox_loop"]
+    # ten rounds of two 32x32->64 products and two three-way xors per lane
+    assert loop["xor3"] == 20 and loop["mad_u64_u32"] >= 20, loop
+    assert loop["valu"] < 70, loop
