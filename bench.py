@@ -4,15 +4,15 @@ Step = one ReduceCL pass (paper sec. 3.1.3) over the 64-partition RDD: 64
 partitions x 2^22 float32 pairs (x ~ N(0,1), y ~ U[0,2), seeded per
 partition), FMUL map z = x*y + 0.1x fused with per-partition SUM and MAX and
 the RDD-level combine, run as one persistent-executor launch over the device
-tile queue, replayed from a cached hipGraph, tile sizes from the tuning
-table.  Inputs are resident in HBM before timing starts.  The metric is
+tile queue of a cached plan, tile sizes from the tuning table.  Inputs are resident in HBM before timing starts.  The metric is
 elements/s; the roofline object reports the executor kernel's algorithmic HBM
 bandwidth (8 B per element) against the 8 TB/s peak.
 
 Extras (same process, untimed relative to the step): the same RDD with one
 launch per partition, the single 2^20 POLY partition, the 256 x 2^24 Monte-Carlo
 partitions, the 4096-partition uneven batch (persistent vs per-partition),
-and the Poisson serving stream (resident executor vs one launch per task).
+the array-valued ReduceCL (vector add) over the resident x tensor, and the
+Poisson serving stream (resident executor vs one launch per task).
 
 Run: python bench.py [--steps K] [--warmup W] [--no-extras] [--serve-seconds S]
 """
@@ -223,14 +223,45 @@ def bench_monte_carlo(ctx, sc, steps=5) -> dict:
     return out
 
 
+def bench_array_reduce(ctx, sc, res, reps=20) -> dict:
+    """Array-valued ReduceCL (vector add along the fixed tree) over the
+    resident x tensor viewed as RDD elements: 64 arrays of 2^22 floats and
+    65536 arrays of 4096 floats (the same 1 GiB).  HBM-bound: 4 B read per
+    element plus the 4 B per column written."""
+    import torch
+    out = {}
+    for name, (k, length) in (("64x2p22", (64, 1 << 22)), ("65536x4096", (65536, 4096))):
+        rows = res.x.view(k, length)
+        o = torch.empty(length, dtype=torch.float32, device="cuda")
+        s = torch.cuda.current_stream()
+        for _ in range(3):
+            ctx.reduce_rows(rows, o, sc.VADD, stream=s)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            ctx.reduce_rows(rows, o, sc.VADD, stream=s)
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        algo = 4 * k * length + 4 * length
+        gbs = algo / (ms / 1e3) / 1e9
+        out[name] = {"us": ms * 1e3, "elements_per_s": k * length / (ms / 1e3),
+                     "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+    return out
+
+
 def bench_uneven(ctx, sc, steps=5) -> dict:
     import torch
 
     import datagen
     sizes, kids = datagen.uneven_sizes()
-    # inputs: one resident pool per input; partition p reads its own slice
-    nx = int(sum(n for n, k in zip(sizes, kids) if k != datagen.MC_PI))
-    ny = int(sum(n for n, k in zip(sizes, kids) if k == datagen.FMUL))
+    # inputs: one resident pool per input; partition p reads its own slice,
+    # which starts 256-byte aligned as a separately allocated partition would
+    def up(v):
+        return (v + 63) // 64 * 64
+    nx = sum(up(int(n)) for n, k in zip(sizes, kids) if k != datagen.MC_PI)
+    ny = sum(up(int(n)) for n, k in zip(sizes, kids) if k == datagen.FMUL)
     x = torch.empty(nx, dtype=torch.float32, device="cuda")
     y = torch.empty(max(ny, 1), dtype=torch.float32, device="cuda")
     tasks, ox, oy, bytes_, elems, mc = [], 0, 0, 0, 0, 0
@@ -241,12 +272,12 @@ def bench_uneven(ctx, sc, steps=5) -> dict:
             continue
         xs = x[ox:ox + n]
         xs.copy_(torch.from_numpy(datagen.x_for(k, n, 0, p)))
-        ox += n
+        ox += up(n)
         ys = None
         if k == datagen.FMUL:
             ys = y[oy:oy + n]
             ys.copy_(torch.from_numpy(datagen.y_for(k, n, 0, p)))
-            oy += n
+            oy += up(n)
         tasks.append(sc.task(k, n, xs, ys, coef=datagen.POLY_COEF if k == 1 else (),
                              c=datagen.FMUL_C))
         bytes_ += n * (4 if k == datagen.POLY else 8)
@@ -394,7 +425,7 @@ def main() -> int:
         "data": "synthetic, seeded per partition (x~N(0,1), y~U[0,2))",
         "config": {"workload": "RDD of 64 partitions x 2^22 float32 pairs; FMUL z=x*y+0.1x; "
                                "per-partition SUM+MAX + RDD total; persistent executor, "
-                               "hipGraph replay", "partitions": parts, "elements": elems,
+                               "cached plan", "partitions": parts, "elements": elems,
                    "mode": "batched"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -417,6 +448,8 @@ def main() -> int:
         ex["monte_carlo"] = bench_monte_carlo(ctx, sc)
         log("extras: uneven batch ...")
         ex["uneven_batch"] = bench_uneven(ctx, sc)
+        log("extras: array-valued reduce ...")
+        ex["array_reduce"] = bench_array_reduce(ctx, sc, res)
         if not args.no_serve:
             for name, per_task in (("resident", False), ("per_task_launch", True)):
                 log(f"extras: serving ({name}) ...")

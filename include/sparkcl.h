@@ -80,8 +80,7 @@ extern "C" {
 /* execution modes of sparkcl_reduce / sparkcl_map_partition */
 #define SPARKCL_PER_LAUNCH 0 /* one kernel launch per partition              */
 #define SPARKCL_BATCHED 1    /* all partitions in one persistent launch over
-                                a device tile queue, replayed from a cached
-                                hipGraph                                     */
+                                a device tile queue (cached per call content) */
 
 typedef struct sparkcl_ctx sparkcl_ctx; /* opaque, library-owned */
 
@@ -156,7 +155,7 @@ typedef struct sparkcl_result {
 SPARKCL_API int sparkcl_init(const sparkcl_config *config, sparkcl_ctx **out);
 
 /* Stop serving (waits up to 10 s for the resident executor to drain), release
-   pinned memory and cached graphs.  The arena itself stays the caller's. */
+   pinned memory and cached plans.  The arena itself stays the caller's. */
 SPARKCL_API int sparkcl_destroy(sparkcl_ctx *ctx);
 
 /* MapCL (sec. 3.1.3): out[i] = kernel(in0[i] [, in1[i]]) for each task
@@ -267,7 +266,7 @@ typedef struct sparkcl_tuning {
 
 SPARKCL_API int sparkcl_get_tuning(sparkcl_ctx *ctx, sparkcl_tuning *out);
 /* Replace the tuning table (validated: tiles must be powers of two in range).
-   Cached graphs are dropped. */
+   Cached plans are dropped. */
 SPARKCL_API int sparkcl_set_tuning(sparkcl_ctx *ctx, const sparkcl_tuning *in);
 
 /* Autotuner: for each kernel and size bucket in [lo_log2, hi_log2], time the
@@ -282,8 +281,9 @@ SPARKCL_API int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi
 SPARKCL_API const char *sparkcl_strerror(int code);
 SPARKCL_API const char *sparkcl_last_error(void);
 
-/* Device kernel time (ms) of the last reduce/map_partition launch sequence on
-   this context, measured with HIP events on the launch stream. */
+/* Device kernel time (ms) of the last blocking reduce/map_partition launch
+   sequence on this context, measured with HIP events on the launch stream
+   (asynchronous calls are not timed, so they add no event packets). */
 SPARKCL_API int sparkcl_last_kernel_ms(sparkcl_ctx *ctx, float *ms);
 
 /* Library version string. */

@@ -3,10 +3,10 @@
 // Execution model: a call's tasks are validated, decomposed into tiles by the
 // tuning table, and uploaded once into arena memory as a Plan (device task
 // table, tile queue, partial slots, sync words, results).  Plans are cached by
-// the content of the call, so a repeated batch skips validation and upload;
-// in batched mode the cached plan also holds an instantiated hipGraph of the
-// persistent executor, which is simply replayed (the kernel leaves its
-// queue and tickets at zero, so nothing is cleared between replays).  This is
+// the content of the call, so a repeated batch skips validation and upload
+// and is one kernel dispatch of the persistent executor (the kernel leaves
+// its queue and tickets at zero, so nothing is cleared between launches).
+// This is
 // the paper's point that a kernel should be instantiated once per worker and
 // cached (sec. 3.1.1.2), and that enough data must be gathered per offload
 // (sec. 3, issue 2).
@@ -111,10 +111,6 @@ uint64_t plan_hash(int kind, int mode, const sparkcl_task *tasks, uint32_t ntask
 
 void free_plan(sparkcl_ctx *ctx, Plan *p)
 {
-    if (p->gexec)
-        (void)hipGraphExecDestroy(p->gexec);
-    if (p->graph)
-        (void)hipGraphDestroy(p->graph);
     for (uint64_t off : p->blocks)
         ctx->arena.release(off);
     delete p;
@@ -195,7 +191,25 @@ int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
     p->ntiles.resize(ntasks);
     p->variants.resize(ntasks);
 
-    const int tm = mode == SPARKCL_BATCHED ? TM_BATCHED : TM_PER_LAUNCH;
+    // Tile table: the batched one, unless the batch would then have fewer
+    // tiles than the executor has blocks (a batch of one or a few partitions,
+    // where the batched table's large tiles would leave most of the GPU
+    // idle); such a batch is cut with the per-launch table instead.  The
+    // choice is a function of the call, so a repeated call is cut the same way.
+    int tm = mode == SPARKCL_BATCHED ? TM_BATCHED : TM_PER_LAUNCH;
+    if (mode == SPARKCL_BATCHED) {
+        uint64_t tiles = 0;
+        uint32_t mask = 0;
+        for (uint32_t i = 0; i < ntasks; ++i) {
+            if (tasks[i].kernel_id < SPARKCL_POLY || tasks[i].kernel_id > SPARKCL_MC_PI)
+                continue; // rejected below
+            const uint32_t T = tile_for(ctx->tuning, TM_BATCHED, tasks[i].kernel_id, tasks[i].n);
+            tiles += std::max<uint64_t>(1, (tasks[i].n + T - 1) / T);
+            mask |= 1u << (tasks[i].kernel_id - 1);
+        }
+        if (tiles < exec_grid(ctx, mask, tiles, ntasks))
+            tm = TM_PER_LAUNCH;
+    }
     std::vector<uint64_t> first(ntasks);
     uint64_t total_tiles = 0;
     uint32_t kid_mask = 0;
@@ -266,9 +280,27 @@ int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
                                   hipMemcpyHostToDevice, stream);
     std::vector<TileRef> tiles;
     if (e == hipSuccess && p->dtiles) {
-        // Tile queue: tasks in order, each task's tiles in order.
+        // Tile queue, longest tiles first (a longest-processing-time list
+        // schedule: the batch then ends on short tiles instead of leaving a
+        // few blocks streaming large tiles while the rest idle).  A tile's
+        // cost is its element count times the kernel's cost per element
+        // (bytes streamed; a Monte-Carlo sample counts like ~5 bytes of HBM
+        // time).  Ties keep task order and each task's tiles together and in
+        // order, so the tiles of a task still run side by side.  The order
+        // only changes when tiles run: every partial and every combine order
+        // is fixed by the decomposition, so results are unaffected.
+        std::vector<uint32_t> order(ntasks);
+        std::vector<uint64_t> cost(ntasks);
+        for (uint32_t i = 0; i < ntasks; ++i) {
+            order[i] = i;
+            const uint32_t kid = tasks[i].kernel_id;
+            const uint64_t w = kid == SPARKCL_POLY ? 4 : kid == SPARKCL_FMUL ? 8 : 5;
+            cost[i] = std::min<uint64_t>(host[i].tile_elems, tasks[i].n) * w;
+        }
+        std::stable_sort(order.begin(), order.end(),
+                         [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
         tiles.reserve(total_tiles);
-        for (uint32_t i = 0; i < ntasks; ++i)
+        for (uint32_t i : order)
             for (uint32_t j = 0; j < p->ntiles[i]; ++j)
                 tiles.push_back(TileRef{i, j});
         e = hipMemcpyAsync(p->dtiles, tiles.data(), sizeof(TileRef) * total_tiles,
@@ -295,25 +327,6 @@ int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
         p->out.ntasks = ntasks;
         p->out.ns_per_tick = ctx->ns_per_tick;
         p->grid = std::min(exec_grid(ctx, kid_mask, p->ntiles_total, ntasks), p->ntiles_total);
-        if (mode == SPARKCL_BATCHED) {
-            hipStream_t cs = ctx->capture_stream;
-            e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-            if (e == hipSuccess) {
-                rc = launch_batch(p->dtasks, p->dtiles, p->ntiles_total, p->grid, p->out, cs);
-                hipError_t e2 = hipStreamEndCapture(cs, &p->graph);
-                if (rc != SPARKCL_OK)
-                    e = hipErrorLaunchFailure;
-                else
-                    e = e2;
-            }
-            if (e == hipSuccess)
-                e = hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0);
-            if (e != hipSuccess) {
-                Plan *raw = p.release();
-                free_plan(ctx, raw);
-                return fail_hip(e, "graph capture of the persistent executor");
-            }
-        }
     }
     p->hash = plan_hash(kind, mode, tasks, ntasks, ures, utot);
     *out = p.release();
@@ -387,11 +400,21 @@ int ensure_pinned(sparkcl_ctx *ctx, uint32_t count)
 
 // Enqueue the launches of a reduce-kind plan on `stream`, bracketed by the
 // context's timing events.
-int sparkcl::enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream)
+int sparkcl::enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream, bool timed)
 {
-    SPARKCL_HIP(hipEventRecord(ctx->ev0, stream));
+    // Timed launches are bracketed by two events (each an extra packet on the
+    // queue, a few microseconds apiece), so only blocking calls and the
+    // autotuner ask for them; asynchronous calls enqueue the kernels alone.
+    if (timed)
+        SPARKCL_HIP(hipEventRecord(ctx->ev0, stream));
     if (p->mode == SPARKCL_BATCHED) {
-        SPARKCL_HIP(hipGraphLaunch(p->gexec, stream));
+        // One dispatch of the persistent executor: the cached plan holds the
+        // uploaded task table and tile queue, and the kernel leaves its queue
+        // head and tickets at zero, so nothing is cleared between launches.
+        int rc = launch_batch(p->dtasks, p->dtiles, p->ntiles_total, p->grid, p->out, stream);
+        if (rc != SPARKCL_OK)
+            return fail(rc, "executor launch failed: " +
+                                std::string(hipGetErrorString(hipGetLastError())));
     } else {
         for (uint32_t i = 0; i < p->ntasks; ++i) {
             const uint32_t cap = exec_grid(ctx, 1u << (p->tasks[i].kernel_id - 1));
@@ -402,8 +425,10 @@ int sparkcl::enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream)
                                     std::string(hipGetErrorString(hipGetLastError())));
         }
     }
-    SPARKCL_HIP(hipEventRecord(ctx->ev1, stream));
-    ctx->have_ms = true;
+    if (timed) {
+        SPARKCL_HIP(hipEventRecord(ctx->ev1, stream));
+        ctx->have_ms = true;
+    }
     return SPARKCL_OK;
 }
 
@@ -420,7 +445,7 @@ int run_blocking(sparkcl_ctx *ctx, int mode, const sparkcl_task *tasks,
         return rc;
     if ((rc = ensure_pinned(ctx, ntasks + 1)) != SPARKCL_OK)
         return rc;
-    if ((rc = enqueue(ctx, p, stream)) != SPARKCL_OK)
+    if ((rc = enqueue(ctx, p, stream, true)) != SPARKCL_OK)
         return rc;
     SPARKCL_HIP(hipMemcpyAsync(ctx->pinned, p->dresults, sizeof(sparkcl_result) * ntasks,
                                hipMemcpyDeviceToHost, stream));
@@ -541,7 +566,6 @@ int sparkcl_init(const sparkcl_config *config, sparkcl_ctx **out)
         ctx->own_arena = true;
     }
     ctx->arena.reset(arena_bytes);
-    SPARKCL_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
     SPARKCL_HIP(hipEventCreate(&ctx->ev0));
     SPARKCL_HIP(hipEventCreate(&ctx->ev1));
     if ((rc = ensure_pinned(ctx.get(), 1024)) != SPARKCL_OK)
@@ -572,8 +596,6 @@ int sparkcl_destroy(sparkcl_ctx *ctx)
         (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1)
         (void)hipEventDestroy(ctx->ev1);
-    if (ctx->capture_stream)
-        (void)hipStreamDestroy(ctx->capture_stream);
     if (ctx->own_arena)
         (void)hipFree(ctx->arena_base);
     delete ctx;
@@ -904,7 +926,7 @@ int sparkcl_reduce_async(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t n
     if ((rc = get_plan(ctx, 0, mode, tasks, ntasks, dev_per_task, dev_total, s, &p)) !=
         SPARKCL_OK)
         return rc;
-    return enqueue(ctx, p, s);
+    return enqueue(ctx, p, s, false);
 }
 
 int sparkcl_submit(sparkcl_ctx *ctx, const sparkcl_task *task, uint64_t *ticket)

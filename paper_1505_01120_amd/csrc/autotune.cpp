@@ -1,11 +1,15 @@
-// Autotuner: picks, per execution mode, registry kernel and log2(n) bucket, the
-// tile size with the lowest median HIP-event time on synthetic device data,
-// then the persistent executor's blocks per CU.  The result is a tuning table
+// Autotuner: picks, by the lowest median HIP-event time on synthetic device
+// data, first each registry kernel's persistent-executor blocks per CU
+// jointly with its tile for large (2^22-element) partitions, then the tile
+// size per execution mode, kernel and log2(n) bucket, then the occupancy for
+// batches of many small tasks.  The result is a tuning table
 // that is written to a JSON cache keyed by the device's gfx arch, so a given
 // machine always decomposes a task the same way (results stay run-to-run
 // identical).  The paper leaves optimisation open (sec. 6); this is ours.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -20,12 +24,12 @@ namespace {
 constexpr uint64_t kPoolElems = 1ull << 28;
 constexpr int kWarm = 3, kReps = 9;
 
-// Elements per timed batch: 1 GiB of input for the streaming kernels (a batch
-// large enough that the tile count per block, not the launch, dominates);
-// 2^26 samples for the Monte-Carlo kernel.
+// Elements per timed batch: 2^28 for the streaming kernels (1 GiB per input
+// array; the tiles per block, not the launch, dominate, as in a large RDD)
+// and 2^27 samples for the Monte-Carlo kernel.
 uint64_t work_elems(uint32_t kid)
 {
-    return kid == SPARKCL_POLY ? (1ull << 28) : kid == SPARKCL_FMUL ? (1ull << 27) : (1ull << 26);
+    return kid == SPARKCL_MC_PI ? (1ull << 27) : (1ull << 28);
 }
 
 uint64_t mix64(uint64_t z)
@@ -52,7 +56,7 @@ int time_reduce(Bench &b, int mode, const std::vector<sparkcl_task> &tasks, floa
         return rc;
     std::vector<float> t;
     for (int r = 0; r < kWarm + kReps; ++r) {
-        if ((rc = enqueue(b.ctx, p, b.s)) != SPARKCL_OK)
+        if ((rc = enqueue(b.ctx, p, b.s, true)) != SPARKCL_OK)
             return rc;
         SPARKCL_HIP(hipEventSynchronize(b.ctx->ev1));
         float v = 0;
@@ -88,17 +92,21 @@ sparkcl_task make_task(const Bench &b, uint32_t kid, uint64_t n, uint64_t i)
     return t;
 }
 
-// Many small tasks of mixed kernels: 2048 tasks, sizes log-uniform in
-// [2^10, 2^20), kernel ids uniform.
+// Many tasks of mixed kernels, shaped like an uneven RDD: 4096 tasks with
+// log-normal sizes (median 2^16, log-sd ln 4, clipped to [2^10, 2^23]) and
+// kernel ids uniform over the registry.
 std::vector<sparkcl_task> make_mixed(const Bench &b)
 {
     std::vector<sparkcl_task> v;
     uint64_t off = 0;
-    for (uint64_t i = 0; i < 2048; ++i) {
-        const uint64_t h = mix64(0x5eed + i);
-        const double e = 10.0 + 10.0 * (double)(h >> 11) * 0x1p-53;
-        const uint64_t n = (uint64_t)std::exp2(e);
-        const uint32_t kid = 1 + (uint32_t)((mix64(h) >> 32) % 3);
+    for (uint64_t i = 0; i < 4096; ++i) {
+        const uint64_t h1 = mix64(0x5eed0000 + 2 * i), h2 = mix64(0x5eed0001 + 2 * i);
+        const double u1 = ((double)(h1 >> 11) + 0.5) * 0x1p-53;
+        const double u2 = (double)(h2 >> 11) * 0x1p-53;
+        const double z = std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+        const double e = std::log(65536.0) + std::log(4.0) * z;
+        const uint64_t n = (uint64_t)std::min(8388608.0, std::max(1024.0, std::rint(std::exp(e))));
+        const uint32_t kid = 1 + (uint32_t)((mix64(h1 ^ h2) >> 32) % 3);
         sparkcl_task t = make_task(b, kid, n, 0);
         if (kid != SPARKCL_MC_PI) {
             if (off + n > kPoolElems)
@@ -163,11 +171,61 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
     }
 
     sparkcl_tuning best = ctx->tuning;
+    const bool verbose = std::getenv("SPARKCL_AUTOTUNE_LOG") != nullptr;
+    // Times `tasks` under tuning `t`; false (with rc set) on failure.
+    auto measure = [&](const sparkcl_tuning &t, int mode,
+                       const std::vector<sparkcl_task> &tasks, float *ms) -> bool {
+        drop_plans(ctx);
+        ctx->tuning = t;
+        rc = time_reduce(b, mode, tasks, ms);
+        return rc == SPARKCL_OK;
+    };
+    auto abort_with = [&](int code) {
+        ctx->tuning = best;
+        cleanup();
+        return code;
+    };
+    const uint32_t occ = (uint32_t)ctx->occ_batch;
+
+    // 1. Executor blocks per CU and the large-partition tile, jointly, per
+    //    kernel, on a 2^28-element batch of 2^22-element partitions (tiles and
+    //    occupancy trade against each other: large tiles want more blocks).
+    //    Ties (within 2%) go to fewer blocks and smaller tiles.
+    constexpr uint32_t kRefLog2 = 22;
+    for (uint32_t kid = SPARKCL_POLY; kid <= SPARKCL_MC_PI; ++kid) {
+        const std::vector<sparkcl_task> tasks =
+            make_tasks(b, kid, 1ull << kRefLog2, SPARKCL_BATCHED);
+        float best_ms = 1e30f;
+        uint32_t best_bpc = 1, best_tile = best.tile[TM_BATCHED][kid - 1][kRefLog2];
+        for (uint32_t bpc = 1; bpc <= occ; ++bpc)
+            for (uint32_t tl = 14; tl <= 20; ++tl) {
+                sparkcl_tuning t = best;
+                t.blocks_per_cu[kid - 1] = bpc;
+                t.tile[TM_BATCHED][kid - 1][kRefLog2] = 1u << tl;
+                float ms = 0;
+                if (!measure(t, SPARKCL_BATCHED, tasks, &ms))
+                    return abort_with(rc);
+                if (verbose)
+                    std::fprintf(stderr, "joint kid %u bpc %u tile 2^%u: %.1f us\n", kid, bpc,
+                                 tl, ms * 1e3f);
+                if (ms < best_ms * 0.98f) {
+                    best_ms = ms;
+                    best_bpc = bpc;
+                    best_tile = 1u << tl;
+                }
+            }
+        best.blocks_per_cu[kid - 1] = best_bpc;
+        best.tile[TM_BATCHED][kid - 1][kRefLog2] = best_tile;
+    }
+
+    // 2. Tile size per (mode, kernel, log2-size bucket) at those occupancies.
     const int modes[2] = {SPARKCL_PER_LAUNCH, SPARKCL_BATCHED};
     for (int mode : modes) {
         const int tm = mode == SPARKCL_BATCHED ? TM_BATCHED : TM_PER_LAUNCH;
         for (uint32_t kid = SPARKCL_POLY; kid <= SPARKCL_MC_PI; ++kid) {
             for (uint32_t bk = lo_log2; bk <= hi_log2; ++bk) {
+                if (tm == TM_BATCHED && bk == kRefLog2)
+                    continue; // tuned jointly above
                 const uint64_t n = 1ull << bk;
                 const std::vector<sparkcl_task> tasks = make_tasks(b, kid, n, mode);
                 float best_ms = 1e30f;
@@ -178,15 +236,14 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
                         break;
                     if (n / T > (1u << 20))
                         continue;
-                    drop_plans(ctx);
-                    ctx->tuning = best;
-                    ctx->tuning.tile[tm][kid - 1][bk] = T;
+                    sparkcl_tuning t = best;
+                    t.tile[tm][kid - 1][bk] = T;
                     float ms = 0;
-                    if ((rc = time_reduce(b, mode, tasks, &ms)) != SPARKCL_OK) {
-                        ctx->tuning = best;
-                        cleanup();
-                        return rc;
-                    }
+                    if (!measure(t, mode, tasks, &ms))
+                        return abort_with(rc);
+                    if (verbose)
+                        std::fprintf(stderr, "tile mode %d kid %u n 2^%u T 2^%u: %.1f us\n",
+                                     mode, kid, bk, tl, ms * 1e3f);
                     if (ms < best_ms * 0.98f) { // prefer the earlier (smaller) on ties
                         best_ms = ms;
                         best_tile = T;
@@ -197,44 +254,19 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
         }
     }
 
-    // Executor occupancy per kernel, on a large batch of that kernel alone.
-    for (uint32_t kid = SPARKCL_POLY; kid <= SPARKCL_MC_PI; ++kid) {
-        const std::vector<sparkcl_task> tasks = make_tasks(b, kid, 1ull << 22, SPARKCL_BATCHED);
-        float best_ms = 1e30f;
-        uint32_t best_bpc = best.blocks_per_cu[kid - 1];
-        for (uint32_t bpc = 1; bpc <= (uint32_t)ctx->occ_batch; ++bpc) {
-            drop_plans(ctx);
-            ctx->tuning = best;
-            ctx->tuning.blocks_per_cu[kid - 1] = bpc;
-            float ms = 0;
-            if ((rc = time_reduce(b, SPARKCL_BATCHED, tasks, &ms)) != SPARKCL_OK) {
-                ctx->tuning = best;
-                cleanup();
-                return rc;
-            }
-            if (ms < best_ms * 0.98f) {
-                best_ms = ms;
-                best_bpc = bpc;
-            }
-        }
-        best.blocks_per_cu[kid - 1] = best_bpc;
-    }
-
-    // Occupancy for batches of many small tasks.
+    // 3. Occupancy for batches of many small tasks.
     {
         const std::vector<sparkcl_task> tasks = make_mixed(b);
         float best_ms = 1e30f;
         uint32_t best_bpc = best.blocks_per_cu_many;
-        for (uint32_t bpc = 1; bpc <= (uint32_t)ctx->occ_batch; ++bpc) {
-            drop_plans(ctx);
-            ctx->tuning = best;
-            ctx->tuning.blocks_per_cu_many = bpc;
+        for (uint32_t bpc = 1; bpc <= occ; ++bpc) {
+            sparkcl_tuning t = best;
+            t.blocks_per_cu_many = bpc;
             float ms = 0;
-            if ((rc = time_reduce(b, SPARKCL_BATCHED, tasks, &ms)) != SPARKCL_OK) {
-                ctx->tuning = best;
-                cleanup();
-                return rc;
-            }
+            if (!measure(t, SPARKCL_BATCHED, tasks, &ms))
+                return abort_with(rc);
+            if (verbose)
+                std::fprintf(stderr, "many bpc %u: %.1f us\n", bpc, ms * 1e3f);
             if (ms < best_ms * 0.98f) {
                 best_ms = ms;
                 best_bpc = bpc;

@@ -3,11 +3,10 @@
 // A partition task (a MapCL / MapCLPartition / ReduceCL application, paper
 // sec. 3.1.3) is cut into tiles of `tile_elems` elements.  One 256-thread
 // block turns one tile into one partial:
-//   1. streaming loop: coalesced 128-bit loads (float4), two register
-//      buffers of kUnroll quads per input so one buffer is in flight while
-//      the other is folded, the registry kernel's map applied per element,
-//      each value added to a per-thread FP64 sum, a running max, or a hit
-//      counter;
+//   1. streaming loop: coalesced 128-bit loads (float4), kUnroll quads per
+//      input in flight per thread, the registry kernel's map applied per
+//      element, each value added to a per-thread FP64 sum, a running max, or
+//      a hit counter;
 //   2. the per-thread values are combined across the wave with cross-lane
 //      shuffles and across the block's waves through LDS in a fixed tree;
 //   3. the partial is published and an arrival ticket taken; the block that
@@ -192,16 +191,11 @@ __device__ __forceinline__ void map_quad(const M &f, const float4 &xv,
 }
 
 // Stream `ng` groups of the calling thread.  Group g is the kUnroll quads
-// base(g) + u * kBlock (u = 0..kUnroll-1), in quads from x4/y4/o4.  The loads
-// of group g+1 are issued before group g is folded, so a wave keeps loads in
-// flight while it computes (with one or two waves per SIMD nothing else
-// would).  Two register buffers alternate; each thread still folds its quads
-// in group order, so the rounding is that of the plain loop.  The
-// steady-state body is straight-line code (no conditional load between the
-// two folds) and the scheduling barriers keep the machine scheduler from
-// hoisting the second load group above the first fold: the compiler's
-// wait-count placement then waits only for the buffer being folded, with the
-// other one still in flight.
+// base(g) + u * kBlock (u = 0..kUnroll-1), in quads from x4/y4/o4: all the
+// group's loads are issued, then the group is folded in order.  (Measured on
+// MI355X: keeping a second group in flight while folding -- a register double
+// buffer -- streams slower than this at every tile size and occupancy; the
+// extra requests in flight cost more at the HBM than the overlap gains.)
 template <class M, bool W, class Base>
 __device__ __forceinline__ void stream_groups(const M &f, const float *x4,
                                               const float *y4, float *o4,
@@ -209,42 +203,19 @@ __device__ __forceinline__ void stream_groups(const M &f, const float *x4,
 {
     constexpr int U = kUnroll;
     constexpr int NY = M::kTwo ? U : 1; // one-input maps carry no y buffer
-    auto load = [&](float4 *xv, float4 *yv, uint64_t q0) {
+    for (uint64_t g = 0; g < ng; ++g) {
+        const uint64_t q0 = base(g);
+        float4 xv[U], yv[NY];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             xv[u] = ld4(x4 + 4 * (q0 + u * kBlock));
             if (M::kTwo)
                 yv[u] = ld4(y4 + 4 * (q0 + u * kBlock));
         }
-    };
-    auto fold = [&](const float4 *xv, const float4 *yv, uint64_t q0) {
 #pragma unroll
         for (int u = 0; u < U; ++u)
             map_quad<M, W>(f, xv[u], M::kTwo ? yv[u] : xv[u],
                            W ? o4 + 4 * (q0 + u * kBlock) : nullptr, a);
-    };
-    if (ng == 0)
-        return;
-    float4 xa[U], ya[NY], xb[U], yb[NY];
-    load(xa, ya, base(0));
-    uint64_t g = 0;
-    for (; g + 2 < ng; g += 2) {
-        const uint64_t qa = base(g), qb = base(g + 1), qc = base(g + 2);
-        load(xb, yb, qb);
-        __builtin_amdgcn_sched_barrier(0);
-        fold(xa, ya, qa);
-        __builtin_amdgcn_sched_barrier(0);
-        load(xa, ya, qc);
-        __builtin_amdgcn_sched_barrier(0);
-        fold(xb, yb, qb);
-        __builtin_amdgcn_sched_barrier(0);
-    }
-    if (g + 1 < ng) {
-        load(xb, yb, base(g + 1));
-        fold(xa, ya, base(g));
-        fold(xb, yb, base(g + 1));
-    } else {
-        fold(xa, ya, base(g));
     }
 }
 

@@ -38,7 +38,7 @@ uint64_t host_ns();
 class Server;
 
 // A cached, uploaded launch: device task table, tile queue, partials, sync
-// words and results, plus (batched mode) an instantiated graph.
+// words and results.
 struct Plan {
     uint64_t hash = 0;
     int kind = 0; // 0 reduce/map_partition, 1 map, 2/3 array reduce (table/rows)
@@ -61,8 +61,6 @@ struct Plan {
     std::vector<uint32_t> variants;
     uint32_t grid = 0;
     LaunchOut out{};
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
 
     // kinds 2 and 3, array-valued ReduceCL: the leaves (a pointer table, or
     // rows of one buffer) and the passes
@@ -81,7 +79,7 @@ struct Plan {
 int get_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
              uint32_t ntasks, sparkcl_result *ures, sparkcl_result *utot,
              hipStream_t stream, Plan **out);
-int enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream);
+int enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream, bool timed);
 void drop_plans(sparkcl_ctx *ctx);
 // Persistent-executor grid for a batch holding the kernels in kid_mask
 // (bit k-1 for kernel id k) and `ntiles` tiles over `ntasks` tasks.
@@ -106,7 +104,6 @@ struct sparkcl_ctx {
 
     std::mutex mu; // plans, events, pinned buffers
     std::list<sparkcl::Plan *> plans; // most recently used first
-    hipStream_t capture_stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool have_ms = false;
     sparkcl_result *pinned = nullptr;

@@ -67,7 +67,7 @@ struct TaskSync {
 static_assert(sizeof(TaskSync) == 16, "TaskSync layout");
 
 // Persistent-executor queue state; every field returns to zero at kernel end
-// so a captured graph can be replayed without clearing it.
+// so the next launch needs no clearing.
 struct BatchCtl {
     uint32_t head;       // next tile to hand out
     uint32_t exited;     // blocks that have left the loop

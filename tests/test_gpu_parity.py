@@ -187,7 +187,7 @@ def test_repeat_is_bit_identical_and_async_matches(ctx, mode):
              for i, k in enumerate([1, 2, 3, 2, 1, 3, 2])]
     d = DevParts(parts)
     first, tot1 = ctx.reduce(d.tasks, mode)
-    for _ in range(3):  # cached plan / graph replay
+    for _ in range(3):  # cached plan, relaunched
         again, tot2 = ctx.reduce(d.tasks, mode)
         assert [r.as_dict() | {"t_start_ns": 0, "t_done_ns": 0} for r in again] == \
                [r.as_dict() | {"t_start_ns": 0, "t_done_ns": 0} for r in first]
