@@ -251,6 +251,23 @@ def bench_array_reduce(ctx, sc, res, reps=20) -> dict:
     return out
 
 
+def bench_selective(ctx, sc, cpu: dict | None) -> dict:
+    """Selective execution: the offload break-even (bytes) against host paths
+    of a few rates, from the GPU's measured fixed offload cost and streaming
+    rate; the oracle's own FMUL rates (8 B per element) when timed."""
+    rates = {"host_1GBps": 1e9, "host_10GBps": 1e10}
+    if cpu:
+        rates["oracle_1_thread"] = 8 * cpu["single_thread_elements_per_s"]
+        rates[f"oracle_{cpu['cores']}_threads"] = 8 * cpu["value"]
+    out = {}
+    try:
+        for name, r in rates.items():
+            out[name] = {"host_bytes_per_s": r, "breakeven_bytes": ctx.offload_breakeven(r)}
+    except sc.SparkclError as e:  # needs 256 MiB of free arena
+        out["error"] = str(e)
+    return out
+
+
 def bench_uneven(ctx, sc, steps=5) -> dict:
     import torch
 
@@ -450,6 +467,8 @@ def main() -> int:
         ex["uneven_batch"] = bench_uneven(ctx, sc)
         log("extras: array-valued reduce ...")
         ex["array_reduce"] = bench_array_reduce(ctx, sc, res)
+        log("extras: selective execution ...")
+        ex["selective_execution"] = bench_selective(ctx, sc, line.get("cpu_baseline"))
         if not args.no_serve:
             for name, per_task in (("resident", False), ("per_task_launch", True)):
                 log(f"extras: serving ({name}) ...")

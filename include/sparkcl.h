@@ -61,6 +61,9 @@ extern "C" {
 #define SPARKCL_ESTOPPED (-7)  /* serving stopped / context being destroyed   */
 #define SPARKCL_ENOMEM (-8)    /* arena exhausted for library workspaces      */
 #define SPARKCL_ENOTFOUND (-9) /* unknown serving ticket                      */
+#define SPARKCL_EDECLINED (-10) /* selective execution: the task is below the
+                                   context's offload threshold and was not
+                                   run; run the host function for it         */
 
 /* ---- registry ---------------------------------------------------------- */
 #define SPARKCL_POLY 1
@@ -116,6 +119,19 @@ typedef struct sparkcl_config {
     const char *tune_cache;     /* JSON tuning cache (tile sizes per kernel
                                    and size bucket, keyed by gfx arch); NULL
                                    -> built-in defaults                      */
+    uint64_t offload_min_bytes; /* selective execution (sec. 3.1.1: the
+                                   kernel may decline accelerated execution
+                                   and mapReturnValue then calls an
+                                   alternative function): a task whose
+                                   offload cost -- bytes read, 4n for POLY,
+                                   8n for FMUL; 4n for MC_PI, whose sample
+                                   costs about as much GPU time as 4 bytes of
+                                   streaming -- is below this is declined:
+                                   not run, result status SPARKCL_EDECLINED
+                                   with sum +0, max -inf, count 0, n 0 (so it
+                                   adds nothing to the RDD total); submit
+                                   returns SPARKCL_EDECLINED.  0 -> never.
+                                   sparkcl_offload_breakeven suggests one.   */
 } sparkcl_config;
 
 /* One partition task: what mapParameters prepares in the paper (Fig 2, Fig 3):
@@ -285,6 +301,17 @@ SPARKCL_API const char *sparkcl_last_error(void);
    sequence on this context, measured with HIP events on the launch stream
    (asynchronous calls are not timed, so they add no event packets). */
 SPARKCL_API int sparkcl_last_kernel_ms(sparkcl_ctx *ctx, float *ms);
+
+/* Selective execution helper: the smallest offload cost (bytes, as defined
+   at sparkcl_config.offload_min_bytes) at which running a task on this GPU
+   beats a host path that processes `host_bytes_per_s`.  The GPU side is
+   measured once per context: the fixed cost of one blocking offload
+   (launch, completion, result copy back) and the streaming rate of a large
+   reduce; then bytes = fixed / (1/host - 1/gpu).  UINT64_MAX if the host
+   path streams at least as fast.  Needs 256 MiB of free arena the first
+   time (ENOMEM otherwise). */
+SPARKCL_API int sparkcl_offload_breakeven(sparkcl_ctx *ctx, double host_bytes_per_s,
+                                          uint64_t *bytes);
 
 /* Library version string. */
 SPARKCL_API const char *sparkcl_version(void);

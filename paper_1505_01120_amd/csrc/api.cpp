@@ -12,6 +12,7 @@
 // (sec. 3, issue 2).
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <string>
 
@@ -76,6 +77,16 @@ int check_task(const sparkcl_task &t, uint32_t *variant)
         *variant = t.out ? V_FMULW : V_FMUL;
     }
     return SPARKCL_OK;
+}
+
+uint64_t offload_cost(const sparkcl_task &t)
+{
+    return t.n * (t.kernel_id == SPARKCL_FMUL ? 8ull : 4ull);
+}
+
+bool declined(const sparkcl_ctx *ctx, const sparkcl_task &t)
+{
+    return ctx->config.offload_min_bytes && offload_cost(t) < ctx->config.offload_min_bytes;
 }
 
 } // namespace sparkcl
@@ -218,9 +229,14 @@ int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
         int rc = check_task(tasks[i], &v);
         if (rc != SPARKCL_OK)
             return fail(rc, "task " + std::to_string(i) + ": " + sparkcl_last_error());
+        // selective execution: a declined task keeps one empty tile, whose
+        // result carries SPARKCL_EDECLINED (maps are never declined)
+        const bool skip = kind == 0 && declined(ctx, tasks[i]);
+        if (skip)
+            v = V_DECLINED;
         p->variants[i] = v;
         const uint32_t T = tile_for(ctx->tuning, tm, tasks[i].kernel_id, tasks[i].n);
-        const uint64_t nt = std::max<uint64_t>(1, (tasks[i].n + T - 1) / T);
+        const uint64_t nt = skip ? 1 : std::max<uint64_t>(1, (tasks[i].n + T - 1) / T);
         if (nt > 0xFFFFFFFFull)
             return fail(SPARKCL_ETOOBIG, "too many tiles in task " + std::to_string(i));
         p->ntiles[i] = (uint32_t)nt;
@@ -295,7 +311,9 @@ int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
             order[i] = i;
             const uint32_t kid = tasks[i].kernel_id;
             const uint64_t w = kid == SPARKCL_POLY ? 4 : kid == SPARKCL_FMUL ? 8 : 5;
-            cost[i] = std::min<uint64_t>(host[i].tile_elems, tasks[i].n) * w;
+            cost[i] = p->variants[i] == V_DECLINED
+                          ? 0
+                          : std::min<uint64_t>(host[i].tile_elems, tasks[i].n) * w;
         }
         std::stable_sort(order.begin(), order.end(),
                          [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
@@ -434,11 +452,11 @@ int sparkcl::enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream, bool timed)
 
 namespace {
 
-int run_blocking(sparkcl_ctx *ctx, int mode, const sparkcl_task *tasks,
-                 uint32_t ntasks, sparkcl_result *per_task, sparkcl_result *total,
-                 hipStream_t stream)
+// The caller holds ctx->mu.
+int run_blocking_locked(sparkcl_ctx *ctx, int mode, const sparkcl_task *tasks,
+                        uint32_t ntasks, sparkcl_result *per_task, sparkcl_result *total,
+                        hipStream_t stream)
 {
-    std::lock_guard<std::mutex> g(ctx->mu);
     Plan *p = nullptr;
     int rc = get_plan(ctx, 0, mode, tasks, ntasks, nullptr, nullptr, stream, &p);
     if (rc != SPARKCL_OK)
@@ -469,6 +487,14 @@ int run_blocking(sparkcl_ctx *ctx, int mode, const sparkcl_task *tasks,
     return SPARKCL_OK;
 }
 
+int run_blocking(sparkcl_ctx *ctx, int mode, const sparkcl_task *tasks,
+                 uint32_t ntasks, sparkcl_result *per_task, sparkcl_result *total,
+                 hipStream_t stream)
+{
+    std::lock_guard<std::mutex> g(ctx->mu);
+    return run_blocking_locked(ctx, mode, tasks, ntasks, per_task, total, stream);
+}
+
 int check_ctx(sparkcl_ctx *ctx)
 {
     if (!ctx)
@@ -496,6 +522,7 @@ const char *sparkcl_strerror(int code)
     case SPARKCL_ESTOPPED: return "stopped";
     case SPARKCL_ENOMEM: return "arena exhausted";
     case SPARKCL_ENOTFOUND: return "unknown ticket";
+    case SPARKCL_EDECLINED: return "declined by selective execution";
     default: return "unknown status";
     }
 }
@@ -927,6 +954,75 @@ int sparkcl_reduce_async(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t n
         SPARKCL_OK)
         return rc;
     return enqueue(ctx, p, s, false);
+}
+
+int sparkcl_offload_breakeven(sparkcl_ctx *ctx, double host_bytes_per_s, uint64_t *bytes)
+{
+    int rc = check_ctx(ctx);
+    if (rc != SPARKCL_OK)
+        return rc;
+    if (!bytes || !(host_bytes_per_s > 0.0))
+        return fail(SPARKCL_EINVAL, "bytes is NULL or the host rate is not positive");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    if (!(ctx->offload_gpu_bps > 0.0)) {
+        // Measured with the threshold off: the fixed cost is the median host
+        // time of a blocking reduce of one element; the streaming rate comes
+        // from a blocking reduce of 2^26 floats (256 MiB) less that cost.
+        constexpr uint64_t kElems = 1ull << 26;
+        const uint64_t off = ctx->arena.alloc(kElems * 4);
+        if (off == Arena::kFail)
+            return fail(SPARKCL_ENOMEM, "offload measurement needs 256 MiB of free arena");
+        float *buf = static_cast<float *>(ctx->dev(off));
+        const uint64_t saved = ctx->config.offload_min_bytes;
+        ctx->config.offload_min_bytes = 0;
+        auto once = [&](uint64_t n, double *sec) -> int {
+            sparkcl_task t;
+            std::memset(&t, 0, sizeof(t));
+            t.kernel_id = SPARKCL_POLY;
+            t.reduce_ops = SPARKCL_SUM;
+            t.n = n;
+            t.in0 = buf;
+            sparkcl_result r;
+            const uint64_t t0 = host_ns();
+            int e = run_blocking_locked(ctx, SPARKCL_BATCHED, &t, 1, &r, nullptr, nullptr);
+            *sec = (double)(host_ns() - t0) * 1e-9;
+            return e;
+        };
+        auto median = [&](uint64_t n, int reps, double *sec) -> int {
+            std::vector<double> v(reps);
+            for (int i = 0; i < reps; ++i) {
+                int e = once(n, &v[i]);
+                if (e != SPARKCL_OK)
+                    return e;
+            }
+            std::sort(v.begin(), v.end());
+            *sec = v[reps / 2];
+            return SPARKCL_OK;
+        };
+        double fixed = 0, big = 0;
+        rc = launch_zero(buf, kElems * 4, nullptr);
+        if (rc == SPARKCL_OK && hipDeviceSynchronize() != hipSuccess)
+            rc = SPARKCL_EHIP;
+        if (rc == SPARKCL_OK)
+            rc = median(1, 15, &fixed);
+        if (rc == SPARKCL_OK)
+            rc = median(kElems, 7, &big);
+        drop_plans(ctx); // the measured plans point into the scratch block
+        ctx->arena.release(off);
+        ctx->config.offload_min_bytes = saved;
+        if (rc != SPARKCL_OK)
+            return fail(rc, std::string("offload measurement failed: ") + sparkcl_last_error());
+        ctx->offload_fixed_s = fixed;
+        ctx->offload_gpu_bps = (double)(kElems * 4) / std::max(big - fixed, 1e-9);
+    }
+    const double inv = 1.0 / host_bytes_per_s - 1.0 / ctx->offload_gpu_bps;
+    if (!(inv > 0.0)) {
+        *bytes = UINT64_MAX;
+        return SPARKCL_OK;
+    }
+    const double b = ctx->offload_fixed_s / inv;
+    *bytes = b >= 1.8e19 ? UINT64_MAX : (uint64_t)std::ceil(b);
+    return SPARKCL_OK;
 }
 
 int sparkcl_submit(sparkcl_ctx *ctx, const sparkcl_task *task, uint64_t *ticket)

@@ -502,12 +502,12 @@ __device__ __forceinline__ Red combine_ordered(uint32_t count, Load load)
 
 __device__ __forceinline__ void write_result(sparkcl_result *dst, uint32_t ops,
                                              const Red &r, uint64_t t_start,
-                                             uint64_t t_done)
+                                             uint64_t t_done, int32_t status = SPARKCL_OK)
 {
     sparkcl_result v;
     v.sum = (ops & SPARKCL_SUM) ? r.s : 0.0;
     v.max = (ops & SPARKCL_MAX) ? r.m : kNegInf;
-    v.status = SPARKCL_OK;
+    v.status = status;
     v.count = (ops & SPARKCL_COUNT) ? r.h : 0;
     v.n = r.n;
     v.t_arrive_ns = 0;
@@ -581,14 +581,14 @@ __device__ __forceinline__ bool run_tile(const TaskDev *__restrict__ tp, uint32_
         FmulMap f{tp->c};
         count = variant == V_FMULW ? tile_map<FmulMap, true>(f, x, y, o, n, T, ntiles, j, a)
                                    : tile_map<FmulMap, false>(f, x, y, o, n, T, ntiles, j, a);
-    } else {
+    } else if (variant == V_MC) {
         const uint64_t begin = (uint64_t)j * T;
         const uint64_t end = min(n, begin + T);
         if (begin < end) {
             tile_mc(uni64(tp->seed), uni(tp->pid), begin, end, a);
             count = end - begin;
         }
-    }
+    } // V_DECLINED: nothing to do; the empty partial leaves the total as is
 
     Red r{a.s, a.m, a.hits, 0};
     r = block_reduce(r);
@@ -625,7 +625,8 @@ __device__ __forceinline__ bool run_tile(const TaskDev *__restrict__ tp, uint32_
     if (threadIdx.x == 0) {
         const uint64_t t_start = ~ld_agent(&sync[idx].t_start);
         write_result(L.results + idx, uni(tp->ops), t, t_start,
-                     device_ns(L.ns_per_tick));
+                     device_ns(L.ns_per_tick),
+                     variant == V_DECLINED ? SPARKCL_EDECLINED : SPARKCL_OK);
         __hip_atomic_store(&sync[idx].t_start, 0ull, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&sync[idx].ticket, 0u, __ATOMIC_RELAXED,

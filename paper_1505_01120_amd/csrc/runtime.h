@@ -31,6 +31,10 @@ int fail_hip(hipError_t e, const char *what);
 
 // Validates one task and derives its kernel body selector.
 int check_task(const sparkcl_task &t, uint32_t *variant);
+// Selective execution: a task's offload cost in bytes, and whether the
+// context's threshold declines it.
+uint64_t offload_cost(const sparkcl_task &t);
+bool declined(const sparkcl_ctx *ctx, const sparkcl_task &t);
 
 // Host steady-clock time in ns.
 uint64_t host_ns();
@@ -106,6 +110,8 @@ struct sparkcl_ctx {
     std::list<sparkcl::Plan *> plans; // most recently used first
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool have_ms = false;
+    double offload_fixed_s = 0.0;   // selective execution: measured fixed
+    double offload_gpu_bps = 0.0;   // cost and streaming rate (0: not yet)
     sparkcl_result *pinned = nullptr;
     uint32_t pinned_cap = 0;
 

@@ -149,6 +149,9 @@ int Server::submit(const sparkcl_task &task, uint64_t *ticket)
     int rc = check_task(task, &variant);
     if (rc != SPARKCL_OK)
         return rc;
+    if (declined(ctx_, task))
+        return fail(SPARKCL_EDECLINED, "offload cost " + std::to_string(offload_cost(task)) +
+                                           " bytes is below the offload threshold");
     const uint32_t tile = tile_for(ctx_->tuning, TM_SERVE, task.kernel_id, task.n);
     const uint64_t nt64 = std::max<uint64_t>(1, (task.n + tile - 1) / tile);
     if (nt64 > tile_cap_)

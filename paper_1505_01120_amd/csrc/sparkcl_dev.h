@@ -23,6 +23,7 @@ enum Variant : uint32_t {
     V_FMUL = 16,  // FMUL, reduce only
     V_FMULW = 17, // FMUL, reduce and write map output
     V_MC = 18,    // MC_PI hit count
+    V_DECLINED = 19, // declined by selective execution: no work, status EDECLINED
     V_COUNT = 19
 };
 

@@ -24,6 +24,7 @@ TUNING_PATH = os.path.join(HERE, "tuning.json")
 
 OK, EINVAL, ENOKERNEL, ETOOBIG, EAGAIN, EHIP, ETIMEDOUT, ESTOPPED, ENOMEM, ENOTFOUND = \
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+EDECLINED = -10
 POLY, FMUL, MC_PI = 1, 2, 3
 SUM, MAX, COUNT = 1, 2, 4
 PER_LAUNCH, BATCHED = 0, 1
@@ -38,7 +39,8 @@ class Config(ctypes.Structure):
                 ("budget_bytes", ctypes.c_uint64),
                 ("exec_blocks_per_cu", ctypes.c_uint32),
                 ("idle_exit_ms", ctypes.c_uint32), ("watchdog_ms", ctypes.c_uint32),
-                ("flags", ctypes.c_uint32), ("tune_cache", ctypes.c_char_p)]
+                ("flags", ctypes.c_uint32), ("tune_cache", ctypes.c_char_p),
+                ("offload_min_bytes", ctypes.c_uint64)]
 
 
 class Task(ctypes.Structure):
@@ -84,7 +86,8 @@ EXPORTS = ("sparkcl_init", "sparkcl_destroy", "sparkcl_map", "sparkcl_map_partit
            "sparkcl_submit", "sparkcl_poll",
            "sparkcl_serve_stats_get", "sparkcl_serve_drain", "sparkcl_get_tuning",
            "sparkcl_set_tuning", "sparkcl_autotune", "sparkcl_strerror",
-           "sparkcl_last_error", "sparkcl_last_kernel_ms", "sparkcl_version")
+           "sparkcl_last_error", "sparkcl_last_kernel_ms", "sparkcl_version",
+           "sparkcl_offload_breakeven")
 
 
 class SparkclError(RuntimeError):
@@ -130,6 +133,7 @@ def load() -> ctypes.CDLL:
             "sparkcl_last_error": ([], ctypes.c_char_p),
             "sparkcl_last_kernel_ms": ([P, ctypes.POINTER(ctypes.c_float)], I32),
             "sparkcl_version": ([], ctypes.c_char_p),
+            "sparkcl_offload_breakeven": ([P, ctypes.c_double, ctypes.POINTER(U64)], I32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -190,7 +194,7 @@ class Context:
     def __init__(self, device: int = 0, arena_bytes: int = 1 << 30, budget_bytes: int = 0,
                  ring_capacity: int = 0, flags: int = 0, tune_cache: str | None = TUNING_PATH,
                  idle_exit_ms: int = 0, watchdog_ms: int = 0, exec_blocks_per_cu: int = 0,
-                 arena=None):
+                 arena=None, offload_min_bytes: int = 0):
         import torch
         L = load()
         self.device = device
@@ -208,6 +212,7 @@ class Context:
         cfg.flags = flags
         self._tune = tune_cache.encode() if tune_cache and os.path.exists(tune_cache) else None
         cfg.tune_cache = self._tune
+        cfg.offload_min_bytes = offload_min_bytes
         h = ctypes.c_void_p()
         _check(L.sparkcl_init(ctypes.byref(cfg), ctypes.byref(h)), "sparkcl_init")
         self._h = h
@@ -320,6 +325,14 @@ class Context:
     def autotune(self, lo_log2: int = 10, hi_log2: int = 22, path: str | None = None) -> None:
         _check(load().sparkcl_autotune(self._h, lo_log2, hi_log2,
                                        path.encode() if path else None), "sparkcl_autotune")
+
+    def offload_breakeven(self, host_bytes_per_s: float) -> int:
+        """Smallest offload cost (bytes) at which this GPU beats a host path of
+        the given throughput (selective execution threshold)."""
+        v = ctypes.c_uint64()
+        _check(load().sparkcl_offload_breakeven(self._h, float(host_bytes_per_s), ctypes.byref(v)),
+               "sparkcl_offload_breakeven")
+        return v.value
 
     def last_kernel_ms(self) -> float:
         v = ctypes.c_float()
