@@ -251,6 +251,45 @@ def bench_array_reduce(ctx, sc, res, reps=20) -> dict:
     return out
 
 
+def bench_host_input(ctx, sc, res, reps=3) -> dict:
+    """Host-resident partitions: the 64 x 2^22 FMUL RDD in pinned host memory,
+    streamed through the staging ring (PCIe-inclusive), against a plain
+    host-to-device copy of the same 2 GiB (the PCIe ceiling)."""
+    import torch
+    n, parts = res.n, res.parts
+    hx = torch.empty(parts * n, dtype=torch.float32).pin_memory()
+    hy = torch.empty(parts * n, dtype=torch.float32).pin_memory()
+    hx.copy_(res.x)
+    hy.copy_(res.y)
+    tasks = [sc.task(sc.FMUL, n, hx[p * n:(p + 1) * n], hy[p * n:(p + 1) * n],
+                     ops=sc.SUM | sc.MAX, c=0.1, host=True) for p in range(parts)]
+    s = torch.cuda.current_stream()
+    dres = torch.empty(64 * parts, dtype=torch.uint8, device="cuda")
+    ctx.reduce_async(tasks, sc.PER_LAUNCH, dres, stream=s)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        ctx.reduce_async(tasks, sc.PER_LAUNCH, dres, stream=s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    dx = torch.empty_like(res.x)
+    e0.record(s)
+    for _ in range(reps):
+        dx.copy_(hx, non_blocking=True)
+        dx.copy_(hy, non_blocking=True)
+    e1.record(s)
+    torch.cuda.synchronize()
+    copy_ms = e0.elapsed_time(e1) / reps
+    nbytes = 8 * parts * n
+    del dx
+    return {"ms": ms, "elements_per_s": parts * n / (ms / 1e3),
+            "pcie_GBps": nbytes / (ms / 1e3) / 1e9,
+            "copy_only_ms": copy_ms, "copy_only_GBps": nbytes / (copy_ms / 1e3) / 1e9,
+            "frac_of_copy": copy_ms / ms}
+
+
 def bench_selective(ctx, sc, cpu: dict | None) -> dict:
     """Selective execution: the offload break-even (bytes) against host paths
     of a few rates, from the GPU's measured fixed offload cost and streaming
@@ -467,6 +506,8 @@ def main() -> int:
         ex["uneven_batch"] = bench_uneven(ctx, sc)
         log("extras: array-valued reduce ...")
         ex["array_reduce"] = bench_array_reduce(ctx, sc, res)
+        log("extras: host-resident partitions ...")
+        ex["host_input"] = bench_host_input(ctx, sc, res)
         log("extras: selective execution ...")
         ex["selective_execution"] = bench_selective(ctx, sc, line.get("cpu_baseline"))
         if not args.no_serve:

@@ -148,8 +148,22 @@ typedef struct sparkcl_task {
     uint32_t degree;       /* POLY: 0..7                                     */
     float coef[8];         /* POLY: coef[k] multiplies x^k                   */
     float c;               /* FMUL constant                                  */
-    uint32_t reserved;     /* 0                                              */
+    uint32_t flags;        /* SPARKCL_TASK_* bits; 0 for device inputs       */
 } sparkcl_task;
+
+/* sparkcl_task.flags: in0 / in1 are HOST arrays (POLY, FMUL; out must be
+   NULL).  sparkcl_reduce / sparkcl_reduce_async then stream the partitions
+   through a ring of device staging slots in the arena: the host-to-device
+   copy of partition i+1 (on the library's copy stream) overlaps the kernel of
+   partition i, each partition one kernel launch cut by the per-launch tile
+   table, whatever `mode` says.  A call's tasks are all host or all device.
+   Host arrays must stay valid until the call's results are ready; pinned
+   memory (hipHostMalloc) overlaps, pageable memory works but copies
+   synchronously.  Each partition's input bytes must fit one staging slot
+   (ETOOBIG beyond 1 GiB).  Results are bit-identical to the same data
+   reduced from device memory in SPARKCL_PER_LAUNCH mode.  Serving takes
+   device inputs only (EINVAL). */
+#define SPARKCL_TASK_HOST_INPUT 1u
 
 /* What mapReturnValue hands back for one partition (or the RDD total). */
 typedef struct sparkcl_result {

@@ -26,6 +26,7 @@ namespace sparkcl {
 namespace {
 thread_local std::string t_last_error;
 constexpr uint32_t kMaxPlans = 32;
+constexpr uint32_t kStagingSlots = 3; // host-input partitions in flight
 constexpr uint64_t kMaxN = 1ull << 40;
 } // namespace
 
@@ -55,6 +56,14 @@ int check_task(const sparkcl_task &t, uint32_t *variant)
     if (t.n > kMaxN)
         return fail(SPARKCL_ETOOBIG, "partition of " + std::to_string(t.n) +
                                          " elements exceeds 2^40");
+    if (t.flags & ~SPARKCL_TASK_HOST_INPUT)
+        return fail(SPARKCL_EINVAL, "unknown task flags");
+    if (t.flags & SPARKCL_TASK_HOST_INPUT) {
+        if (t.kernel_id == SPARKCL_MC_PI)
+            return fail(SPARKCL_EINVAL, "MC_PI has no input arrays to stream from the host");
+        if (t.out)
+            return fail(SPARKCL_EINVAL, "host-input tasks take out == NULL");
+    }
     if (t.kernel_id == SPARKCL_MC_PI) {
         if (t.reduce_ops != SPARKCL_COUNT)
             return fail(SPARKCL_EINVAL, "MC_PI takes reduce_ops == SPARKCL_COUNT");
@@ -122,6 +131,14 @@ uint64_t plan_hash(int kind, int mode, const sparkcl_task *tasks, uint32_t ntask
 
 void free_plan(sparkcl_ctx *ctx, Plan *p)
 {
+    for (hipEvent_t e : p->ev_copied)
+        if (e)
+            (void)hipEventDestroy(e);
+    for (hipEvent_t e : p->ev_done)
+        if (e)
+            (void)hipEventDestroy(e);
+    if (p->ev_start)
+        (void)hipEventDestroy(p->ev_start);
     for (uint64_t off : p->blocks)
         ctx->arena.release(off);
     delete p;
@@ -202,13 +219,22 @@ int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
     p->ntiles.resize(ntasks);
     p->variants.resize(ntasks);
 
+    // Host-input partitions (all or none of the call's tasks) are streamed
+    // through staging slots, one per-launch kernel each.
+    const bool host_in = kind == 0 && ntasks > 0 && (tasks[0].flags & SPARKCL_TASK_HOST_INPUT);
+    for (uint32_t i = 0; i < ntasks; ++i)
+        if (((tasks[i].flags & SPARKCL_TASK_HOST_INPUT) != 0) != host_in)
+            return fail(SPARKCL_EINVAL, kind == 0 ? "a call's tasks must be all host-input or all device-input"
+                                                  : "maps take device arrays");
+    p->host = host_in;
+
     // Tile table: the batched one, unless the batch would then have fewer
     // tiles than the executor has blocks (a batch of one or a few partitions,
     // where the batched table's large tiles would leave most of the GPU
     // idle); such a batch is cut with the per-launch table instead.  The
     // choice is a function of the call, so a repeated call is cut the same way.
-    int tm = mode == SPARKCL_BATCHED ? TM_BATCHED : TM_PER_LAUNCH;
-    if (mode == SPARKCL_BATCHED) {
+    int tm = mode == SPARKCL_BATCHED && !host_in ? TM_BATCHED : TM_PER_LAUNCH;
+    if (tm == TM_BATCHED) {
         uint64_t tiles = 0;
         uint32_t mask = 0;
         for (uint32_t i = 0; i < ntasks; ++i) {
@@ -266,8 +292,24 @@ int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
         ALLOC(dctl, sizeof(BatchCtl));
         ALLOC(dresults, sizeof(sparkcl_result) * ntasks);
         ALLOC(dtotal, sizeof(sparkcl_result));
-        if (mode == SPARKCL_BATCHED)
+        if (mode == SPARKCL_BATCHED && !host_in)
             ALLOC(dtiles, sizeof(TileRef) * total_tiles);
+    }
+    if (host_in) {
+        // Staging ring: each slot holds one partition's x and y, each placed
+        // at the host array's offset modulo 16 bytes so the kernel sees the
+        // same quad alignment (and cuts the same tiles) as on the host.
+        uint64_t slot = 256;
+        for (uint32_t i = 0; i < ntasks; ++i) {
+            const uint64_t xb = (tasks[i].n * 4 + 16 + 255) / 256 * 256;
+            const uint64_t yb = tasks[i].kernel_id == SPARKCL_FMUL ? xb : 0;
+            slot = std::max(slot, xb + yb);
+        }
+        if (slot > (1ull << 30))
+            return fail(SPARKCL_ETOOBIG, "a host-input partition exceeds the 1 GiB staging slot");
+        p->nslots = std::min<uint32_t>(ntasks, kStagingSlots);
+        p->slot_bytes = slot;
+        ALLOC(staging, slot * p->nslots);
     }
 #undef ALLOC
 
@@ -291,6 +333,14 @@ int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
         d.ntiles = p->ntiles[i];
         d.index = i;
         d.partials = p->dparts ? p->dparts + first[i] : nullptr;
+        if (host_in) {
+            char *base = p->staging + (uint64_t)(i % p->nslots) * p->slot_bytes;
+            d.in0 = reinterpret_cast<const float *>(base + ((uintptr_t)t.in0 & 15u));
+            const uint64_t xb = (t.n * 4 + 16 + 255) / 256 * 256;
+            d.in1 = t.kernel_id == SPARKCL_FMUL
+                        ? reinterpret_cast<const float *>(base + xb + ((uintptr_t)t.in1 & 15u))
+                        : nullptr;
+        }
     }
     hipError_t e = hipMemcpyAsync(p->dtasks, host.data(), sizeof(TaskDev) * ntasks,
                                   hipMemcpyHostToDevice, stream);
@@ -345,6 +395,21 @@ int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
         p->out.ntasks = ntasks;
         p->out.ns_per_tick = ctx->ns_per_tick;
         p->grid = std::min(exec_grid(ctx, kid_mask, p->ntiles_total, ntasks), p->ntiles_total);
+    }
+    if (host_in) {
+        p->ev_copied.assign(p->nslots, nullptr);
+        p->ev_done.assign(p->nslots, nullptr);
+        hipError_t ee = hipEventCreateWithFlags(&p->ev_start, hipEventDisableTiming);
+        for (uint32_t k = 0; k < p->nslots && ee == hipSuccess; ++k) {
+            ee = hipEventCreateWithFlags(&p->ev_copied[k], hipEventDisableTiming);
+            if (ee == hipSuccess)
+                ee = hipEventCreateWithFlags(&p->ev_done[k], hipEventDisableTiming);
+        }
+        if (ee != hipSuccess) {
+            Plan *raw = p.release();
+            free_plan(ctx, raw);
+            return fail_hip(ee, "staging events");
+        }
     }
     p->hash = plan_hash(kind, mode, tasks, ntasks, ures, utot);
     *out = p.release();
@@ -425,7 +490,41 @@ int sparkcl::enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream, bool timed)
     // autotuner ask for them; asynchronous calls enqueue the kernels alone.
     if (timed)
         SPARKCL_HIP(hipEventRecord(ctx->ev0, stream));
-    if (p->mode == SPARKCL_BATCHED) {
+    if (p->host) {
+        // Staged pipeline: partition i is copied into slot i mod S on the copy
+        // stream once the kernel that last used the slot is done, and its
+        // kernel runs on `stream` once the copy is done.  The first copies
+        // wait for everything already queued on `stream` (an earlier launch
+        // of this plan may still read the slots).
+        hipStream_t cs = ctx->copy_stream;
+        SPARKCL_HIP(hipEventRecord(p->ev_start, stream));
+        SPARKCL_HIP(hipStreamWaitEvent(cs, p->ev_start, 0));
+        for (uint32_t i = 0; i < p->ntasks; ++i) {
+            const sparkcl_task &t = p->tasks[i];
+            const uint32_t k = i % p->nslots;
+            if (i >= p->nslots)
+                SPARKCL_HIP(hipStreamWaitEvent(cs, p->ev_done[k], 0));
+            char *base = p->staging + (uint64_t)k * p->slot_bytes;
+            if (t.n) {
+                SPARKCL_HIP(hipMemcpyAsync(base + ((uintptr_t)t.in0 & 15u), t.in0, t.n * 4,
+                                           hipMemcpyHostToDevice, cs));
+                if (t.kernel_id == SPARKCL_FMUL) {
+                    const uint64_t xb = (t.n * 4 + 16 + 255) / 256 * 256;
+                    SPARKCL_HIP(hipMemcpyAsync(base + xb + ((uintptr_t)t.in1 & 15u), t.in1,
+                                               t.n * 4, hipMemcpyHostToDevice, cs));
+                }
+            }
+            SPARKCL_HIP(hipEventRecord(p->ev_copied[k], cs));
+            SPARKCL_HIP(hipStreamWaitEvent(stream, p->ev_copied[k], 0));
+            const uint32_t cap = exec_grid(ctx, 1u << (t.kernel_id - 1));
+            int rc = launch_task(p->dtasks + i, p->ntiles[i], std::min(cap, p->ntiles[i]),
+                                 p->out, stream);
+            if (rc != SPARKCL_OK)
+                return fail(rc, "kernel launch failed: " +
+                                    std::string(hipGetErrorString(hipGetLastError())));
+            SPARKCL_HIP(hipEventRecord(p->ev_done[k], stream));
+        }
+    } else if (p->mode == SPARKCL_BATCHED) {
         // One dispatch of the persistent executor: the cached plan holds the
         // uploaded task table and tile queue, and the kernel leaves its queue
         // head and tickets at zero, so nothing is cleared between launches.
@@ -595,6 +694,7 @@ int sparkcl_init(const sparkcl_config *config, sparkcl_ctx **out)
     ctx->arena.reset(arena_bytes);
     SPARKCL_HIP(hipEventCreate(&ctx->ev0));
     SPARKCL_HIP(hipEventCreate(&ctx->ev1));
+    SPARKCL_HIP(hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking));
     if ((rc = ensure_pinned(ctx.get(), 1024)) != SPARKCL_OK)
         return rc;
     rc = Server::create(ctx.get(), &ctx->server);
@@ -623,6 +723,8 @@ int sparkcl_destroy(sparkcl_ctx *ctx)
         (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1)
         (void)hipEventDestroy(ctx->ev1);
+    if (ctx->copy_stream)
+        (void)hipStreamDestroy(ctx->copy_stream);
     if (ctx->own_arena)
         (void)hipFree(ctx->arena_base);
     delete ctx;

@@ -696,8 +696,8 @@ __global__ __launch_bounds__(kBlock) void k_task(const TaskDev *__restrict__ tas
 // Persistent executor: a fixed grid of blocks takes tiles from the queue with
 // one atomic each until the queue is empty; thread 0 asks for the next tile
 // while the current one streams, so the queue round trip is hidden.  The last
-// block to leave resets the queue head, so the launch can be replayed from a
-// graph as is.
+// block to leave resets the queue head, so the next launch of the same plan
+// needs no clearing.
 __global__ __launch_bounds__(kBlock) void k_batch(const TaskDev *__restrict__ tasks,
                                                   const TileRef *__restrict__ tiles,
                                                   uint32_t ntiles, LaunchOut L)

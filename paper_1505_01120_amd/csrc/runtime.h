@@ -77,6 +77,14 @@ struct Plan {
     uint64_t leaf_stride = 0;
     std::vector<const float *> leaves;
     std::vector<TreeArgs> passes;
+
+    // host-input partitions: the staging ring and its events
+    bool host = false;
+    uint32_t nslots = 0;
+    uint64_t slot_bytes = 0;
+    char *staging = nullptr;
+    hipEvent_t ev_start = nullptr;
+    std::vector<hipEvent_t> ev_copied, ev_done;
 };
 
 // Plan cache and launch helpers (api.cpp); the caller holds ctx->mu.
@@ -109,6 +117,7 @@ struct sparkcl_ctx {
     std::mutex mu; // plans, events, pinned buffers
     std::list<sparkcl::Plan *> plans; // most recently used first
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipStream_t copy_stream = nullptr; // host-input staging copies
     bool have_ms = false;
     double offload_fixed_s = 0.0;   // selective execution: measured fixed
     double offload_gpu_bps = 0.0;   // cost and streaming rate (0: not yet)

@@ -149,6 +149,8 @@ int Server::submit(const sparkcl_task &task, uint64_t *ticket)
     int rc = check_task(task, &variant);
     if (rc != SPARKCL_OK)
         return rc;
+    if (task.flags & SPARKCL_TASK_HOST_INPUT)
+        return fail(SPARKCL_EINVAL, "serving takes device-resident inputs");
     if (declined(ctx_, task))
         return fail(SPARKCL_EDECLINED, "offload cost " + std::to_string(offload_cost(task)) +
                                            " bytes is below the offload threshold");

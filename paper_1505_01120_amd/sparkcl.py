@@ -29,6 +29,7 @@ POLY, FMUL, MC_PI = 1, 2, 3
 SUM, MAX, COUNT = 1, 2, 4
 PER_LAUNCH, BATCHED = 0, 1
 VADD, VMAX = 1, 2
+TASK_HOST_INPUT = 1
 FLAG_SERVE_PER_TASK = 1
 TUNE_BUCKETS, TUNE_MODES = 32, 3
 
@@ -49,7 +50,7 @@ class Task(ctypes.Structure):
                 ("in1", ctypes.c_void_p), ("out", ctypes.c_void_p),
                 ("seed", ctypes.c_uint64), ("partition_id", ctypes.c_uint32),
                 ("degree", ctypes.c_uint32), ("coef", ctypes.c_float * 8),
-                ("c", ctypes.c_float), ("reserved", ctypes.c_uint32)]
+                ("c", ctypes.c_float), ("flags", ctypes.c_uint32)]
 
 
 class Result(ctypes.Structure):
@@ -156,13 +157,19 @@ def _ptr(t) -> int | None:
         return None
     if isinstance(t, int):
         return t
-    return t.data_ptr()
+    if hasattr(t, "data_ptr"):
+        return t.data_ptr()
+    return t.ctypes.data  # numpy array
 
 
 def task(kernel_id: int, n: int, x=None, y=None, out=None, ops: int | None = None,
-         seed: int = 0, pid: int = 0, coef: Sequence[float] = (), c: float = 0.1) -> Task:
-    """A partition task; x / y / out are device tensors (or raw device addresses)."""
+         seed: int = 0, pid: int = 0, coef: Sequence[float] = (), c: float = 0.1,
+         host: bool = False) -> Task:
+    """A partition task; x / y / out are device tensors (or raw device
+    addresses).  host=True: x / y are host arrays (CPU tensors, preferably
+    pinned, numpy arrays or raw host addresses) streamed by the library."""
     t = Task()
+    t.flags = TASK_HOST_INPUT if host else 0
     t.kernel_id = kernel_id
     t.reduce_ops = ops if ops is not None else (COUNT if kernel_id == MC_PI else SUM | MAX)
     t.n = n
