@@ -290,6 +290,46 @@ def bench_host_input(ctx, sc, res, reps=3) -> dict:
             "frac_of_copy": copy_ms / ms}
 
 
+def bench_wordcount(ctx, sc, reps=5) -> dict:
+    """WordCount (sec. 3.2.3) over 1 GiB of device text: a 64 MiB Zipf corpus
+    (vocabulary 10^5, s = 1, ending in a newline) repeated 16 times.  Checked
+    against the oracle on the 64 MiB base (every count times 16); the oracle's
+    single-thread rate on the base is the CPU baseline."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import oracle
+    base_n, rep = 64 << 20, 16
+    base = datagen.corpus(base_n - 1, vocab=100_000)
+    base = np.concatenate([base, np.frombuffer(b"\n", dtype=np.uint8)])
+    text = torch.from_numpy(base).cuda().repeat(rep)
+    cap = 1 << 20
+    keys = torch.empty(cap, dtype=torch.int64, device="cuda")
+    counts = torch.empty(cap, dtype=torch.int64, device="cuda")
+    ctx.wordcount(text, cap, keys, counts)           # warm-up
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        _, _, nd, nw = ctx.wordcount(text, cap, keys, counts)
+        times.append(time.perf_counter() - t0)
+    sec = sorted(times)[len(times) // 2]
+    t0 = time.perf_counter()
+    ok, oc, on = oracle.wordcount(base)
+    cpu_sec = time.perf_counter() - t0
+    k = keys[:nd].cpu().numpy().view(np.uint64)
+    c = counts[:nd].cpu().numpy().view(np.uint64)
+    order = np.argsort(k)
+    exact = bool(nw == rep * on and np.array_equal(k[order], ok) and
+                 np.array_equal(c[order], oc * np.uint64(rep)))
+    nbytes = base_n * rep
+    return {"ms": sec * 1e3, "GBps": nbytes / sec / 1e9, "words_per_s": nw / sec,
+            "hbm_frac": nbytes / sec / 1e9 / HBM_PEAK_GBS, "words": nw, "distinct": nd,
+            "matches_oracle": exact, "timing": "host-observed blocking call, median of 5",
+            "cpu_baseline": {"GBps": base_n / cpu_sec / 1e9, "cores": 1, "kind": "oracle",
+                             "sample": "the 64 MiB base corpus, one thread"}}
+
+
 def bench_selective(ctx, sc, cpu: dict | None) -> dict:
     """Selective execution: the offload break-even (bytes) against host paths
     of a few rates, from the GPU's measured fixed offload cost and streaming
@@ -508,6 +548,8 @@ def main() -> int:
         ex["array_reduce"] = bench_array_reduce(ctx, sc, res)
         log("extras: host-resident partitions ...")
         ex["host_input"] = bench_host_input(ctx, sc, res)
+        log("extras: word count ...")
+        ex["wordcount"] = bench_wordcount(ctx, sc)
         log("extras: selective execution ...")
         ex["selective_execution"] = bench_selective(ctx, sc, line.get("cpu_baseline"))
         if not args.no_serve:

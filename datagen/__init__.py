@@ -61,6 +61,10 @@ def _L() -> ctypes.CDLL:
                                        ctypes.c_uint64, ctypes.c_uint32,
                                        ctypes.c_uint32, ctypes.c_int, ctypes.c_int]
             L.datagen_fill.restype = ctypes.c_int
+            L.datagen_fill_at.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
+                                          ctypes.c_uint64, ctypes.c_uint32,
+                                          ctypes.c_uint32, ctypes.c_int, ctypes.c_int]
+            L.datagen_fill_at.restype = ctypes.c_int
             _lib = L
     return _lib
 
@@ -70,13 +74,15 @@ def _threads() -> int:
 
 
 def fill(n: int, seed: int, pid: int, tag: int, dist: int,
-         out: np.ndarray | None = None) -> np.ndarray:
-    """n draws of stream (seed, pid, tag) in distribution `dist`."""
+         out: np.ndarray | None = None, first: int = 0) -> np.ndarray:
+    """Draws first .. first + n - 1 of stream (seed, pid, tag) in
+    distribution `dist`."""
     if out is None:
         out = np.empty(n, _DTYPE[dist])
     assert out.dtype == _DTYPE[dist] and out.flags.c_contiguous and out.size == n
     if n:
-        rc = _L().datagen_fill(out.ctypes.data, n, seed, pid, tag, dist, _threads())
+        rc = _L().datagen_fill_at(out.ctypes.data, first, n, seed, pid, tag, dist,
+                                  _threads())
         if rc != 0:
             raise ValueError("datagen: bad distribution")
     return out
@@ -199,3 +205,51 @@ def serving_trace(count: int, rate: float = 20000.0, median: int = 65536,
         room = np.maximum(pool - sizes, 0).astype(np.uint64) + np.uint64(1)
         offs = ((w % room) // np.uint64(64) * np.uint64(64)).astype(np.int64)
     return Trace(t, sizes, kids, offs)
+
+
+# --- WordCount corpus ----------------------------------------------------------
+
+def vocabulary(size: int, seed: int = 0, max_len: int = 12) -> list[bytes]:
+    """`size` synthetic words of lowercase letters, lengths uniform on
+    [1, max_len] (stream tag 9) and letters uniform on a..z (tag 10, 16
+    draws per word)."""
+    lens = 1 + (fill(size, seed, 0, 9, WORDS) % np.uint64(max_len)).astype(np.int64)
+    letters = (fill(size * 16, seed, 0, 10, WORDS) % np.uint64(26)).astype(np.uint8) + ord("a")
+    letters = letters.reshape(size, 16)
+    return [letters[i, :lens[i]].tobytes() for i in range(size)]
+
+
+def corpus(nbytes: int, vocab: int = 100_000, zipf_s: float = 1.0, seed: int = 0,
+           newline_every: int = 16, chunk_words: int = 1 << 22) -> np.ndarray:
+    """A synthetic text of exactly `nbytes` bytes: words drawn from a Zipf(s)
+    law over the vocabulary's ranks (uniforms from stream (seed, 1, 11)), each
+    followed by a space, or by a newline with probability 1/newline_every
+    (stream (seed, 1, 12)); the last word may be cut at the end.  The bytes
+    do not depend on chunk_words.  Returned as a uint8 array."""
+    words = vocabulary(vocab, seed)
+    wlen = np.array([len(w) for w in words], dtype=np.int64)
+    flat = np.frombuffer(b"".join(words), dtype=np.uint8)
+    woff = np.concatenate(([0], np.cumsum(wlen)[:-1]))
+    weights = np.arange(1, vocab + 1, dtype=np.float64) ** -zipf_s
+    cdf = np.cumsum(weights)
+    cdf /= cdf[-1]
+    out = np.empty(nbytes, dtype=np.uint8)
+    pos, first = 0, 0
+    while pos < nbytes:
+        # a token is at least 2 bytes, so this many words always suffice
+        m = int(min(chunk_words, (nbytes - pos) // 2 + 1))
+        u = fill(m, seed, 1, 11, U01_64, first=first)
+        sep = fill(m, seed, 1, 12, WORDS, first=first)
+        ranks = np.minimum(np.searchsorted(cdf, u, side="right"), vocab - 1)
+        tl = wlen[ranks] + 1                       # word and its separator
+        ends = np.cumsum(tl)
+        starts = ends - tl
+        idx = np.repeat(woff[ranks] - starts, tl) + np.arange(ends[-1])
+        tok = flat[np.minimum(idx, flat.size - 1)]
+        sepc = np.where(sep % np.uint64(newline_every) == 0, ord("\n"), ord(" ")).astype(np.uint8)
+        tok[ends - 1] = sepc
+        take = min(tok.size, nbytes - pos)
+        out[pos:pos + take] = tok[:take]
+        pos += take
+        first += m
+    return out

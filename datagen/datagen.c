@@ -58,14 +58,14 @@ static double normal_from(uint64_t w)
 
 typedef struct {
     void *out;
-    uint64_t begin, end, key;
+    uint64_t begin, end, key, first;
     int dist;
 } job;
 
 static void fill_range(const job *j)
 {
     for (uint64_t i = j->begin; i < j->end; ++i) {
-        uint64_t w = word(j->key, i);
+        uint64_t w = word(j->key, j->first + i);
         switch (j->dist) {
         case DIST_WORDS:
             ((uint64_t *)j->out)[i] = w;
@@ -98,10 +98,11 @@ static void *fill_thread(void *arg)
     return NULL;
 }
 
-/* Fill out[0..n) with stream (seed, pid, tag) in distribution `dist`, using
- * up to `nthreads` threads.  Returns 0, or -1 for an unknown distribution. */
-int datagen_fill(void *out, uint64_t n, uint64_t seed, uint32_t pid,
-                 uint32_t tag, int dist, int nthreads)
+/* Fill out[0..n) with draws first .. first + n - 1 of stream (seed, pid,
+ * tag) in distribution `dist`, using up to `nthreads` threads.  Returns 0, or
+ * -1 for an unknown distribution. */
+int datagen_fill_at(void *out, uint64_t first, uint64_t n, uint64_t seed,
+                    uint32_t pid, uint32_t tag, int dist, int nthreads)
 {
     if (dist < DIST_WORDS || dist > DIST_U01_64)
         return -1;
@@ -122,7 +123,7 @@ int datagen_fill(void *out, uint64_t n, uint64_t seed, uint32_t pid,
             b = n;
         if (e > n)
             e = n;
-        jobs[t] = (job){out, b, e, key, dist};
+        jobs[t] = (job){out, b, e, key, first, dist};
         if (t > 0)
             running[t] = pthread_create(&th[t], NULL, fill_thread, &jobs[t]) == 0;
     }
@@ -134,4 +135,11 @@ int datagen_fill(void *out, uint64_t n, uint64_t seed, uint32_t pid,
             fill_range(&jobs[t]); /* thread could not start: fill here */
     }
     return 0;
+}
+
+/* Fill out[0..n) with the first n draws of stream (seed, pid, tag). */
+int datagen_fill(void *out, uint64_t n, uint64_t seed, uint32_t pid,
+                 uint32_t tag, int dist, int nthreads)
+{
+    return datagen_fill_at(out, 0, n, seed, pid, tag, dist, nthreads);
 }

@@ -316,6 +316,20 @@ SPARKCL_API const char *sparkcl_last_error(void);
    (asynchronous calls are not timed, so they add no event packets). */
 SPARKCL_API int sparkcl_last_kernel_ms(sparkcl_ctx *ctx, float *ms);
 
+/* WordCount (sec. 3.2.3, the Spark word-count demo as a SparkCL kernel) over
+   `nbytes` bytes of device text: a word is a maximal run of bytes that are
+   not ASCII whitespace (space, tab, LF, VT, FF, CR), counted under the 64-bit
+   FNV-1a hash of its bytes.  The distinct keys and their counts go to
+   keys[] / counts[] (device arrays of `capacity` entries, caller-owned), in no
+   particular order; *ndistinct and *nwords (host) receive the number of
+   distinct keys and of words.  Blocking.  The counting table comes from the
+   arena (16 B per slot, two slots per key of capacity, at least 1024):
+   ENOMEM if it does not fit; ETOOBIG if there are more distinct keys than
+   `capacity` (*ndistinct is then at least capacity + 1). */
+SPARKCL_API int sparkcl_wordcount(sparkcl_ctx *ctx, const uint8_t *text, uint64_t nbytes,
+                                  uint64_t *keys, uint64_t *counts, uint64_t capacity,
+                                  uint64_t *ndistinct, uint64_t *nwords, void *stream);
+
 /* Selective execution helper: the smallest offload cost (bytes, as defined
    at sparkcl_config.offload_min_bytes) at which running a task on this GPU
    beats a host path that processes `host_bytes_per_s`.  The GPU side is

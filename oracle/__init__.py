@@ -83,6 +83,11 @@ def lib() -> ctypes.CDLL:
             L.oracle_task_run.restype = ctypes.c_int
             L.oracle_tree_reduce_arrays.argtypes = [U32, P, U32, U64, P]
             L.oracle_tree_reduce_arrays.restype = ctypes.c_int
+            L.oracle_fnv1a64.argtypes = [P, U64]
+            L.oracle_fnv1a64.restype = U64
+            L.oracle_wordcount.argtypes = [P, U64, P, P, U64, ctypes.POINTER(U64),
+                                           ctypes.POINTER(U64)]
+            L.oracle_wordcount.restype = ctypes.c_int
             L.oracle_rdd_total.argtypes = [ctypes.POINTER(Result), U64, U32,
                                            ctypes.POINTER(Result)]
             _lib = L
@@ -209,3 +214,24 @@ def tree_reduce_arrays(arrays, combiner: int = VADD) -> np.ndarray:
     if rc != 0:
         raise ValueError(f"oracle_tree_reduce_arrays rejected combiner {combiner}")
     return out
+
+
+def fnv1a64(b: bytes) -> int:
+    """O10's word key: 64-bit FNV-1a of the bytes."""
+    buf = np.frombuffer(bytes(b), dtype=np.uint8)
+    return int(lib().oracle_fnv1a64(_ptr(buf) if buf.size else None, buf.size))
+
+
+def wordcount(text) -> tuple[np.ndarray, np.ndarray, int]:
+    """O10: (keys ascending, counts, total words) of a byte string or uint8 array."""
+    t = np.frombuffer(text, dtype=np.uint8) if isinstance(text, (bytes, bytearray)) \
+        else np.ascontiguousarray(text, dtype=np.uint8)
+    cap = max(1, t.size // 2 + 1)
+    keys = np.empty(cap, dtype=np.uint64)
+    counts = np.empty(cap, dtype=np.uint64)
+    nd, nw = ctypes.c_uint64(), ctypes.c_uint64()
+    rc = lib().oracle_wordcount(_ptr(t) if t.size else None, t.size, _ptr(keys), _ptr(counts),
+                                cap, ctypes.byref(nd), ctypes.byref(nw))
+    if rc != 0:
+        raise MemoryError("oracle_wordcount failed")
+    return keys[:nd.value].copy(), counts[:nd.value].copy(), nw.value

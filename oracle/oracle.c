@@ -268,3 +268,77 @@ int oracle_tree_reduce_arrays(uint32_t combiner, const float *const *arrays,
         out[i] = tree_at(combiner, arrays, 0, k, i);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* O10 WordCount (sec. 3.2.3).  Tokenise in byte order, hash each word with
+ * 64-bit FNV-1a (offset basis 14695981039346656037, prime 1099511628211:
+ * for each byte, xor it in, then multiply modulo 2^64), collect the keys,
+ * sort them and count the runs.                                              */
+static int is_space(uint8_t b)
+{
+    return b == 0x20 || (b >= 0x09 && b <= 0x0d);
+}
+
+uint64_t oracle_fnv1a64(const uint8_t *bytes, uint64_t len)
+{
+    uint64_t h = 14695981039346656037ull;
+    for (uint64_t i = 0; i < len; ++i) {
+        h ^= bytes[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+static int cmp_u64(const void *a, const void *b)
+{
+    const uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return x < y ? -1 : x > y ? 1 : 0;
+}
+
+int oracle_wordcount(const uint8_t *text, uint64_t nbytes, uint64_t *keys,
+                     uint64_t *counts, uint64_t cap, uint64_t *ndistinct,
+                     uint64_t *nwords)
+{
+    uint64_t nw = 0, room = 1024;
+    uint64_t *all = malloc(room * sizeof(uint64_t));
+    if (!all)
+        return -1;
+    uint64_t i = 0;
+    while (i < nbytes) {
+        if (is_space(text[i])) {
+            ++i;
+            continue;
+        }
+        uint64_t j = i;
+        while (j < nbytes && !is_space(text[j]))
+            ++j;
+        if (nw == room) {
+            room *= 2;
+            uint64_t *grown = realloc(all, room * sizeof(uint64_t));
+            if (!grown) {
+                free(all);
+                return -1;
+            }
+            all = grown;
+        }
+        all[nw++] = oracle_fnv1a64(text + i, j - i);
+        i = j;
+    }
+    qsort(all, nw, sizeof(uint64_t), cmp_u64);
+    uint64_t nd = 0;
+    for (uint64_t k = 0; k < nw;) {
+        uint64_t e = k;
+        while (e < nw && all[e] == all[k])
+            ++e;
+        if (nd < cap) {
+            keys[nd] = all[k];
+            counts[nd] = e - k;
+        }
+        ++nd;
+        k = e;
+    }
+    free(all);
+    *ndistinct = nd;
+    *nwords = nw;
+    return nd <= cap ? 0 : -1;
+}

@@ -99,6 +99,17 @@ enum { ORACLE_VADD = 1, ORACLE_VMAX = 2 };
 int oracle_tree_reduce_arrays(uint32_t combiner, const float *const *arrays,
                               uint32_t k, uint64_t len, float *out);
 
+/* O10 WordCount (sec. 3.2.3: the Spark word-count demo as a SparkCL kernel).
+ *     A word is a maximal run of bytes that are not ASCII whitespace (space,
+ *     tab, LF, VT, FF, CR); its key is the 64-bit FNV-1a hash of its bytes
+ *     (Fowler, Noll, Vo).  Writes the distinct keys in ascending order with
+ *     their counts (up to `cap` of them), *ndistinct and *nwords.  Returns 0,
+ *     or -1 if there are more than `cap` distinct keys or memory runs out. */
+uint64_t oracle_fnv1a64(const uint8_t *bytes, uint64_t len);
+int oracle_wordcount(const uint8_t *text, uint64_t nbytes, uint64_t *keys,
+                     uint64_t *counts, uint64_t cap, uint64_t *ndistinct,
+                     uint64_t *nwords);
+
 #ifdef __cplusplus
 }
 #endif

@@ -924,6 +924,243 @@ __global__ __launch_bounds__(kBlock) void k_zero(uint32_t *p, uint64_t words)
         p[i] = 0u;
 }
 
+// ---- WordCount --------------------------------------------------------------
+// The word-count demo (sec. 3.2.3) as a partition kernel over a byte stream:
+// a word is a maximal run of non-whitespace bytes, counted under the 64-bit
+// FNV-1a hash of its bytes (Fowler, Noll, Vo: xor the byte in, multiply by
+// the 64-bit FNV prime).  Blocks stage 4 KiB chunks of text (plus a 256-byte
+// look-ahead) in LDS; the thread owning a word's first byte hashes it and
+// counts it in the block's LDS hash table (the paper's "local data"), which
+// absorbs the frequent words of a skewed vocabulary; words that find no LDS
+// slot within a few probes, and the LDS table at the end, go to one global
+// open-addressing table with device-scope atomics.  Counts are integers, so
+// the result does not depend on which block counts which word.
+constexpr uint32_t kWcChunk = 4096;   // bytes per chunk: 16 per thread
+constexpr uint32_t kWcLook = 256;     // look-ahead bytes staged after a chunk
+constexpr uint32_t kWcSlots = 2048;   // LDS hash slots per block
+constexpr uint32_t kWcProbes = 32;    // LDS probes before a word spills
+static_assert(kWcChunk == 16 * kBlock, "one 16-byte span per thread");
+
+__device__ __forceinline__ bool wc_space(uint32_t b)
+{
+    return b == 0x20u || (b - 0x09u) <= 4u; // space, tab, LF, VT, FF, CR
+}
+
+__device__ __forceinline__ uint64_t fnv_step(uint64_t h, uint32_t b)
+{
+    return (h ^ (uint64_t)b) * 1099511628211ull;
+}
+
+// Add c to key h in the global table (keys 0 = empty; a word whose hash is 0
+// is counted in ctl[1] instead).
+__device__ void wc_global_add(const WcArgs &a, uint64_t h, uint64_t c)
+{
+    if (h == 0) {
+        atomicAdd((unsigned long long *)&a.ctl[1], (unsigned long long)c);
+        return;
+    }
+    // A full table has been flagged already: stop probing (the call fails
+    // with ETOOBIG).  Probe sequences are bounded too: at the load factor of
+    // 1/2 that a table within capacity keeps, a run of 2^16 occupied slots
+    // does not happen, so only an overflowing table reaches the bound.
+    if (__hip_atomic_load(&a.ctl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        return;
+    uint64_t s = h & a.mask;
+    const uint64_t probes = min(a.mask, (uint64_t)0xFFFF);
+    for (uint64_t probe = 0; probe <= probes; ++probe) {
+        const uint64_t k = a.keys[s];
+        if (k == h) {
+            atomicAdd((unsigned long long *)&a.counts[s], (unsigned long long)c);
+            return;
+        }
+        if (k == 0) {
+            const uint64_t old =
+                atomicCAS((unsigned long long *)&a.keys[s], 0ull, (unsigned long long)h);
+            if (old == 0 || old == h) {
+                atomicAdd((unsigned long long *)&a.counts[s], (unsigned long long)c);
+                return;
+            }
+        }
+        s = (s + 1) & a.mask;
+    }
+    atomicOr((unsigned long long *)&a.ctl[2], 1ull); // table full
+}
+
+__device__ __forceinline__ void wc_local_add(uint64_t *sk, uint64_t *sc, const WcArgs &a,
+                                             uint64_t h)
+{
+    if (h != 0) {
+        uint32_t s = (uint32_t)h & (kWcSlots - 1);
+        for (uint32_t p = 0; p < kWcProbes; ++p) {
+            const uint64_t k = sk[s];
+            if (k == h) {
+                atomicAdd((unsigned long long *)&sc[s], 1ull);
+                return;
+            }
+            if (k == 0) {
+                const uint64_t old =
+                    atomicCAS((unsigned long long *)&sk[s], 0ull, (unsigned long long)h);
+                if (old == 0 || old == h) {
+                    atomicAdd((unsigned long long *)&sc[s], 1ull);
+                    return;
+                }
+            }
+            s = (s + 1) & (kWcSlots - 1);
+        }
+    }
+    wc_global_add(a, h, 1);
+}
+
+// 16 bytes of text at byte `pos` (a thread's span), bytes at or past n read
+// as spaces, so no word starts or continues there.
+__device__ __forceinline__ uint4 wc_span(const uint8_t *text, uint64_t n, uint64_t pos,
+                                         bool vec)
+{
+    if (vec && pos + 16 <= n)
+        return *reinterpret_cast<const uint4 *>(text + pos);
+    uint32_t w[4] = {0x20202020u, 0x20202020u, 0x20202020u, 0x20202020u};
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        if (pos + k < n) {
+            const uint32_t sh = 8 * (k & 3);
+            w[k >> 2] = (w[k >> 2] & ~(0xFFu << sh)) | ((uint32_t)text[pos + k] << sh);
+        }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Byte k (0..15) of a span held in registers: a 64-bit select and a shift
+// (no indexed register array, which the compiler would put in scratch).
+__device__ __forceinline__ uint32_t span_byte(uint64_t lo, uint64_t hi, uint32_t k)
+{
+    const uint64_t half = k < 8 ? lo : hi;
+    return (uint32_t)(half >> (8 * (k & 7))) & 0xFFu;
+}
+
+// Block barrier for LDS traffic only: waits for this wave's LDS operations,
+// not for its global loads in flight (the next chunk's prefetch).
+__device__ __forceinline__ void lds_barrier()
+{
+    __asm__ __volatile__("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F); // lgkmcnt(0); vmcnt, expcnt untouched
+    __builtin_amdgcn_s_barrier();
+    __asm__ __volatile__("" ::: "memory");
+}
+
+__global__ __launch_bounds__(kBlock) void k_wordcount(WcArgs a)
+{
+    __shared__ uint64_t sk[kWcSlots];
+    __shared__ uint64_t sc[kWcSlots];
+    __shared__ uint4 st4[(kWcChunk + kWcLook) / 16];
+    __shared__ uint32_t sh_prev;
+    const uint8_t *st = reinterpret_cast<const uint8_t *>(st4);
+    for (uint32_t i = threadIdx.x; i < kWcSlots; i += kBlock) {
+        sk[i] = 0;
+        sc[i] = 0;
+    }
+    const uint8_t *text = a.text;
+    const uint64_t n = a.n;
+    const bool vec = ((uintptr_t)text & 15u) == 0;
+    const uint32_t tid = threadIdx.x;
+    const uint64_t nchunks = (n + kWcChunk - 1) / kWcChunk;
+    constexpr uint32_t kLookSpans = kWcLook / 16;
+    // this thread's span of the first chunk, its look-ahead span and (thread
+    // 0) the byte before the chunk, loaded ahead of use
+    uint64_t c = blockIdx.x;
+    uint4 cur = wc_span(text, n, c * kWcChunk + 16 * tid, vec);
+    uint4 look = make_uint4(0, 0, 0, 0);
+    if (tid < kLookSpans)
+        look = wc_span(text, n, c * kWcChunk + kWcChunk + 16 * tid, vec);
+    uint32_t prevb = (tid == 0 && c > 0 && c < nchunks) ? text[c * kWcChunk - 1] : 0x20u;
+    uint64_t words = 0;
+    for (; c < nchunks; c += gridDim.x) {
+        const uint64_t c0 = c * kWcChunk;
+        lds_barrier(); // the previous chunk's scan is done with the staging
+        const uint4 mine = cur;
+        st4[tid] = mine;
+        if (tid < kLookSpans)
+            st4[kBlock + tid] = look;
+        if (tid == 0)
+            sh_prev = prevb;
+        const uint64_t cn = c + gridDim.x;
+        if (cn < nchunks) { // prefetch the block's next chunk
+            cur = wc_span(text, n, cn * kWcChunk + 16 * tid, vec);
+            if (tid < kLookSpans)
+                look = wc_span(text, n, cn * kWcChunk + kWcChunk + 16 * tid, vec);
+            if (tid == 0)
+                prevb = text[cn * kWcChunk - 1];
+        }
+        lds_barrier(); // staged
+        const uint32_t prev = tid ? st[16 * tid - 1] : sh_prev;
+        const uint64_t lo = ((uint64_t)mine.y << 32) | mine.x;
+        const uint64_t hi = ((uint64_t)mine.w << 32) | mine.z;
+        uint32_t sep = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < 16; ++k)
+            sep |= (uint32_t)wc_space(span_byte(lo, hi, k)) << k;
+        uint32_t starts = ~sep & ((sep << 1) | (uint32_t)wc_space(prev)) & 0xFFFFu;
+        while (starts) {
+            const uint32_t p = __builtin_ctz(starts);
+            starts &= starts - 1;
+            const uint32_t after = sep >> p;
+            const uint32_t e = after ? p + __builtin_ctz(after) : 16u;
+            uint64_t h = 14695981039346656037ull;
+            for (uint32_t k = p; k < e; ++k)
+                h = fnv_step(h, span_byte(lo, hi, k));
+            if (e == 16) {
+                // the word runs past this span: staged bytes, then the text
+                for (uint64_t j = 16 * tid + 16;; ++j) {
+                    uint32_t b;
+                    if (j < kWcChunk + kWcLook)
+                        b = st[j];
+                    else if (c0 + j < n)
+                        b = text[c0 + j];
+                    else
+                        break;
+                    if (wc_space(b))
+                        break;
+                    h = fnv_step(h, b);
+                }
+            }
+            wc_local_add(sk, sc, a, h);
+            ++words;
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < kWcSlots; i += kBlock)
+        if (sk[i])
+            wc_global_add(a, sk[i], sc[i]);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        words += __shfl_xor(words, o);
+    if ((tid & 63u) == 0 && words)
+        atomicAdd((unsigned long long *)&a.ctl[0], (unsigned long long)words);
+}
+
+// Compaction of the global table into the caller's key/count arrays
+// (unordered); ctl[3] counts the distinct keys, also those past `cap`.
+__global__ __launch_bounds__(kBlock) void k_wc_compact(WcArgs a, uint64_t *out_keys,
+                                                      uint64_t *out_counts, uint64_t cap)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t s = (uint64_t)blockIdx.x * kBlock + threadIdx.x; s <= a.mask; s += stride) {
+        const uint64_t k = a.keys[s];
+        if (k == 0)
+            continue;
+        const uint64_t pos = atomicAdd((unsigned long long *)&a.ctl[3], 1ull);
+        if (pos < cap) {
+            out_keys[pos] = k;
+            out_counts[pos] = a.counts[s];
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.ctl[1]) {
+        const uint64_t pos = atomicAdd((unsigned long long *)&a.ctl[3], 1ull);
+        if (pos < cap) {
+            out_keys[pos] = 0;
+            out_counts[pos] = a.ctl[1];
+        }
+    }
+}
+
 // Synthetic data for the autotuner: a cheap hash pattern in [-1, 1).
 __global__ __launch_bounds__(kBlock) void k_fill_pattern(float *p, uint64_t n,
                                                          uint32_t salt)
@@ -1142,6 +1379,30 @@ int launch_map(const TaskDev *dtask, uint64_t n, uint32_t variant, uint32_t grid
     hipLaunchKernelGGL(k_map, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
                        dtask, n, variant);
     return hip_status(hipGetLastError());
+}
+
+int launch_wordcount(const WcArgs &a, uint32_t grid, void *stream)
+{
+    if (grid == 0 || !a.keys || !a.counts || !a.ctl || ((a.mask + 1) & a.mask))
+        return SPARKCL_EINVAL;
+    hipLaunchKernelGGL(k_wordcount, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, a);
+    return hip_status(hipGetLastError());
+}
+
+int launch_wc_compact(const WcArgs &a, uint64_t *keys, uint64_t *counts, uint64_t cap,
+                      uint32_t grid, void *stream)
+{
+    if (grid == 0)
+        return SPARKCL_EINVAL;
+    hipLaunchKernelGGL(k_wc_compact, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, a,
+                       keys, counts, cap);
+    return hip_status(hipGetLastError());
+}
+
+int wordcount_blocks_per_cu(int *out)
+{
+    return hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        out, reinterpret_cast<const void *>(k_wordcount), kBlock, 0));
 }
 
 int launch_tree(const TreeArgs &a, uint32_t combiner, bool vec4, void *stream)

@@ -106,6 +106,7 @@ struct sparkcl_ctx {
     int cus = 0;
     uint32_t ns_per_tick = 10;
     int occ_batch = 1; // batch-executor blocks per CU that fit
+    int occ_wordcount = 0; // word-count blocks per CU that fit (0: not yet asked)
 
     char *arena_base = nullptr;
     bool own_arena = false;

@@ -151,6 +151,22 @@ struct TreeArgs {
     uint32_t chunk;
 };
 int launch_tree(const TreeArgs &a, uint32_t combiner, bool vec4, void *stream);
+// WordCount: text of n bytes counted into the global open-addressing table
+// keys/counts of mask + 1 slots (a power of two, cleared beforehand); ctl[0]
+// words, ctl[1] count of the key 0, ctl[2] table-full flag, ctl[3] distinct
+// keys written by the compaction.
+struct WcArgs {
+    const uint8_t *text;
+    uint64_t n;
+    uint64_t *keys;
+    uint64_t *counts;
+    uint64_t mask;
+    uint64_t *ctl;
+};
+int launch_wordcount(const WcArgs &a, uint32_t grid, void *stream);
+int launch_wc_compact(const WcArgs &a, uint64_t *keys, uint64_t *counts, uint64_t cap,
+                      uint32_t grid, void *stream);
+int wordcount_blocks_per_cu(int *out);
 // Resident serving executor: block 0 dispatches, the rest run tiles.  Each
 // launch first discards tickets left unpublished by the previous launch.
 int launch_serve(const ServeArgs &a, uint32_t workers, void *stream);

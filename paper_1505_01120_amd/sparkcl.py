@@ -88,7 +88,7 @@ EXPORTS = ("sparkcl_init", "sparkcl_destroy", "sparkcl_map", "sparkcl_map_partit
            "sparkcl_serve_stats_get", "sparkcl_serve_drain", "sparkcl_get_tuning",
            "sparkcl_set_tuning", "sparkcl_autotune", "sparkcl_strerror",
            "sparkcl_last_error", "sparkcl_last_kernel_ms", "sparkcl_version",
-           "sparkcl_offload_breakeven")
+           "sparkcl_offload_breakeven", "sparkcl_wordcount")
 
 
 class SparkclError(RuntimeError):
@@ -135,6 +135,8 @@ def load() -> ctypes.CDLL:
             "sparkcl_last_kernel_ms": ([P, ctypes.POINTER(ctypes.c_float)], I32),
             "sparkcl_version": ([], ctypes.c_char_p),
             "sparkcl_offload_breakeven": ([P, ctypes.c_double, ctypes.POINTER(U64)], I32),
+            "sparkcl_wordcount": ([P, P, U64, P, P, U64, ctypes.POINTER(U64),
+                                   ctypes.POINTER(U64), P], I32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -333,12 +335,28 @@ class Context:
         _check(load().sparkcl_autotune(self._h, lo_log2, hi_log2,
                                        path.encode() if path else None), "sparkcl_autotune")
 
+    def wordcount(self, text, capacity: int, keys=None, counts=None, stream=None):
+        """WordCount over a device uint8 tensor: (keys, counts, distinct, words),
+        keys/counts as int64 device tensors of `capacity` (first `distinct`
+        entries valid, unordered)."""
+        import torch
+        if keys is None:
+            keys = torch.empty(max(capacity, 1), dtype=torch.int64, device=text.device)
+        if counts is None:
+            counts = torch.empty(max(capacity, 1), dtype=torch.int64, device=text.device)
+        nd, nw = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(load().sparkcl_wordcount(self._h, _ptr(text), text.numel(), _ptr(keys),
+                                        _ptr(counts), capacity, ctypes.byref(nd),
+                                        ctypes.byref(nw), _stream(stream, self.device)),
+               "sparkcl_wordcount")
+        return keys, counts, nd.value, nw.value
+
     def offload_breakeven(self, host_bytes_per_s: float) -> int:
         """Smallest offload cost (bytes) at which this GPU beats a host path of
         the given throughput (selective execution threshold)."""
         v = ctypes.c_uint64()
         _check(load().sparkcl_offload_breakeven(self._h, float(host_bytes_per_s), ctypes.byref(v)),
-               "sparkcl_offload_breakeven")
+               "sparkcl_offload_breakeven", "sparkcl_wordcount")
         return v.value
 
     def last_kernel_ms(self) -> float:

@@ -1,0 +1,82 @@
+"""GPU parity of WordCount (sec. 3.2.3): sparkcl_wordcount through the C
+ABI against the oracle, exactly: the same distinct keys with the same counts
+(the GPU's output order is free, so both sides are compared sorted by key)
+and the same number of words."""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+import paper_1505_01120_amd as sc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = sc.Context(device=0, arena_bytes=1 << 30)
+    yield c
+    c.destroy()
+
+
+def gpu_count(ctx, text: np.ndarray, offset: int = 0, capacity=None):
+    buf = torch.zeros(text.size + offset + 16, dtype=torch.uint8, device="cuda")
+    view = buf[offset:offset + text.size]
+    view.copy_(torch.from_numpy(text))
+    cap = capacity if capacity is not None else text.size // 2 + 1
+    keys, counts, nd, nw = ctx.wordcount(view, cap)
+    k = keys[:nd].cpu().numpy().view(np.uint64)
+    c = counts[:nd].cpu().numpy().view(np.uint64)
+    order = np.argsort(k)
+    return k[order], c[order], nw
+
+
+def check(ctx, text, offset=0):
+    text = np.frombuffer(text, dtype=np.uint8) if isinstance(text, bytes) else text
+    gk, gc, gn = gpu_count(ctx, text, offset)
+    ok, oc, on = oracle.wordcount(text)
+    assert gn == on, (gn, on)
+    assert np.array_equal(gk, ok) and np.array_equal(gc, oc)
+
+
+EDGE = [b"", b"a", b" ", b"  a  ", b"a b\tc\nd\re\x0bf\x0cg", b"\x00\x01 \x7f\xff",
+        b"x" * 10_000, b" \t\n\r\x0b\x0c" * 100]
+
+
+@pytest.mark.parametrize("i", range(len(EDGE)))
+def test_edge_texts(ctx, i):
+    check(ctx, EDGE[i])
+
+
+@pytest.mark.parametrize("n", [4095, 4096, 4097, 4351, 4352, 4353, 8192 + 7])
+def test_words_across_chunk_and_lookahead_edges(ctx, n):
+    # words of every length 1..600 laid end to end, cut at n bytes
+    parts, rng = [], np.random.default_rng(n)
+    while sum(map(len, parts)) < n:
+        parts.append(b"q" * int(rng.integers(1, 600)) + b" ")
+    check(ctx, b"".join(parts)[:n])
+
+
+@pytest.mark.parametrize("offset", [0, 1, 7, 15])
+def test_random_bytes_any_alignment(ctx, offset):
+    rng = np.random.default_rng(offset)
+    check(ctx, rng.integers(0, 256, (1 << 20) + 13, dtype=np.uint8), offset)
+
+
+@pytest.mark.parametrize("vocab,nbytes", [(10, 1 << 20), (20_000, 8 << 20), (1_000_000, 16 << 20)])
+def test_zipf_corpus(ctx, vocab, nbytes):
+    check(ctx, datagen.corpus(nbytes, vocab=vocab, seed=vocab))
+
+
+def test_capacity_overflow(ctx):
+    text = datagen.corpus(1 << 20, vocab=20_000)
+    ok, _, _ = oracle.wordcount(text)
+    cap = len(ok) - 1
+    buf = torch.from_numpy(text).cuda()
+    with pytest.raises(sc.SparkclError) as e:
+        ctx.wordcount(buf, cap)
+    assert e.value.code == sc.ETOOBIG
+    # exactly enough room succeeds
+    keys, counts, nd, nw = ctx.wordcount(buf, len(ok))
+    assert nd == len(ok)

@@ -1,0 +1,47 @@
+"""Pins of the oracle's WordCount (O10; sec. 3.2.3): the FNV-1a 64 key
+against its published test vectors, and tokenisation and counting against
+Python's own whitespace split and collections.Counter."""
+from collections import Counter
+
+import numpy as np
+
+
+def by_key(oracle, words):
+    c = Counter(words)
+    pairs = sorted((oracle.fnv1a64(w), n) for w, n in c.items())
+    return [k for k, _ in pairs], [n for _, n in pairs]
+
+
+def test_fnv1a64_published_vectors(oracle):
+    # Fowler/Noll/Vo FNV-1a, 64-bit: empty string, "a", "foobar"
+    assert oracle.fnv1a64(b"") == 0xCBF29CE484222325
+    assert oracle.fnv1a64(b"a") == 0xAF63DC4C8601EC8C
+    assert oracle.fnv1a64(b"foobar") == 0x85944171F73967E8
+
+
+def check(oracle, text: bytes):
+    keys, counts, nw = oracle.wordcount(text)
+    words = text.split()      # Python splits bytes on the same six whitespace bytes
+    k, n = by_key(oracle, words)
+    assert nw == len(words)
+    assert keys.tolist() == k and counts.tolist() == n
+    assert len(set(k)) == len(set(words))   # no key collisions in these inputs
+
+
+def test_edge_texts(oracle):
+    for t in [b"", b"a", b" ", b"  a  ", b"a b\tc\nd\re\x0bf\x0cg", b"\x00\x01 \x7f\xff",
+              b"x" * 5000, b"ab ab  ab\n\nab", b" \t\n\r\x0b\x0c" * 10]:
+        check(oracle, t)
+
+
+def test_random_bytes(oracle):
+    rng = np.random.default_rng(3)
+    check(oracle, rng.integers(0, 256, 1 << 16, dtype=np.uint8).tobytes())
+    # mostly spaces: many one- and two-byte words
+    t = rng.choice(np.frombuffer(b"  \n\tab", dtype=np.uint8), 1 << 16)
+    check(oracle, t.tobytes())
+
+
+def test_synthetic_corpus(oracle, datagen):
+    text = datagen.corpus(1 << 20, vocab=20_000)
+    check(oracle, text.tobytes())
