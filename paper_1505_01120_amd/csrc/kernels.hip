@@ -938,7 +938,7 @@ __global__ __launch_bounds__(kBlock) void k_zero(uint32_t *p, uint64_t words)
 constexpr uint32_t kWcChunk = 4096;   // bytes per chunk: 16 per thread
 constexpr uint32_t kWcLook = 256;     // look-ahead bytes staged after a chunk
 constexpr uint32_t kWcSlots = 2048;   // LDS hash slots per block
-constexpr uint32_t kWcProbes = 32;    // LDS probes before a word spills
+constexpr uint32_t kWcProbes = 8;     // LDS probes before a word spills
 static_assert(kWcChunk == 16 * kBlock, "one 16-byte span per thread");
 
 __device__ __forceinline__ bool wc_space(uint32_t b)
@@ -959,15 +959,17 @@ __device__ void wc_global_add(const WcArgs &a, uint64_t h, uint64_t c)
         atomicAdd((unsigned long long *)&a.ctl[1], (unsigned long long)c);
         return;
     }
-    // A full table has been flagged already: stop probing (the call fails
-    // with ETOOBIG).  Probe sequences are bounded too: at the load factor of
-    // 1/2 that a table within capacity keeps, a run of 2^16 occupied slots
-    // does not happen, so only an overflowing table reaches the bound.
-    if (__hip_atomic_load(&a.ctl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-        return;
+    // Probe sequences are bounded: at the load factor of 1/2 that a table
+    // within capacity keeps, a run of 2^16 occupied slots does not happen, so
+    // only an overflowing table reaches the bound.  Every 64 probes the
+    // table-full flag is checked, so once the table is full the remaining
+    // words stop early (the call fails with ETOOBIG).
     uint64_t s = h & a.mask;
     const uint64_t probes = min(a.mask, (uint64_t)0xFFFF);
     for (uint64_t probe = 0; probe <= probes; ++probe) {
+        if ((probe & 63) == 63 &&
+            __hip_atomic_load(&a.ctl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            return;
         const uint64_t k = a.keys[s];
         if (k == h) {
             atomicAdd((unsigned long long *)&a.counts[s], (unsigned long long)c);
@@ -1051,6 +1053,7 @@ __global__ __launch_bounds__(kBlock) void k_wordcount(WcArgs a)
     __shared__ uint64_t sk[kWcSlots];
     __shared__ uint64_t sc[kWcSlots];
     __shared__ uint4 st4[(kWcChunk + kWcLook) / 16];
+    __shared__ uint64_t emit[kWaves][64 * 8]; // a 16-byte span holds <= 8 word starts
     __shared__ uint32_t sh_prev;
     const uint8_t *st = reinterpret_cast<const uint8_t *>(st4);
     for (uint32_t i = threadIdx.x; i < kWcSlots; i += kBlock) {
@@ -1060,9 +1063,11 @@ __global__ __launch_bounds__(kBlock) void k_wordcount(WcArgs a)
     const uint8_t *text = a.text;
     const uint64_t n = a.n;
     const bool vec = ((uintptr_t)text & 15u) == 0;
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    uint64_t *buf = emit[wave];
     const uint64_t nchunks = (n + kWcChunk - 1) / kWcChunk;
     constexpr uint32_t kLookSpans = kWcLook / 16;
+    constexpr uint64_t kBasis = 14695981039346656037ull;
     // this thread's span of the first chunk, its look-ahead span and (thread
     // 0) the byte before the chunk, loaded ahead of use
     uint64_t c = blockIdx.x;
@@ -1091,39 +1096,67 @@ __global__ __launch_bounds__(kBlock) void k_wordcount(WcArgs a)
         }
         lds_barrier(); // staged
         const uint32_t prev = tid ? st[16 * tid - 1] : sh_prev;
+        const uint4 nxt = st4[tid + 1]; // the following span (or look-ahead)
         const uint64_t lo = ((uint64_t)mine.y << 32) | mine.x;
         const uint64_t hi = ((uint64_t)mine.w << 32) | mine.z;
+        const uint64_t lo2 = ((uint64_t)nxt.y << 32) | nxt.x;
         uint32_t sep = 0;
 #pragma unroll
         for (uint32_t k = 0; k < 16; ++k)
             sep |= (uint32_t)wc_space(span_byte(lo, hi, k)) << k;
-        uint32_t starts = ~sep & ((sep << 1) | (uint32_t)wc_space(prev)) & 0xFFFFu;
-        while (starts) {
-            const uint32_t p = __builtin_ctz(starts);
-            starts &= starts - 1;
-            const uint32_t after = sep >> p;
-            const uint32_t e = after ? p + __builtin_ctz(after) : 16u;
-            uint64_t h = 14695981039346656037ull;
-            for (uint32_t k = p; k < e; ++k)
-                h = fnv_step(h, span_byte(lo, hi, k));
-            if (e == 16) {
-                // the word runs past this span: staged bytes, then the text
-                for (uint64_t j = 16 * tid + 16;; ++j) {
-                    uint32_t b;
-                    if (j < kWcChunk + kWcLook)
-                        b = st[j];
-                    else if (c0 + j < n)
-                        b = text[c0 + j];
-                    else
-                        break;
-                    if (wc_space(b))
-                        break;
-                    h = fnv_step(h, b);
-                }
-            }
-            wc_local_add(sk, sc, a, h);
-            ++words;
+        const uint32_t starts = ~sep & ((sep << 1) | (uint32_t)wc_space(prev)) & 0xFFFFu;
+        const uint32_t mycount = __builtin_popcount(starts);
+        // exclusive prefix sum of the word counts over the wave's lanes
+        uint32_t incl = mycount;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t v = __shfl_up(incl, o);
+            if (lane >= (uint32_t)o)
+                incl += v;
         }
+        const uint32_t total = __shfl(incl, 63);
+        uint32_t slot = incl - mycount;
+        // All lanes walk their 16 bytes and the first 8 of the next span in
+        // step: a word that starts in this span is hashed byte by byte and
+        // written to the wave's buffer when its separator comes.
+        uint64_t h = kBasis;
+        bool inw = false;
+#pragma unroll
+        for (uint32_t k = 0; k < 24; ++k) {
+            const uint32_t byte = k < 16 ? span_byte(lo, hi, k) : span_byte(lo2, 0, k - 16);
+            const bool sp = wc_space(byte);
+            if (k < 16 && ((starts >> k) & 1u)) {
+                inw = true;
+                h = kBasis;
+            }
+            if (inw && !sp)
+                h = fnv_step(h, byte);
+            if (inw && sp) {
+                buf[slot++] = h;
+                inw = false;
+            }
+        }
+        if (inw) {
+            // a word longer than what is left of the 24 bytes: the rest comes
+            // from the staging (then the text), one byte at a time
+            for (uint64_t j = 16 * tid + 24;; ++j) {
+                uint32_t byte;
+                if (j < kWcChunk + kWcLook)
+                    byte = st[j];
+                else if (c0 + j < n)
+                    byte = text[c0 + j];
+                else
+                    break;
+                if (wc_space(byte))
+                    break;
+                h = fnv_step(h, byte);
+            }
+            buf[slot++] = h;
+        }
+        words += mycount;
+        // the wave's words, 64 at a time, into the block's LDS table
+        for (uint32_t i = lane; i < total; i += 64)
+            wc_local_add(sk, sc, a, buf[i]);
     }
     __syncthreads();
     for (uint32_t i = tid; i < kWcSlots; i += kBlock)
@@ -1132,7 +1165,7 @@ __global__ __launch_bounds__(kBlock) void k_wordcount(WcArgs a)
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1)
         words += __shfl_xor(words, o);
-    if ((tid & 63u) == 0 && words)
+    if (lane == 0 && words)
         atomicAdd((unsigned long long *)&a.ctl[0], (unsigned long long)words);
 }
 
