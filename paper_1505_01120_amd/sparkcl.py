@@ -356,7 +356,7 @@ class Context:
         the given throughput (selective execution threshold)."""
         v = ctypes.c_uint64()
         _check(load().sparkcl_offload_breakeven(self._h, float(host_bytes_per_s), ctypes.byref(v)),
-               "sparkcl_offload_breakeven", "sparkcl_wordcount")
+               "sparkcl_offload_breakeven")
         return v.value
 
     def last_kernel_ms(self) -> float:
