@@ -220,6 +220,28 @@ SPARKCL_API int sparkcl_reduce_async(sparkcl_ctx *ctx, const sparkcl_task *tasks
                          sparkcl_result *dev_per_task,
                          sparkcl_result *dev_total, void *stream);
 
+/* One stage of a fused map chain: a registry map applied to the running
+   value of the chain.  Stages are POLY (kernel_id SPARKCL_POLY, degree 0..7,
+   coef[k] multiplies v^k). */
+typedef struct sparkcl_stage {
+    uint32_t kernel_id;
+    uint32_t degree;
+    float coef[8];
+} sparkcl_stage;
+
+/* ReduceCL over fused map chains (a Spark stage: map -> map -> ... ->
+   reduce, pipelined in one pass; sec. 3.1.3): each task's own map (POLY or
+   FMUL, with its parameters) is followed by the `nstages` stages in order,
+   each evaluated one binary32 multiply and add per Horner step with no
+   contraction, then the task's reductions; task.out, if set, receives the
+   chain's final values (bit-exact).  At most 4 stages; MC_PI and host-input
+   tasks are rejected (EINVAL).  One kernel launch per partition with the
+   per-launch tile table; per_task / total as in sparkcl_reduce.  Blocking. */
+SPARKCL_API int sparkcl_reduce_chain(sparkcl_ctx *ctx, const sparkcl_task *tasks,
+                                     uint32_t ntasks, const sparkcl_stage *stages,
+                                     uint32_t nstages, sparkcl_result *per_task,
+                                     sparkcl_result *total, void *stream);
+
 /* Array-valued ReduceCL (sec. 3.1.3 item 3; the Fig 3 vector add; sec.
    3.2.2): the RDD's elements are `k` float arrays of `len` elements each, in
    RDD order; arrays[] is a HOST array of k DEVICE pointers (caller-owned, any

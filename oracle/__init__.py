@@ -235,3 +235,16 @@ def wordcount(text) -> tuple[np.ndarray, np.ndarray, int]:
     if rc != 0:
         raise MemoryError("oracle_wordcount failed")
     return keys[:nd.value].copy(), counts[:nd.value].copy(), nw.value
+
+
+def chain_map(x, y, kid: int, coef=(), c=np.float32(0.1), stages=()) -> np.ndarray:
+    """A fused map chain by composition of O1/O2: the task's map (POLY with
+    `coef`, or FMUL with `c`), then each POLY stage in `stages` (coefficient
+    tuples) applied to the running values."""
+    v = poly_map(x, coef) if kid == ORACLE_POLY else fmul_map(x, y, c)
+    for st in stages:
+        v = poly_map(v, st)
+    return v
+
+
+ORACLE_POLY, ORACLE_FMUL = 1, 2

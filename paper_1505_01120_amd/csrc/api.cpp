@@ -490,7 +490,17 @@ int sparkcl::enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream, bool timed)
     // autotuner ask for them; asynchronous calls enqueue the kernels alone.
     if (timed)
         SPARKCL_HIP(hipEventRecord(ctx->ev0, stream));
-    if (p->host) {
+    if (p->kind == 4) {
+        // map chains: one launch per partition with the plan's stage table
+        for (uint32_t i = 0; i < p->ntasks; ++i) {
+            const uint32_t cap = exec_grid(ctx, 1u << (p->tasks[i].kernel_id - 1));
+            int rc = launch_chain(p->dtasks + i, p->dchain, p->ntiles[i],
+                                  std::min(cap, p->ntiles[i]), p->out, stream);
+            if (rc != SPARKCL_OK)
+                return fail(rc, "kernel launch failed: " +
+                                    std::string(hipGetErrorString(hipGetLastError())));
+        }
+    } else if (p->host) {
         // Staged pipeline: partition i is copied into slot i mod S on the copy
         // stream once the kernel that last used the slot is done, and its
         // kernel runs on `stream` once the copy is done.  The first copies
@@ -551,15 +561,12 @@ int sparkcl::enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream, bool timed)
 
 namespace {
 
-// The caller holds ctx->mu.
-int run_blocking_locked(sparkcl_ctx *ctx, int mode, const sparkcl_task *tasks,
-                        uint32_t ntasks, sparkcl_result *per_task, sparkcl_result *total,
-                        hipStream_t stream)
+// Launches plan `p` and copies its results back (the caller holds ctx->mu).
+int launch_and_collect(sparkcl_ctx *ctx, Plan *p, const sparkcl_task *tasks,
+                       uint32_t ntasks, sparkcl_result *per_task, sparkcl_result *total,
+                       hipStream_t stream)
 {
-    Plan *p = nullptr;
-    int rc = get_plan(ctx, 0, mode, tasks, ntasks, nullptr, nullptr, stream, &p);
-    if (rc != SPARKCL_OK)
-        return rc;
+    int rc;
     if ((rc = ensure_pinned(ctx, ntasks + 1)) != SPARKCL_OK)
         return rc;
     if ((rc = enqueue(ctx, p, stream, true)) != SPARKCL_OK)
@@ -584,6 +591,19 @@ int run_blocking_locked(sparkcl_ctx *ctx, int mode, const sparkcl_task *tasks,
             total->count = 0;
     }
     return SPARKCL_OK;
+}
+
+
+// The caller holds ctx->mu.
+int run_blocking_locked(sparkcl_ctx *ctx, int mode, const sparkcl_task *tasks,
+                        uint32_t ntasks, sparkcl_result *per_task, sparkcl_result *total,
+                        hipStream_t stream)
+{
+    Plan *p = nullptr;
+    int rc = get_plan(ctx, 0, mode, tasks, ntasks, nullptr, nullptr, stream, &p);
+    if (rc != SPARKCL_OK)
+        return rc;
+    return launch_and_collect(ctx, p, tasks, ntasks, per_task, total, stream);
 }
 
 int run_blocking(sparkcl_ctx *ctx, int mode, const sparkcl_task *tasks,
@@ -1056,6 +1076,74 @@ int sparkcl_reduce_async(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t n
         SPARKCL_OK)
         return rc;
     return enqueue(ctx, p, s, false);
+}
+
+int sparkcl_reduce_chain(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t ntasks,
+                         const sparkcl_stage *stages, uint32_t nstages,
+                         sparkcl_result *per_task, sparkcl_result *total, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc != SPARKCL_OK)
+        return rc;
+    if ((ntasks && !tasks) || (nstages && !stages))
+        return fail(SPARKCL_EINVAL, "tasks/stages is NULL");
+    if (nstages > (uint32_t)kMaxPost)
+        return fail(SPARKCL_EINVAL, "more than " + std::to_string(kMaxPost) + " chain stages");
+    ChainDev chain;
+    std::memset(&chain, 0, sizeof(chain));
+    chain.npost = nstages;
+    for (uint32_t s = 0; s < nstages; ++s) {
+        if (stages[s].kernel_id != SPARKCL_POLY || stages[s].degree > 7)
+            return fail(SPARKCL_EINVAL, "chain stage " + std::to_string(s) +
+                                            " must be POLY of degree <= 7");
+        chain.deg[s] = stages[s].degree;
+        std::memcpy(chain.coef[s], stages[s].coef, sizeof(chain.coef[s]));
+    }
+    for (uint32_t i = 0; i < ntasks; ++i)
+        if (tasks[i].kernel_id == SPARKCL_MC_PI || (tasks[i].flags & SPARKCL_TASK_HOST_INPUT))
+            return fail(SPARKCL_EINVAL, "map chains take POLY/FMUL tasks with device inputs");
+    if (ntasks == 0)
+        return SPARKCL_OK;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint64_t h = fnv1a(plan_hash(4, SPARKCL_PER_LAUNCH, tasks, ntasks, nullptr, nullptr),
+                             &chain, sizeof(chain));
+    Plan *p = nullptr;
+    for (auto it = ctx->plans.begin(); it != ctx->plans.end(); ++it) {
+        Plan *q = *it;
+        if (q->kind == 4 && q->hash == h && q->ntasks == ntasks &&
+            std::memcmp(q->tasks.data(), tasks, sizeof(sparkcl_task) * ntasks) == 0 &&
+            std::memcmp(&q->chain, &chain, sizeof(chain)) == 0) {
+            ctx->plans.splice(ctx->plans.begin(), ctx->plans, it);
+            p = q;
+            break;
+        }
+    }
+    if (!p) {
+        while (ctx->plans.size() >= kMaxPlans)
+            evict_one(ctx);
+        if ((rc = build_plan(ctx, 0, SPARKCL_PER_LAUNCH, tasks, ntasks, nullptr, nullptr, st,
+                             &p)) != SPARKCL_OK)
+            return rc;
+        p->kind = 4;
+        p->chain = chain;
+        p->hash = h;
+        void *d = nullptr;
+        if ((rc = arena_alloc(ctx, p, sizeof(ChainDev), &d)) != SPARKCL_OK) {
+            free_plan(ctx, p);
+            return rc;
+        }
+        p->dchain = static_cast<ChainDev *>(d);
+        hipError_t e = hipMemcpyAsync(d, &p->chain, sizeof(ChainDev), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            free_plan(ctx, p);
+            return fail_hip(e, "chain upload");
+        }
+        ctx->plans.push_front(p);
+    }
+    return launch_and_collect(ctx, p, tasks, ntasks, per_task, total, st);
 }
 
 int sparkcl_wordcount(sparkcl_ctx *ctx, const uint8_t *text, uint64_t nbytes, uint64_t *keys,

@@ -534,61 +534,19 @@ __device__ __forceinline__ void read_result(const sparkcl_result *p, double &s,
 // ---- one tile, start to finish ------------------------------------------
 // Returns true in the block that completed the task (after writing its
 // result); callers use it only for the RDD-level step.
-__device__ __forceinline__ bool run_tile(const TaskDev *__restrict__ tp, uint32_t j,
-                         const LaunchOut &L)
+template <class Body>
+__device__ __forceinline__ bool run_tile_with(const TaskDev *__restrict__ tp, uint32_t j,
+                                              const LaunchOut &L, Body body)
 {
     __shared__ uint32_t sh_last;
     TaskSync *__restrict__ sync = L.sync;
     const uint64_t t0 = device_ns(L.ns_per_tick);
 
     const uint32_t variant = uni(tp->variant);
-    const uint32_t T = uni(tp->tile_elems);
     const uint32_t ntiles = uni(tp->ntiles);
-    const uint64_t n = uni64(tp->n);
 
     Acc a;
-    uint64_t count = 0;
-    const float *x = tp->in0;
-    const float *y = tp->in1;
-    float *o = tp->out;
-    if (variant < V_FMUL) {
-        const bool w = variant >= V_POLYW;
-        const uint32_t d = variant & 7u;
-        float k[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-            k[i] = tp->coef[i];
-#define SPARKCL_POLY_CASE(D)                                                   \
-    case D: {                                                                  \
-        PolyMap<D> f;                                                          \
-        for (int i = 0; i < 8; ++i)                                            \
-            f.k[i] = k[i];                                                     \
-        count = w ? tile_map<PolyMap<D>, true>(f, x, y, o, n, T, ntiles, j, a)  \
-                  : tile_map<PolyMap<D>, false>(f, x, y, o, n, T, ntiles, j, a); \
-    } break;
-        switch (d) {
-            SPARKCL_POLY_CASE(0)
-            SPARKCL_POLY_CASE(1)
-            SPARKCL_POLY_CASE(2)
-            SPARKCL_POLY_CASE(3)
-            SPARKCL_POLY_CASE(4)
-            SPARKCL_POLY_CASE(5)
-            SPARKCL_POLY_CASE(6)
-            SPARKCL_POLY_CASE(7)
-        }
-#undef SPARKCL_POLY_CASE
-    } else if (variant == V_FMUL || variant == V_FMULW) {
-        FmulMap f{tp->c};
-        count = variant == V_FMULW ? tile_map<FmulMap, true>(f, x, y, o, n, T, ntiles, j, a)
-                                   : tile_map<FmulMap, false>(f, x, y, o, n, T, ntiles, j, a);
-    } else if (variant == V_MC) {
-        const uint64_t begin = (uint64_t)j * T;
-        const uint64_t end = min(n, begin + T);
-        if (begin < end) {
-            tile_mc(uni64(tp->seed), uni(tp->pid), begin, end, a);
-            count = end - begin;
-        }
-    } // V_DECLINED: nothing to do; the empty partial leaves the total as is
+    const uint64_t count = body(a);
 
     Red r{a.s, a.m, a.hits, 0};
     r = block_reduce(r);
@@ -648,6 +606,62 @@ __device__ __forceinline__ bool run_tile(const TaskDev *__restrict__ tp, uint32_
     return true;
 }
 
+// The registry kernels' tile body (maps fused with their reductions, or the
+// Monte-Carlo count) run through the common tile epilogue.
+__device__ __forceinline__ bool run_tile(const TaskDev *__restrict__ tp, uint32_t j,
+                                         const LaunchOut &L)
+{
+    return run_tile_with(tp, j, L, [&](Acc &a) -> uint64_t {
+        const uint32_t variant = uni(tp->variant);
+        const uint32_t T = uni(tp->tile_elems);
+        const uint32_t ntiles = uni(tp->ntiles);
+        const uint64_t n = uni64(tp->n);
+        uint64_t count = 0;
+        const float *x = tp->in0;
+        const float *y = tp->in1;
+        float *o = tp->out;
+        if (variant < V_FMUL) {
+            const bool w = variant >= V_POLYW;
+            const uint32_t d = variant & 7u;
+            float k[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                k[i] = tp->coef[i];
+#define SPARKCL_POLY_CASE(D)                                                   \
+        case D: {                                                                  \
+            PolyMap<D> f;                                                          \
+            for (int i = 0; i < 8; ++i)                                            \
+                f.k[i] = k[i];                                                     \
+            count = w ? tile_map<PolyMap<D>, true>(f, x, y, o, n, T, ntiles, j, a)  \
+                      : tile_map<PolyMap<D>, false>(f, x, y, o, n, T, ntiles, j, a); \
+        } break;
+            switch (d) {
+                SPARKCL_POLY_CASE(0)
+                SPARKCL_POLY_CASE(1)
+                SPARKCL_POLY_CASE(2)
+                SPARKCL_POLY_CASE(3)
+                SPARKCL_POLY_CASE(4)
+                SPARKCL_POLY_CASE(5)
+                SPARKCL_POLY_CASE(6)
+                SPARKCL_POLY_CASE(7)
+            }
+#undef SPARKCL_POLY_CASE
+        } else if (variant == V_FMUL || variant == V_FMULW) {
+            FmulMap f{tp->c};
+            count = variant == V_FMULW ? tile_map<FmulMap, true>(f, x, y, o, n, T, ntiles, j, a)
+                                       : tile_map<FmulMap, false>(f, x, y, o, n, T, ntiles, j, a);
+        } else if (variant == V_MC) {
+            const uint64_t begin = (uint64_t)j * T;
+            const uint64_t end = min(n, begin + T);
+            if (begin < end) {
+                tile_mc(uni64(tp->seed), uni(tp->pid), begin, end, a);
+                count = end - begin;
+            }
+        } // V_DECLINED: nothing to do; the empty partial leaves the total as is
+        return count;
+    });
+}
+
 // RDD-level step, run by the block that completed a task: the block that
 // completes the launch's last task folds all partition results in task order.
 __device__ __forceinline__ void rdd_step(const LaunchOut &L)
@@ -679,6 +693,85 @@ __device__ __forceinline__ void rdd_step(const LaunchOut &L)
         own_stores_complete();
     }
     __syncthreads();
+}
+
+// ---- fused map chains ------------------------------------------------------
+// A task's registry map followed by up to kMaxPost POLY stages on the running
+// binary32 value (map -> map -> ... -> reduce in one pass).  The stage
+// degrees are run-time values, so the Horner loops are not unrolled; every
+// step is still one binary32 multiply and one add in the written order.
+__device__ __forceinline__ float horner_rt(const float *k, uint32_t d, float x)
+{
+    float t = k[d];
+    for (int i = (int)d - 1; i >= 0; --i) {
+        const float p = t * x;
+        t = p + k[i];
+    }
+    return t;
+}
+
+// The stage coefficients stay in the (uniform) task and chain tables and are
+// read with scalar loads inside the Horner loops: copied into a per-thread
+// array indexed by run-time degrees they would live in scratch memory.
+template <bool TWO> struct ChainMap {
+    static constexpr bool kTwo = TWO;
+    const float *k0;
+    uint32_t d0;
+    float c;
+    const ChainDev *ch;
+    uint32_t npost;
+    __device__ __forceinline__ float operator()(float x, float y) const
+    {
+        float v;
+        if (TWO) {
+            const float xy = x * y;
+            const float cx = c * x;
+            v = xy + cx;
+        } else {
+            v = horner_rt(k0, d0, x);
+        }
+        for (uint32_t s = 0; s < npost; ++s)
+            v = horner_rt(ch->coef[s], uni(ch->deg[s]), v);
+        return v;
+    }
+};
+
+template <bool TWO>
+__device__ __forceinline__ ChainMap<TWO> chain_map(const TaskDev *tp, const ChainDev *ch)
+{
+    return ChainMap<TWO>{tp->coef, uni(tp->variant) & 7u, tp->c, ch, uni(ch->npost)};
+}
+
+// One partition with a map chain: blocks stride over its tiles.
+__global__ __launch_bounds__(kBlock) void k_chain(const TaskDev *__restrict__ task,
+                                                  const ChainDev *__restrict__ chain,
+                                                  LaunchOut L)
+{
+    const uint32_t ntiles = uni(task->ntiles);
+    for (uint32_t j = blockIdx.x; j < ntiles; j += gridDim.x) {
+        const bool done = run_tile_with(task, j, L, [&](Acc &a) -> uint64_t {
+            const uint32_t variant = uni(task->variant);
+            if (variant == V_DECLINED)
+                return 0;
+            const uint32_t T = uni(task->tile_elems);
+            const uint64_t n = uni64(task->n);
+            const float *x = task->in0;
+            const float *y = task->in1;
+            float *o = task->out;
+            const bool two = variant == V_FMUL || variant == V_FMULW;
+            const bool w = variant == V_FMULW || (variant >= V_POLYW && variant < V_FMUL);
+            if (two) {
+                const ChainMap<true> f = chain_map<true>(task, chain);
+                return w ? tile_map<ChainMap<true>, true>(f, x, y, o, n, T, ntiles, j, a)
+                         : tile_map<ChainMap<true>, false>(f, x, y, o, n, T, ntiles, j, a);
+            }
+            const ChainMap<false> f = chain_map<false>(task, chain);
+            return w ? tile_map<ChainMap<false>, true>(f, x, y, o, n, T, ntiles, j, a)
+                     : tile_map<ChainMap<false>, false>(f, x, y, o, n, T, ntiles, j, a);
+        });
+        if (done)
+            rdd_step(L);
+    }
 }
 
 // ---- kernels --------------------------------------------------------------
@@ -1391,6 +1484,17 @@ int launch_task(const TaskDev *dtask, uint32_t ntiles, uint32_t grid,
     grid = grid < ntiles ? grid : ntiles;
     hipLaunchKernelGGL(k_task, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
                        dtask, out);
+    return hip_status(hipGetLastError());
+}
+
+int launch_chain(const TaskDev *dtask, const ChainDev *chain, uint32_t ntiles,
+                 uint32_t grid, const LaunchOut &out, void *stream)
+{
+    if (ntiles == 0 || grid == 0 || !chain)
+        return SPARKCL_EINVAL;
+    grid = grid < ntiles ? grid : ntiles;
+    hipLaunchKernelGGL(k_chain, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, dtask,
+                       chain, out);
     return hip_status(hipGetLastError());
 }
 

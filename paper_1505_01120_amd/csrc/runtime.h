@@ -45,7 +45,7 @@ class Server;
 // words and results.
 struct Plan {
     uint64_t hash = 0;
-    int kind = 0; // 0 reduce/map_partition, 1 map, 2/3 array reduce (table/rows)
+    int kind = 0; // 0 reduce/map_partition, 1 map, 2/3 array reduce (table/rows), 4 chain
     int mode = 0;
     std::vector<sparkcl_task> tasks;
     sparkcl_result *user_results = nullptr;
@@ -77,6 +77,10 @@ struct Plan {
     uint64_t leaf_stride = 0;
     std::vector<const float *> leaves;
     std::vector<TreeArgs> passes;
+
+    // kind 4, map chains: the stage table
+    ChainDev chain{};
+    ChainDev *dchain = nullptr;
 
     // host-input partitions: the staging ring and its events
     bool host = false;

@@ -137,6 +137,15 @@ int launch_batch(const TaskDev *dtasks, const TileRef *tiles, uint32_t ntiles,
 int launch_map(const TaskDev *dtask, uint64_t n, uint32_t variant,
                uint32_t grid, void *stream);
 int launch_zero(void *p, uint64_t bytes, void *stream);
+// Map chains: up to kMaxPost POLY stages after a task's registry map.
+constexpr int kMaxPost = 4;
+struct ChainDev {
+    uint32_t npost;
+    uint32_t deg[kMaxPost];
+    float coef[kMaxPost][8];
+};
+int launch_chain(const TaskDev *dtask, const ChainDev *chain, uint32_t ntiles,
+                 uint32_t grid, const LaunchOut &out, void *stream);
 // Array-valued ReduceCL, one pass: reduces `count` leaves of `len` floats
 // (from the device pointer table `ptrs`, or, when ptrs is null, the rows
 // base + i * stride) in chunks of `chunk` leaves; chunk c's tree goes to

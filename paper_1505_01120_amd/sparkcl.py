@@ -69,6 +69,21 @@ class Tuning(ctypes.Structure):
                 ("tile", ((ctypes.c_uint32 * TUNE_BUCKETS) * 3) * TUNE_MODES)]
 
 
+class Stage(ctypes.Structure):
+    _fields_ = [("kernel_id", ctypes.c_uint32), ("degree", ctypes.c_uint32),
+                ("coef", ctypes.c_float * 8)]
+
+
+def stage(coef: Sequence[float]) -> Stage:
+    """A POLY chain stage with coefficients coef[k] of v^k."""
+    s = Stage()
+    s.kernel_id = POLY
+    s.degree = max(len(coef) - 1, 0)
+    for i, v in enumerate(coef):
+        s.coef[i] = v
+    return s
+
+
 class ServeStats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in (
         "submitted", "admitted", "completed", "failed", "pending", "in_flight",
@@ -83,7 +98,7 @@ assert ctypes.sizeof(Task) == 96 and ctypes.sizeof(Result) == 64
 # Every symbol declared in include/sparkcl.h.
 EXPORTS = ("sparkcl_init", "sparkcl_destroy", "sparkcl_map", "sparkcl_map_partition",
            "sparkcl_reduce", "sparkcl_reduce_async", "sparkcl_reduce_arrays",
-           "sparkcl_reduce_rows",
+           "sparkcl_reduce_rows", "sparkcl_reduce_chain",
            "sparkcl_submit", "sparkcl_poll",
            "sparkcl_serve_stats_get", "sparkcl_serve_drain", "sparkcl_get_tuning",
            "sparkcl_set_tuning", "sparkcl_autotune", "sparkcl_strerror",
@@ -123,6 +138,7 @@ def load() -> ctypes.CDLL:
             "sparkcl_reduce_async": ([P, TP, U32, I32, P, P, P], I32),
             "sparkcl_reduce_arrays": ([P, U32, ctypes.POINTER(P), U32, U64, P, P], I32),
             "sparkcl_reduce_rows": ([P, U32, P, U64, U32, U64, P, P], I32),
+            "sparkcl_reduce_chain": ([P, TP, U32, ctypes.POINTER(Stage), U32, RP, RP, P], I32),
             "sparkcl_submit": ([P, TP, ctypes.POINTER(U64)], I32),
             "sparkcl_poll": ([P, U64, RP], I32),
             "sparkcl_serve_stats_get": ([P, ctypes.POINTER(ServeStats)], I32),
@@ -275,6 +291,18 @@ class Context:
         _check(load().sparkcl_reduce_async(self._h, arr, n, mode, _ptr(dev_results),
                                            _ptr(dev_total), _stream(stream, self.device)),
                "sparkcl_reduce_async")
+
+    def reduce_chain(self, tasks: Iterable[Task], stages: Sequence[Stage],
+                     stream=None) -> tuple[list[Result], Result]:
+        """ReduceCL over fused map chains: each task's map, then `stages`."""
+        arr, n = _array(tasks)
+        st = (Stage * max(len(stages), 1))(*stages)
+        res = (Result * max(n, 1))()
+        tot = Result()
+        _check(load().sparkcl_reduce_chain(self._h, arr, n, st, len(stages), res,
+                                           ctypes.byref(tot), _stream(stream, self.device)),
+               "sparkcl_reduce_chain")
+        return list(res[:n]), tot
 
     def reduce_arrays(self, arrays: Sequence, out, combiner: int = VADD,
                       stream=None) -> None:
