@@ -1263,20 +1263,64 @@ __global__ __launch_bounds__(kBlock) void k_wordcount(WcArgs a)
 }
 
 // Compaction of the global table into the caller's key/count arrays
-// (unordered); ctl[3] counts the distinct keys, also those past `cap`.
+// (unordered); ctl[3] counts the distinct keys, also those past `cap`.  Each
+// block owns a contiguous range of slots: it counts its keys, reserves room
+// with one atomic add (a counter bumped once per key would serialise on
+// that one address), then writes its keys in slot order at its offset.
 __global__ __launch_bounds__(kBlock) void k_wc_compact(WcArgs a, uint64_t *out_keys,
                                                       uint64_t *out_counts, uint64_t cap)
 {
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t s = (uint64_t)blockIdx.x * kBlock + threadIdx.x; s <= a.mask; s += stride) {
-        const uint64_t k = a.keys[s];
-        if (k == 0)
-            continue;
-        const uint64_t pos = atomicAdd((unsigned long long *)&a.ctl[3], 1ull);
-        if (pos < cap) {
-            out_keys[pos] = k;
-            out_counts[pos] = a.counts[s];
+    __shared__ uint32_t sh_wave[kWaves];
+    __shared__ uint64_t sh_base;
+    const uint64_t slots = a.mask + 1;
+    const uint64_t per = (slots + gridDim.x - 1) / gridDim.x;
+    const uint64_t lo = min(slots, (uint64_t)blockIdx.x * per);
+    const uint64_t hi = min(slots, lo + per);
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    // pass 1: this block's key count
+    uint32_t mine = 0;
+    for (uint64_t s = lo + threadIdx.x; s < hi; s += kBlock)
+        mine += a.keys[s] != 0;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        mine += __shfl_xor(mine, o);
+    if (lane == 0)
+        sh_wave[wave] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t total = 0;
+        for (int w = 0; w < kWaves; ++w)
+            total += sh_wave[w];
+        sh_base = total ? atomicAdd((unsigned long long *)&a.ctl[3], (unsigned long long)total)
+                        : 0;
+    }
+    __syncthreads();
+    // pass 2: keys in slot order, kBlock slots at a time, placed by a block
+    // prefix sum of the occupied slots
+    uint64_t base = sh_base;
+    __syncthreads();
+    for (uint64_t s0 = lo; s0 < hi; s0 += kBlock) {
+        const uint64_t s = s0 + threadIdx.x;
+        const uint64_t k = s < hi ? a.keys[s] : 0;
+        const uint64_t ballot = __ballot(k != 0);
+        const uint32_t before = __popcll(ballot & ((1ull << lane) - 1));
+        if (lane == 0)
+            sh_wave[wave] = __popcll(ballot);
+        __syncthreads();
+        uint32_t off = 0, total = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            off += w < (int)wave ? sh_wave[w] : 0;
+            total += sh_wave[w];
         }
+        if (k != 0) {
+            const uint64_t pos = base + off + before;
+            if (pos < cap) {
+                out_keys[pos] = k;
+                out_counts[pos] = a.counts[s];
+            }
+        }
+        base += total;
+        __syncthreads();
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && a.ctl[1]) {
         const uint64_t pos = atomicAdd((unsigned long long *)&a.ctl[3], 1ull);
