@@ -290,6 +290,30 @@ def bench_host_input(ctx, sc, res, reps=3) -> dict:
             "frac_of_copy": copy_ms / ms}
 
 
+def bench_chain(ctx, sc, res, reps=5) -> dict:
+    """Fused map chain (sec. 3.1.3): the 64 x 2^22 FMUL RDD, then two POLY
+    stages, reduced (SUM+MAX) in one pass with nothing materialised.  Unfused,
+    the same chain is three passes (x,y -> z, z -> w, w -> reduce: 24 B per
+    element against the fused pass's 8).  Kernel time of the blocking call
+    (its own events), median of `reps`."""
+    import statistics
+    tasks = [sc.task(sc.FMUL, res.n, res.x[p * res.n:(p + 1) * res.n],
+                     res.y[p * res.n:(p + 1) * res.n], ops=sc.SUM | sc.MAX, c=0.1)
+             for p in range(res.parts)]
+    stages = [sc.stage((0.5, -0.25, 0.125)), sc.stage((1.0, 2.0))]
+    ctx.reduce_chain(tasks, stages)
+    ms = []
+    for _ in range(reps):
+        ctx.reduce_chain(tasks, stages)
+        ms.append(ctx.last_kernel_ms())
+    k = statistics.median(ms)
+    elems = res.parts * res.n
+    return {"kernel_ms": k, "stages": "FMUL -> POLY2 -> POLY1", "elements_per_s": elems / (k / 1e3),
+            "hbm_GBps": 8 * elems / (k / 1e3) / 1e9,
+            "frac_of_hbm_peak": 8 * elems / (k / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "unfused_bytes_per_element": 24, "fused_bytes_per_element": 8}
+
+
 def bench_wordcount(ctx, sc, reps=5) -> dict:
     """WordCount (sec. 3.2.3) over 1 GiB of device text: a 64 MiB Zipf corpus
     (vocabulary 10^5, s = 1, ending in a newline) repeated 16 times.  Checked
@@ -381,7 +405,8 @@ def bench_uneven(ctx, sc, steps=5) -> dict:
     dres = torch.empty(64 * len(tasks), dtype=torch.uint8, device="cuda")
     out = {"partitions": len(tasks), "elements": int(sizes.sum()),
            "hbm_bytes": bytes_, "mc_samples": mc}
-    for name, mode in (("batched", sc.BATCHED), ("per_launch", sc.PER_LAUNCH)):
+    for name, mode in (("batched", sc.BATCHED), ("graph", sc.GRAPH),
+                       ("per_launch", sc.PER_LAUNCH)):
         wall, ev = time_async(ctx, sc, tasks, mode, steps, 2, dres, None)
         out[name] = {"ms": ev, "wall_ms": wall,
                      "elements_per_s": int(sizes.sum()) / (ev / 1e3)}
@@ -538,6 +563,11 @@ def main() -> int:
         wl, el = time_async(ctx, sc, tasks, sc.PER_LAUNCH, max(5, args.steps // 5), 2, dres, dtot)
         ex["fmul_rdd_per_launch"] = {"ms": el, "wall_ms": wl, "elements_per_s": elems / (el / 1e3),
                                      "hbm_GBps": algo_bytes / (el / 1e3) / 1e9}
+        log("extras: graph replay RDD ...")
+        wg, eg = time_async(ctx, sc, tasks, sc.GRAPH, args.steps, 2, dres, dtot)
+        ex["fmul_rdd_graph"] = {"ms": eg, "wall_ms": wg, "elements_per_s": elems / (eg / 1e3),
+                                "hbm_GBps": algo_bytes / (eg / 1e3) / 1e9,
+                                "note": "the batched launch replayed from its cached hipGraph"}
         log("extras: single partition ...")
         ex["single_partition_poly"] = bench_single_partition(ctx, sc)
         log("extras: monte carlo ...")
@@ -548,6 +578,8 @@ def main() -> int:
         ex["array_reduce"] = bench_array_reduce(ctx, sc, res)
         log("extras: host-resident partitions ...")
         ex["host_input"] = bench_host_input(ctx, sc, res)
+        log("extras: fused map chain ...")
+        ex["map_chain"] = bench_chain(ctx, sc, res)
         log("extras: word count ...")
         ex["wordcount"] = bench_wordcount(ctx, sc)
         log("extras: selective execution ...")

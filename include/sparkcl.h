@@ -84,6 +84,10 @@ extern "C" {
 #define SPARKCL_PER_LAUNCH 0 /* one kernel launch per partition              */
 #define SPARKCL_BATCHED 1    /* all partitions in one persistent launch over
                                 a device tile queue (cached per call content) */
+#define SPARKCL_GRAPH 2      /* the BATCHED launch captured once into a
+                                hipGraph kept with the cached plan, and
+                                replayed on every later call with the same
+                                content (device-resident inputs only) */
 
 typedef struct sparkcl_ctx sparkcl_ctx; /* opaque, library-owned */
 
@@ -196,8 +200,8 @@ SPARKCL_API int sparkcl_map(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_
 
 /* MapCLPartition (sec. 3.1.3): run a partition kernel (MC_PI, ops COUNT) on
    each task and write one partition-level result per task into results[]
-   (host memory, ntasks entries).  mode: SPARKCL_PER_LAUNCH or
-   SPARKCL_BATCHED.  Blocking. */
+   (host memory, ntasks entries).  mode: SPARKCL_PER_LAUNCH,
+   SPARKCL_BATCHED or SPARKCL_GRAPH.  Blocking. */
 SPARKCL_API int sparkcl_map_partition(sparkcl_ctx *ctx, const sparkcl_task *tasks,
                           uint32_t ntasks, int mode, sparkcl_result *results,
                           void *stream);
@@ -214,7 +218,14 @@ SPARKCL_API int sparkcl_reduce(sparkcl_ctx *ctx, const sparkcl_task *tasks,
 /* The same as sparkcl_reduce without the host synchronisation: results are
    written by the GPU to dev_per_task[ntasks] and *dev_total (device memory,
    caller-owned; either may be NULL) in stream order.  Calls that share a
-   context must not overlap in time on different streams. */
+   context must not overlap in time on different streams.
+   Stream capture: a call on a stream that is being captured into the
+   caller's own graph records the plan's launches into that graph, with no
+   memset nodes (the executor leaves its queue head and tickets at zero for
+   the next replay).  The plan must already be cached, so make the same call
+   once outside the capture first; otherwise, and for host-input tasks, the
+   call returns SPARKCL_EINVAL.  With SPARKCL_GRAPH under capture the plan's
+   launches are recorded directly instead of nesting its graph. */
 SPARKCL_API int sparkcl_reduce_async(sparkcl_ctx *ctx, const sparkcl_task *tasks,
                          uint32_t ntasks, int mode,
                          sparkcl_result *dev_per_task,
@@ -235,8 +246,9 @@ typedef struct sparkcl_stage {
    each evaluated one binary32 multiply and add per Horner step with no
    contraction, then the task's reductions; task.out, if set, receives the
    chain's final values (bit-exact).  At most 4 stages; MC_PI and host-input
-   tasks are rejected (EINVAL).  One kernel launch per partition with the
-   per-launch tile table; per_task / total as in sparkcl_reduce.  Blocking. */
+   tasks are rejected (EINVAL).  All partitions run in one persistent launch
+   over the batched tile queue, as SPARKCL_BATCHED; per_task / total as in
+   sparkcl_reduce.  Blocking. */
 SPARKCL_API int sparkcl_reduce_chain(sparkcl_ctx *ctx, const sparkcl_task *tasks,
                                      uint32_t ntasks, const sparkcl_stage *stages,
                                      uint32_t nstages, sparkcl_result *per_task,

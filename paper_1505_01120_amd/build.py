@@ -33,7 +33,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsparkcl.so")
 HOST_LIB = os.path.join(HERE, "libsparkcl_host.so")
 ISA_JSON = os.path.join(HERE, "isa.json")
-KERNELS = ("k_task", "k_batch", "k_serve", "k_map")
+KERNELS = ("k_task", "k_batch", "k_serve", "k_map", "k_chain", "k_tree", "k_wordcount", "k_wc_compact")
 ARCH = "gfx950"
 
 HIP_SOURCES = ["kernels.hip", "api.cpp", "serve.cpp", "autotune.cpp", "tuning.cpp"]
@@ -66,15 +66,16 @@ def isa_report(asm: str) -> dict:
     out = {}
     meta = asm[asm.find("amdhsa.kernels:"):]
     for k in KERNELS:
-        m = re.search(r"\.name:\s+_ZN7sparkcl12_GLOBAL__N_1\d+" + k + r"E.*?(?=\n  - \.|\Z)",
-                      meta, re.S)
-        if not m:
+        # a template kernel has one entry per instantiation: keep the worst
+        blocks = re.findall(r"\.name:\s+_ZN7sparkcl12_GLOBAL__N_1\d+" + k + r"[EI].*?(?=\n  - \.|\Z)",
+                            meta, re.S)
+        if not blocks:
             continue
-        block = m.group(0)
 
         def field(name):
-            f = re.search(r"\." + name + r":\s+(\d+)", block)
-            return int(f.group(1)) if f else None
+            vals = [re.search(r"\." + name + r":\s+(\d+)", b) for b in blocks]
+            vals = [int(f.group(1)) for f in vals if f]
+            return max(vals) if vals else None
         out[k] = {"vgpr": field("vgpr_count"), "sgpr": field("sgpr_count"),
                   "private_segment_bytes": field("private_segment_fixed_size"),
                   "vgpr_spills": field("vgpr_spill_count"),

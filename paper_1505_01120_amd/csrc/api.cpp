@@ -139,6 +139,10 @@ void free_plan(sparkcl_ctx *ctx, Plan *p)
             (void)hipEventDestroy(e);
     if (p->ev_start)
         (void)hipEventDestroy(p->ev_start);
+    if (p->gexec)
+        (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph)
+        (void)hipGraphDestroy(p->graph);
     for (uint64_t off : p->blocks)
         ctx->arena.release(off);
     delete p;
@@ -233,7 +237,9 @@ int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
     // where the batched table's large tiles would leave most of the GPU
     // idle); such a batch is cut with the per-launch table instead.  The
     // choice is a function of the call, so a repeated call is cut the same way.
-    int tm = mode == SPARKCL_BATCHED && !host_in ? TM_BATCHED : TM_PER_LAUNCH;
+    if (host_in && mode == SPARKCL_GRAPH)
+        return fail(SPARKCL_EINVAL, "host-input tasks run in PER_LAUNCH or BATCHED mode");
+    int tm = mode != SPARKCL_PER_LAUNCH && !host_in ? TM_BATCHED : TM_PER_LAUNCH;
     if (tm == TM_BATCHED) {
         uint64_t tiles = 0;
         uint32_t mask = 0;
@@ -292,7 +298,7 @@ int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
         ALLOC(dctl, sizeof(BatchCtl));
         ALLOC(dresults, sizeof(sparkcl_result) * ntasks);
         ALLOC(dtotal, sizeof(sparkcl_result));
-        if (mode == SPARKCL_BATCHED && !host_in)
+        if (mode != SPARKCL_PER_LAUNCH && !host_in)
             ALLOC(dtiles, sizeof(TileRef) * total_tiles);
     }
     if (host_in) {
@@ -443,6 +449,9 @@ int sparkcl::get_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *
             return SPARKCL_OK;
         }
     }
+    if (capturing(stream))
+        return fail(SPARKCL_EINVAL, "no cached plan for this call on a stream under capture: "
+                                    "make the same call once before capturing");
     while (ctx->plans.size() >= kMaxPlans)
         evict_one(ctx);
     Plan *p = nullptr;
@@ -481,6 +490,40 @@ int ensure_pinned(sparkcl_ctx *ctx, uint32_t count)
 
 } // namespace
 
+bool sparkcl::capturing(hipStream_t stream)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
+namespace {
+
+// The kernel launches of a device-input kind-0 plan.
+int launch_device(sparkcl_ctx *ctx, Plan *p, hipStream_t stream)
+{
+    if (p->mode != SPARKCL_PER_LAUNCH) {
+        // One dispatch of the persistent executor: the cached plan holds the
+        // uploaded task table and tile queue, and the kernel leaves its queue
+        // head and tickets at zero, so nothing is cleared between launches.
+        int rc = launch_batch(p->dtasks, p->dtiles, p->ntiles_total, p->grid, p->out, stream);
+        if (rc != SPARKCL_OK)
+            return fail(rc, "executor launch failed: " +
+                                std::string(hipGetErrorString(hipGetLastError())));
+        return SPARKCL_OK;
+    }
+    for (uint32_t i = 0; i < p->ntasks; ++i) {
+        const uint32_t cap = exec_grid(ctx, 1u << (p->tasks[i].kernel_id - 1));
+        int rc = launch_task(p->dtasks + i, p->ntiles[i], std::min(cap, p->ntiles[i]),
+                             p->out, stream);
+        if (rc != SPARKCL_OK)
+            return fail(rc, "kernel launch failed: " +
+                                std::string(hipGetErrorString(hipGetLastError())));
+    }
+    return SPARKCL_OK;
+}
+
+} // namespace
+
 // Enqueue the launches of a reduce-kind plan on `stream`, bracketed by the
 // context's timing events.
 int sparkcl::enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream, bool timed)
@@ -491,16 +534,16 @@ int sparkcl::enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream, bool timed)
     if (timed)
         SPARKCL_HIP(hipEventRecord(ctx->ev0, stream));
     if (p->kind == 4) {
-        // map chains: one launch per partition with the plan's stage table
-        for (uint32_t i = 0; i < p->ntasks; ++i) {
-            const uint32_t cap = exec_grid(ctx, 1u << (p->tasks[i].kernel_id - 1));
-            int rc = launch_chain(p->dtasks + i, p->dchain, p->ntiles[i],
-                                  std::min(cap, p->ntiles[i]), p->out, stream);
-            if (rc != SPARKCL_OK)
-                return fail(rc, "kernel launch failed: " +
-                                    std::string(hipGetErrorString(hipGetLastError())));
-        }
+        // map chains: the persistent executor over the plan's batched tile
+        // queue, with the plan's stage table
+        int rc = launch_chain(p->dtasks, p->dtiles, p->ntiles_total, p->dchain, p->grid, p->out,
+                              stream);
+        if (rc != SPARKCL_OK)
+            return fail(rc, "chain launch failed: " +
+                                std::string(hipGetErrorString(hipGetLastError())));
     } else if (p->host) {
+        if (capturing(stream))
+            return fail(SPARKCL_EINVAL, "host-input tasks cannot be captured into a graph");
         // Staged pipeline: partition i is copied into slot i mod S on the copy
         // stream once the kernel that last used the slot is done, and its
         // kernel runs on `stream` once the copy is done.  The first copies
@@ -534,23 +577,37 @@ int sparkcl::enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream, bool timed)
                                     std::string(hipGetErrorString(hipGetLastError())));
             SPARKCL_HIP(hipEventRecord(p->ev_done[k], stream));
         }
-    } else if (p->mode == SPARKCL_BATCHED) {
-        // One dispatch of the persistent executor: the cached plan holds the
-        // uploaded task table and tile queue, and the kernel leaves its queue
-        // head and tickets at zero, so nothing is cleared between launches.
-        int rc = launch_batch(p->dtasks, p->dtiles, p->ntiles_total, p->grid, p->out, stream);
-        if (rc != SPARKCL_OK)
-            return fail(rc, "executor launch failed: " +
-                                std::string(hipGetErrorString(hipGetLastError())));
-    } else {
-        for (uint32_t i = 0; i < p->ntasks; ++i) {
-            const uint32_t cap = exec_grid(ctx, 1u << (p->tasks[i].kernel_id - 1));
-            int rc = launch_task(p->dtasks + i, p->ntiles[i], std::min(cap, p->ntiles[i]),
-                                 p->out, stream);
-            if (rc != SPARKCL_OK)
-                return fail(rc, "kernel launch failed: " +
-                                    std::string(hipGetErrorString(hipGetLastError())));
+    } else if (p->mode == SPARKCL_GRAPH && !capturing(stream)) {
+        // The launches below, captured once on the library's own stream into
+        // a graph kept with the plan, then replayed: one graph launch per
+        // call.  Under the caller's capture they are recorded directly.
+        if (!p->gexec) {
+            hipStream_t cs = ctx->capture_stream;
+            SPARKCL_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            const int rc = launch_device(ctx, p, cs);
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(cs, &g);
+            if (rc != SPARKCL_OK) {
+                if (g)
+                    (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess)
+                return fail_hip(e, "graph capture");
+            hipGraphExec_t x = nullptr;
+            const hipError_t ei = hipGraphInstantiateWithFlags(&x, g, 0);
+            if (ei != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                return fail_hip(ei, "graph instantiate");
+            }
+            p->graph = g;
+            p->gexec = x;
         }
+        SPARKCL_HIP(hipGraphLaunch(p->gexec, stream));
+    } else {
+        const int rc = launch_device(ctx, p, stream);
+        if (rc != SPARKCL_OK)
+            return rc;
     }
     if (timed) {
         SPARKCL_HIP(hipEventRecord(ctx->ev1, stream));
@@ -610,6 +667,8 @@ int run_blocking(sparkcl_ctx *ctx, int mode, const sparkcl_task *tasks,
                  uint32_t ntasks, sparkcl_result *per_task, sparkcl_result *total,
                  hipStream_t stream)
 {
+    if (capturing(stream))
+        return fail(SPARKCL_EINVAL, "a blocking call cannot run on a stream under capture");
     std::lock_guard<std::mutex> g(ctx->mu);
     return run_blocking_locked(ctx, mode, tasks, ntasks, per_task, total, stream);
 }
@@ -695,6 +754,10 @@ int sparkcl_init(const sparkcl_config *config, sparkcl_ctx **out)
     if (rc != SPARKCL_OK)
         return fail(rc, "occupancy query failed");
     ctx->occ_batch = std::max(1, occ);
+    occ = 0;
+    if ((rc = chain_blocks_per_cu(&occ)) != SPARKCL_OK)
+        return fail(rc, "occupancy query failed");
+    ctx->occ_chain = std::max(1, occ);
 
     tuning_defaults(&ctx->tuning);
     if (config->tune_cache) {
@@ -715,6 +778,7 @@ int sparkcl_init(const sparkcl_config *config, sparkcl_ctx **out)
     SPARKCL_HIP(hipEventCreate(&ctx->ev0));
     SPARKCL_HIP(hipEventCreate(&ctx->ev1));
     SPARKCL_HIP(hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking));
+    SPARKCL_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
     if ((rc = ensure_pinned(ctx.get(), 1024)) != SPARKCL_OK)
         return rc;
     rc = Server::create(ctx.get(), &ctx->server);
@@ -745,6 +809,8 @@ int sparkcl_destroy(sparkcl_ctx *ctx)
         (void)hipEventDestroy(ctx->ev1);
     if (ctx->copy_stream)
         (void)hipStreamDestroy(ctx->copy_stream);
+    if (ctx->capture_stream)
+        (void)hipStreamDestroy(ctx->capture_stream);
     if (ctx->own_arena)
         (void)hipFree(ctx->arena_base);
     delete ctx;
@@ -982,6 +1048,9 @@ int reduce_tree(sparkcl_ctx *ctx, uint32_t combiner, const float *const *arrays,
             break;
         }
     if (!p) {
+        if (capturing(s))
+            return fail(SPARKCL_EINVAL, "no cached plan for this call on a stream under capture: "
+                                        "make the same call once before capturing");
         while (ctx->plans.size() >= kMaxPlans)
             evict_one(ctx);
         if ((rc = build_tree_plan(ctx, combiner, arrays, base, stride, k, len, out, s, &p)) !=
@@ -1022,7 +1091,7 @@ int sparkcl_map_partition(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t 
         return rc;
     if (ntasks && (!tasks || !results))
         return fail(SPARKCL_EINVAL, "tasks/results is NULL");
-    if (mode != SPARKCL_PER_LAUNCH && mode != SPARKCL_BATCHED)
+    if (mode != SPARKCL_PER_LAUNCH && mode != SPARKCL_BATCHED && mode != SPARKCL_GRAPH)
         return fail(SPARKCL_EINVAL, "unknown mode");
     for (uint32_t i = 0; i < ntasks; ++i)
         if (tasks[i].kernel_id != SPARKCL_MC_PI)
@@ -1043,7 +1112,7 @@ int sparkcl_reduce(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t ntasks,
         return rc;
     if (ntasks && !tasks)
         return fail(SPARKCL_EINVAL, "tasks is NULL");
-    if (mode != SPARKCL_PER_LAUNCH && mode != SPARKCL_BATCHED)
+    if (mode != SPARKCL_PER_LAUNCH && mode != SPARKCL_BATCHED && mode != SPARKCL_GRAPH)
         return fail(SPARKCL_EINVAL, "unknown mode");
     if (ntasks == 0) {
         if (total) {
@@ -1067,7 +1136,7 @@ int sparkcl_reduce_async(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t n
         return SPARKCL_OK;
     if (!tasks)
         return fail(SPARKCL_EINVAL, "tasks is NULL");
-    if (mode != SPARKCL_PER_LAUNCH && mode != SPARKCL_BATCHED)
+    if (mode != SPARKCL_PER_LAUNCH && mode != SPARKCL_BATCHED && mode != SPARKCL_GRAPH)
         return fail(SPARKCL_EINVAL, "unknown mode");
     std::lock_guard<std::mutex> g(ctx->mu);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1106,7 +1175,9 @@ int sparkcl_reduce_chain(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t n
         return SPARKCL_OK;
     std::lock_guard<std::mutex> g(ctx->mu);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const uint64_t h = fnv1a(plan_hash(4, SPARKCL_PER_LAUNCH, tasks, ntasks, nullptr, nullptr),
+    if (capturing(st))
+        return fail(SPARKCL_EINVAL, "a blocking call cannot run on a stream under capture");
+    const uint64_t h = fnv1a(plan_hash(4, SPARKCL_BATCHED, tasks, ntasks, nullptr, nullptr),
                              &chain, sizeof(chain));
     Plan *p = nullptr;
     for (auto it = ctx->plans.begin(); it != ctx->plans.end(); ++it) {
@@ -1122,12 +1193,32 @@ int sparkcl_reduce_chain(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t n
     if (!p) {
         while (ctx->plans.size() >= kMaxPlans)
             evict_one(ctx);
-        if ((rc = build_plan(ctx, 0, SPARKCL_PER_LAUNCH, tasks, ntasks, nullptr, nullptr, st,
+        if ((rc = build_plan(ctx, 0, SPARKCL_BATCHED, tasks, ntasks, nullptr, nullptr, st,
                              &p)) != SPARKCL_OK)
             return rc;
         p->kind = 4;
         p->chain = chain;
         p->hash = h;
+        if (!ctx->config.exec_blocks_per_cu) {
+            // The chain's Horner steps add dependent VALU work per element,
+            // whose latency more waves per CU hide.  Measured on MI355X (64 x
+            // 2^22 FMUL partitions): no steps streams best at the map's own
+            // tuned occupancy, 3 steps at 2 blocks per CU, 28 steps (four
+            // degree-7 stages) at 4.
+            uint32_t steps = 0;
+            for (uint32_t s = 0; s < nstages; ++s)
+                steps += chain.deg[s];
+            uint32_t base = 0;
+            for (uint32_t i = 0; i < ntasks; ++i)
+                if (tasks[i].kernel_id == SPARKCL_POLY)
+                    base = std::max(base, tasks[i].degree);
+            steps += base;
+            const uint32_t want = steps == 0 ? 0 : steps <= 4 ? 2 : steps <= 12 ? 3 : 4;
+            const uint32_t cus = (uint32_t)ctx->cus;
+            const uint32_t per_cu =
+                std::min(std::max((p->grid + cus - 1) / cus, want), (uint32_t)ctx->occ_chain);
+            p->grid = std::min(per_cu * cus, p->ntiles_total);
+        }
         void *d = nullptr;
         if ((rc = arena_alloc(ctx, p, sizeof(ChainDev), &d)) != SPARKCL_OK) {
             free_plan(ctx, p);

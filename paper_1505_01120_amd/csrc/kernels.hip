@@ -130,6 +130,7 @@ __device__ __forceinline__ void own_stores_complete()
 // ---- registry maps (one binary32 operation per step, in order) -----------
 template <int D> struct PolyMap {
     static constexpr bool kTwo = false;
+    static constexpr bool kGroup = false;
     float k[8];
     __device__ __forceinline__ float operator()(float x, float) const
     {
@@ -145,6 +146,7 @@ template <int D> struct PolyMap {
 
 struct FmulMap {
     static constexpr bool kTwo = true;
+    static constexpr bool kGroup = false;
     float c;
     __device__ __forceinline__ float operator()(float x, float y) const
     {
@@ -196,6 +198,10 @@ __device__ __forceinline__ void map_quad(const M &f, const float4 &xv,
 // MI355X: keeping a second group in flight while folding -- a register double
 // buffer -- streams slower than this at every tile size and occupancy; the
 // extra requests in flight cost more at the HBM than the overlap gains.)
+//
+// A map with run-time steps (kGroup: a fused chain) maps the whole group at
+// once, so each step's uniform test and coefficient is paid once per group
+// of 4 kUnroll elements per thread rather than once per element.
 template <class M, bool W, class Base>
 __device__ __forceinline__ void stream_groups(const M &f, const float *x4,
                                               const float *y4, float *o4,
@@ -212,10 +218,24 @@ __device__ __forceinline__ void stream_groups(const M &f, const float *x4,
             if (M::kTwo)
                 yv[u] = ld4(y4 + 4 * (q0 + u * kBlock));
         }
+        if constexpr (M::kGroup) {
+            float v[4 * U];
+            f.template group<U>(xv, M::kTwo ? yv : xv, v);
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            map_quad<M, W>(f, xv[u], M::kTwo ? yv[u] : xv[u],
-                           W ? o4 + 4 * (q0 + u * kBlock) : nullptr, a);
+            for (int u = 0; u < U; ++u) {
+                if (W)
+                    st4(o4 + 4 * (q0 + u * kBlock),
+                        make_float4(v[4 * u], v[4 * u + 1], v[4 * u + 2], v[4 * u + 3]));
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    a.add(v[4 * u + e]);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                map_quad<M, W>(f, xv[u], M::kTwo ? yv[u] : xv[u],
+                               W ? o4 + 4 * (q0 + u * kBlock) : nullptr, a);
+        }
     }
 }
 
@@ -697,41 +717,96 @@ __device__ __forceinline__ void rdd_step(const LaunchOut &L)
 
 // ---- fused map chains ------------------------------------------------------
 // A task's registry map followed by up to kMaxPost POLY stages on the running
-// binary32 value (map -> map -> ... -> reduce in one pass).  The stage
-// degrees are run-time values, so the Horner loops are not unrolled; every
-// step is still one binary32 multiply and one add in the written order.
-__device__ __forceinline__ float horner_rt(const float *k, uint32_t d, float x)
+// binary32 value (map -> map -> ... -> reduce in one pass).  Every Horner step
+// is one binary32 multiply and one add in the written order.  Degrees are
+// run-time values: a stage's eight coefficients are loaded (scalar loads from
+// the uniform task or chain table) into registers at the stage's start, and
+// its steps are unrolled to degree 7, each taken under a uniform test, so the
+// coefficients are indexed by constants and the tests cost one scalar branch
+// per group of values.
+
+// t[e] <- p(x[e]) for the degree-d polynomial with coefficients kp[0..d].
+template <int NV>
+__device__ __forceinline__ void horner_group(const float *__restrict__ kp, uint32_t d,
+                                             const float *x, float *t)
 {
-    float t = k[d];
-    for (int i = (int)d - 1; i >= 0; --i) {
-        const float p = t * x;
-        t = p + k[i];
+    float k[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        k[i] = kp[i];
+    float top = k[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+        top = d == (uint32_t)i ? k[i] : top;
+#pragma unroll
+    for (int e = 0; e < NV; ++e)
+        t[e] = top;
+#pragma unroll
+    for (int i = 6; i >= 0; --i) {
+        if ((uint32_t)i < d) {
+#pragma unroll
+            for (int e = 0; e < NV; ++e) {
+                const float p = t[e] * x[e];
+                t[e] = p + k[i];
+            }
+        }
     }
-    return t;
 }
 
-// The stage coefficients stay in the (uniform) task and chain tables and are
-// read with scalar loads inside the Horner loops: copied into a per-thread
-// array indexed by run-time degrees they would live in scratch memory.
 template <bool TWO> struct ChainMap {
     static constexpr bool kTwo = TWO;
-    const float *k0;
+    static constexpr bool kGroup = true;
+    const float *k0; // the task's own POLY coefficients
     uint32_t d0;
     float c;
     const ChainDev *ch;
     uint32_t npost;
+
+    // v[0..NV) <- the chain over x[0..NV) (and y), in element order
+    template <int NV>
+    __device__ __forceinline__ void apply(float *x, const float *y, float *v) const
+    {
+        if (TWO) {
+#pragma unroll
+            for (int e = 0; e < NV; ++e) {
+                const float xy = x[e] * y[e];
+                const float cx = c * x[e];
+                v[e] = xy + cx;
+            }
+        } else {
+            horner_group<NV>(k0, d0, x, v);
+        }
+        for (uint32_t s = 0; s < npost; ++s) {
+#pragma unroll
+            for (int e = 0; e < NV; ++e)
+                x[e] = v[e];
+            horner_group<NV>(ch->coef[s], uni(ch->deg[s]), x, v);
+        }
+    }
+    template <int U>
+    __device__ __forceinline__ void group(const float4 *xv, const float4 *yv, float *v) const
+    {
+        constexpr int NV = 4 * U;
+        float x[NV], y[TWO ? NV : 1];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            x[4 * u] = xv[u].x;
+            x[4 * u + 1] = xv[u].y;
+            x[4 * u + 2] = xv[u].z;
+            x[4 * u + 3] = xv[u].w;
+            if (TWO) {
+                y[4 * u] = yv[u].x;
+                y[4 * u + 1] = yv[u].y;
+                y[4 * u + 2] = yv[u].z;
+                y[4 * u + 3] = yv[u].w;
+            }
+        }
+        apply<NV>(x, y, v);
+    }
     __device__ __forceinline__ float operator()(float x, float y) const
     {
         float v;
-        if (TWO) {
-            const float xy = x * y;
-            const float cx = c * x;
-            v = xy + cx;
-        } else {
-            v = horner_rt(k0, d0, x);
-        }
-        for (uint32_t s = 0; s < npost; ++s)
-            v = horner_rt(ch->coef[s], uni(ch->deg[s]), v);
+        apply<1>(&x, &y, &v);
         return v;
     }
 };
@@ -742,36 +817,32 @@ __device__ __forceinline__ ChainMap<TWO> chain_map(const TaskDev *tp, const Chai
     return ChainMap<TWO>{tp->coef, uni(tp->variant) & 7u, tp->c, ch, uni(ch->npost)};
 }
 
-// One partition with a map chain: blocks stride over its tiles.
-__global__ __launch_bounds__(kBlock) void k_chain(const TaskDev *__restrict__ task,
-                                                  const ChainDev *__restrict__ chain,
-                                                  LaunchOut L)
+// Tile j of a task with a map chain, through the common tile epilogue.
+__device__ __forceinline__ bool chain_tile(const TaskDev *__restrict__ tp,
+                                           const ChainDev *__restrict__ chain, uint32_t j,
+                                           const LaunchOut &L)
 {
-    const uint32_t ntiles = uni(task->ntiles);
-    for (uint32_t j = blockIdx.x; j < ntiles; j += gridDim.x) {
-        const bool done = run_tile_with(task, j, L, [&](Acc &a) -> uint64_t {
-            const uint32_t variant = uni(task->variant);
-            if (variant == V_DECLINED)
-                return 0;
-            const uint32_t T = uni(task->tile_elems);
-            const uint64_t n = uni64(task->n);
-            const float *x = task->in0;
-            const float *y = task->in1;
-            float *o = task->out;
-            const bool two = variant == V_FMUL || variant == V_FMULW;
-            const bool w = variant == V_FMULW || (variant >= V_POLYW && variant < V_FMUL);
-            if (two) {
-                const ChainMap<true> f = chain_map<true>(task, chain);
-                return w ? tile_map<ChainMap<true>, true>(f, x, y, o, n, T, ntiles, j, a)
-                         : tile_map<ChainMap<true>, false>(f, x, y, o, n, T, ntiles, j, a);
-            }
-            const ChainMap<false> f = chain_map<false>(task, chain);
-            return w ? tile_map<ChainMap<false>, true>(f, x, y, o, n, T, ntiles, j, a)
-                     : tile_map<ChainMap<false>, false>(f, x, y, o, n, T, ntiles, j, a);
-        });
-        if (done)
-            rdd_step(L);
-    }
+    return run_tile_with(tp, j, L, [&](Acc &a) -> uint64_t {
+        const uint32_t variant = uni(tp->variant);
+        if (variant == V_DECLINED)
+            return 0;
+        const uint32_t T = uni(tp->tile_elems);
+        const uint32_t nt = uni(tp->ntiles);
+        const uint64_t n = uni64(tp->n);
+        const float *x = tp->in0;
+        const float *y = tp->in1;
+        float *o = tp->out;
+        const bool two = variant == V_FMUL || variant == V_FMULW;
+        const bool w = variant == V_FMULW || (variant >= V_POLYW && variant < V_FMUL);
+        if (two) {
+            const ChainMap<true> f = chain_map<true>(tp, chain);
+            return w ? tile_map<ChainMap<true>, true>(f, x, y, o, n, T, nt, j, a)
+                     : tile_map<ChainMap<true>, false>(f, x, y, o, n, T, nt, j, a);
+        }
+        const ChainMap<false> f = chain_map<false>(tp, chain);
+        return w ? tile_map<ChainMap<false>, true>(f, x, y, o, n, T, nt, j, a)
+                 : tile_map<ChainMap<false>, false>(f, x, y, o, n, T, nt, j, a);
+    });
 }
 
 // ---- kernels --------------------------------------------------------------
@@ -791,9 +862,10 @@ __global__ __launch_bounds__(kBlock) void k_task(const TaskDev *__restrict__ tas
 // while the current one streams, so the queue round trip is hidden.  The last
 // block to leave resets the queue head, so the next launch of the same plan
 // needs no clearing.
-__global__ __launch_bounds__(kBlock) void k_batch(const TaskDev *__restrict__ tasks,
-                                                  const TileRef *__restrict__ tiles,
-                                                  uint32_t ntiles, LaunchOut L)
+template <class Tile>
+__device__ __forceinline__ void executor(const TaskDev *__restrict__ tasks,
+                                         const TileRef *__restrict__ tiles, uint32_t ntiles,
+                                         const LaunchOut &L, Tile tile)
 {
     __shared__ uint32_t sh_tile;
     if (threadIdx.x == 0)
@@ -809,7 +881,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const TaskDev *__restrict__ ta
                                           __HIP_MEMORY_SCOPE_AGENT);
         const TileRef tr = tiles[t];
         const TaskDev *tp = tasks + uni(tr.task);
-        if (run_tile(tp, uni(tr.tile), L))
+        if (tile(tp, uni(tr.tile)))
             rdd_step(L);
         if (threadIdx.x == 0)
             sh_tile = next;
@@ -827,6 +899,25 @@ __global__ __launch_bounds__(kBlock) void k_batch(const TaskDev *__restrict__ ta
                                __HIP_MEMORY_SCOPE_AGENT);
         }
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch(const TaskDev *__restrict__ tasks,
+                                                  const TileRef *__restrict__ tiles,
+                                                  uint32_t ntiles, LaunchOut L)
+{
+    executor(tasks, tiles, ntiles, L,
+             [&](const TaskDev *tp, uint32_t j) { return run_tile(tp, j, L); });
+}
+
+// The persistent executor over tasks that share one map chain.
+__global__ __launch_bounds__(kBlock) void k_chain(const TaskDev *__restrict__ tasks,
+                                                  const TileRef *__restrict__ tiles,
+                                                  uint32_t ntiles,
+                                                  const ChainDev *__restrict__ chain,
+                                                  LaunchOut L)
+{
+    executor(tasks, tiles, ntiles, L,
+             [&](const TaskDev *tp, uint32_t j) { return chain_tile(tp, chain, j, L); });
 }
 
 // MapCL materialisation only (no reduction): out[i] = map(x[i] [, y[i]]),
@@ -1531,14 +1622,13 @@ int launch_task(const TaskDev *dtask, uint32_t ntiles, uint32_t grid,
     return hip_status(hipGetLastError());
 }
 
-int launch_chain(const TaskDev *dtask, const ChainDev *chain, uint32_t ntiles,
-                 uint32_t grid, const LaunchOut &out, void *stream)
+int launch_chain(const TaskDev *dtasks, const TileRef *tiles, uint32_t ntiles,
+                 const ChainDev *chain, uint32_t grid, const LaunchOut &out, void *stream)
 {
     if (ntiles == 0 || grid == 0 || !chain)
         return SPARKCL_EINVAL;
-    grid = grid < ntiles ? grid : ntiles;
-    hipLaunchKernelGGL(k_chain, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, dtask,
-                       chain, out);
+    hipLaunchKernelGGL(k_chain, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, dtasks,
+                       tiles, ntiles, chain, out);
     return hip_status(hipGetLastError());
 }
 
@@ -1663,6 +1753,12 @@ int batch_blocks_per_cu(int *out)
 {
     return hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(
         out, reinterpret_cast<const void *>(k_batch), kBlock, 0));
+}
+
+int chain_blocks_per_cu(int *out)
+{
+    return hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        out, reinterpret_cast<const void *>(k_chain), kBlock, 0));
 }
 
 } // namespace sparkcl

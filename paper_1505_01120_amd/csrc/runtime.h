@@ -89,12 +89,19 @@ struct Plan {
     char *staging = nullptr;
     hipEvent_t ev_start = nullptr;
     std::vector<hipEvent_t> ev_copied, ev_done;
+
+    // SPARKCL_GRAPH: the plan's launches captured once, replayed per call
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
 };
 
 // Plan cache and launch helpers (api.cpp); the caller holds ctx->mu.
+// A call on a stream under capture may only reuse a cached plan: building
+// one uploads and synchronises, which a capture cannot hold.
 int get_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
              uint32_t ntasks, sparkcl_result *ures, sparkcl_result *utot,
              hipStream_t stream, Plan **out);
+bool capturing(hipStream_t stream);
 int enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream, bool timed);
 void drop_plans(sparkcl_ctx *ctx);
 // Persistent-executor grid for a batch holding the kernels in kid_mask
@@ -110,6 +117,7 @@ struct sparkcl_ctx {
     int cus = 0;
     uint32_t ns_per_tick = 10;
     int occ_batch = 1; // batch-executor blocks per CU that fit
+    int occ_chain = 1; // chain-executor blocks per CU that fit
     int occ_wordcount = 0; // word-count blocks per CU that fit (0: not yet asked)
 
     char *arena_base = nullptr;
@@ -123,6 +131,7 @@ struct sparkcl_ctx {
     std::list<sparkcl::Plan *> plans; // most recently used first
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipStream_t copy_stream = nullptr; // host-input staging copies
+    hipStream_t capture_stream = nullptr; // builds SPARKCL_GRAPH plans' graphs
     bool have_ms = false;
     double offload_fixed_s = 0.0;   // selective execution: measured fixed
     double offload_gpu_bps = 0.0;   // cost and streaming rate (0: not yet)

@@ -144,8 +144,10 @@ struct ChainDev {
     uint32_t deg[kMaxPost];
     float coef[kMaxPost][8];
 };
-int launch_chain(const TaskDev *dtask, const ChainDev *chain, uint32_t ntiles,
-                 uint32_t grid, const LaunchOut &out, void *stream);
+// One persistent-executor launch over a batched tile queue whose tasks all
+// run the chain `chain` after their own map.
+int launch_chain(const TaskDev *dtasks, const TileRef *tiles, uint32_t ntiles,
+                 const ChainDev *chain, uint32_t grid, const LaunchOut &out, void *stream);
 // Array-valued ReduceCL, one pass: reduces `count` leaves of `len` floats
 // (from the device pointer table `ptrs`, or, when ptrs is null, the rows
 // base + i * stride) in chunks of `chunk` leaves; chunk c's tree goes to
@@ -182,5 +184,6 @@ int launch_serve(const ServeArgs &a, uint32_t workers, void *stream);
 int launch_fill_pattern(float *p, uint64_t n, uint32_t salt, void *stream);
 // Blocks of the batch executor that fit on one CU at once.
 int batch_blocks_per_cu(int *out);
+int chain_blocks_per_cu(int *out);
 
 } // namespace sparkcl

@@ -27,7 +27,7 @@ OK, EINVAL, ENOKERNEL, ETOOBIG, EAGAIN, EHIP, ETIMEDOUT, ESTOPPED, ENOMEM, ENOTF
 EDECLINED = -10
 POLY, FMUL, MC_PI = 1, 2, 3
 SUM, MAX, COUNT = 1, 2, 4
-PER_LAUNCH, BATCHED = 0, 1
+PER_LAUNCH, BATCHED, GRAPH = 0, 1, 2
 VADD, VMAX = 1, 2
 TASK_HOST_INPUT = 1
 FLAG_SERVE_PER_TASK = 1

@@ -49,7 +49,7 @@ def test_empty_chain_equals_plain_reduce(ctx):
     parts = [datagen.make_part(datagen.FMUL, 300_001, 3), datagen.make_part(datagen.POLY, 77_777, 4)]
     d = DevParts(parts)
     a, ta = ctx.reduce_chain(d.tasks, [])
-    b, tb = ctx.reduce(d.tasks, sc.PER_LAUNCH)
+    b, tb = ctx.reduce(d.tasks, sc.BATCHED)
     for x, y in zip(a, b):
         assert (x.sum, x.max, x.n) == (y.sum, y.max, y.n)
 

@@ -16,7 +16,7 @@ from gpu_helpers import DevParts, check_result, check_total, dev, oracle_result
 
 pytestmark = pytest.mark.gpu
 
-MODES = [sc.PER_LAUNCH, sc.BATCHED]
+MODES = [sc.PER_LAUNCH, sc.BATCHED, sc.GRAPH]
 EDGE_N = [0, 1, 3, 4, 5, 63, 64, 65, 255, 257, 1023, 1025, 4095, 4097, 65535,
           65537, 131073, 1 << 20, (1 << 20) + 3]
 

@@ -308,7 +308,7 @@ def test_hot_kernels_keep_registers_and_no_scratch():
         libbuild.build()
         with open(libbuild.ISA_JSON) as f:
             isa = json.load(f)
-    for k in ("k_task", "k_batch", "k_serve", "k_map"):
+    for k in libbuild.KERNELS:
         assert isa[k]["private_segment_bytes"] == 0, (k, isa[k])
         assert isa[k]["vgpr_spills"] == 0, (k, isa[k])
         assert isa[k]["vgpr"] <= 128, (k, isa[k])
@@ -316,3 +316,20 @@ def test_hot_kernels_keep_registers_and_no_scratch():
     # ten rounds of two 32x32->64 products and two three-way xors per lane
     assert loop["xor3"] == 20 and loop["mad_u64_u32"] >= 20, loop
     assert loop["valu"] < 70, loop
+
+
+def test_header_constants_match_the_binding():
+    """Every numeric #define of the C header that the Python binding also
+    names (without the SPARKCL_ prefix) has the same value there."""
+    with open(HEADER) as f:
+        text = f.read()
+    seen = {}
+    for name, val in re.findall(r"^#define SPARKCL_(\w+)\s+\(?(-?\d+)u?\)?", text, re.M):
+        seen[name] = int(val)
+    for name in ("PER_LAUNCH", "BATCHED", "GRAPH", "POLY", "FMUL", "MC_PI", "SUM", "MAX",
+                 "COUNT", "VADD", "VMAX", "TASK_HOST_INPUT", "FLAG_SERVE_PER_TASK", "OK",
+                 "EINVAL", "EDECLINED", "TUNE_BUCKETS", "TUNE_MODES"):
+        assert name in seen, name
+    for name, val in seen.items():
+        if hasattr(sc, name):
+            assert getattr(sc, name) == val, (name, getattr(sc, name), val)
