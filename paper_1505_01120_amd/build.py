@@ -33,7 +33,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsparkcl.so")
 HOST_LIB = os.path.join(HERE, "libsparkcl_host.so")
 ISA_JSON = os.path.join(HERE, "isa.json")
-KERNELS = ("k_task", "k_batch", "k_serve", "k_map", "k_chain", "k_tree", "k_wordcount", "k_wc_compact")
+KERNELS = ("k_task", "k_batch", "k_serve", "k_map", "k_chain", "k_tree", "k_tree_wide", "k_wordcount",
+           "k_wc_compact")
 ARCH = "gfx950"
 
 HIP_SOURCES = ["kernels.hip", "api.cpp", "serve.cpp", "autotune.cpp", "tuning.cpp"]

@@ -931,11 +931,32 @@ int build_tree_plan(sparkcl_ctx *ctx, uint32_t combiner, const float *const *arr
     std::vector<uint32_t> rows; // output rows of each pass
     uint32_t count = k;
     for (;;) {
-        uint32_t chunk;
+        uint32_t chunk = 0, cpt = 1;
+        // float4 columns: the wide kernel (leaf pairs, 2 or 4 columns per
+        // thread, chunks of up to 64 leaves) when its grid still fills half
+        // the GPU's block slots and at most one more pass follows (many
+        // short columns fold better in the deeper chunks of the 8-leaf
+        // kernel: 65536 rows of 4096 floats took 189 us through 64-leaf
+        // chunks and four passes, 181 us in three); the most columns per
+        // thread first
+        if (vec4) {
+            const uint32_t ch = std::min<uint32_t>(count, kTreeWideChunk);
+            const uint64_t nch = (count + (uint64_t)ch - 1) / ch;
+            for (uint32_t c : {4u, 2u}) {
+                const uint64_t cb = (len / 4 + (uint64_t)kBlock * c - 1) / ((uint64_t)kBlock * c);
+                if (nch <= kTreeWideChunk && cb * nch >= target / 2) {
+                    cpt = c;
+                    chunk = ch;
+                    break;
+                }
+            }
+        }
         // One pass when the columns alone fill the GPU (then long per-thread
         // chains are hidden by other waves) or the chain is short; else fold
         // chunks so the grid of columns x chunks fills the GPU.
-        if (count <= kTreeMaxChunk && (colblocks >= target || count <= 64)) {
+        if (cpt > 1) {
+            // chosen above
+        } else if (count <= kTreeMaxChunk && (colblocks >= target || count <= 64)) {
             chunk = count; // final pass
         } else {
             chunk = pow2_floor(std::max<uint64_t>(1, (uint64_t)count * colblocks / target));
@@ -951,6 +972,7 @@ int build_tree_plan(sparkcl_ctx *ctx, uint32_t combiner, const float *const *arr
         a.len = len;
         a.count = count;
         a.chunk = chunk;
+        a.cpt = cpt;
         p->passes.push_back(a);
         rows.push_back(nchunks);
         if (nchunks == 1)

@@ -1101,6 +1101,94 @@ __global__ __launch_bounds__(kBlock) void k_tree(TreeArgs a)
     TV::st(a.out + (uint64_t)c * a.len + col, acc);
 }
 
+// Wide variant (float4 columns only): a thread owns CPT float4 columns kBlock
+// quads apart, so a block reads CPT * 4 KiB of one leaf contiguously, and the
+// leaves are walked two at a time: each pair is a perfect subtree that enters
+// the counter at level 1.  Fewer leaves and longer runs of each leaf in
+// flight keep the HBM row buffers open (measured on MI355X over 64 arrays of
+// 2^22 floats: one or two leaves at a time with 16-32 KiB per leaf per block
+// stream at 6.6-6.9 TB/s; eight leaves of 4 KiB at 5.3).  The counter holds
+// kTreeWideSlots levels per column, so a chunk has at most 64 leaves.
+constexpr int kTreeWideSlots = 7;
+static_assert(kTreeWideChunk == 1u << (kTreeWideSlots - 1), "chunk fits the counter");
+
+template <int L, uint32_t COMB, int CPT>
+__device__ __forceinline__ void tree_insert_cols(float4 (&slot)[kTreeWideSlots][CPT],
+                                                 uint32_t pos, float4 (&v)[CPT])
+{
+    const uint32_t full = (uint32_t)__builtin_ctz(~(pos >> L));
+#pragma unroll
+    for (int j = L; j < kTreeWideSlots; ++j) {
+        if ((uint32_t)j < L + full) {
+#pragma unroll
+            for (int c = 0; c < CPT; ++c)
+                v[c] = comb<COMB>(slot[j][c], v[c]);
+        } else if ((uint32_t)j == L + full) {
+#pragma unroll
+            for (int c = 0; c < CPT; ++c)
+                slot[j][c] = v[c];
+        }
+    }
+}
+
+template <uint32_t COMB, int CPT>
+__global__ __launch_bounds__(kBlock) void k_tree_wide(TreeArgs a)
+{
+    const uint64_t nq = a.len >> 2;
+    const uint64_t q0 = (uint64_t)blockIdx.x * kBlock * CPT + threadIdx.x;
+    if (q0 >= nq)
+        return; // no barriers below
+    bool ok[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+        ok[c] = q0 + (uint64_t)c * kBlock < nq;
+    const uint32_t ch = blockIdx.y;
+    const uint32_t k0 = ch * a.chunk;
+    const uint32_t m = min(a.count - k0, a.chunk);
+    auto leaf = [&](uint32_t i) -> const float * {
+        const uint32_t kk = k0 + i;
+        return (a.ptrs ? a.ptrs[kk] : a.base + (uint64_t)kk * a.stride) + 4 * q0;
+    };
+    auto load = [&](uint32_t i, float4 (&v)[CPT]) {
+        const float *p = leaf(i);
+#pragma unroll
+        for (int c = 0; c < CPT; ++c)
+            v[c] = ok[c] ? ld4(p + 4 * (uint64_t)c * kBlock) : float4{};
+    };
+    float4 slot[kTreeWideSlots][CPT];
+    uint32_t i = 0;
+    for (; i + 2 <= m; i += 2) {
+        float4 l[CPT], r[CPT];
+        load(i, l);
+        load(i + 1, r);
+#pragma unroll
+        for (int c = 0; c < CPT; ++c)
+            l[c] = comb<COMB>(l[c], r[c]);
+        tree_insert_cols<1, COMB, CPT>(slot, i, l);
+    }
+    if (i < m) {
+        float4 v[CPT];
+        load(i, v);
+        tree_insert_cols<0, COMB, CPT>(slot, i, v);
+    }
+    float4 acc[CPT];
+    bool have = false;
+#pragma unroll
+    for (int j = 0; j < kTreeWideSlots; ++j) {
+        if (m & (1u << j)) {
+#pragma unroll
+            for (int c = 0; c < CPT; ++c)
+                acc[c] = have ? comb<COMB>(slot[j][c], acc[c]) : slot[j][c];
+            have = true;
+        }
+    }
+    float *o = a.out + (uint64_t)ch * a.len + 4 * q0;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+        if (ok[c])
+            st4(o + 4 * (uint64_t)c * kBlock, acc[c]);
+}
+
 __global__ __launch_bounds__(kBlock) void k_zero(uint32_t *p, uint64_t words)
 {
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
@@ -1687,12 +1775,34 @@ int launch_tree(const TreeArgs &a, uint32_t combiner, bool vec4, void *stream)
         return SPARKCL_EINVAL;
     if (vec4 && (a.len & 3u))
         return SPARKCL_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (a.cpt != 1) {
+        if (!vec4 || (a.cpt != 2 && a.cpt != 4) || a.chunk > kTreeWideChunk ||
+            (combiner != SPARKCL_VADD && combiner != SPARKCL_VMAX))
+            return SPARKCL_EINVAL;
+        const uint64_t per_block = (uint64_t)kBlock * a.cpt;
+        const uint64_t cb = ((a.len >> 2) + per_block - 1) / per_block;
+        if (cb > 0x7fffffffull)
+            return SPARKCL_EINVAL;
+        const dim3 grid((uint32_t)cb, nchunks);
+        if (combiner == SPARKCL_VADD) {
+            if (a.cpt == 4)
+                hipLaunchKernelGGL((k_tree_wide<SPARKCL_VADD, 4>), grid, dim3(kBlock), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_tree_wide<SPARKCL_VADD, 2>), grid, dim3(kBlock), 0, s, a);
+        } else {
+            if (a.cpt == 4)
+                hipLaunchKernelGGL((k_tree_wide<SPARKCL_VMAX, 4>), grid, dim3(kBlock), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_tree_wide<SPARKCL_VMAX, 2>), grid, dim3(kBlock), 0, s, a);
+        }
+        return hip_status(hipGetLastError());
+    }
     const uint32_t V = vec4 ? 4 : 1;
     const uint64_t colblocks = (a.len + (uint64_t)kBlock * V - 1) / ((uint64_t)kBlock * V);
     if (colblocks > 0x7fffffffull)
         return SPARKCL_EINVAL;
     const dim3 grid((uint32_t)colblocks, nchunks);
-    hipStream_t s = (hipStream_t)stream;
     if (combiner == SPARKCL_VADD) {
         if (vec4)
             hipLaunchKernelGGL((k_tree<4, SPARKCL_VADD>), grid, dim3(kBlock), 0, s, a);

@@ -160,7 +160,10 @@ struct TreeArgs {
     uint64_t len;
     uint32_t count;
     uint32_t chunk;
+    uint32_t cpt; // float4 columns per thread: 1 (8-leaf groups), or 2 / 4
+                  // (leaf pairs, chunks of at most kTreeWideChunk leaves)
 };
+constexpr uint32_t kTreeWideChunk = 64;
 int launch_tree(const TreeArgs &a, uint32_t combiner, bool vec4, void *stream);
 // WordCount: text of n bytes counted into the global open-addressing table
 // keys/counts of mask + 1 slots (a power of two, cleared beforehand); ctl[0]

@@ -114,6 +114,28 @@ def test_full_size_64_arrays_of_2p22(ctx):
         assert np.array_equal(got[lo:lo + 4096].view(np.uint32), want.view(np.uint32)), lo
 
 
+# Shapes that fill the GPU with float4 columns take the wide kernel (leaf
+# pairs, 2 or 4 float4 columns per thread, chunks of 64 leaves): multi-pass
+# with a ragged last chunk, an odd leaf at the end, and columns that end
+# inside a block's span.  Columns are checked on samples against the oracle.
+@pytest.mark.parametrize("k,length,comb", [(130, (1 << 20) + 4, sc.VADD),
+                                           (77, (1 << 21) + 12, sc.VADD),
+                                           (77, (1 << 21) + 12, sc.VMAX),
+                                           (3, (1 << 21) + 4, sc.VADD),
+                                           (200, 1 << 19, sc.VADD)])
+def test_wide_kernel_shapes(ctx, k, length, comb):
+    dev = torch.empty((k, length), dtype=torch.float32, device="cuda")
+    for e in range(k):
+        dev[e].copy_(torch.from_numpy(datagen.fill(length, k, e, 1, datagen.NORMAL)))
+    out = torch.full((length,), float("nan"), device="cuda")
+    ctx.reduce_arrays(list(dev), out, comb)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for lo in (0, 4096 * 3 + 8, length // 2 - 100, length - 5000):
+        want = oracle.tree_reduce_arrays(dev[:, lo:lo + 5000].cpu().numpy(), comb)
+        assert np.array_equal(got[lo:lo + 5000].view(np.uint32), want.view(np.uint32)), (k, lo)
+
+
 def test_errors(ctx):
     x = torch.zeros(64, device="cuda")
     out = torch.zeros(64, device="cuda")
@@ -136,6 +158,7 @@ def test_errors(ctx):
 # ---- rows of one buffer (sparkcl_reduce_rows) ---------------------------------
 
 @pytest.mark.parametrize("k,length,pad", [(1, 100, 0), (9, 4096, 0), (64, 65_536, 1024),
+                                          (150, (1 << 20) + 8, 4),
                                           (300, 1000, 3), (65_536, 64, 0),
                                           (1 << 20, 16, 0), (5000, 12, 4)])
 def test_rows_match_oracle(ctx, k, length, pad):

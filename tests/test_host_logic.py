@@ -308,10 +308,13 @@ def test_hot_kernels_keep_registers_and_no_scratch():
         libbuild.build()
         with open(libbuild.ISA_JSON) as f:
             isa = json.load(f)
+    # the wide array reduce holds a 7-level counter for 4 float4 columns per
+    # thread and runs at three waves per SIMD (at most 168 VGPRs)
+    limit = {"k_tree_wide": 168}
     for k in libbuild.KERNELS:
         assert isa[k]["private_segment_bytes"] == 0, (k, isa[k])
         assert isa[k]["vgpr_spills"] == 0, (k, isa[k])
-        assert isa[k]["vgpr"] <= 128, (k, isa[k])
+        assert isa[k]["vgpr"] <= limit.get(k, 128), (k, isa[k])
     loop = isa["philox_loop"]
     # ten rounds of two 32x32->64 products and two three-way xors per lane
     assert loop["xor3"] == 20 and loop["mad_u64_u32"] >= 20, loop
