@@ -487,6 +487,9 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--mc-only", action="store_true",
+                    help="only run the Monte-Carlo partition workload (256 x 2^24 samples) "
+                         "and print its line: the short program that VALU counters profile")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (3 times): the "
                          "reference kernel that scales the HBM byte counters")
@@ -512,6 +515,14 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copy", "bytes_read": src.numel() * 4,
                           "bytes_written": dst.numel() * 4, "launches": 3}))
+        return 0
+
+    if args.mc_only:
+        ctx = sc.Context(device=0, arena_bytes=1 << 28)
+        line = {"workload": "Monte-Carlo partitions, 256 x 2^24 Philox4x32-10 samples, batched",
+                **bench_monte_carlo(ctx, sc)}
+        ctx.destroy()
+        print(json.dumps(line), flush=True)
         return 0
 
     parts, n = 64, 1 << 22
