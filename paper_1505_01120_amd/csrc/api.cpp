@@ -209,9 +209,10 @@ uint32_t sparkcl::exec_grid(const sparkcl_ctx *ctx, uint32_t kid_mask, uint64_t 
 
 namespace {
 
+// per_cu: executor blocks per CU for this plan (0: the tuned choice).
 int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
                uint32_t ntasks, sparkcl_result *ures, sparkcl_result *utot,
-               hipStream_t stream, Plan **out)
+               hipStream_t stream, Plan **out, uint32_t per_cu = 0)
 {
     std::unique_ptr<Plan> p(new Plan);
     p->kind = kind;
@@ -250,7 +251,7 @@ int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
             tiles += std::max<uint64_t>(1, (tasks[i].n + T - 1) / T);
             mask |= 1u << (tasks[i].kernel_id - 1);
         }
-        if (tiles < exec_grid(ctx, mask, tiles, ntasks))
+        if (tiles < (per_cu ? per_cu * (uint32_t)ctx->cus : exec_grid(ctx, mask, tiles, ntasks)))
             tm = TM_PER_LAUNCH;
     }
     std::vector<uint64_t> first(ntasks);
@@ -400,7 +401,9 @@ int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
         p->out.total = utot ? utot : p->dtotal;
         p->out.ntasks = ntasks;
         p->out.ns_per_tick = ctx->ns_per_tick;
-        p->grid = std::min(exec_grid(ctx, kid_mask, p->ntiles_total, ntasks), p->ntiles_total);
+        p->grid = std::min(per_cu ? per_cu * (uint32_t)ctx->cus
+                                  : exec_grid(ctx, kid_mask, p->ntiles_total, ntasks),
+                           p->ntiles_total);
     }
     if (host_in) {
         p->ev_copied.assign(p->nslots, nullptr);
@@ -1215,18 +1218,17 @@ int sparkcl_reduce_chain(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t n
     if (!p) {
         while (ctx->plans.size() >= kMaxPlans)
             evict_one(ctx);
-        if ((rc = build_plan(ctx, 0, SPARKCL_BATCHED, tasks, ntasks, nullptr, nullptr, st,
-                             &p)) != SPARKCL_OK)
-            return rc;
-        p->kind = 4;
-        p->chain = chain;
-        p->hash = h;
+        // The chain's Horner steps add dependent VALU work per element, whose
+        // latency more waves per CU hide.  Measured on MI355X (64 x 2^22 FMUL
+        // partitions): no steps streams best at the map's tuned occupancy
+        // (1 block per CU, 316 us), 3 steps at 3 blocks per CU (357 us, 407 at
+        // 1), 28 steps (four degree-7 stages) at 4 (399 us, 791 at 1).  A grid
+        // of more blocks than the batched table has tiles takes the
+        // per-launch table's smaller tiles, so blocks keep pulling tiles from
+        // the queue (with one large tile per block, blocks placed unevenly on
+        // the CUs decide the time: 440-490 us at 2 per CU).
+        uint32_t per_cu = 0;
         if (!ctx->config.exec_blocks_per_cu) {
-            // The chain's Horner steps add dependent VALU work per element,
-            // whose latency more waves per CU hide.  Measured on MI355X (64 x
-            // 2^22 FMUL partitions): no steps streams best at the map's own
-            // tuned occupancy, 3 steps at 2 blocks per CU, 28 steps (four
-            // degree-7 stages) at 4.
             uint32_t steps = 0;
             for (uint32_t s = 0; s < nstages; ++s)
                 steps += chain.deg[s];
@@ -1235,12 +1237,15 @@ int sparkcl_reduce_chain(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t n
                 if (tasks[i].kernel_id == SPARKCL_POLY)
                     base = std::max(base, tasks[i].degree);
             steps += base;
-            const uint32_t want = steps == 0 ? 0 : steps <= 4 ? 2 : steps <= 12 ? 3 : 4;
-            const uint32_t cus = (uint32_t)ctx->cus;
-            const uint32_t per_cu =
-                std::min(std::max((p->grid + cus - 1) / cus, want), (uint32_t)ctx->occ_chain);
-            p->grid = std::min(per_cu * cus, p->ntiles_total);
+            const uint32_t want = steps == 0 ? 0 : steps <= 12 ? 3 : 4;
+            per_cu = std::min(want, (uint32_t)ctx->occ_chain);
         }
+        if ((rc = build_plan(ctx, 0, SPARKCL_BATCHED, tasks, ntasks, nullptr, nullptr, st,
+                             &p, per_cu)) != SPARKCL_OK)
+            return rc;
+        p->kind = 4;
+        p->chain = chain;
+        p->hash = h;
         void *d = nullptr;
         if ((rc = arena_alloc(ctx, p, sizeof(ChainDev), &d)) != SPARKCL_OK) {
             free_plan(ctx, p);
