@@ -490,6 +490,8 @@ def main() -> int:
     ap.add_argument("--mc-only", action="store_true",
                     help="only run the Monte-Carlo partition workload (256 x 2^24 samples) "
                          "and print its line: the short program that VALU counters profile")
+    ap.add_argument("--wc-only", action="store_true",
+                    help="only run WordCount over 1 GiB of text and print its line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (3 times): the "
                          "reference kernel that scales the HBM byte counters")
@@ -517,6 +519,13 @@ def main() -> int:
                           "bytes_written": dst.numel() * 4, "launches": 3}))
         return 0
 
+    if args.wc_only:
+        ctx = sc.Context(device=0, arena_bytes=1 << 30)
+        line = {"workload": "WordCount, 1 GiB of Zipf text (vocabulary 10^5)",
+                **bench_wordcount(ctx, sc)}
+        ctx.destroy()
+        print(json.dumps(line), flush=True)
+        return 0
     if args.mc_only:
         ctx = sc.Context(device=0, arena_bytes=1 << 28)
         line = {"workload": "Monte-Carlo partitions, 256 x 2^24 Philox4x32-10 samples, batched",
