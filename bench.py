@@ -414,68 +414,93 @@ def bench_uneven(ctx, sc, steps=5) -> dict:
     return out
 
 
+def trace_tasks(sc, tr, xp: int, yp: int):
+    """The serving trace as a contiguous array of sparkcl_task (filled column
+    by column; a numpy record type with the C struct's layout)."""
+    import numpy as np
+
+    import datagen
+    dt = np.dtype([("kernel_id", "<u4"), ("reduce_ops", "<u4"), ("n", "<u8"), ("in0", "<u8"),
+                   ("in1", "<u8"), ("out", "<u8"), ("seed", "<u8"), ("partition_id", "<u4"),
+                   ("degree", "<u4"), ("coef", "<f4", (8,)), ("c", "<f4"), ("flags", "<u4")])
+    assert dt.itemsize == ctypes.sizeof(sc.Task)
+    assert all(dt.fields[f][1] == getattr(sc.Task, f).offset for f in dt.names)
+    count = len(tr.sizes)
+    a = np.zeros(count, dtype=dt)
+    kid = tr.kids.astype(np.uint32)
+    mc, fm, po = kid == datagen.MC_PI, kid == datagen.FMUL, kid == datagen.POLY
+    a["kernel_id"] = kid
+    a["reduce_ops"] = np.where(mc, sc.COUNT, sc.SUM | sc.MAX)
+    a["n"] = tr.sizes
+    off = tr.offsets.astype(np.uint64) * np.uint64(4)
+    a["in0"] = np.where(mc, np.uint64(0), np.uint64(xp) + off)
+    a["in1"] = np.where(fm, np.uint64(yp) + off, np.uint64(0))
+    a["partition_id"] = np.where(mc, np.arange(count, dtype=np.uint32), 0)
+    a["degree"] = np.where(po, len(datagen.POLY_COEF) - 1, 0)
+    a["coef"][po, :len(datagen.POLY_COEF)] = datagen.POLY_COEF
+    a["c"] = datagen.FMUL_C
+    return a
+
+
 def serve_run(sc, res: Resident, seconds: float, warm: float, per_task: bool,
               rate: float = 20000.0) -> dict:
-    """Open-loop Poisson stream: submit at the scheduled arrival times, latency
-    = host-observed completion - scheduled arrival (no coordinated omission)."""
+    """Open-loop Poisson stream, replayed by the native load generator
+    (submit at the scheduled arrival times, poll for completions); latency =
+    the server's completion stamp - scheduled arrival (no coordinated
+    omission: a late submit counts against the server)."""
+    import numpy as np
+
     import datagen
     count = int((seconds + warm) * rate)
     pool = res.parts * res.n
     tr = datagen.serving_trace(count, rate=rate, pool=pool)
+    tasks = trace_tasks(sc, tr, res.x.data_ptr(), res.y.data_ptr())
+    sched = np.ascontiguousarray((tr.t_arrive * 1e9).astype(np.int64))
+    done = np.zeros(count, np.int64)
+    status = np.zeros(count, np.int32)
+    lg = ctypes.CDLL(os.path.join(os.path.dirname(os.path.abspath(sc.__file__)),
+                                  "libsparkcl_loadgen.so"))
+    run = lg.sparkcl_loadgen_run
+    run.restype = ctypes.c_int
+    run.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                    ctypes.c_int64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int64),
+                    ctypes.c_void_p, ctypes.c_void_p]
     ctx = sc.Context(device=0, arena_bytes=1 << 30, budget_bytes=64 << 30,
                      flags=sc.FLAG_SERVE_PER_TASK if per_task else 0)
-    xp, yp = res.x.data_ptr(), res.y.data_ptr()
-    tasks = []
-    for i in range(count):
-        k, n, off = int(tr.kids[i]), int(tr.sizes[i]), int(tr.offsets[i])
-        if k == datagen.MC_PI:
-            tasks.append(sc.task(k, n, pid=i))
-        else:
-            tasks.append(sc.task(k, n, xp + 4 * off, yp + 4 * off if k == datagen.FMUL else None,
-                                 coef=datagen.POLY_COEF if k == datagen.POLY else (),
-                                 c=datagen.FMUL_C))
-    sched = (tr.t_arrive * 1e9).astype("int64")
-    tickets = [0] * count
-    results = [None] * count
-    L = sc.load()
-    h = ctx._h
-    r = sc.Result()
-    outstanding = []
-    t0 = time.monotonic_ns() + 20_000_000
-    i = 0
-    while i < count or outstanding:
-        now = time.monotonic_ns()
-        while i < count and t0 + sched[i] <= now:
-            tk = ctypes.c_uint64()
-            rc = L.sparkcl_submit(h, ctypes.byref(tasks[i]), ctypes.byref(tk))
-            if rc != 0:
-                raise RuntimeError(f"submit failed: {rc}")
-            tickets[i] = tk.value
-            outstanding.append(i)
-            i += 1
-        keep = []
-        for j in outstanding:
-            if L.sparkcl_poll(h, tickets[j], ctypes.byref(r)) == 0:
-                results[j] = (r.t_done_ns, r.status, r.n)
-            else:
-                keep.append(j)
-        outstanding = keep
+    t0 = ctypes.c_int64()
+    rc = run(ctx._h, tasks.ctypes.data, sched.ctypes.data, count, 20_000_000, 10_000,
+             ctypes.byref(t0), done.ctypes.data, status.ctypes.data)
     stats = ctx.serve_stats()
     ctx.destroy()
+    if rc != 0:
+        raise RuntimeError(f"load generator failed: {sc.strerror(rc)}")
     first = int(warm * rate)
-    lat = sorted((results[j][0] - (t0 + sched[j])) / 1e3 for j in range(first, count))
-    failed = sum(1 for j in range(count) if results[j][1] != 0)
-    span = (max(results[j][0] for j in range(first, count)) - (t0 + sched[first])) / 1e9
-    elems = sum(int(tr.sizes[j]) for j in range(first, count))
+    lat = np.sort((done[first:] - (t0.value + sched[first:])) / 1e3)
+    failed = int(np.count_nonzero(status))
+    span = (int(done[first:].max()) - (t0.value + int(sched[first]))) / 1e9
+    elems = int(tr.sizes[first:].sum())
 
     def pct(p):
-        return lat[min(len(lat) - 1, int(math.ceil(p / 100 * len(lat))) - 1)]
-    return {"tasks": count - first, "failed": failed, "p50_us": pct(50), "p99_us": pct(99),
-            "p999_us": pct(99.9), "mean_us": statistics.fmean(lat),
-            "tasks_per_s": (count - first) / span, "elements_per_s": elems / span,
+        return float(lat[min(len(lat) - 1, int(math.ceil(p / 100 * len(lat))) - 1)])
+    return {"offered_per_s": rate, "tasks": count - first, "failed": failed,
+            "p50_us": pct(50), "p99_us": pct(99), "p999_us": pct(99.9),
+            "mean_us": float(lat.mean()), "tasks_per_s": (count - first) / span,
+            "elements_per_s": elems / span,
             "executor_launches": stats["executor_launches"],
             "admission_waits": stats["admission_waits"],
             "budget_peak_bytes": stats["budget_peak"]}
+
+
+def serve_sweep(sc, res: Resident, rates=(20e3, 50e3, 100e3, 200e3, 400e3, 800e3, 1.6e6),
+                seconds: float = 1.0, warm: float = 0.25) -> list:
+    """The resident server at rising offered rates, up to saturation (where
+    completions fall behind arrivals and the latency grows with the queue)."""
+    out = []
+    for r in rates:
+        row = serve_run(sc, res, seconds, warm, False, r)
+        out.append({k: row[k] for k in ("offered_per_s", "tasks_per_s", "p50_us", "p99_us",
+                                        "p999_us", "failed", "admission_waits")})
+    return out
 
 
 def main() -> int:
@@ -609,6 +634,8 @@ def main() -> int:
                 log(f"extras: serving ({name}) ...")
                 ex.setdefault("serving", {})[name] = serve_run(
                     sc, res, args.serve_seconds, 1.0, per_task)
+            log("extras: serving rate sweep ...")
+            ex["serving"]["resident_rate_sweep"] = serve_sweep(sc, res)
         line["extras"] = ex
     ctx.destroy()
     print(json.dumps(line), flush=True)

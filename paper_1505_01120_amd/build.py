@@ -5,6 +5,9 @@ Produces, next to this file:
                          with hipcc --offload-arch=gfx950;
   libsparkcl_host.so  -- the pure host logic (arena, admission, tuning cache)
                          behind a small C shim, built with g++, for CPU tests;
+  libsparkcl_loadgen.so -- an open-loop serving load generator over the public
+                         C ABI (submit / poll at scheduled arrival times), for
+                         the serving benchmark;
   isa.json            -- resource figures of the kernels' own gfx950 code
                          (registers, private segment, VALU instructions per
                          Philox block), read from the device assembly of this
@@ -32,6 +35,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsparkcl.so")
 HOST_LIB = os.path.join(HERE, "libsparkcl_host.so")
+LOADGEN_LIB = os.path.join(HERE, "libsparkcl_loadgen.so")
 ISA_JSON = os.path.join(HERE, "isa.json")
 KERNELS = ("k_task", "k_batch", "k_serve", "k_map", "k_chain", "k_tree", "k_tree_wide", "k_wordcount",
            "k_wc_compact")
@@ -135,6 +139,12 @@ def build(verbose: bool = False) -> str:
     _run(["g++", *COMMON, "-shared", *[os.path.join(CSRC, s) for s in HOST_SOURCES],
           "-o", tmp])
     os.replace(tmp, HOST_LIB)
+
+    # the serving load generator: host code on top of the public C ABI
+    tmp = LOADGEN_LIB + ".tmp"
+    _run(["g++", *COMMON, "-shared", os.path.join(CSRC, "loadgen.cpp"), "-L", HERE,
+          "-l:libsparkcl.so", "-Wl,-rpath,$ORIGIN", "-o", tmp])
+    os.replace(tmp, LOADGEN_LIB)
     with open(asm) as f:
         report = isa_report(f.read())
     with open(os.path.join(CSRC, "kernels.hip"), "rb") as f:

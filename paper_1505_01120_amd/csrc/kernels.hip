@@ -1544,10 +1544,14 @@ __global__ __launch_bounds__(kBlock) void k_fill_pattern(float *p, uint64_t n,
 static_assert(offsetof(TaskDev, ntiles) == 96, "word 24 of a descriptor");
 static_assert(offsetof(TaskDev, tile_first) == 120, "words 30-31 of a descriptor");
 
+// Descriptors copied per round of the dispatcher: one per 32-thread group, so
+// a burst of arrivals costs one host-memory round trip per 8 tasks.
+constexpr uint32_t kServeBatch = kBlock / 32;
+
 __device__ __forceinline__ void serve_dispatch(const ServeArgs &a)
 {
     __shared__ uint64_t sh_tail, sh_stop;
-    __shared__ uint32_t sh_nt, sh_first_lo, sh_first_hi;
+    __shared__ uint32_t sh_nt[kServeBatch], sh_first_lo[kServeBatch], sh_first_hi[kServeBatch];
     uint64_t taken = uni64(ld_agent(&a.dev->taken));
     uint64_t last = wall_clock64();
     for (;;) {
@@ -1569,30 +1573,44 @@ __device__ __forceinline__ void serve_dispatch(const ServeArgs &a)
         }
         if (tail > taken) {
             uint64_t pub = 0;
-            for (uint64_t s = taken; s < tail; ++s) {
+            // Descriptors taken .. tail-1, kServeBatch at a time: group g of
+            // 32 threads copies descriptor s0 + g (one 32-bit word per
+            // thread) from the host ring to the device table and writes its
+            // tile-map entries.  The tile ranges of different descriptors are
+            // disjoint (the host assigned them), so the groups work apart.
+            const uint32_t g = threadIdx.x >> 5, l = threadIdx.x & 31u;
+            for (uint64_t s0 = taken; s0 < tail; s0 += kServeBatch) {
+                const uint64_t s = s0 + g;
                 const uint32_t slot = (uint32_t)(s & (a.cap - 1));
-                if (threadIdx.x < 32) {
+                uint32_t nt = 0;
+                uint64_t first = 0;
+                if (s < tail) {
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
                     uint32_t *src = reinterpret_cast<uint32_t *>(
-                                        const_cast<TaskDev *>(a.ring + slot)) + threadIdx.x;
-                    uint32_t *dst = reinterpret_cast<uint32_t *>(a.table + slot) + threadIdx.x;
+                                        const_cast<TaskDev *>(a.ring + slot)) + l;
+                    uint32_t *dst = reinterpret_cast<uint32_t *>(a.table + slot) + l;
                     const uint32_t w = __hip_atomic_load(src, __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_SYSTEM);
                     __hip_atomic_store(dst, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (threadIdx.x == 24)
-                        sh_nt = w;
-                    if (threadIdx.x == 30)
-                        sh_first_lo = w;
-                    if (threadIdx.x == 31)
-                        sh_first_hi = w;
+                    if (l == 24)
+                        sh_nt[g] = w;
+                    if (l == 30)
+                        sh_first_lo[g] = w;
+                    if (l == 31)
+                        sh_first_hi[g] = w;
                 }
                 __syncthreads();
-                const uint64_t first = ((uint64_t)uni(sh_first_hi) << 32) | uni(sh_first_lo);
-                const uint32_t nt = uni(sh_nt);
-                for (uint32_t k = threadIdx.x; k < nt; k += kBlock)
-                    __hip_atomic_store(a.tilemap + ((first + k) & (a.tile_cap - 1)), slot,
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                pub = first + nt;
+                if (s < tail) {
+                    nt = sh_nt[g];
+                    first = ((uint64_t)sh_first_hi[g] << 32) | sh_first_lo[g];
+                    for (uint32_t k = l; k < nt; k += 32)
+                        __hip_atomic_store(a.tilemap + ((first + k) & (a.tile_cap - 1)), slot,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                // the last descriptor of the round ends the published range
+                const uint32_t last = (uint32_t)min((uint64_t)kServeBatch, tail - s0) - 1;
+                pub = (((uint64_t)uni(sh_first_hi[last]) << 32) | uni(sh_first_lo[last])) +
+                      uni(sh_nt[last]);
                 __syncthreads();
             }
             // table and tile-map entries were written with agent-scope atomic

@@ -185,3 +185,37 @@ def test_serve_watchdog_fails_long_task_then_recovers():
             check_result(q, oracle_result(p), p.kid, p.ops, f"n={p.n}")
     finally:
         c.destroy()
+
+
+def test_native_load_generator_replays_a_trace(ctx):
+    """The serving benchmark's load generator (libsparkcl_loadgen.so, over the
+    public C ABI): a short Poisson trace is submitted at its scheduled times,
+    every task completes with status OK after its scheduled arrival, and the
+    results it collects are the server's."""
+    import ctypes
+    import os
+
+    parts = mixed_parts(64, 5)
+    d = DevParts(parts)
+    count = 2000
+    tasks = (sc.Task * count)(*[d.tasks[i % len(parts)] for i in range(count)])
+    sched = (np.arange(count, dtype=np.int64) * 50_000)  # 20K tasks/s
+    done = np.zeros(count, np.int64)
+    status = np.full(count, -99, np.int32)
+    lg = ctypes.CDLL(os.path.join(os.path.dirname(os.path.abspath(sc.__file__)),
+                                  "libsparkcl_loadgen.so"))
+    run = lg.sparkcl_loadgen_run
+    run.restype = ctypes.c_int
+    run.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                    ctypes.c_int64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int64),
+                    ctypes.c_void_p, ctypes.c_void_p]
+    t0 = ctypes.c_int64()
+    rc = run(ctx._h, ctypes.addressof(tasks), sched.ctypes.data, count, 5_000_000, 10_000,
+             ctypes.byref(t0), done.ctypes.data, status.ctypes.data)
+    assert rc == 0
+    assert np.all(status == 0)
+    assert np.all(done >= t0.value + sched)
+    # unsorted arrival times are refused
+    bad = sched[::-1].copy()
+    assert run(ctx._h, ctypes.addressof(tasks), bad.ctypes.data, count, 0, 1000,
+               ctypes.byref(t0), done.ctypes.data, status.ctypes.data) == sc.EINVAL

@@ -336,3 +336,17 @@ def test_header_constants_match_the_binding():
     for name, val in seen.items():
         if hasattr(sc, name):
             assert getattr(sc, name) == val, (name, getattr(sc, name), val)
+
+
+def test_load_generator_library_exports_one_entry(lib):
+    """The serving load generator is its own library on top of the C ABI:
+    one exported entry point, refusing bad arguments without a GPU."""
+    if not os.path.exists(libbuild.LOADGEN_LIB):
+        libbuild.build()
+    out = subprocess.run(["nm", "-D", "--defined-only", libbuild.LOADGEN_LIB],
+                         capture_output=True, text=True, check=True).stdout
+    assert sorted(set(re.findall(r" T (\w+)", out))) == ["sparkcl_loadgen_run"]
+    lg = ctypes.CDLL(libbuild.LOADGEN_LIB)
+    t0 = ctypes.c_int64()
+    assert lg.sparkcl_loadgen_run(None, None, None, ctypes.c_uint64(0), ctypes.c_int64(0),
+                                  ctypes.c_uint32(0), ctypes.byref(t0), None, None) == sc.EINVAL
