@@ -168,8 +168,15 @@ def cpu_baseline(res: Resident, reps: int = 3) -> dict:
     run([0, 1])
     single = 2 * res.n / (time.perf_counter() - t1)
     med = statistics.median(times)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                         "")
+    except OSError:
+        pass
     return {"value": res.parts * res.n / med, "unit": "elements/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "host_cpus": os.cpu_count(), "cpu_model": model,
             "sample": f"all {res.parts} partitions x {res.n} pairs, partition-parallel over "
                       f"{cores} threads, median of {reps}",
             "single_thread_elements_per_s": single}
@@ -411,6 +418,17 @@ def bench_uneven(ctx, sc, steps=5) -> dict:
         out[name] = {"ms": ev, "wall_ms": wall,
                      "elements_per_s": int(sizes.sum()) / (ev / 1e3)}
     out["batched_speedup"] = out["per_launch"]["ms"] / out["batched"]["ms"]
+    # lower bound: the larger of the HBM time of the POLY/FMUL bytes and the
+    # VALU time of the Monte-Carlo samples (Philox blocks x VALU per block)
+    t_hbm = bytes_ / (HBM_PEAK_GBS * 1e9) * 1e3
+    isa = load_isa()
+    valu = isa["philox_loop"]["valu"] if isa and "philox_loop" in isa else None
+    if valu:
+        t_valu = (mc / 2) * valu / (ALU_PEAK_TOPS * 1e12) * 1e3
+        bound = max(t_hbm, t_valu)
+        out["lower_bound"] = {"hbm_ms": t_hbm, "mc_valu_ms": t_valu, "ms": bound,
+                              "hbm_frac": t_hbm / out["batched"]["ms"],
+                              "bound_frac": bound / out["batched"]["ms"]}
     return out
 
 
