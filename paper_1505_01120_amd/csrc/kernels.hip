@@ -552,6 +552,25 @@ __device__ __forceinline__ void read_result(const sparkcl_result *p, double &s,
 }
 
 // ---- one tile, start to finish ------------------------------------------
+// Thread 0 of the block that completes a task: write its result and, when
+// serving, publish the completion word.
+__device__ __forceinline__ void finish_task(const TaskDev *__restrict__ tp, const LaunchOut &L,
+                                            const Red &t, uint64_t t_start, uint32_t variant,
+                                            uint32_t idx)
+{
+    write_result(L.results + idx, uni(tp->ops), t, t_start, device_ns(L.ns_per_tick),
+                 variant == V_DECLINED ? SPARKCL_EDECLINED : SPARKCL_OK);
+    if (L.done) {
+        // Serving: the result lives in host memory; publish it with a
+        // system-scope release so the host sees the result before the word.
+        __threadfence_system();
+        __hip_atomic_store(L.done + idx, uni64(tp->seq) + 1, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+    } else {
+        own_stores_complete();
+    }
+}
+
 // Returns true in the block that completed the task (after writing its
 // result); callers use it only for the RDD-level step.
 template <class Body>
@@ -572,6 +591,17 @@ __device__ __forceinline__ bool run_tile_with(const TaskDev *__restrict__ tp, ui
     r = block_reduce(r);
 
     const uint32_t idx = uni(tp->index);
+    if (ntiles == 1) {
+        // A task of one tile: its block finishes the task by construction,
+        // so the partial, the start-time word and the arrival ticket (three
+        // round trips to memory-side atomics) are skipped.  The ordered
+        // combine of a single partial is the partial itself, except that its
+        // FP64 sum starts from +0.0, which the + 0.0 below reproduces.
+        if (threadIdx.x == 0)
+            finish_task(tp, L, Red{r.s + 0.0, r.m, r.h, count}, t0, variant, idx);
+        __syncthreads();
+        return true;
+    }
     if (threadIdx.x == 0) {
         store_partial(tp->partials + j, r.s, r.m, r.h, count);
         // t_start keeps the bitwise complement of the earliest tile start, so
@@ -602,22 +632,11 @@ __device__ __forceinline__ bool run_tile_with(const TaskDev *__restrict__ tp, ui
     });
     if (threadIdx.x == 0) {
         const uint64_t t_start = ~ld_agent(&sync[idx].t_start);
-        write_result(L.results + idx, uni(tp->ops), t, t_start,
-                     device_ns(L.ns_per_tick),
-                     variant == V_DECLINED ? SPARKCL_EDECLINED : SPARKCL_OK);
         __hip_atomic_store(&sync[idx].t_start, 0ull, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&sync[idx].ticket, 0u, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-        if (L.done) {
-            // Serving: the result lives in host memory; publish it with a
-            // system-scope release so the host sees the result before the word.
-            __threadfence_system();
-            __hip_atomic_store(L.done + idx, uni64(tp->seq) + 1, __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_SYSTEM);
-        } else {
-            own_stores_complete();
-        }
+        finish_task(tp, L, t, t_start, variant, idx);
     }
     // A barrier closes every thread-0 region that ends a loop iteration of the
     // callers: without it the compiler may sink the region past the loop
