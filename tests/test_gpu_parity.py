@@ -262,6 +262,34 @@ def test_monte_carlo_full_size(ctx):
         assert per[pid].count == oracle.mc_count(0, pid, n), f"pid {pid}"
 
 
+def test_beyond_32_bit_element_counts(ctx):
+    # One partition of 2^32 + 7 floats (16 GiB): element indices past 32 bits
+    # in the batched, graph and per-launch paths and in the materialised map.
+    # x is 1 except at a few marked positions, so the sum has a closed form
+    # that FP64 holds exactly (integers and halves below 2^53).
+    n = (1 << 32) + 7
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    marks = [0, (1 << 31) + 1, (1 << 32) - 1, 1 << 32, n - 1]
+    vals = [2.0, 3.0, 0.5, 4.0, 8.0]
+    for i, v in zip(marks, vals):
+        x[i] = v
+    want = float(n - len(marks)) + sum(vals)
+    t = sc.task(sc.POLY, n, x, coef=(0.0, 1.0))  # y = x
+    for mode in MODES:
+        per, tot = ctx.reduce([t], mode)
+        assert (per[0].n, per[0].sum, per[0].max, per[0].status) == (n, want, 8.0, 0), mode
+        assert (tot.n, tot.sum) == (n, want)
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+    ctx.map([sc.task(sc.POLY, n, x, out=out, coef=(0.5, 2.0))])  # y = 0.5 + 2x, exact
+    torch.cuda.synchronize()
+    for i, v in zip(marks, vals):
+        assert out[i].item() == 0.5 + 2.0 * v, i
+    for i in (1, 12345, (1 << 32) + 3):
+        assert out[i].item() == 2.5, i
+    del x, out
+    torch.cuda.empty_cache()
+
+
 def test_uneven_batch_reduced(ctx):
     # log-normal sizes (median 4K, clipped 16..256K) with mixed kernels
     sizes = datagen.lognormal_sizes(300, 5, 3, 4096, math.log(4.0), 16, 262144)
