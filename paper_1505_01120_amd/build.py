@@ -41,7 +41,8 @@ KERNELS = ("k_task", "k_batch", "k_serve", "k_map", "k_chain", "k_tree", "k_tree
            "k_wc_compact")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["kernels.hip", "api.cpp", "serve.cpp", "autotune.cpp", "tuning.cpp"]
+HIP_SOURCES = ["kernels.hip", "api.cpp", "arrays.cpp", "chain.cpp", "wordcount.cpp", "serve.cpp",
+               "autotune.cpp", "tuning.cpp"]
 HOST_SOURCES = ["tuning.cpp", "hostlogic_capi.cpp"]
 
 COMMON = ["-std=c++17", "-O3", "-fPIC", "-fvisibility=hidden", "-Wall", "-Wextra", "-Wno-unused-parameter",

@@ -25,9 +25,7 @@ namespace sparkcl {
 
 namespace {
 thread_local std::string t_last_error;
-constexpr uint32_t kMaxPlans = 32;
 constexpr uint32_t kStagingSlots = 3; // host-input partitions in flight
-constexpr uint64_t kMaxN = 1ull << 40;
 } // namespace
 
 int fail(int code, const std::string &msg)
@@ -98,9 +96,6 @@ bool declined(const sparkcl_ctx *ctx, const sparkcl_task &t)
     return ctx->config.offload_min_bytes && offload_cost(t) < ctx->config.offload_min_bytes;
 }
 
-} // namespace sparkcl
-
-namespace {
 
 // FNV-style hash over 8-byte words (byte tail folded in), for plan lookup.
 uint64_t fnv1a(uint64_t h, const void *p, size_t n)
@@ -177,7 +172,7 @@ int arena_alloc(sparkcl_ctx *ctx, Plan *p, uint64_t bytes, void **out)
     }
 }
 
-} // namespace
+} // namespace sparkcl
 
 uint32_t sparkcl::exec_grid(const sparkcl_ctx *ctx, uint32_t kid_mask, uint64_t ntiles,
                             uint64_t ntasks)
@@ -207,12 +202,9 @@ uint32_t sparkcl::exec_grid(const sparkcl_ctx *ctx, uint32_t kid_mask, uint64_t 
     return std::max(1u, std::min(per_cu, occ)) * (uint32_t)ctx->cus;
 }
 
-namespace {
-
-// per_cu: executor blocks per CU for this plan (0: the tuned choice).
-int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
-               uint32_t ntasks, sparkcl_result *ures, sparkcl_result *utot,
-               hipStream_t stream, Plan **out, uint32_t per_cu = 0)
+int sparkcl::build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
+                        uint32_t ntasks, sparkcl_result *ures, sparkcl_result *utot,
+                        hipStream_t stream, Plan **out, uint32_t per_cu)
 {
     std::unique_ptr<Plan> p(new Plan);
     p->kind = kind;
@@ -381,19 +373,19 @@ int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
         // (Sorted by cost alone, the large streaming tiles all came first and
         // the Monte-Carlo tiles bunched later; on the 4096-task uneven batch
         // the mix took 651 us against 498 us for its streaming part alone.)
+        auto work = [&](uint32_t i) {
+            const uint32_t kid = tasks[i].kernel_id;
+            return (double)tasks[i].n * (kid == SPARKCL_POLY ? 4 : kid == SPARKCL_FMUL ? 8 : 5);
+        };
         std::vector<uint32_t> mem, alu;
         double tot_mem = 0, tot_alu = 0;
         for (uint32_t i : order) {
-            const double work = (double)tasks[i].n *
-                                (tasks[i].kernel_id == SPARKCL_POLY   ? 4
-                                 : tasks[i].kernel_id == SPARKCL_FMUL ? 8
-                                                                      : 5);
             if (tasks[i].kernel_id == SPARKCL_MC_PI) {
                 alu.push_back(i);
-                tot_alu += work;
+                tot_alu += work(i);
             } else {
                 mem.push_back(i);
-                tot_mem += work;
+                tot_mem += work(i);
             }
         }
         tiles.reserve(total_tiles);
@@ -404,11 +396,7 @@ int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
                 ia == alu.size() ||
                 (im < mem.size() && done_mem * tot_alu <= done_alu * tot_mem);
             const uint32_t i = take_mem ? mem[im++] : alu[ia++];
-            const double work = (double)tasks[i].n *
-                                (tasks[i].kernel_id == SPARKCL_POLY   ? 4
-                                 : tasks[i].kernel_id == SPARKCL_FMUL ? 8
-                                                                      : 5);
-            (take_mem ? done_mem : done_alu) += work;
+            (take_mem ? done_mem : done_alu) += work(i);
             for (uint32_t j = 0; j < p->ntiles[i]; ++j)
                 tiles.push_back(TileRef{i, j});
         }
@@ -459,8 +447,6 @@ int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
     return SPARKCL_OK;
 }
 
-} // namespace
-
 int sparkcl::get_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
                       uint32_t ntasks, sparkcl_result *ures, sparkcl_result *utot,
                       hipStream_t stream, Plan **out)
@@ -508,9 +494,7 @@ void sparkcl::drop_plans(sparkcl_ctx *ctx)
     ctx->plans.clear();
 }
 
-namespace {
-
-int ensure_pinned(sparkcl_ctx *ctx, uint32_t count)
+int sparkcl::ensure_pinned(sparkcl_ctx *ctx, uint32_t count)
 {
     if (count <= ctx->pinned_cap)
         return SPARKCL_OK;
@@ -525,7 +509,6 @@ int ensure_pinned(sparkcl_ctx *ctx, uint32_t count)
     return SPARKCL_OK;
 }
 
-} // namespace
 
 bool sparkcl::capturing(hipStream_t stream)
 {
@@ -653,12 +636,9 @@ int sparkcl::enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream, bool timed)
     return SPARKCL_OK;
 }
 
-namespace {
-
-// Launches plan `p` and copies its results back (the caller holds ctx->mu).
-int launch_and_collect(sparkcl_ctx *ctx, Plan *p, const sparkcl_task *tasks,
-                       uint32_t ntasks, sparkcl_result *per_task, sparkcl_result *total,
-                       hipStream_t stream)
+int sparkcl::launch_and_collect(sparkcl_ctx *ctx, Plan *p, const sparkcl_task *tasks,
+                                uint32_t ntasks, sparkcl_result *per_task,
+                                sparkcl_result *total, hipStream_t stream)
 {
     int rc;
     if ((rc = ensure_pinned(ctx, ntasks + 1)) != SPARKCL_OK)
@@ -687,6 +667,15 @@ int launch_and_collect(sparkcl_ctx *ctx, Plan *p, const sparkcl_task *tasks,
     return SPARKCL_OK;
 }
 
+int sparkcl::check_ctx(sparkcl_ctx *ctx)
+{
+    if (!ctx)
+        return fail(SPARKCL_EINVAL, "null context");
+    SPARKCL_HIP(hipSetDevice(ctx->device));
+    return SPARKCL_OK;
+}
+
+namespace {
 
 // The caller holds ctx->mu.
 int run_blocking_locked(sparkcl_ctx *ctx, int mode, const sparkcl_task *tasks,
@@ -708,14 +697,6 @@ int run_blocking(sparkcl_ctx *ctx, int mode, const sparkcl_task *tasks,
         return fail(SPARKCL_EINVAL, "a blocking call cannot run on a stream under capture");
     std::lock_guard<std::mutex> g(ctx->mu);
     return run_blocking_locked(ctx, mode, tasks, ntasks, per_task, total, stream);
-}
-
-int check_ctx(sparkcl_ctx *ctx)
-{
-    if (!ctx)
-        return fail(SPARKCL_EINVAL, "null context");
-    SPARKCL_HIP(hipSetDevice(ctx->device));
-    return SPARKCL_OK;
 }
 
 } // namespace
@@ -887,261 +868,6 @@ int sparkcl_map(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t ntasks, vo
     return SPARKCL_OK;
 }
 
-namespace {
-
-constexpr uint32_t kTreeMaxK = 1u << 24;
-constexpr uint32_t kTreeMaxChunk = 4096; // leaves per chunk the kernel's counter holds
-constexpr uint32_t kTreeMaxChunks = 65535;
-
-uint32_t pow2_floor(uint64_t v)
-{
-    uint32_t p = 1;
-    while ((uint64_t)p * 2 <= v && p < (1u << 31))
-        p *= 2;
-    return p;
-}
-
-// Array reduces are keyed by kind (2: pointer table, 3: rows of one buffer),
-// combiner, shape, output and the leaves (the table, or base and stride).
-uint64_t tree_hash(int kind, uint32_t combiner, const float *const *arrays,
-                   const float *base, uint64_t stride, uint32_t k, uint64_t len,
-                   const float *out)
-{
-    uint64_t h = 0xCBF29CE484222325ull;
-    h = fnv1a(h, &kind, sizeof(kind));
-    h = fnv1a(h, &combiner, sizeof(combiner));
-    h = fnv1a(h, &k, sizeof(k));
-    h = fnv1a(h, &len, sizeof(len));
-    h = fnv1a(h, &out, sizeof(out));
-    h = fnv1a(h, &base, sizeof(base));
-    h = fnv1a(h, &stride, sizeof(stride));
-    return arrays ? fnv1a(h, arrays, sizeof(const float *) * k) : h;
-}
-
-bool tree_plan_matches(const Plan *p, int kind, uint64_t h, uint32_t combiner,
-                       const float *const *arrays, const float *base, uint64_t stride,
-                       uint32_t k, uint64_t len, const float *out)
-{
-    if (p->kind != kind || p->hash != h || p->combiner != combiner || p->len != len ||
-        p->user_out != out || p->nleaves != k || p->leaf_base != base ||
-        p->leaf_stride != stride)
-        return false;
-    return !arrays ||
-           std::memcmp(p->leaves.data(), arrays, sizeof(const float *) * k) == 0;
-}
-
-// Splits the reduction into passes: each pass folds chunks of `chunk` leaves
-// (a power of two unless it is the last pass), with enough chunks that the
-// grid fills the GPU when the arrays are short, and writes one row per
-// chunk; the next pass folds those rows.
-int build_tree_plan(sparkcl_ctx *ctx, uint32_t combiner, const float *const *arrays,
-                    const float *base, uint64_t stride, uint32_t k, uint64_t len,
-                    float *out, hipStream_t stream, Plan **res)
-{
-    std::unique_ptr<Plan> p(new Plan);
-    p->kind = arrays ? 2 : 3;
-    p->combiner = combiner;
-    p->len = len;
-    p->user_out = out;
-    p->nleaves = k;
-    p->leaf_base = base;
-    p->leaf_stride = stride;
-    bool vec4 = (len & 3u) == 0 && ((uintptr_t)out & 15u) == 0;
-    if (arrays) {
-        p->leaves.assign(arrays, arrays + k);
-        for (uint32_t i = 0; i < k; ++i) {
-            if (!arrays[i])
-                return fail(SPARKCL_EINVAL, "array " + std::to_string(i) + " is NULL");
-            if ((uintptr_t)arrays[i] & 3u)
-                return fail(SPARKCL_EINVAL, "arrays must be 4-byte aligned");
-            if ((uintptr_t)arrays[i] & 15u)
-                vec4 = false;
-        }
-    } else if (((uintptr_t)base & 15u) || (stride & 3u)) {
-        vec4 = false;
-    }
-    p->vec4 = vec4;
-    const uint64_t V = vec4 ? 4 : 1;
-    const uint64_t colblocks = (len + kBlock * V - 1) / (kBlock * V);
-    const uint64_t target = 4ull * (uint64_t)ctx->cus; // blocks that fill the GPU
-
-    std::vector<uint32_t> rows; // output rows of each pass
-    uint32_t count = k;
-    for (;;) {
-        uint32_t chunk = 0, cpt = 1;
-        // float4 columns: the wide kernel (leaf pairs, 2 or 4 columns per
-        // thread, chunks of up to 64 leaves) when its grid still fills half
-        // the GPU's block slots and at most one more pass follows (many
-        // short columns fold better in the deeper chunks of the 8-leaf
-        // kernel: 65536 rows of 4096 floats took 189 us through 64-leaf
-        // chunks and four passes, 181 us in three); the most columns per
-        // thread first
-        if (vec4) {
-            const uint32_t ch = std::min<uint32_t>(count, kTreeWideChunk);
-            const uint64_t nch = (count + (uint64_t)ch - 1) / ch;
-            for (uint32_t c : {4u, 2u}) {
-                const uint64_t cb = (len / 4 + (uint64_t)kBlock * c - 1) / ((uint64_t)kBlock * c);
-                if (nch <= kTreeWideChunk && cb * nch >= target / 2) {
-                    cpt = c;
-                    chunk = ch;
-                    break;
-                }
-            }
-        }
-        // One pass when the columns alone fill the GPU (then long per-thread
-        // chains are hidden by other waves) or the chain is short; else fold
-        // chunks so the grid of columns x chunks fills the GPU.
-        if (cpt > 1) {
-            // chosen above
-        } else if (count <= kTreeMaxChunk && (colblocks >= target || count <= 64)) {
-            chunk = count; // final pass
-        } else {
-            chunk = pow2_floor(std::max<uint64_t>(1, (uint64_t)count * colblocks / target));
-            chunk = std::max<uint32_t>(chunk, 8);
-            chunk = std::min<uint32_t>(chunk, kTreeMaxChunk);
-            while ((count + (uint64_t)chunk - 1) / chunk > kTreeMaxChunks)
-                chunk *= 2;
-            if (chunk >= count)
-                chunk = count;
-        }
-        const uint32_t nchunks = (uint32_t)((count + (uint64_t)chunk - 1) / chunk);
-        TreeArgs a{};
-        a.len = len;
-        a.count = count;
-        a.chunk = chunk;
-        a.cpt = cpt;
-        p->passes.push_back(a);
-        rows.push_back(nchunks);
-        if (nchunks == 1)
-            break;
-        count = nchunks;
-    }
-
-    // scratch: rows of pass 0 in buffer 0, of pass 1 in buffer 1, then alternate
-    float *scratch[2] = {nullptr, nullptr};
-    for (size_t i = 0; i + 1 < p->passes.size() && i < 2; ++i) {
-        const uint64_t bytes = (uint64_t)rows[i] * len * 4;
-        void *q = nullptr;
-        int rc = arena_alloc(ctx, p.get(), std::max<uint64_t>(bytes, 256), &q);
-        if (rc != SPARKCL_OK) {
-            Plan *raw = p.release();
-            free_plan(ctx, raw);
-            return rc;
-        }
-        scratch[i] = static_cast<float *>(q);
-    }
-    void *dptrs = nullptr;
-    if (arrays) {
-        int rc = arena_alloc(ctx, p.get(), sizeof(const float *) * k, &dptrs);
-        if (rc != SPARKCL_OK) {
-            Plan *raw = p.release();
-            free_plan(ctx, raw);
-            return rc;
-        }
-    }
-    for (size_t i = 0; i < p->passes.size(); ++i) {
-        TreeArgs &a = p->passes[i];
-        if (i == 0) {
-            a.ptrs = static_cast<const float *const *>(dptrs);
-            a.base = base;
-            a.stride = stride;
-        } else {
-            a.base = scratch[(i - 1) % 2];
-            a.stride = len;
-        }
-        a.out = (i + 1 == p->passes.size()) ? out : scratch[i % 2];
-    }
-    if (arrays) {
-        hipError_t e = hipMemcpyAsync(dptrs, p->leaves.data(), sizeof(const float *) * k,
-                                      hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess)
-            e = hipStreamSynchronize(stream);
-        if (e != hipSuccess) {
-            Plan *raw = p.release();
-            free_plan(ctx, raw);
-            return fail_hip(e, "upload of the array table");
-        }
-    }
-    p->hash = tree_hash(p->kind, combiner, arrays, base, stride, k, len, out);
-    *res = p.release();
-    return SPARKCL_OK;
-}
-
-} // namespace
-
-namespace {
-
-int reduce_tree(sparkcl_ctx *ctx, uint32_t combiner, const float *const *arrays,
-                const float *base, uint64_t stride, uint32_t k, uint64_t len, float *out,
-                void *stream)
-{
-    int rc = check_ctx(ctx);
-    if (rc != SPARKCL_OK)
-        return rc;
-    if (combiner != SPARKCL_VADD && combiner != SPARKCL_VMAX)
-        return fail(SPARKCL_EINVAL, "combiner " + std::to_string(combiner) +
-                                        " is not SPARKCL_VADD or SPARKCL_VMAX");
-    if (k == 0 || (!arrays && !base))
-        return fail(SPARKCL_EINVAL, "an array reduce needs at least one array");
-    if (k > kTreeMaxK)
-        return fail(SPARKCL_ETOOBIG, "more than 2^24 arrays");
-    if (len > kMaxN)
-        return fail(SPARKCL_ETOOBIG, "arrays longer than 2^40 elements");
-    if (!arrays && (((uintptr_t)base & 3u) || (k > 1 && stride < len)))
-        return fail(SPARKCL_EINVAL, "rows must be 4-byte aligned and row_stride >= len");
-    if (len == 0)
-        return SPARKCL_OK;
-    if (!out)
-        return fail(SPARKCL_EINVAL, "out is NULL");
-    if ((uintptr_t)out & 3u)
-        return fail(SPARKCL_EINVAL, "out must be 4-byte aligned");
-    std::lock_guard<std::mutex> g(ctx->mu);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const int kind = arrays ? 2 : 3;
-    const uint64_t h = tree_hash(kind, combiner, arrays, base, stride, k, len, out);
-    Plan *p = nullptr;
-    for (auto it = ctx->plans.begin(); it != ctx->plans.end(); ++it)
-        if (tree_plan_matches(*it, kind, h, combiner, arrays, base, stride, k, len, out)) {
-            p = *it;
-            ctx->plans.splice(ctx->plans.begin(), ctx->plans, it);
-            break;
-        }
-    if (!p) {
-        if (capturing(s))
-            return fail(SPARKCL_EINVAL, "no cached plan for this call on a stream under capture: "
-                                        "make the same call once before capturing");
-        while (ctx->plans.size() >= kMaxPlans)
-            evict_one(ctx);
-        if ((rc = build_tree_plan(ctx, combiner, arrays, base, stride, k, len, out, s, &p)) !=
-            SPARKCL_OK)
-            return rc;
-        ctx->plans.push_front(p);
-    }
-    for (const TreeArgs &a : p->passes)
-        if ((rc = launch_tree(a, combiner, p->vec4, s)) != SPARKCL_OK)
-            return fail(rc, "array reduce launch failed");
-    return SPARKCL_OK;
-}
-
-} // namespace
-
-int sparkcl_reduce_arrays(sparkcl_ctx *ctx, uint32_t combiner, const float *const *arrays,
-                          uint32_t k, uint64_t len, float *out, void *stream)
-{
-    if (k && !arrays)
-        return fail(SPARKCL_EINVAL, "arrays is NULL");
-    return reduce_tree(ctx, combiner, arrays, nullptr, 0, k, len, out, stream);
-}
-
-int sparkcl_reduce_rows(sparkcl_ctx *ctx, uint32_t combiner, const float *base,
-                        uint64_t row_stride, uint32_t k, uint64_t len, float *out,
-                        void *stream)
-{
-    if (k && !base)
-        return fail(SPARKCL_EINVAL, "base is NULL");
-    return reduce_tree(ctx, combiner, nullptr, base, row_stride, k, len, out, stream);
-}
-
 int sparkcl_map_partition(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t ntasks,
                           int mode, sparkcl_result *results, void *stream)
 {
@@ -1204,169 +930,6 @@ int sparkcl_reduce_async(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t n
         SPARKCL_OK)
         return rc;
     return enqueue(ctx, p, s, false);
-}
-
-int sparkcl_reduce_chain(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t ntasks,
-                         const sparkcl_stage *stages, uint32_t nstages,
-                         sparkcl_result *per_task, sparkcl_result *total, void *stream)
-{
-    int rc = check_ctx(ctx);
-    if (rc != SPARKCL_OK)
-        return rc;
-    if ((ntasks && !tasks) || (nstages && !stages))
-        return fail(SPARKCL_EINVAL, "tasks/stages is NULL");
-    if (nstages > (uint32_t)kMaxPost)
-        return fail(SPARKCL_EINVAL, "more than " + std::to_string(kMaxPost) + " chain stages");
-    ChainDev chain;
-    std::memset(&chain, 0, sizeof(chain));
-    chain.npost = nstages;
-    for (uint32_t s = 0; s < nstages; ++s) {
-        if (stages[s].kernel_id != SPARKCL_POLY || stages[s].degree > 7)
-            return fail(SPARKCL_EINVAL, "chain stage " + std::to_string(s) +
-                                            " must be POLY of degree <= 7");
-        chain.deg[s] = stages[s].degree;
-        std::memcpy(chain.coef[s], stages[s].coef, sizeof(chain.coef[s]));
-    }
-    for (uint32_t i = 0; i < ntasks; ++i)
-        if (tasks[i].kernel_id == SPARKCL_MC_PI || (tasks[i].flags & SPARKCL_TASK_HOST_INPUT))
-            return fail(SPARKCL_EINVAL, "map chains take POLY/FMUL tasks with device inputs");
-    if (ntasks == 0)
-        return SPARKCL_OK;
-    std::lock_guard<std::mutex> g(ctx->mu);
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (capturing(st))
-        return fail(SPARKCL_EINVAL, "a blocking call cannot run on a stream under capture");
-    const uint64_t h = fnv1a(plan_hash(4, SPARKCL_BATCHED, tasks, ntasks, nullptr, nullptr),
-                             &chain, sizeof(chain));
-    Plan *p = nullptr;
-    for (auto it = ctx->plans.begin(); it != ctx->plans.end(); ++it) {
-        Plan *q = *it;
-        if (q->kind == 4 && q->hash == h && q->ntasks == ntasks &&
-            std::memcmp(q->tasks.data(), tasks, sizeof(sparkcl_task) * ntasks) == 0 &&
-            std::memcmp(&q->chain, &chain, sizeof(chain)) == 0) {
-            ctx->plans.splice(ctx->plans.begin(), ctx->plans, it);
-            p = q;
-            break;
-        }
-    }
-    if (!p) {
-        while (ctx->plans.size() >= kMaxPlans)
-            evict_one(ctx);
-        // The chain's Horner steps add dependent VALU work per element, whose
-        // latency more waves per CU hide.  Measured on MI355X (64 x 2^22 FMUL
-        // partitions): no steps streams best at the map's tuned occupancy
-        // (1 block per CU, 316 us), 3 steps at 3 blocks per CU (357 us, 407 at
-        // 1), 28 steps (four degree-7 stages) at 4 (399 us, 791 at 1).  A grid
-        // of more blocks than the batched table has tiles takes the
-        // per-launch table's smaller tiles, so blocks keep pulling tiles from
-        // the queue (with one large tile per block, blocks placed unevenly on
-        // the CUs decide the time: 440-490 us at 2 per CU).
-        uint32_t per_cu = 0;
-        if (!ctx->config.exec_blocks_per_cu) {
-            uint32_t steps = 0;
-            for (uint32_t s = 0; s < nstages; ++s)
-                steps += chain.deg[s];
-            uint32_t base = 0;
-            for (uint32_t i = 0; i < ntasks; ++i)
-                if (tasks[i].kernel_id == SPARKCL_POLY)
-                    base = std::max(base, tasks[i].degree);
-            steps += base;
-            const uint32_t want = steps == 0 ? 0 : steps <= 12 ? 3 : 4;
-            per_cu = std::min(want, (uint32_t)ctx->occ_chain);
-        }
-        if ((rc = build_plan(ctx, 0, SPARKCL_BATCHED, tasks, ntasks, nullptr, nullptr, st,
-                             &p, per_cu)) != SPARKCL_OK)
-            return rc;
-        p->kind = 4;
-        p->chain = chain;
-        p->hash = h;
-        void *d = nullptr;
-        if ((rc = arena_alloc(ctx, p, sizeof(ChainDev), &d)) != SPARKCL_OK) {
-            free_plan(ctx, p);
-            return rc;
-        }
-        p->dchain = static_cast<ChainDev *>(d);
-        hipError_t e = hipMemcpyAsync(d, &p->chain, sizeof(ChainDev), hipMemcpyHostToDevice, st);
-        if (e == hipSuccess)
-            e = hipStreamSynchronize(st);
-        if (e != hipSuccess) {
-            free_plan(ctx, p);
-            return fail_hip(e, "chain upload");
-        }
-        ctx->plans.push_front(p);
-    }
-    return launch_and_collect(ctx, p, tasks, ntasks, per_task, total, st);
-}
-
-int sparkcl_wordcount(sparkcl_ctx *ctx, const uint8_t *text, uint64_t nbytes, uint64_t *keys,
-                      uint64_t *counts, uint64_t capacity, uint64_t *ndistinct,
-                      uint64_t *nwords, void *stream)
-{
-    int rc = check_ctx(ctx);
-    if (rc != SPARKCL_OK)
-        return rc;
-    if (!ndistinct || !nwords || (nbytes && !text) || (capacity && (!keys || !counts)))
-        return fail(SPARKCL_EINVAL, "NULL argument");
-    *ndistinct = 0;
-    *nwords = 0;
-    if (nbytes == 0)
-        return SPARKCL_OK;
-    std::lock_guard<std::mutex> g(ctx->mu);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    // open addressing at load <= 1/2: room for capacity + 1 keys (so one key
-    // past the capacity is still seen), never more than the text can hold
-    uint64_t need = std::min<uint64_t>(capacity + 1, nbytes / 2 + 1);
-    uint64_t slots = 1024;
-    while (slots < 2 * need)
-        slots *= 2;
-    const uint64_t bytes = slots * 16 + 64;
-    const uint64_t off = ctx->arena.alloc(bytes);
-    if (off == Arena::kFail)
-        return fail(SPARKCL_ENOMEM, "word-count table of " + std::to_string(bytes) +
-                                        " bytes does not fit the arena");
-    char *base = static_cast<char *>(ctx->dev(off));
-    WcArgs a{};
-    a.text = text;
-    a.n = nbytes;
-    a.keys = reinterpret_cast<uint64_t *>(base);
-    a.counts = reinterpret_cast<uint64_t *>(base + slots * 8);
-    a.ctl = reinterpret_cast<uint64_t *>(base + slots * 16);
-    a.mask = slots - 1;
-    if (!ctx->occ_wordcount) {
-        int occ = 0;
-        if (wordcount_blocks_per_cu(&occ) != SPARKCL_OK || occ < 1)
-            occ = 1;
-        ctx->occ_wordcount = occ;
-    }
-    const uint64_t nchunks = (nbytes + 4095) / 4096;
-    const uint32_t grid =
-        (uint32_t)std::min<uint64_t>(nchunks, (uint64_t)ctx->occ_wordcount * ctx->cus);
-    const uint32_t cgrid =
-        (uint32_t)std::min<uint64_t>((slots + kBlock - 1) / kBlock, 4ull * ctx->cus);
-    if ((rc = ensure_pinned(ctx, 1)) == SPARKCL_OK &&
-        (rc = launch_zero(base, bytes, s)) == SPARKCL_OK &&
-        (rc = launch_wordcount(a, grid, s)) == SPARKCL_OK &&
-        (rc = launch_wc_compact(a, keys, counts, capacity, cgrid, s)) == SPARKCL_OK) {
-        hipError_t e = hipMemcpyAsync(ctx->pinned, a.ctl, 32, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess)
-            e = hipStreamSynchronize(s);
-        if (e != hipSuccess)
-            rc = fail_hip(e, "word count");
-    } else if (rc != SPARKCL_OK) {
-        (void)hipStreamSynchronize(s);
-        rc = fail(rc, "word-count launch failed");
-    }
-    ctx->arena.release(off);
-    if (rc != SPARKCL_OK)
-        return rc;
-    uint64_t ctl[4];
-    std::memcpy(ctl, ctx->pinned, sizeof(ctl));
-    *nwords = ctl[0];
-    *ndistinct = ctl[3];
-    if (ctl[2] || ctl[3] > capacity)
-        return fail(SPARKCL_ETOOBIG, "more distinct words than the capacity of " +
-                                         std::to_string(capacity));
-    return SPARKCL_OK;
 }
 
 int sparkcl_offload_breakeven(sparkcl_ctx *ctx, double host_bytes_per_s, uint64_t *bytes)

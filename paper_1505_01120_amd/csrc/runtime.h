@@ -1,5 +1,5 @@
-// Internal runtime types shared by the C ABI (api.cpp) and the serving loop
-// (serve.cpp).
+// Internal runtime types shared by the C ABI (api.cpp, arrays.cpp, chain.cpp,
+// wordcount.cpp) and the serving loop (serve.cpp).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -96,6 +96,33 @@ struct Plan {
 };
 
 // Plan cache and launch helpers (api.cpp); the caller holds ctx->mu.
+constexpr uint32_t kMaxPlans = 32;     // cached plans per context
+constexpr uint64_t kMaxN = 1ull << 40; // elements (or samples, bytes) per task
+
+// Plan cache helpers (api.cpp); the caller holds ctx->mu.
+uint64_t fnv1a(uint64_t h, const void *p, size_t n);
+uint64_t plan_hash(int kind, int mode, const sparkcl_task *tasks, uint32_t ntasks,
+                   const void *ures, const void *utot);
+void free_plan(sparkcl_ctx *ctx, Plan *p);
+// Evicts the least recently used plan (after a device-wide wait); false if
+// no plan is left.
+bool evict_one(sparkcl_ctx *ctx);
+// Arena block for plan p, evicting older plans while the arena is full.
+int arena_alloc(sparkcl_ctx *ctx, Plan *p, uint64_t bytes, void **out);
+// A reduce-kind plan (kind 0) for the call; per_cu: executor blocks per CU
+// (0: the tuned choice).
+int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
+               uint32_t ntasks, sparkcl_result *ures, sparkcl_result *utot,
+               hipStream_t stream, Plan **out, uint32_t per_cu = 0);
+// Launches plan p (timed) and copies its results to host memory.
+int launch_and_collect(sparkcl_ctx *ctx, Plan *p, const sparkcl_task *tasks,
+                       uint32_t ntasks, sparkcl_result *per_task, sparkcl_result *total,
+                       hipStream_t stream);
+// A non-null context, made current on this thread.
+int check_ctx(sparkcl_ctx *ctx);
+// Pinned host staging for at least `count` results.
+int ensure_pinned(sparkcl_ctx *ctx, uint32_t count);
+
 // A call on a stream under capture may only reuse a cached plan: building
 // one uploads and synchronises, which a capture cannot hold.
 int get_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,

@@ -1,0 +1,85 @@
+// WordCount (sec. 3.2.3): words of a device-resident byte stream counted under
+// their 64-bit FNV-1a key, in per-block LDS tables that spill to one global
+// open-addressing table, then compacted into the caller's arrays.
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "runtime.h"
+
+using namespace sparkcl;
+
+extern "C" {
+
+int sparkcl_wordcount(sparkcl_ctx *ctx, const uint8_t *text, uint64_t nbytes, uint64_t *keys,
+                      uint64_t *counts, uint64_t capacity, uint64_t *ndistinct,
+                      uint64_t *nwords, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc != SPARKCL_OK)
+        return rc;
+    if (!ndistinct || !nwords || (nbytes && !text) || (capacity && (!keys || !counts)))
+        return fail(SPARKCL_EINVAL, "NULL argument");
+    *ndistinct = 0;
+    *nwords = 0;
+    if (nbytes == 0)
+        return SPARKCL_OK;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // open addressing at load <= 1/2: room for capacity + 1 keys (so one key
+    // past the capacity is still seen), never more than the text can hold
+    uint64_t need = std::min<uint64_t>(capacity + 1, nbytes / 2 + 1);
+    uint64_t slots = 1024;
+    while (slots < 2 * need)
+        slots *= 2;
+    const uint64_t bytes = slots * 16 + 64;
+    const uint64_t off = ctx->arena.alloc(bytes);
+    if (off == Arena::kFail)
+        return fail(SPARKCL_ENOMEM, "word-count table of " + std::to_string(bytes) +
+                                        " bytes does not fit the arena");
+    char *base = static_cast<char *>(ctx->dev(off));
+    WcArgs a{};
+    a.text = text;
+    a.n = nbytes;
+    a.keys = reinterpret_cast<uint64_t *>(base);
+    a.counts = reinterpret_cast<uint64_t *>(base + slots * 8);
+    a.ctl = reinterpret_cast<uint64_t *>(base + slots * 16);
+    a.mask = slots - 1;
+    if (!ctx->occ_wordcount) {
+        int occ = 0;
+        if (wordcount_blocks_per_cu(&occ) != SPARKCL_OK || occ < 1)
+            occ = 1;
+        ctx->occ_wordcount = occ;
+    }
+    const uint64_t nchunks = (nbytes + 4095) / 4096;
+    const uint32_t grid =
+        (uint32_t)std::min<uint64_t>(nchunks, (uint64_t)ctx->occ_wordcount * ctx->cus);
+    const uint32_t cgrid =
+        (uint32_t)std::min<uint64_t>((slots + kBlock - 1) / kBlock, 4ull * ctx->cus);
+    if ((rc = ensure_pinned(ctx, 1)) == SPARKCL_OK &&
+        (rc = launch_zero(base, bytes, s)) == SPARKCL_OK &&
+        (rc = launch_wordcount(a, grid, s)) == SPARKCL_OK &&
+        (rc = launch_wc_compact(a, keys, counts, capacity, cgrid, s)) == SPARKCL_OK) {
+        hipError_t e = hipMemcpyAsync(ctx->pinned, a.ctl, 32, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess)
+            rc = fail_hip(e, "word count");
+    } else if (rc != SPARKCL_OK) {
+        (void)hipStreamSynchronize(s);
+        rc = fail(rc, "word-count launch failed");
+    }
+    ctx->arena.release(off);
+    if (rc != SPARKCL_OK)
+        return rc;
+    uint64_t ctl[4];
+    std::memcpy(ctl, ctx->pinned, sizeof(ctl));
+    *nwords = ctl[0];
+    *ndistinct = ctl[3];
+    if (ctl[2] || ctl[3] > capacity)
+        return fail(SPARKCL_ETOOBIG, "more distinct words than the capacity of " +
+                                         std::to_string(capacity));
+    return SPARKCL_OK;
+}
+
+} // extern "C"
