@@ -297,6 +297,21 @@ def bench_host_input(ctx, sc, res, reps=3) -> dict:
             "frac_of_copy": copy_ms / ms}
 
 
+def bench_misaligned(ctx, sc, res, dres, dtot, steps) -> dict:
+    """The 64 x 2^22 FMUL RDD with every y partition shifted one element (4
+    bytes) off x's 16-byte alignment: y's quads are then read at 4-byte
+    alignment."""
+    import torch
+    y2 = torch.empty(res.parts * res.n + 4, dtype=torch.float32, device="cuda")
+    y2[1:1 + res.parts * res.n].copy_(res.y)
+    n = res.n
+    tasks = [sc.task(sc.FMUL, n, res.x[p * n:(p + 1) * n], y2[1 + p * n:1 + (p + 1) * n],
+                     ops=sc.SUM | sc.MAX, c=0.1) for p in range(res.parts)]
+    w, e = time_async(ctx, sc, tasks, sc.BATCHED, steps, 2, dres, dtot)
+    del y2
+    return {"ms": e, "wall_ms": w, "hbm_GBps": 8 * res.parts * n / (e / 1e3) / 1e9}
+
+
 def bench_chain(ctx, sc, res, reps=5) -> dict:
     """Fused map chain (sec. 3.1.3): the 64 x 2^22 FMUL RDD, then two POLY
     stages, reduced (SUM+MAX) in one pass with nothing materialised.  Unfused,
@@ -378,7 +393,7 @@ def bench_selective(ctx, sc, cpu: dict | None) -> dict:
     return out
 
 
-def bench_uneven(ctx, sc, steps=5) -> dict:
+def bench_uneven(ctx, sc, steps=20) -> dict:
     import torch
 
     import datagen
@@ -414,7 +429,7 @@ def bench_uneven(ctx, sc, steps=5) -> dict:
            "hbm_bytes": bytes_, "mc_samples": mc}
     for name, mode in (("batched", sc.BATCHED), ("graph", sc.GRAPH),
                        ("per_launch", sc.PER_LAUNCH)):
-        wall, ev = time_async(ctx, sc, tasks, mode, steps, 2, dres, None)
+        wall, ev = time_async(ctx, sc, tasks, mode, steps, 3, dres, None)
         out[name] = {"ms": ev, "wall_ms": wall,
                      "elements_per_s": int(sizes.sum()) / (ev / 1e3)}
     out["batched_speedup"] = out["per_launch"]["ms"] / out["batched"]["ms"]
@@ -626,6 +641,8 @@ def main() -> int:
         wl, el = time_async(ctx, sc, tasks, sc.PER_LAUNCH, max(5, args.steps // 5), 2, dres, dtot)
         ex["fmul_rdd_per_launch"] = {"ms": el, "wall_ms": wl, "elements_per_s": elems / (el / 1e3),
                                      "hbm_GBps": algo_bytes / (el / 1e3) / 1e9}
+        log("extras: RDD with y one element off x's alignment ...")
+        ex["fmul_rdd_y_misaligned"] = bench_misaligned(ctx, sc, res, dres, dtot, args.steps)
         log("extras: graph replay RDD ...")
         wg, eg = time_async(ctx, sc, tasks, sc.GRAPH, args.steps, 2, dres, dtot)
         ex["fmul_rdd_graph"] = {"ms": eg, "wall_ms": wg, "elements_per_s": elems / (eg / 1e3),

@@ -101,6 +101,23 @@ __device__ __forceinline__ float4 ld4(const float *p)
     const f4v v = __builtin_nontemporal_load((gf4 *)p);
     return make_float4(v.x, v.y, v.z, v.w);
 }
+// y and out need only 4-byte alignment: a 16-byte access at a 4-byte-aligned
+// address is still one dwordx4 instruction (the memory pipeline splits it
+// over the two 16-byte segments it touches), so arrays whose misalignments
+// differ from x's stream as quads too.
+typedef float f4a4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef __attribute__((address_space(1))) const f4a4 gf4u;
+typedef __attribute__((address_space(1))) f4a4 gf4uw;
+__device__ __forceinline__ float4 ld4u(const float *p)
+{
+    const f4a4 v = __builtin_nontemporal_load((gf4u *)p);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st4u(float *p, const float4 &v)
+{
+    const f4a4 w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, (gf4uw *)p);
+}
 __device__ __forceinline__ float ld1(const float *p)
 {
     return __builtin_nontemporal_load((gf1 *)p);
@@ -185,7 +202,7 @@ __device__ __forceinline__ void map_quad(const M &f, const float4 &xv,
     v.z = f(xv.z, yv.z);
     v.w = f(xv.w, yv.w);
     if (W)
-        st4(o, v);
+        st4u(o, v);
     a.add(v.x);
     a.add(v.y);
     a.add(v.z);
@@ -216,7 +233,7 @@ __device__ __forceinline__ void stream_groups(const M &f, const float *x4,
         for (int u = 0; u < U; ++u) {
             xv[u] = ld4(x4 + 4 * (q0 + u * kBlock));
             if (M::kTwo)
-                yv[u] = ld4(y4 + 4 * (q0 + u * kBlock));
+                yv[u] = ld4u(y4 + 4 * (q0 + u * kBlock));
         }
         if constexpr (M::kGroup) {
             float v[4 * U];
@@ -224,8 +241,8 @@ __device__ __forceinline__ void stream_groups(const M &f, const float *x4,
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (W)
-                    st4(o4 + 4 * (q0 + u * kBlock),
-                        make_float4(v[4 * u], v[4 * u + 1], v[4 * u + 2], v[4 * u + 3]));
+                    st4u(o4 + 4 * (q0 + u * kBlock),
+                         make_float4(v[4 * u], v[4 * u + 1], v[4 * u + 2], v[4 * u + 3]));
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
                     a.add(v[4 * u + e]);
@@ -253,29 +270,18 @@ __device__ __forceinline__ void map_scalar(const M &f, const float *x,
     }
 }
 
-// Whether a task's arrays share one 16-byte misalignment (so the aligned
-// middle can be read as float4 quads), and the length of the scalar head
-// that reaches the first quad boundary.
-template <class M, bool W>
-__device__ __forceinline__ bool quad_aligned(const float *x, const float *y,
-                                             const float *out, uint64_t n,
-                                             uint32_t &head)
+// The scalar head of a task's range: the elements before x reaches a 16-byte
+// boundary.  The quads after it are aligned for x; y and out, at any 4-byte
+// alignment, are read and written with the same quad indices.
+__device__ __forceinline__ uint32_t quad_head(const float *x, uint64_t n)
 {
-    const uintptr_t ax = (uintptr_t)x;
-    bool vec = true;
-    if (M::kTwo && ((ax ^ (uintptr_t)y) & 15u))
-        vec = false;
-    if (W && ((ax ^ (uintptr_t)out) & 15u))
-        vec = false;
-    const uint32_t mis = (uint32_t)((ax & 15u) >> 2);
-    head = vec ? (uint32_t)min((uint64_t)((4u - mis) & 3u), n) : 0u;
-    return vec;
+    const uint32_t mis = (uint32_t)(((uintptr_t)x & 15u) >> 2);
+    return (uint32_t)min((uint64_t)((4u - mis) & 3u), n);
 }
 
-// Contiguous tile [begin, end): the aligned middle in float4 quads (thread t
-// owns quads t, t+B, t+2B, ...), the unaligned head and the ragged tail as
-// single elements owned by threads 0..2.  If the arrays do not share one
-// 16-byte misalignment, every element goes through the scalar strided loop.
+// Contiguous tile [begin, end): the middle in float4 quads (thread t owns
+// quads t, t+B, t+2B, ...), the head before x's first 16-byte boundary and
+// the ragged tail as single elements owned by threads 0..2.
 template <class M, bool W>
 __device__ __forceinline__ void tile_contiguous(const M &f,
                                                 const float *__restrict__ x,
@@ -289,11 +295,7 @@ __device__ __forceinline__ void tile_contiguous(const M &f,
     const float *xb = x + begin;
     const float *yb = M::kTwo ? y + begin : nullptr;
     float *ob = W ? out + begin : nullptr;
-    uint32_t head = 0;
-    if (!quad_aligned<M, W>(xb, yb, ob, len, head)) {
-        map_scalar<M, W>(f, xb, yb, ob, 0, len, a);
-        return;
-    }
+    const uint32_t head = quad_head(xb, len);
     map_scalar<M, W>(f, xb, yb, ob, 0, head, a);
 
     constexpr uint32_t kStep = kUnroll * kBlock;
@@ -308,13 +310,13 @@ __device__ __forceinline__ void tile_contiguous(const M &f,
     stream_groups<M, W>(f, x4, y4, o4, full,
                         [&](uint64_t g) { return (uint64_t)tid + g * kStep; }, a);
     for (uint32_t q = tid + full * kStep; q < nq; q += kBlock)
-        map_quad<M, W>(f, ld4(x4 + 4u * q), M::kTwo ? ld4(y4 + 4u * q) : float4{},
+        map_quad<M, W>(f, ld4(x4 + 4u * q), M::kTwo ? ld4u(y4 + 4u * q) : float4{},
                        W ? o4 + 4u * q : nullptr, a);
     map_scalar<M, W>(f, xb, yb, ob, head + 4u * nq, len, a);
 }
 
 // Interleaved layout of a whole task (tiles of at least kChunkElems
-// elements, arrays sharing one 16-byte misalignment): the task's aligned
+// elements): the task's quad-aligned
 // middle is cut into chunks of kBlock * kUnroll quads, and tile j of nt owns
 // chunks j, j + nt, j + 2 nt, ...; tile 0 also owns the unaligned head and
 // the ragged tail.  Tiles that run at the same time (the queue hands out a
@@ -348,7 +350,7 @@ __device__ __forceinline__ uint64_t tile_interleaved(const M &f,
         const uint64_t q0 = nfull * kChunkQuads;
         for (uint32_t q = tid; q < rem; q += kBlock)
             map_quad<M, W>(f, ld4(x4 + 4 * (q0 + q)),
-                           M::kTwo ? ld4(y4 + 4 * (q0 + q)) : float4{},
+                           M::kTwo ? ld4u(y4 + 4 * (q0 + q)) : float4{},
                            W ? o4 + 4 * (q0 + q) : nullptr, a);
         count += 4 * rem;
     }
@@ -360,18 +362,17 @@ __device__ __forceinline__ uint64_t tile_interleaved(const M &f,
     return count;
 }
 
-// Tile j of an elementwise task: interleaved when the tile size allows and
-// the arrays are quad-compatible, else the contiguous range [jT, jT + T).
-// Returns the number of elements covered.
+// Tile j of an elementwise task: interleaved when the tile size allows,
+// else the contiguous range [jT, jT + T).  Returns the number of elements
+// covered.
 template <class M, bool W>
 __device__ __forceinline__ uint64_t tile_map(const M &f, const float *x,
                                              const float *y, float *out,
                                              uint64_t n, uint32_t T, uint32_t nt,
                                              uint32_t j, Acc &a)
 {
-    uint32_t head = 0;
-    if (T >= kChunkElems && quad_aligned<M, W>(x, y, out, n, head))
-        return tile_interleaved<M, W>(f, x, y, out, n, head, nt, j, a);
+    if (T >= kChunkElems)
+        return tile_interleaved<M, W>(f, x, y, out, n, quad_head(x, n), nt, j, a);
     const uint64_t begin = (uint64_t)j * T;
     const uint64_t end = min(n, begin + T);
     if (begin < end)
@@ -948,28 +949,22 @@ __device__ __forceinline__ void map_only(const M &f, const float *__restrict__ x
 {
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     const uint64_t gtid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    const uintptr_t ax = (uintptr_t)x;
-    bool vec = ((ax ^ (uintptr_t)out) & 15u) == 0;
-    if (M::kTwo && ((ax ^ (uintptr_t)y) & 15u))
-        vec = false;
-    const uint64_t head = vec ? min((uint64_t)((4u - ((ax & 15u) >> 2)) & 3u), n) : n;
+    const uint64_t head = quad_head(x, n);
     for (uint64_t i = gtid; i < head; i += stride)
         st1(out + i, f(ld1(x + i), M::kTwo ? ld1(y + i) : 0.0f));
-    if (!vec)
-        return;
     const uint64_t nq = (n - head) >> 2;
     const float *x4 = x + head;
     const float *y4 = M::kTwo ? y + head : nullptr;
     float *o4 = out + head;
     for (uint64_t q = gtid; q < nq; q += stride) {
         const float4 xv = ld4(x4 + 4 * q);
-        const float4 yv = M::kTwo ? ld4(y4 + 4 * q) : xv;
+        const float4 yv = M::kTwo ? ld4u(y4 + 4 * q) : xv;
         float4 v;
         v.x = f(xv.x, yv.x);
         v.y = f(xv.y, yv.y);
         v.z = f(xv.z, yv.z);
         v.w = f(xv.w, yv.w);
-        st4(o4 + 4 * q, v);
+        st4u(o4 + 4 * q, v);
     }
     const uint64_t t0 = head + 4 * nq;
     if (gtid < n - t0)
