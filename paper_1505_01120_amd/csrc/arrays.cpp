@@ -69,7 +69,10 @@ int build_tree_plan(sparkcl_ctx *ctx, uint32_t combiner, const float *const *arr
     p->nleaves = k;
     p->leaf_base = base;
     p->leaf_stride = stride;
-    bool vec4 = (len & 3u) == 0 && ((uintptr_t)out & 15u) == 0;
+    // float4 columns whenever the length is a multiple of 4: leaves and out
+    // need only their 4-byte alignment (a 16-byte access at a 4-byte-aligned
+    // address is one dwordx4 instruction)
+    const bool vec4 = (len & 3u) == 0;
     if (arrays) {
         p->leaves.assign(arrays, arrays + k);
         for (uint32_t i = 0; i < k; ++i) {
@@ -77,11 +80,7 @@ int build_tree_plan(sparkcl_ctx *ctx, uint32_t combiner, const float *const *arr
                 return fail(SPARKCL_EINVAL, "array " + std::to_string(i) + " is NULL");
             if ((uintptr_t)arrays[i] & 3u)
                 return fail(SPARKCL_EINVAL, "arrays must be 4-byte aligned");
-            if ((uintptr_t)arrays[i] & 15u)
-                vec4 = false;
         }
-    } else if (((uintptr_t)base & 15u) || (stride & 3u)) {
-        vec4 = false;
     }
     p->vec4 = vec4;
     const uint64_t V = vec4 ? 4 : 1;

@@ -1034,8 +1034,8 @@ template <> struct TreeVec<1> {
 };
 template <> struct TreeVec<4> {
     typedef float4 T;
-    static __device__ __forceinline__ T ld(const float *p) { return ld4(p); }
-    static __device__ __forceinline__ void st(float *p, T v) { st4(p, v); }
+    static __device__ __forceinline__ T ld(const float *p) { return ld4u(p); }
+    static __device__ __forceinline__ void st(float *p, T v) { st4u(p, v); }
 };
 
 template <uint32_t COMB>
@@ -1167,7 +1167,7 @@ __global__ __launch_bounds__(kBlock) void k_tree_wide(TreeArgs a)
         const float *p = leaf(i);
 #pragma unroll
         for (int c = 0; c < CPT; ++c)
-            v[c] = ok[c] ? ld4(p + 4 * (uint64_t)c * kBlock) : float4{};
+            v[c] = ok[c] ? ld4u(p + 4 * (uint64_t)c * kBlock) : float4{};
     };
     float4 slot[kTreeWideSlots][CPT];
     uint32_t i = 0;
@@ -1200,7 +1200,7 @@ __global__ __launch_bounds__(kBlock) void k_tree_wide(TreeArgs a)
 #pragma unroll
     for (int c = 0; c < CPT; ++c)
         if (ok[c])
-            st4(o + 4 * (uint64_t)c * kBlock, acc[c]);
+            st4u(o + 4 * (uint64_t)c * kBlock, acc[c]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_zero(uint32_t *p, uint64_t words)

@@ -66,8 +66,12 @@ def test_vmax_matches_oracle(ctx, k, length):
 
 
 @pytest.mark.parametrize("offset", [1, 2, 3])
-def test_unaligned_arrays_take_the_scalar_path(ctx, offset):
+def test_unaligned_arrays(ctx, offset):
+    # arrays (and their rows) 4, 8 or 12 bytes off a 16-byte boundary: float4
+    # columns at 4-byte alignment; an odd length takes the scalar columns
     check(ctx, rdd(37, 4096, seed=offset), offset=offset)
+    check(ctx, rdd(37, 4095, seed=offset), offset=offset)
+    check(ctx, rdd(130, 1 << 20, seed=offset), offset=offset)
 
 
 def test_ill_conditioned_tree_is_bit_exact(ctx):
