@@ -323,6 +323,14 @@ typedef struct sparkcl_tuning {
                                     on average), where per-tile latency
                                     rather than streaming depth dominates;
                                     0 = as many as fit                        */
+    uint32_t tile_many[3];       /* batched tile size per kernel for a batch of
+                                    many tasks of widely spread sizes (at
+                                    least 512 tasks whose sizes span 4 or
+                                    more log2 buckets), in place of the
+                                    per-bucket table: there, small tasks run
+                                    best whole and large ones in mid-sized
+                                    tiles; 0 = use the table, else a power of
+                                    two from 2^10 to 2^22                     */
     /* tile size in elements (samples for MC_PI) for [mode][kernel-1][log2 n];
        powers of two from 2^10 to 2^22. */
     uint32_t tile[SPARKCL_TUNE_MODES][3][SPARKCL_TUNE_BUCKETS];

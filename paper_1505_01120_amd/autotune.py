@@ -35,6 +35,7 @@ def main(argv=None) -> int:
     kern = ["poly", "fmul", "mc_pi"]
     summary = {"blocks_per_cu": list(t.blocks_per_cu),
                "blocks_per_cu_many": t.blocks_per_cu_many,
+               "tile_many": list(t.tile_many),
                "tiles": {m: {k: list(t.tile[i][j][args.lo:args.hi + 1])
                              for j, k in enumerate(kern)} for i, m in enumerate(names[:2])}}
     print(json.dumps(summary), flush=True)

@@ -233,13 +233,34 @@ int sparkcl::build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task
     if (host_in && mode == SPARKCL_GRAPH)
         return fail(SPARKCL_EINVAL, "host-input tasks run in PER_LAUNCH or BATCHED mode");
     int tm = mode != SPARKCL_PER_LAUNCH && !host_in ? TM_BATCHED : TM_PER_LAUNCH;
+    // A batch of many tasks of widely spread sizes takes the tuned mixed-batch
+    // tile sizes instead of the per-bucket table (tuned on batches of one
+    // size).  On the 4096-task uneven batch, one 2^16 tile size for the
+    // streaming kernels ran it in 515 us against 553 us with the table: small
+    // tasks then run whole and large ones in mid-sized interleaved tiles.
+    bool mixed = false;
+    if (tm == TM_BATCHED && ntasks >= kMixedMinTasks) {
+        uint32_t lo = SPARKCL_TUNE_BUCKETS, hi = 0;
+        for (uint32_t i = 0; i < ntasks; ++i) {
+            const uint32_t b = size_bucket(tasks[i].n);
+            lo = std::min(lo, b);
+            hi = std::max(hi, b);
+        }
+        mixed = hi >= lo + kMixedMinSpan;
+    }
+    auto tile_of = [&](int mode_table, const sparkcl_task &t) -> uint32_t {
+        if (mode_table == TM_BATCHED && mixed && t.kernel_id >= SPARKCL_POLY &&
+            t.kernel_id <= SPARKCL_MC_PI && ctx->tuning.tile_many[t.kernel_id - 1])
+            return ctx->tuning.tile_many[t.kernel_id - 1];
+        return tile_for(ctx->tuning, mode_table, t.kernel_id, t.n);
+    };
     if (tm == TM_BATCHED) {
         uint64_t tiles = 0;
         uint32_t mask = 0;
         for (uint32_t i = 0; i < ntasks; ++i) {
             if (tasks[i].kernel_id < SPARKCL_POLY || tasks[i].kernel_id > SPARKCL_MC_PI)
                 continue; // rejected below
-            const uint32_t T = tile_for(ctx->tuning, TM_BATCHED, tasks[i].kernel_id, tasks[i].n);
+            const uint32_t T = tile_of(TM_BATCHED, tasks[i]);
             tiles += std::max<uint64_t>(1, (tasks[i].n + T - 1) / T);
             mask |= 1u << (tasks[i].kernel_id - 1);
         }
@@ -260,7 +281,7 @@ int sparkcl::build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task
         if (skip)
             v = V_DECLINED;
         p->variants[i] = v;
-        const uint32_t T = tile_for(ctx->tuning, tm, tasks[i].kernel_id, tasks[i].n);
+        const uint32_t T = tile_of(tm, tasks[i]);
         const uint64_t nt = skip ? 1 : std::max<uint64_t>(1, (tasks[i].n + T - 1) / T);
         if (nt > 0xFFFFFFFFull)
             return fail(SPARKCL_ETOOBIG, "too many tiles in task " + std::to_string(i));
@@ -328,7 +349,7 @@ int sparkcl::build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task
         d.variant = p->variants[i];
         std::memcpy(d.coef, t.coef, sizeof(d.coef));
         d.c = t.c;
-        d.tile_elems = tile_for(ctx->tuning, tm, t.kernel_id, t.n);
+        d.tile_elems = tile_of(tm, t);
         d.ntiles = p->ntiles[i];
         d.index = i;
         d.partials = p->dparts ? p->dparts + first[i] : nullptr;

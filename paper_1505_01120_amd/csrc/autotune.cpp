@@ -254,7 +254,41 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
         }
     }
 
-    // 3. Occupancy for batches of many small tasks.
+    // 3. Tile sizes for batches of many tasks of spread sizes (the mixed
+    //    batch), against the per-bucket table (0): one size shared by the
+    //    two streaming kernels, whose tiles run side by side in HBM, then the
+    //    Monte-Carlo kernel's.
+    {
+        const std::vector<sparkcl_task> tasks = make_mixed(b);
+        for (int group = 0; group < 2; ++group) {
+            float best_ms = 1e30f;
+            uint32_t best_T = 0;
+            for (uint32_t tl = 13; tl <= 19; ++tl) {
+                const uint32_t T = tl == 13 ? 0u : 1u << tl; // 0 first: the table
+                sparkcl_tuning t = best;
+                if (group == 0)
+                    t.tile_many[SPARKCL_POLY - 1] = t.tile_many[SPARKCL_FMUL - 1] = T;
+                else
+                    t.tile_many[SPARKCL_MC_PI - 1] = T;
+                float ms = 0;
+                if (!measure(t, SPARKCL_BATCHED, tasks, &ms))
+                    return abort_with(rc);
+                if (verbose)
+                    std::fprintf(stderr, "mixed %s tile %u: %.1f us\n",
+                                 group == 0 ? "streaming" : "mc_pi", T, ms * 1e3f);
+                if (ms < best_ms * 0.98f) {
+                    best_ms = ms;
+                    best_T = T;
+                }
+            }
+            if (group == 0)
+                best.tile_many[SPARKCL_POLY - 1] = best.tile_many[SPARKCL_FMUL - 1] = best_T;
+            else
+                best.tile_many[SPARKCL_MC_PI - 1] = best_T;
+        }
+    }
+
+    // 4. Occupancy for batches of many small tasks.
     {
         const std::vector<sparkcl_task> tasks = make_mixed(b);
         float best_ms = 1e30f;

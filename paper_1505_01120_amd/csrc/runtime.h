@@ -97,6 +97,10 @@ struct Plan {
 
 // Plan cache and launch helpers (api.cpp); the caller holds ctx->mu.
 constexpr uint32_t kMaxPlans = 32;     // cached plans per context
+// A batched call is "mixed" (takes sparkcl_tuning.tile_many) with at least
+// this many tasks whose sizes span at least this many log2 buckets.
+constexpr uint32_t kMixedMinTasks = 512;
+constexpr uint32_t kMixedMinSpan = 4;
 constexpr uint64_t kMaxN = 1ull << 40; // elements (or samples, bytes) per task
 
 // Plan cache helpers (api.cpp); the caller holds ctx->mu.

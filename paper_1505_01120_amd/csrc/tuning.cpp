@@ -214,6 +214,15 @@ int tuning_validate(const sparkcl_tuning *t, std::string *why)
                 *why = "blocks_per_cu above 32";
             return SPARKCL_EINVAL;
         }
+    for (int k = 0; k < 3; ++k) {
+        const uint32_t v = t->tile_many[k];
+        if (v != 0 && (v < (1u << kMinTileLog2) || v > (1u << kMaxTileLog2) || (v & (v - 1)))) {
+            if (why)
+                *why = std::string("tile_many[") + kKernelNames[k] + "] = " +
+                       std::to_string(v) + " is neither 0 nor a power of two in [2^10, 2^22]";
+            return SPARKCL_EINVAL;
+        }
+    }
     for (int m = 0; m < SPARKCL_TUNE_MODES; ++m)
         for (int k = 0; k < 3; ++k)
             for (int b = 0; b < SPARKCL_TUNE_BUCKETS; ++b) {
@@ -274,6 +283,15 @@ bool tuning_parse_json(const std::string &text,
         }
         if (const Json *b = e.get("blocks_per_cu_many"))
             t.blocks_per_cu_many = (uint32_t)b->num;
+        if (const Json *b = e.get("tile_many")) {
+            if (b->kind != Json::ARR || b->arr.size() != 3) {
+                if (err)
+                    *err = "tile_many must be an array of 3";
+                return false;
+            }
+            for (int k = 0; k < 3; ++k)
+                t.tile_many[k] = (uint32_t)b->arr[k].num;
+        }
         if (const Json *tile = e.get("tile")) {
             for (int m = 0; m < SPARKCL_TUNE_MODES; ++m) {
                 const Json *mj = tile->get(kModeNames[m]);
@@ -315,7 +333,8 @@ std::string tuning_to_json(const std::map<std::string, sparkcl_tuning> &all)
         o << " \"" << kv.first << "\": {\n  \"blocks_per_cu\": [" << t.blocks_per_cu[0]
           << ", " << t.blocks_per_cu[1] << ", " << t.blocks_per_cu[2]
           << "],\n  \"blocks_per_cu_many\": " << t.blocks_per_cu_many
-          << ",\n  \"tile\": {\n";
+          << ",\n  \"tile_many\": [" << t.tile_many[0] << ", " << t.tile_many[1] << ", "
+          << t.tile_many[2] << "],\n  \"tile\": {\n";
         for (int m = 0; m < SPARKCL_TUNE_MODES; ++m) {
             o << "   \"" << kModeNames[m] << "\": {\n";
             for (int k = 0; k < 3; ++k) {

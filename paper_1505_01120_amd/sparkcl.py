@@ -66,6 +66,7 @@ class Result(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_uint32 * 3), ("blocks_per_cu_many", ctypes.c_uint32),
+                ("tile_many", ctypes.c_uint32 * 3),
                 ("tile", ((ctypes.c_uint32 * TUNE_BUCKETS) * 3) * TUNE_MODES)]
 
 

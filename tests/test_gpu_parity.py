@@ -290,6 +290,25 @@ def test_beyond_32_bit_element_counts(ctx):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("many", [(4096, 8192, 2048), (1 << 16, 1 << 16, 1 << 15), (0, 1024, 0)])
+def test_mixed_batch_tile_sizes(ctx, many):
+    # 600 tasks spanning many size buckets take the mixed-batch tile sizes
+    # (sparkcl_tuning.tile_many, 0 = the per-bucket table) in batched modes
+    sizes = datagen.lognormal_sizes(600, 9, 3, 8192, math.log(4.0), 16, 300_000)
+    kids = datagen.uniform_kernel_ids(600, 9, 4)
+    parts = [datagen.make_part(int(k), int(n), i) for i, (n, k) in enumerate(zip(sizes, kids))]
+    saved = ctx.get_tuning()
+    t = sc.Tuning.from_buffer_copy(saved)
+    for k in range(3):
+        t.tile_many[k] = many[k]
+    ctx.set_tuning(t)
+    try:
+        for mode in (sc.BATCHED, sc.GRAPH):
+            run_and_check(ctx, parts, mode)
+    finally:
+        ctx.set_tuning(saved)
+
+
 def test_uneven_batch_reduced(ctx):
     # log-normal sizes (median 4K, clipped 16..256K) with mixed kernels
     sizes = datagen.lognormal_sizes(300, 5, 3, 4096, math.log(4.0), 16, 262144)

@@ -263,6 +263,7 @@ def test_tuning_json_roundtrip(host, tmp_path):
     t = sc.Tuning()
     host.hl_tuning_defaults(ctypes.byref(t))
     t.blocks_per_cu[0], t.blocks_per_cu[1], t.blocks_per_cu[2] = 1, 2, 7
+    t.tile_many[0], t.tile_many[1] = 1 << 16, 1 << 17
     t.tile[1][1][22] = 1 << 16
     path = str(tmp_path / "tune.json").encode()
     assert host.hl_tuning_save(path, b"gfx950:sramecc+:xnack-", ctypes.byref(t)) == 1
@@ -283,6 +284,11 @@ def test_tuning_json_roundtrip(host, tmp_path):
     assert host.hl_tuning_parse(b'{"gfx950": {"blocks_per_cu": 3}}', err, 256) == 1
     assert host.hl_tuning_parse(b'{"gfx950": {"blocks_per_cu": 40}}', err, 256) == -1
     assert host.hl_tuning_parse(b'{"gfx950": [}', err, 256) == -1
+    # mixed-batch tiles: three entries, each 0 or a power of two in range
+    assert host.hl_tuning_parse(b'{"gfx950": {"tile_many": [0, 65536, 0]}}', err, 256) == 1
+    assert host.hl_tuning_parse(b'{"gfx950": {"tile_many": [0, 65536]}}', err, 256) == -1
+    assert host.hl_tuning_parse(b'{"gfx950": {"tile_many": [0, 3000, 0]}}', err, 256) == -1
+    assert b"tile_many" in err.value
 
 
 def test_committed_tuning_cache_is_valid(host):
