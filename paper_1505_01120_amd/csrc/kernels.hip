@@ -1318,6 +1318,22 @@ __device__ __forceinline__ uint4 wc_span(const uint8_t *text, uint64_t n, uint64
 
 // Byte k (0..15) of a span held in registers: a 64-bit select and a shift
 // (no indexed register array, which the compiler would put in scratch).
+// Bit i of the result is set when byte i of w (little-endian) is whitespace
+// (wc_space), for the four bytes at once: with each byte's top bit forced to
+// 1, the per-byte subtractions below cannot borrow across bytes, so the top
+// bit of each byte of (w | 0x80..) - c tells whether its low 7 bits are >= c;
+// bytes of 0x80 and above are never whitespace.
+__device__ __forceinline__ uint32_t space_bits4(uint32_t w)
+{
+    const uint32_t top = 0x80808080u;
+    const uint32_t up = w | top;
+    const uint32_t ge09 = (up - 0x09090909u) & top;
+    const uint32_t ge0e = (up - 0x0E0E0E0Eu) & top;
+    const uint32_t ne20 = (((w ^ 0x20202020u) & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) & top;
+    const uint32_t ws = ((ge09 & ~ge0e) | (~ne20 & top)) & ~w & top;
+    return ((ws >> 7) & 1u) | ((ws >> 14) & 2u) | ((ws >> 21) & 4u) | ((ws >> 28) & 8u);
+}
+
 __device__ __forceinline__ uint32_t span_byte(uint64_t lo, uint64_t hi, uint32_t k)
 {
     const uint64_t half = k < 8 ? lo : hi;
@@ -1386,10 +1402,10 @@ __global__ __launch_bounds__(kBlock) void k_wordcount(WcArgs a)
         const uint64_t lo = ((uint64_t)mine.y << 32) | mine.x;
         const uint64_t hi = ((uint64_t)mine.w << 32) | mine.z;
         const uint64_t lo2 = ((uint64_t)nxt.y << 32) | nxt.x;
-        uint32_t sep = 0;
-#pragma unroll
-        for (uint32_t k = 0; k < 16; ++k)
-            sep |= (uint32_t)wc_space(span_byte(lo, hi, k)) << k;
+        // whitespace bits of the 16 bytes and of the first 8 of the next span
+        const uint32_t sep = space_bits4(mine.x) | (space_bits4(mine.y) << 4) |
+                             (space_bits4(mine.z) << 8) | (space_bits4(mine.w) << 12);
+        const uint32_t sep24 = sep | (space_bits4(nxt.x) << 16) | (space_bits4(nxt.y) << 20);
         const uint32_t starts = ~sep & ((sep << 1) | (uint32_t)wc_space(prev)) & 0xFFFFu;
         const uint32_t mycount = __builtin_popcount(starts);
         // exclusive prefix sum of the word counts over the wave's lanes
@@ -1405,22 +1421,26 @@ __global__ __launch_bounds__(kBlock) void k_wordcount(WcArgs a)
         // All lanes walk their 16 bytes and the first 8 of the next span in
         // step: a word that starts in this span is hashed byte by byte and
         // written to the wave's buffer when its separator comes.
+        // The steps are branch-free selects on 0/1 integers, except the
+        // store of a finished key.
         uint64_t h = kBasis;
-        bool inw = false;
+        uint32_t inw = 0;
 #pragma unroll
         for (uint32_t k = 0; k < 24; ++k) {
             const uint32_t byte = k < 16 ? span_byte(lo, hi, k) : span_byte(lo2, 0, k - 16);
-            const bool sp = wc_space(byte);
-            if (k < 16 && ((starts >> k) & 1u)) {
-                inw = true;
-                h = kBasis;
+            const uint32_t sp = (sep24 >> k) & 1u;
+            if (k < 16) {
+                const uint32_t st = (starts >> k) & 1u;
+                h = st ? kBasis : h;
+                inw |= st;
             }
-            if (inw && !sp)
-                h = fnv_step(h, byte);
-            if (inw && sp) {
-                buf[slot++] = h;
-                inw = false;
-            }
+            const uint64_t hn = fnv_step(h, byte);
+            const uint32_t emit = inw & sp;
+            h = (inw & (sp ^ 1u)) ? hn : h;
+            if (emit)
+                buf[slot] = h;
+            slot += emit;
+            inw &= sp ^ 1u;
         }
         if (inw) {
             // a word longer than what is left of the 24 bytes: the rest comes
