@@ -367,7 +367,8 @@ SPARKCL_API int sparkcl_last_kernel_ms(sparkcl_ctx *ctx, float *ms);
    distinct keys and of words.  Blocking.  The counting table comes from the
    arena (16 B per slot, two slots per key of capacity, at least 1024):
    ENOMEM if it does not fit; ETOOBIG if there are more distinct keys than
-   `capacity` (*ndistinct is then at least capacity + 1). */
+   `capacity` (*ndistinct is then at least capacity + 1), or if nbytes
+   exceeds 2^40. */
 SPARKCL_API int sparkcl_wordcount(sparkcl_ctx *ctx, const uint8_t *text, uint64_t nbytes,
                                   uint64_t *keys, uint64_t *counts, uint64_t capacity,
                                   uint64_t *ndistinct, uint64_t *nwords, void *stream);

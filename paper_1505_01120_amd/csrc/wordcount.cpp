@@ -24,6 +24,9 @@ int sparkcl_wordcount(sparkcl_ctx *ctx, const uint8_t *text, uint64_t nbytes, ui
     *nwords = 0;
     if (nbytes == 0)
         return SPARKCL_OK;
+    if (nbytes > kMaxN)
+        return fail(SPARKCL_ETOOBIG, "text of " + std::to_string(nbytes) +
+                                         " bytes exceeds 2^40");
     std::lock_guard<std::mutex> g(ctx->mu);
     hipStream_t s = static_cast<hipStream_t>(stream);
     // open addressing at load <= 1/2: room for capacity + 1 keys (so one key
