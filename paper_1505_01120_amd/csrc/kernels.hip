@@ -12,14 +12,15 @@
 //   3. the partial is published and an arrival ticket taken; the block that
 //      takes the last ticket combines the task's partials in FP64 in a fixed
 //      order and writes the partition result (the tree-reduce of ReduceCL,
-//      sec. 3.1.3 and 3.2.2).  The block that finishes the last task of a
-//      launch folds the partition results into the RDD-level total.
+//      sec. 3.1.3 and 3.2.2); a task of one tile is finished by its block
+//      directly.  The block that finishes the last task of a launch folds
+//      the partition results into the RDD-level total.
 // Tiles of at least one chunk (kBlock x kUnroll quads) deal a task's chunks
 // round-robin to its tiles, so the tiles that run together read one sliding
 // window of the task; smaller tiles are contiguous ranges.  Every element's
 // owner thread and every combine order depend only on the tile size, the
-// block size and the inputs' 16-byte alignment, so results are identical run
-// to run and across execution modes with the same tiles.
+// block size and x's 16-byte alignment, so results are identical run to run
+// and across execution modes with the same tiles.
 //
 // Compiled with -ffp-contract=off: the maps are the binary32 definition
 // operation by operation.  No MFMA: nothing on this path is a contraction.
@@ -1223,7 +1224,7 @@ __global__ __launch_bounds__(kBlock) void k_zero(uint32_t *p, uint64_t words)
 // the result does not depend on which block counts which word.
 constexpr uint32_t kWcChunk = 4096;   // bytes per chunk: 16 per thread
 constexpr uint32_t kWcLook = 256;     // look-ahead bytes staged after a chunk
-constexpr uint32_t kWcSlots = 2048;   // LDS hash slots per block
+constexpr uint32_t kWcSlots = 1024;   // LDS hash slots per block
 constexpr uint32_t kWcProbes = 8;     // LDS probes before a word spills
 static_assert(kWcChunk == 16 * kBlock, "one 16-byte span per thread");
 
@@ -1274,7 +1275,11 @@ __device__ void wc_global_add(const WcArgs &a, uint64_t h, uint64_t c)
     atomicOr((unsigned long long *)&a.ctl[2], 1ull); // table full
 }
 
-__device__ __forceinline__ void wc_local_add(uint64_t *sk, uint64_t *sc, const WcArgs &a,
+// The LDS counts are 32-bit: a block counts at most one word per two bytes
+// of the text it scans, and a block scans either one 4 KiB chunk or at most
+// 1/256 of the text (a grid of at least one block per CU), which is limited
+// to 2^40 bytes.
+__device__ __forceinline__ void wc_local_add(uint64_t *sk, uint32_t *sc, const WcArgs &a,
                                              uint64_t h)
 {
     if (h != 0) {
@@ -1282,14 +1287,14 @@ __device__ __forceinline__ void wc_local_add(uint64_t *sk, uint64_t *sc, const W
         for (uint32_t p = 0; p < kWcProbes; ++p) {
             const uint64_t k = sk[s];
             if (k == h) {
-                atomicAdd((unsigned long long *)&sc[s], 1ull);
+                atomicAdd(&sc[s], 1u);
                 return;
             }
             if (k == 0) {
                 const uint64_t old =
                     atomicCAS((unsigned long long *)&sk[s], 0ull, (unsigned long long)h);
                 if (old == 0 || old == h) {
-                    atomicAdd((unsigned long long *)&sc[s], 1ull);
+                    atomicAdd(&sc[s], 1u);
                     return;
                 }
             }
@@ -1353,7 +1358,7 @@ __device__ __forceinline__ void lds_barrier()
 __global__ __launch_bounds__(kBlock) void k_wordcount(WcArgs a)
 {
     __shared__ uint64_t sk[kWcSlots];
-    __shared__ uint64_t sc[kWcSlots];
+    __shared__ uint32_t sc[kWcSlots];
     __shared__ uint4 st4[(kWcChunk + kWcLook) / 16];
     __shared__ uint64_t emit[kWaves][64 * 8]; // a 16-byte span holds <= 8 word starts
     __shared__ uint32_t sh_prev;
