@@ -1225,7 +1225,7 @@ __global__ __launch_bounds__(kBlock) void k_zero(uint32_t *p, uint64_t words)
 constexpr uint32_t kWcChunk = 4096;   // bytes per chunk: 16 per thread
 constexpr uint32_t kWcLook = 256;     // look-ahead bytes staged after a chunk
 constexpr uint32_t kWcSlots = 1024;   // LDS hash slots per block
-constexpr uint32_t kWcProbes = 8;     // LDS probes before a word spills
+constexpr uint32_t kWcProbes = 4;     // LDS probes before a word spills
 static_assert(kWcChunk == 16 * kBlock, "one 16-byte span per thread");
 
 __device__ __forceinline__ bool wc_space(uint32_t b)
