@@ -257,8 +257,7 @@ SPARKCL_API int sparkcl_reduce_chain(sparkcl_ctx *ctx, const sparkcl_task *tasks
 /* Array-valued ReduceCL (sec. 3.1.3 item 3; the Fig 3 vector add; sec.
    3.2.2): the RDD's elements are `k` float arrays of `len` elements each, in
    RDD order; arrays[] is a HOST array of k DEVICE pointers (caller-owned, any
-   4-byte alignment; 16-byte-aligned arrays with len % 4 == 0 take the float4
-   path).  The combiner (SPARKCL_VADD or SPARKCL_VMAX) folds them pairwise
+   4-byte alignment; with len % 4 == 0 the columns are read as float4).  The combiner (SPARKCL_VADD or SPARKCL_VMAX) folds them pairwise
    along a fixed tree -- over elements [k0, k1) the split is at k0 plus the
    largest power of two below the count, left part the left operand -- and
    the result goes to out[0..len) (device memory; it may be one of the

@@ -1,7 +1,8 @@
 """GPU parity of the array-valued ReduceCL (sec. 3.1.3 item 3, Fig 3, sec.
 3.2.2): sparkcl_reduce_arrays through the C ABI against the oracle's fixed
-tree, bit for bit, over single- and multi-pass shapes, the float4 and the
-scalar paths, both combiners, and the argument errors."""
+tree, bit for bit, over single- and multi-pass shapes, the float4 columns
+(any 4-byte alignment) and the scalar ones (lengths not a multiple of 4),
+both combiners, and the argument errors."""
 import numpy as np
 import pytest
 import torch

@@ -86,8 +86,8 @@ def test_ops_subsets(ctx, mode):
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("xoff,yoff", [(1, 1), (2, 2), (3, 3), (1, 2), (0, 3)])
 def test_unaligned_inputs(ctx, mode, xoff, yoff):
-    # equal misalignment takes the float4 path with a scalar head; unequal
-    # misalignment takes the scalar path
+    # float4 quads after a scalar head up to x's first 16-byte boundary; y
+    # is read with the same quad indices at its own (4-byte) alignment
     parts = [datagen.make_part(datagen.FMUL, n, pid) for pid, n in
              enumerate([5, 1000, 65537, 300_000])]
     parts += [datagen.make_part(datagen.POLY, 65539, 9)]
