@@ -88,7 +88,7 @@ struct Plan {
     uint64_t slot_bytes = 0;
     char *staging = nullptr;
     hipEvent_t ev_start = nullptr;
-    std::vector<hipEvent_t> ev_copied, ev_done;
+    std::vector<hipEvent_t> ev_copied, ev_copied2, ev_done; // x copied, y copied, slot free
 
     // SPARKCL_GRAPH: the plan's launches captured once, replayed per call
     hipGraph_t graph = nullptr;
@@ -161,7 +161,8 @@ struct sparkcl_ctx {
     std::mutex mu; // plans, events, pinned buffers
     std::list<sparkcl::Plan *> plans; // most recently used first
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    hipStream_t copy_stream = nullptr; // host-input staging copies
+    hipStream_t copy_stream = nullptr;  // host-input staging copies of x
+    hipStream_t copy_stream2 = nullptr; // and of y
     hipStream_t capture_stream = nullptr; // builds SPARKCL_GRAPH plans' graphs
     bool have_ms = false;
     double offload_fixed_s = 0.0;   // selective execution: measured fixed
