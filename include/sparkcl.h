@@ -217,7 +217,8 @@ SPARKCL_API int sparkcl_reduce(sparkcl_ctx *ctx, const sparkcl_task *tasks,
 
 /* The same as sparkcl_reduce without the host synchronisation: results are
    written by the GPU to dev_per_task[ntasks] and *dev_total (device memory,
-   caller-owned; either may be NULL) in stream order.  Calls that share a
+   caller-owned; either may be NULL; with dev_per_task set and dev_total NULL
+   the RDD-level total is not computed) in stream order.  Calls that share a
    context must not overlap in time on different streams.
    Stream capture: a call on a stream that is being captured into the
    caller's own graph records the plan's launches into that graph, with no

@@ -445,7 +445,11 @@ int sparkcl::build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task
         p->out.ctl = p->dctl;
         p->out.results = ures ? ures : p->dresults;
         p->out.total = utot ? utot : p->dtotal;
-        p->out.ntasks = ntasks;
+        // The RDD-level step (one memory-side atomic per finished task, all
+        // on one counter) runs only when the total is wanted: an
+        // asynchronous call that names per-task results but no total skips
+        // it.  Blocking calls (ures == NULL) always return the total.
+        p->out.ntasks = (ures && !utot) ? 0 : ntasks;
         p->out.ns_per_tick = ctx->ns_per_tick;
         p->grid = std::min(per_cu ? per_cu * (uint32_t)ctx->cus
                                   : exec_grid(ctx, kid_mask, p->ntiles_total, ntasks),

@@ -703,8 +703,26 @@ __device__ __forceinline__ bool run_tile(const TaskDev *__restrict__ tp, uint32_
     });
 }
 
-// RDD-level step, run by the block that completed a task: the block that
-// completes the launch's last task folds all partition results in task order.
+// The RDD-level total: all partition results folded in task order (run by
+// one block once every task of the launch has its result).
+__device__ __forceinline__ void rdd_total(const LaunchOut &L)
+{
+    const sparkcl_result *res = L.results;
+    Red t = combine_ordered(L.ntasks, [&](uint32_t k, double &s, float &m,
+                                          uint64_t &h, uint64_t &n) {
+        read_result(res + k, s, m, h, n);
+    });
+    if (threadIdx.x == 0 && L.total) {
+        write_result(L.total, SPARKCL_SUM | SPARKCL_MAX | SPARKCL_COUNT, t, 0,
+                     device_ns(L.ns_per_tick));
+        own_stores_complete();
+    }
+    __syncthreads();
+}
+
+// RDD-level step of the per-partition launches, run by the block that
+// completed a task: the block that completes the last task of the sequence
+// folds all partition results.
 __device__ __forceinline__ void rdd_step(const LaunchOut &L)
 {
     __shared__ uint32_t sh_last;
@@ -720,15 +738,8 @@ __device__ __forceinline__ void rdd_step(const LaunchOut &L)
     __syncthreads();
     if (!last)
         return;
-    const sparkcl_result *res = L.results;
-    Red t = combine_ordered(L.ntasks, [&](uint32_t k, double &s, float &m,
-                                          uint64_t &h, uint64_t &n) {
-        read_result(res + k, s, m, h, n);
-    });
+    rdd_total(L);
     if (threadIdx.x == 0) {
-        if (L.total)
-            write_result(L.total, SPARKCL_SUM | SPARKCL_MAX | SPARKCL_COUNT, t,
-                         0, device_ns(L.ns_per_tick));
         __hip_atomic_store(&L.ctl->rdd_ticket, 0u, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
         own_stores_complete();
@@ -902,18 +913,30 @@ __device__ __forceinline__ void executor(const TaskDev *__restrict__ tasks,
                                           __HIP_MEMORY_SCOPE_AGENT);
         const TileRef tr = tiles[t];
         const TaskDev *tp = tasks + uni(tr.task);
-        if (tile(tp, uni(tr.tile)))
-            rdd_step(L);
+        tile(tp, uni(tr.tile));
         if (threadIdx.x == 0)
             sh_tile = next;
         __syncthreads();
         t = uni(sh_tile);
         __syncthreads();
     }
+    // The last block to leave has every task's result (each block waited for
+    // its own stores before it counted itself out): it folds the RDD total,
+    // once per launch instead of one contended ticket per task, and resets
+    // the queue for the next launch.
+    __shared__ uint32_t sh_out;
     if (threadIdx.x == 0) {
         own_stores_complete();
-        if (__hip_atomic_fetch_add(&L.ctl->exited, 1u, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1) {
+        sh_out = __hip_atomic_fetch_add(&L.ctl->exited, 1u, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1
+                     ? 1u
+                     : 0u;
+    }
+    __syncthreads();
+    if (uni(sh_out) != 0) {
+        if (L.ntasks != 0)
+            rdd_total(L);
+        if (threadIdx.x == 0) {
             __hip_atomic_store(&L.ctl->head, 0u, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&L.ctl->exited, 0u, __ATOMIC_RELAXED,
