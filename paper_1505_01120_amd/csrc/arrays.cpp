@@ -90,18 +90,28 @@ int build_tree_plan(sparkcl_ctx *ctx, uint32_t combiner, const float *const *arr
     std::vector<uint32_t> rows; // output rows of each pass
     uint32_t count = k;
     for (;;) {
-        uint32_t chunk = 0, cpt = 1;
+        uint32_t chunk = 0, cpt = 1, threads = kBlock;
         // float4 columns: the wide kernel (leaf pairs, 2 or 4 columns per
         // thread, chunks of up to 64 leaves) when its grid still fills half
         // the GPU's block slots and at most one more pass follows (many
         // short columns fold better in the deeper chunks of the 8-leaf
         // kernel: 65536 rows of 4096 floats took 189 us through 64-leaf
         // chunks and four passes, 181 us in three); the most columns per
-        // thread first
+        // thread first, in blocks of kTreeWideBig threads when those alone
+        // give every CU two blocks (64 arrays of 2^22 floats: 163 us against
+        // 170 us in 256-thread blocks)
         if (vec4) {
             const uint32_t ch = std::min<uint32_t>(count, kTreeWideChunk);
             const uint64_t nch = (count + (uint64_t)ch - 1) / ch;
+            const uint64_t cb_big = (len / 4 + kTreeWideBig * 4ull - 1) / (kTreeWideBig * 4ull);
+            if (nch <= kTreeWideChunk && cb_big * nch >= 2ull * (uint64_t)ctx->cus) {
+                cpt = 4;
+                threads = kTreeWideBig;
+                chunk = ch;
+            }
             for (uint32_t c : {4u, 2u}) {
+                if (cpt > 1)
+                    break;
                 const uint64_t cb = (len / 4 + (uint64_t)kBlock * c - 1) / ((uint64_t)kBlock * c);
                 if (nch <= kTreeWideChunk && cb * nch >= target / 2) {
                     cpt = c;
@@ -132,6 +142,7 @@ int build_tree_plan(sparkcl_ctx *ctx, uint32_t combiner, const float *const *arr
         a.count = count;
         a.chunk = chunk;
         a.cpt = cpt;
+        a.threads = threads;
         p->passes.push_back(a);
         rows.push_back(nchunks);
         if (nchunks == 1)

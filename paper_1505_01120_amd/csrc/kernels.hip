@@ -1139,13 +1139,14 @@ __global__ __launch_bounds__(kBlock) void k_tree(TreeArgs a)
     TV::st(a.out + (uint64_t)c * a.len + col, acc);
 }
 
-// Wide variant (float4 columns only): a thread owns CPT float4 columns kBlock
-// quads apart, so a block reads CPT * 4 KiB of one leaf contiguously, and the
-// leaves are walked two at a time: each pair is a perfect subtree that enters
-// the counter at level 1.  Fewer leaves and longer runs of each leaf in
-// flight keep the HBM row buffers open (measured on MI355X over 64 arrays of
-// 2^22 floats: one or two leaves at a time with 16-32 KiB per leaf per block
-// stream at 6.6-6.9 TB/s; eight leaves of 4 KiB at 5.3).  The counter holds
+// Wide variant (float4 columns only): a thread owns CPT float4 columns BT
+// quads apart, so a block of BT threads reads CPT * BT * 16 bytes of one leaf
+// contiguously, and the leaves are walked two at a time: each pair is a
+// perfect subtree that enters the counter at level 1.  Fewer leaves and
+// longer runs of each leaf in flight keep the HBM row buffers open (measured
+// on MI355X over 64 arrays of 2^22 floats: 32 KiB per leaf per block, as 512
+// threads of 4 columns, streams at 6.7 TB/s; 16 KiB per leaf per block in
+// 256 threads at 6.4; eight leaves of 4 KiB at 5.3).  The counter holds
 // kTreeWideSlots levels per column, so a chunk has at most 64 leaves.
 constexpr int kTreeWideSlots = 7;
 static_assert(kTreeWideChunk == 1u << (kTreeWideSlots - 1), "chunk fits the counter");
@@ -1169,17 +1170,17 @@ __device__ __forceinline__ void tree_insert_cols(float4 (&slot)[kTreeWideSlots][
     }
 }
 
-template <uint32_t COMB, int CPT>
-__global__ __launch_bounds__(kBlock) void k_tree_wide(TreeArgs a)
+template <uint32_t COMB, int CPT, int BT>
+__global__ __launch_bounds__(BT) void k_tree_wide(TreeArgs a)
 {
     const uint64_t nq = a.len >> 2;
-    const uint64_t q0 = (uint64_t)blockIdx.x * kBlock * CPT + threadIdx.x;
+    const uint64_t q0 = (uint64_t)blockIdx.x * BT * CPT + threadIdx.x;
     if (q0 >= nq)
         return; // no barriers below
     bool ok[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c)
-        ok[c] = q0 + (uint64_t)c * kBlock < nq;
+        ok[c] = q0 + (uint64_t)c * BT < nq;
     const uint32_t ch = blockIdx.y;
     const uint32_t k0 = ch * a.chunk;
     const uint32_t m = min(a.count - k0, a.chunk);
@@ -1191,7 +1192,7 @@ __global__ __launch_bounds__(kBlock) void k_tree_wide(TreeArgs a)
         const float *p = leaf(i);
 #pragma unroll
         for (int c = 0; c < CPT; ++c)
-            v[c] = ok[c] ? ld4u(p + 4 * (uint64_t)c * kBlock) : float4{};
+            v[c] = ok[c] ? ld4u(p + 4 * (uint64_t)c * BT) : float4{};
     };
     float4 slot[kTreeWideSlots][CPT];
     uint32_t i = 0;
@@ -1224,7 +1225,7 @@ __global__ __launch_bounds__(kBlock) void k_tree_wide(TreeArgs a)
 #pragma unroll
     for (int c = 0; c < CPT; ++c)
         if (ok[c])
-            st4u(o + 4 * (uint64_t)c * kBlock, acc[c]);
+            st4u(o + 4 * (uint64_t)c * BT, acc[c]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_zero(uint32_t *p, uint64_t words)
@@ -1858,23 +1859,29 @@ int launch_tree(const TreeArgs &a, uint32_t combiner, bool vec4, void *stream)
     hipStream_t s = (hipStream_t)stream;
     if (a.cpt != 1) {
         if (!vec4 || (a.cpt != 2 && a.cpt != 4) || a.chunk > kTreeWideChunk ||
-            (combiner != SPARKCL_VADD && combiner != SPARKCL_VMAX))
+            (combiner != SPARKCL_VADD && combiner != SPARKCL_VMAX) ||
+            (a.threads != (uint32_t)kBlock && !(a.threads == kTreeWideBig && a.cpt == 4)))
             return SPARKCL_EINVAL;
-        const uint64_t per_block = (uint64_t)kBlock * a.cpt;
+        const uint64_t per_block = (uint64_t)a.threads * a.cpt;
         const uint64_t cb = ((a.len >> 2) + per_block - 1) / per_block;
         if (cb > 0x7fffffffull)
             return SPARKCL_EINVAL;
         const dim3 grid((uint32_t)cb, nchunks);
+        const dim3 block(a.threads);
         if (combiner == SPARKCL_VADD) {
-            if (a.cpt == 4)
-                hipLaunchKernelGGL((k_tree_wide<SPARKCL_VADD, 4>), grid, dim3(kBlock), 0, s, a);
+            if (a.threads == kTreeWideBig)
+                hipLaunchKernelGGL((k_tree_wide<SPARKCL_VADD, 4, kTreeWideBig>), grid, block, 0, s, a);
+            else if (a.cpt == 4)
+                hipLaunchKernelGGL((k_tree_wide<SPARKCL_VADD, 4, kBlock>), grid, block, 0, s, a);
             else
-                hipLaunchKernelGGL((k_tree_wide<SPARKCL_VADD, 2>), grid, dim3(kBlock), 0, s, a);
+                hipLaunchKernelGGL((k_tree_wide<SPARKCL_VADD, 2, kBlock>), grid, block, 0, s, a);
         } else {
-            if (a.cpt == 4)
-                hipLaunchKernelGGL((k_tree_wide<SPARKCL_VMAX, 4>), grid, dim3(kBlock), 0, s, a);
+            if (a.threads == kTreeWideBig)
+                hipLaunchKernelGGL((k_tree_wide<SPARKCL_VMAX, 4, kTreeWideBig>), grid, block, 0, s, a);
+            else if (a.cpt == 4)
+                hipLaunchKernelGGL((k_tree_wide<SPARKCL_VMAX, 4, kBlock>), grid, block, 0, s, a);
             else
-                hipLaunchKernelGGL((k_tree_wide<SPARKCL_VMAX, 2>), grid, dim3(kBlock), 0, s, a);
+                hipLaunchKernelGGL((k_tree_wide<SPARKCL_VMAX, 2, kBlock>), grid, block, 0, s, a);
         }
         return hip_status(hipGetLastError());
     }

@@ -162,8 +162,11 @@ struct TreeArgs {
     uint32_t chunk;
     uint32_t cpt; // float4 columns per thread: 1 (8-leaf groups), or 2 / 4
                   // (leaf pairs, chunks of at most kTreeWideChunk leaves)
+    uint32_t threads; // block threads of the leaf-pair kernel: kBlock, or
+                      // kTreeWideBig with 4 columns per thread
 };
 constexpr uint32_t kTreeWideChunk = 64;
+constexpr uint32_t kTreeWideBig = 512;
 int launch_tree(const TreeArgs &a, uint32_t combiner, bool vec4, void *stream);
 // WordCount: text of n bytes counted into the global open-addressing table
 // keys/counts of mask + 1 slots (a power of two, cleared beforehand); ctl[0]

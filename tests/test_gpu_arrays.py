@@ -122,12 +122,19 @@ def test_full_size_64_arrays_of_2p22(ctx):
 # Shapes that fill the GPU with float4 columns take the wide kernel (leaf
 # pairs, 2 or 4 float4 columns per thread, chunks of 64 leaves): multi-pass
 # with a ragged last chunk, an odd leaf at the end, and columns that end
-# inside a block's span.  Columns are checked on samples against the oracle.
+# inside a block's span.  Grids of 512-thread blocks (2048 quads each) that
+# give every CU two blocks (512 on 256 CUs) take its 512-thread form: the
+# last two shapes,
+# the second of them in two passes (its 65th leaf is a chunk of its own, and
+# the pass over the two chunk rows takes the 256-thread form).  Columns are
+# checked on samples against the oracle.
 @pytest.mark.parametrize("k,length,comb", [(130, (1 << 20) + 4, sc.VADD),
                                            (77, (1 << 21) + 12, sc.VADD),
                                            (77, (1 << 21) + 12, sc.VMAX),
                                            (3, (1 << 21) + 4, sc.VADD),
-                                           (200, 1 << 19, sc.VADD)])
+                                           (200, 1 << 19, sc.VADD),
+                                           (3, 4 * (2048 * 512 + 100), sc.VADD),
+                                           (65, 4 * (2048 * 256 + 36), sc.VMAX)])
 def test_wide_kernel_shapes(ctx, k, length, comb):
     dev = torch.empty((k, length), dtype=torch.float32, device="cuda")
     for e in range(k):
