@@ -184,6 +184,45 @@ def cpu_baseline(res: Resident, reps: int = 3) -> dict:
 
 # ---- extras -----------------------------------------------------------------
 
+def read_ceiling(sc, res: Resident, reps: int = 20) -> dict:
+    """The measured HBM read-stream ceiling: a plain kernel that only reads
+    the RDD's x and y (nontemporal float4 loads, grid-stride), timed with HIP
+    events at 1, 2 and 4 blocks per CU; the best rate is the ceiling."""
+    import torch
+    lib = ctypes.CDLL(os.path.join(os.path.dirname(os.path.abspath(sc.__file__)),
+                                   "libsparkcl_probe.so"))
+    fn = lib.sparkcl_probe_read2
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                   ctypes.c_void_p, ctypes.c_void_p]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    n = res.parts * res.n
+    sink = torch.empty(4 * cus, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    out = {}
+    for per_cu in (1, 2, 4):
+        grid = per_cu * cus
+
+        def launch():
+            rc = fn(res.x.data_ptr(), res.y.data_ptr(), n, grid, sink.data_ptr(),
+                    stream.cuda_stream)
+            if rc != 0:
+                raise RuntimeError(f"sparkcl_probe_read2 failed ({rc})")
+        for _ in range(3):
+            launch()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            launch()
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[f"{per_cu}_per_cu"] = {"ms": ms, "GBps": 8 * n / (ms / 1e3) / 1e9}
+    best = max(v["GBps"] for v in out.values())
+    return {"GBps": best, "frac_of_peak": best / HBM_PEAK_GBS, "kernel": "k_read_ceiling",
+            "bytes_per_launch": 8 * n, "grids": out}
+
+
 def bench_single_partition(ctx, sc, reps=50) -> dict:
     import torch
 
@@ -610,6 +649,8 @@ def main() -> int:
     algo_bytes = 8 * elems
     achieved = algo_bytes / (ev_ms / 1e3) / 1e9
     traffic = load_traffic("fmul_rdd_batched")
+    log("read ceiling ...")
+    ceiling = read_ceiling(sc, res)
     line = {
         "metric": "mapCL+reduceCL elements/s and % peak HBM GB/s; p50/p99 task latency",
         "value": elems / (wall_ms / 1e3),
@@ -631,7 +672,10 @@ def main() -> int:
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "kernel": "k_batch",
                      "algorithmic_bytes_per_launch": algo_bytes,
-                     "kernel_ms_per_launch": ev_ms},
+                     "kernel_ms_per_launch": ev_ms,
+                     "read_ceiling_GBps": ceiling["GBps"],
+                     "frac_of_read_ceiling": achieved / ceiling["GBps"]},
+        "read_ceiling": ceiling,
     }
     if not args.no_cpu:
         log("cpu baseline ...")

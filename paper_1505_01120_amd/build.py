@@ -8,6 +8,8 @@ Produces, next to this file:
   libsparkcl_loadgen.so -- an open-loop serving load generator over the public
                          C ABI (submit / poll at scheduled arrival times), for
                          the serving benchmark;
+  libsparkcl_probe.so -- a plain read-only streaming kernel, the bench's
+                         measured HBM read ceiling;
   isa.json            -- resource figures of the kernels' own gfx950 code
                          (registers, private segment, VALU instructions per
                          Philox block), read from the device assembly of this
@@ -36,6 +38,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsparkcl.so")
 HOST_LIB = os.path.join(HERE, "libsparkcl_host.so")
 LOADGEN_LIB = os.path.join(HERE, "libsparkcl_loadgen.so")
+PROBE_LIB = os.path.join(HERE, "libsparkcl_probe.so")
 ISA_JSON = os.path.join(HERE, "isa.json")
 KERNELS = ("k_task", "k_batch", "k_serve", "k_map", "k_chain", "k_tree", "k_tree_wide", "k_wordcount",
            "k_wc_compact")
@@ -128,10 +131,19 @@ def build(verbose: bool = False) -> str:
               os.path.join(CSRC, "kernels.hip"), "-o", asm])
         return asm
 
+    def probe_lib() -> None:
+        # the read-ceiling kernel: a library of its own, outside the API
+        tmp = PROBE_LIB + ".tmp"
+        _run([cc, *COMMON, *HIP_FLAGS, "-shared", "-x", "hip", os.path.join(CSRC, "probe.hip"),
+              "-o", tmp])
+        os.replace(tmp, PROBE_LIB)
+
     with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
         asm_job = ex.submit(device_asm)
+        probe_job = ex.submit(probe_lib)
         objs = list(ex.map(compile_hip, HIP_SOURCES))
         asm = asm_job.result()
+        probe_job.result()
     tmp = LIB + ".tmp"
     _run([cc, "-shared", "-fPIC", "--offload-arch=" + ARCH, *objs, "-o", tmp, "-lpthread"])
     os.replace(tmp, LIB)

@@ -356,3 +356,24 @@ def test_load_generator_library_exports_one_entry(lib):
     t0 = ctypes.c_int64()
     assert lg.sparkcl_loadgen_run(None, None, None, ctypes.c_uint64(0), ctypes.c_int64(0),
                                   ctypes.c_uint32(0), ctypes.byref(t0), None, None) == sc.EINVAL
+
+
+def test_read_ceiling_library_exports_one_entry(lib):
+    """The read-ceiling kernel is a library of its own, outside the API: one
+    exported entry point, refusing bad arguments before any HIP call."""
+    if not os.path.exists(libbuild.PROBE_LIB):
+        libbuild.build()
+    out = subprocess.run(["nm", "-D", "--defined-only", libbuild.PROBE_LIB],
+                         capture_output=True, text=True, check=True).stdout
+    assert sorted(set(re.findall(r" T (\w+)", out))) == ["sparkcl_probe_read2"]
+    pr = ctypes.CDLL(libbuild.PROBE_LIB)
+    fn = pr.sparkcl_probe_read2
+    fn.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                   ctypes.c_void_p, ctypes.c_void_p]
+    assert fn(None, None, 4096, 1, None, None) == sc.EINVAL
+    # 16-byte aligned stand-ins that are never dereferenced: every call below
+    # fails its size or alignment check first
+    assert fn(16, 32, 4096, 0, 64, None) == sc.EINVAL          # empty grid
+    assert fn(16, 32, 4095, 1, 64, None) == sc.EINVAL          # n not a whole pass
+    assert fn(16, 32, 4096 * 3, 2, 64, None) == sc.EINVAL      # 1.5 passes of 2 blocks
+    assert fn(20, 32, 4096, 1, 64, None) == sc.EINVAL          # x not 16-byte aligned
