@@ -228,11 +228,13 @@ int sparkcl::build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task
                                                   : "maps take device arrays");
     p->host = host_in;
 
-    // Tile table: the batched one, unless the batch would then have fewer
-    // tiles than the executor has blocks (a batch of one or a few partitions,
-    // where the batched table's large tiles would leave most of the GPU
-    // idle); such a batch is cut with the per-launch table instead.  The
-    // choice is a function of the call, so a repeated call is cut the same way.
+    // Tile table: the batched one, unless the batch would then give the
+    // executor's blocks fewer than two tiles each (a batch of one or a few
+    // partitions, where the batched table's large tiles would leave most of
+    // the GPU idle, or about one large tile per block, where the time is set
+    // by how unevenly the blocks land on the CUs); such a batch is cut with
+    // the per-launch table instead.  The choice is a function of the call,
+    // so a repeated call is cut the same way.
     if (host_in && mode == SPARKCL_GRAPH)
         return fail(SPARKCL_EINVAL, "host-input tasks run in PER_LAUNCH or BATCHED mode");
     int tm = mode != SPARKCL_PER_LAUNCH && !host_in ? TM_BATCHED : TM_PER_LAUNCH;
@@ -267,7 +269,9 @@ int sparkcl::build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task
             tiles += std::max<uint64_t>(1, (tasks[i].n + T - 1) / T);
             mask |= 1u << (tasks[i].kernel_id - 1);
         }
-        if (tiles < (per_cu ? per_cu * (uint32_t)ctx->cus : exec_grid(ctx, mask, tiles, ntasks)))
+        const uint64_t grid =
+            per_cu ? per_cu * (uint32_t)ctx->cus : exec_grid(ctx, mask, tiles, ntasks);
+        if (tiles < 2 * grid)
             tm = TM_PER_LAUNCH;
     }
     std::vector<uint64_t> first(ntasks);

@@ -60,12 +60,13 @@ int sparkcl_reduce_chain(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t n
         // The chain's Horner steps add dependent VALU work per element, whose
         // latency more waves per CU hide.  Measured on MI355X (64 x 2^22 FMUL
         // partitions): no steps streams best at the map's tuned occupancy
-        // (1 block per CU, 316 us), 3 steps at 3 blocks per CU (357 us, 407 at
-        // 1), 28 steps (four degree-7 stages) at 4 (399 us, 791 at 1).  A grid
-        // of more blocks than the batched table has tiles takes the
-        // per-launch table's smaller tiles, so blocks keep pulling tiles from
-        // the queue (with one large tile per block, blocks placed unevenly on
-        // the CUs decide the time: 440-490 us at 2 per CU).
+        // (1 block per CU, 316 us), 3 steps at 2 blocks per CU (347-353 us;
+        // 356-358 at 3, 407 at 1), 28 steps (four degree-7 stages) at 4
+        // (393-414 us; 425-438 at 3, 505-565 at 2, 791 at 1).  A grid that
+        // would get fewer than two of the batched table's tiles per block
+        // takes the per-launch table's smaller tiles, so blocks keep pulling
+        // tiles from the queue (with one large tile per block, blocks placed
+        // unevenly on the CUs decide the time: 440-490 us at 2 per CU).
         uint32_t per_cu = 0;
         if (!ctx->config.exec_blocks_per_cu) {
             uint32_t steps = 0;
@@ -76,7 +77,7 @@ int sparkcl_reduce_chain(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t n
                 if (tasks[i].kernel_id == SPARKCL_POLY)
                     base = std::max(base, tasks[i].degree);
             steps += base;
-            const uint32_t want = steps == 0 ? 0 : steps <= 12 ? 3 : 4;
+            const uint32_t want = steps == 0 ? 0 : steps <= 4 ? 2 : steps <= 12 ? 3 : 4;
             per_cu = std::min(want, (uint32_t)ctx->occ_chain);
         }
         if ((rc = build_plan(ctx, 0, SPARKCL_BATCHED, tasks, ntasks, nullptr, nullptr, st,
