@@ -180,6 +180,21 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
         rc = time_reduce(b, mode, tasks, ms);
         return rc == SPARKCL_OK;
     };
+    // A batched candidate the plan would not take (its blocks would get
+    // fewer than two tiles each, and the plan then cuts the batch with the
+    // per-launch table) is not measured, so no entry records a tile size
+    // that never ran.
+    auto batched_takes = [&](const sparkcl_tuning &t, uint32_t kid,
+                             const std::vector<sparkcl_task> &tasks, uint32_t T) {
+        uint64_t tiles = 0;
+        for (const sparkcl_task &x : tasks)
+            tiles += std::max<uint64_t>(1, (x.n + T - 1) / T);
+        const sparkcl_tuning keep = ctx->tuning;
+        ctx->tuning = t;
+        const uint64_t grid = exec_grid(ctx, 1u << (kid - 1), tiles, tasks.size());
+        ctx->tuning = keep;
+        return tiles >= 2 * grid;
+    };
     auto abort_with = [&](int code) {
         ctx->tuning = best;
         cleanup();
@@ -202,6 +217,8 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
                 sparkcl_tuning t = best;
                 t.blocks_per_cu[kid - 1] = bpc;
                 t.tile[TM_BATCHED][kid - 1][kRefLog2] = 1u << tl;
+                if (!batched_takes(t, kid, tasks, 1u << tl))
+                    continue;
                 float ms = 0;
                 if (!measure(t, SPARKCL_BATCHED, tasks, &ms))
                     return abort_with(rc);
@@ -238,6 +255,8 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
                         continue;
                     sparkcl_tuning t = best;
                     t.tile[tm][kid - 1][bk] = T;
+                    if (tm == TM_BATCHED && !batched_takes(t, kid, tasks, T))
+                        continue;
                     float ms = 0;
                     if (!measure(t, mode, tasks, &ms))
                         return abort_with(rc);
