@@ -332,7 +332,9 @@ typedef struct sparkcl_tuning {
                                     tiles; 0 = use the table, else a power of
                                     two from 2^10 to 2^22                     */
     /* tile size in elements (samples for MC_PI) for [mode][kernel-1][log2 n];
-       powers of two from 2^10 to 2^22. */
+       powers of two from 2^10 to 2^22.  A batched call whose executor blocks
+       would get fewer than two of the batched row's tiles each is cut with
+       the per-launch row instead. */
     uint32_t tile[SPARKCL_TUNE_MODES][3][SPARKCL_TUNE_BUCKETS];
 } sparkcl_tuning;
 
