@@ -8,7 +8,7 @@ import torch
 import datagen
 import oracle
 import paper_1505_01120_amd as sc
-from gpu_helpers import DevParts, check_result
+from gpu_helpers import DevParts, check_result, check_total
 
 pytestmark = pytest.mark.gpu
 
@@ -79,3 +79,20 @@ def test_chain_errors(ctx):
     with pytest.raises(sc.SparkclError) as e:
         ctx.reduce_chain([sc.task(sc.MC_PI, 100)], [])
     assert e.value.code == sc.EINVAL
+
+
+def test_chain_full_size(ctx):
+    # The 64 x 2^22 FMUL RDD (x~N(0,1), y~U[0,2)) through FMUL -> POLY2 ->
+    # POLY1, reduced without materialising anything: the fused chain at full
+    # size in the launch configuration the benchmark times (the chain rule's
+    # occupancy, the per-launch tiles that follow from it).  Every partition's
+    # SUM and MAX against the oracle's composed maps, and the RDD total.
+    parts = datagen.fmul_rdd()
+    d = DevParts(parts)
+    stages = STAGES[:2]
+    per, tot = ctx.reduce_chain(d.tasks, [sc.stage(s) for s in stages])
+    torch.cuda.synchronize()
+    results = [want(p, stages)[1] for p in parts]
+    for p, g, o in zip(parts, per, results):
+        check_result(g, o, p.kid, p.ops, f"pid={p.pid}")
+    check_total(tot, results, datagen.SUM | datagen.MAX)
