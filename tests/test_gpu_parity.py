@@ -316,3 +316,46 @@ def test_uneven_batch_reduced(ctx):
     parts = [datagen.make_part(int(k), int(n), i) for i, (n, k) in enumerate(zip(sizes, kids))]
     for mode in MODES:
         run_and_check(ctx, parts, mode)
+
+
+def test_uneven_batch_full_size(ctx):
+    # The benchmark's 4096-partition log-normal batch (mixed kernels; one
+    # device pool per input, each partition's slice 256-byte aligned) at full
+    # size, in its batched launch (the mixed-batch tiles and occupancy).
+    # Every partition's n and status; 64 sampled partitions (the 8 smallest,
+    # the 8 largest and 48 seeded picks) against the oracle.
+    sizes, kids = datagen.uneven_sizes()
+
+    def up(v):
+        return (v + 63) // 64 * 64
+    nx = sum(up(int(n)) for n, k in zip(sizes, kids) if k != datagen.MC_PI)
+    ny = sum(up(int(n)) for n, k in zip(sizes, kids) if k == datagen.FMUL)
+    x = torch.empty(nx, dtype=torch.float32, device="cuda")
+    y = torch.empty(max(ny, 1), dtype=torch.float32, device="cuda")
+    tasks, ox, oy = [], 0, 0
+    for p, (n, k) in enumerate(zip(map(int, sizes), map(int, kids))):
+        if k == datagen.MC_PI:
+            tasks.append(sc.task(k, n, pid=p))
+            continue
+        xs = x[ox:ox + n]
+        xs.copy_(torch.from_numpy(datagen.x_for(k, n, 0, p)))
+        ox += up(n)
+        ys = None
+        if k == datagen.FMUL:
+            ys = y[oy:oy + n]
+            ys.copy_(torch.from_numpy(datagen.y_for(k, n, 0, p)))
+            oy += up(n)
+        tasks.append(sc.task(k, n, xs, ys, coef=datagen.POLY_COEF if k == 1 else (),
+                             c=datagen.FMUL_C))
+    per, tot = ctx.reduce(tasks, sc.BATCHED)
+    for i, r in enumerate(per):
+        assert r.status == 0 and r.n == int(sizes[i]), (i, r.status, r.n, int(sizes[i]))
+    order = np.argsort(sizes, kind="stable")
+    rng = np.random.default_rng(7)
+    pick = sorted(set(order[:8].tolist()) | set(order[-8:].tolist()) |
+                  set(rng.choice(len(sizes), 48, replace=False).tolist()))
+    for i in pick:
+        p = datagen.make_part(int(kids[i]), int(sizes[i]), i)
+        check_result(per[i], oracle_result(p), p.kid, p.ops, f"pid={i} kid={p.kid} n={p.n}")
+    assert tot.n == int(sizes.sum())
+    assert tot.count == sum(r.count for r in per)
