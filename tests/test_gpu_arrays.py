@@ -188,6 +188,23 @@ def test_rows_match_oracle(ctx, k, length, pad):
         assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), (k, length, pad, comb)
 
 
+def test_rows_full_size_65536_of_4096(ctx):
+    # The 1 GiB RDD as 65536 rows of 4096 floats (the benchmark's second
+    # array shape, three passes of the 8-leaf kernel); both combiners, with
+    # columns checked on samples against the oracle's tree over all 65536 rows
+    k, length = 65_536, 4096
+    host = datagen.fill(k * length, 11, 0, 1, datagen.NORMAL).reshape(k, length)
+    rows = torch.from_numpy(host).cuda()
+    out = torch.full((length,), float("nan"), device="cuda")
+    for comb in (sc.VADD, sc.VMAX):
+        ctx.reduce_rows(rows, out, comb)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        for lo in (0, 2000, length - 64):
+            want = oracle.tree_reduce_arrays(np.ascontiguousarray(host[:, lo:lo + 64]), comb)
+            assert np.array_equal(got[lo:lo + 64].view(np.uint32), want.view(np.uint32)), (comb, lo)
+
+
 def test_rows_errors(ctx):
     buf = torch.zeros(64, device="cuda")
     out = torch.zeros(16, device="cuda")
