@@ -80,3 +80,22 @@ def test_capacity_overflow(ctx):
     # exactly enough room succeeds
     keys, counts, nd, nw = ctx.wordcount(buf, len(ok))
     assert nd == len(ok)
+
+
+def test_full_size_1gib(ctx):
+    # The benchmark's 1 GiB text: a 64 MiB Zipf corpus (vocabulary 10^5,
+    # ending in a newline, so no word spans two copies) repeated 16 times.
+    # Same keys as the oracle on the base, every count and the word total
+    # 16 times the base's.
+    base_n, rep = 64 << 20, 16
+    base = datagen.corpus(base_n - 1, vocab=100_000)
+    base = np.concatenate([base, np.frombuffer(b"\n", dtype=np.uint8)])
+    text = torch.from_numpy(base).cuda().repeat(rep)
+    ok, oc, on = oracle.wordcount(base)
+    keys, counts, nd, nw = ctx.wordcount(text, 1 << 20)  # the benchmark's capacity
+    k = keys[:nd].cpu().numpy().view(np.uint64)
+    c = counts[:nd].cpu().numpy().view(np.uint64)
+    order = np.argsort(k)
+    assert nw == rep * on, (nw, rep * on)
+    assert np.array_equal(k[order], ok)
+    assert np.array_equal(c[order], oc * np.uint64(rep))
