@@ -236,14 +236,34 @@ def test_errors(ctx):
 
 def test_fmul_rdd_full_size(ctx):
     # 64 partitions x 2^22 pairs (x~N(0,1), y~U[0,2)); every partition checked
+    # in each mode, then in the benchmark's two other launch configurations
+    # of the same RDD: every y one element off x's 16-byte alignment
+    # (batched), and the partitions streamed from pinned host memory
     parts = datagen.fmul_rdd()
+    want = [oracle_result(p) for p in parts]
+
+    def check_all(per, tot, where):
+        for p, g, o in zip(parts, per, want):
+            check_result(g, o, p.kid, p.ops, f"pid={p.pid} {where}")
+        check_total(tot, want, datagen.SUM | datagen.MAX)
+
     d = DevParts(parts)
     for mode in MODES:
         per, tot = ctx.reduce(d.tasks, mode)
-        want = [oracle_result(p) for p in parts]
-        for p, g, o in zip(parts, per, want):
-            check_result(g, o, p.kid, p.ops, f"pid={p.pid} mode={mode}")
-        check_total(tot, want, datagen.SUM | datagen.MAX)
+        check_all(per, tot, f"mode={mode}")
+    del d
+    d = DevParts(parts, 0, 1)
+    per, tot = ctx.reduce(d.tasks, sc.BATCHED)
+    check_all(per, tot, "y one element off")
+    del d
+    keep, htasks = [], []
+    for p in parts:
+        hx = torch.from_numpy(p.x).pin_memory()
+        hy = torch.from_numpy(p.y).pin_memory()
+        keep += [hx, hy]
+        htasks.append(sc.task(p.kid, p.n, hx, hy, ops=p.ops, c=p.c, host=True))
+    per, tot = ctx.reduce(htasks, sc.BATCHED)
+    check_all(per, tot, "host input")
 
 
 def test_monte_carlo_full_size(ctx):
