@@ -437,7 +437,7 @@ def bench_selective(ctx, sc, cpu: dict | None) -> dict:
     return out
 
 
-def bench_uneven(ctx, sc, steps=20) -> dict:
+def bench_uneven(ctx, sc, steps=20, ceiling_gbps: float | None = None) -> dict:
     import torch
 
     import datagen
@@ -488,6 +488,13 @@ def bench_uneven(ctx, sc, steps=20) -> dict:
         out["lower_bound"] = {"hbm_ms": t_hbm, "mc_valu_ms": t_valu, "ms": bound,
                               "hbm_frac": t_hbm / out["batched"]["ms"],
                               "bound_frac": bound / out["batched"]["ms"]}
+        if ceiling_gbps:
+            # the same bound with the HBM time at the measured read ceiling
+            t_ceil = bytes_ / (ceiling_gbps * 1e9) * 1e3
+            b2 = max(t_ceil, t_valu)
+            out["lower_bound"].update({"hbm_ms_at_read_ceiling": t_ceil,
+                                       "ms_at_read_ceiling": b2,
+                                       "bound_frac_at_read_ceiling": b2 / out["batched"]["ms"]})
     return out
 
 
@@ -702,7 +709,7 @@ def main() -> int:
         log("extras: monte carlo ...")
         ex["monte_carlo"] = bench_monte_carlo(ctx, sc)
         log("extras: uneven batch ...")
-        ex["uneven_batch"] = bench_uneven(ctx, sc)
+        ex["uneven_batch"] = bench_uneven(ctx, sc, ceiling_gbps=ceiling["GBps"])
         log("extras: array-valued reduce ...")
         ex["array_reduce"] = bench_array_reduce(ctx, sc, res)
         log("extras: host-resident partitions ...")
@@ -711,6 +718,10 @@ def main() -> int:
         ex["map_chain"] = bench_chain(ctx, sc, res)
         log("extras: word count ...")
         ex["wordcount"] = bench_wordcount(ctx, sc)
+        # the HBM-bound extras against the measured read ceiling as well
+        for v in ex["array_reduce"].values():
+            v["frac_of_read_ceiling"] = v["hbm_gbs"] / ceiling["GBps"]
+        ex["map_chain"]["frac_of_read_ceiling"] = ex["map_chain"]["hbm_GBps"] / ceiling["GBps"]
         log("extras: selective execution ...")
         ex["selective_execution"] = bench_selective(ctx, sc, line.get("cpu_baseline"))
         if not args.no_serve:
