@@ -1097,6 +1097,8 @@ int sparkcl_set_tuning(sparkcl_ctx *ctx, const sparkcl_tuning *in)
     std::lock_guard<std::mutex> g(ctx->mu);
     drop_plans(ctx);
     ctx->tuning = *in;
+    if (ctx->server)
+        ctx->server->set_tuning(*in);
     return SPARKCL_OK;
 }
 

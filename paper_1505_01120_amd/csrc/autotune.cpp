@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "runtime.h"
+#include "serve.h"
 
 using namespace sparkcl;
 
@@ -329,6 +330,8 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
     }
 
     ctx->tuning = best;
+    if (ctx->server)
+        ctx->server->set_tuning(best);
     cleanup();
     if (path) {
         std::string err;

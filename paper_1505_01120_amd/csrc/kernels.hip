@@ -1598,11 +1598,18 @@ __global__ __launch_bounds__(kBlock) void k_fill_pattern(float *p, uint64_t n,
 // host memory and then its completion word.  Every wait is bounded: the
 // dispatcher leaves on the host's stop word, or after idle_ticks without new
 // work, setting the stop bit of the published-tile word (and the abort bit
-// when the host asked to abort); a worker leaves at once on abort, when its
-// ticket is unpublished and the stop bit is set, or after four idle periods.  Tickets are issued in order and a worker never leaves holding a
-// published ticket, so every published tile runs before the grid drains.  A
-// ticket left unpublished at exit is discarded by the next launch's prologue,
-// which restarts the tickets at the published count.
+// when the host asked to abort).  A worker leaves only on the abort bit, or
+// when the stop bit is set and its ticket is unpublished: a claimed ticket is
+// never given up while the dispatcher lives, however long the wait for its
+// tile (under a light load the highest claims wait for hundreds of tasks).
+// The stop bit is or-ed into the final published count, so a worker that sees
+// it also sees every tile that will ever be published in this launch.
+// Tickets are issued in order and a worker never leaves holding a published
+// ticket, so every published tile runs before the grid drains.  A ticket left
+// unpublished at exit is discarded by the next launch's prologue, which
+// restarts the tickets at the published count.  A dispatcher that stops
+// polling would leave the workers waiting; the host's watchdog covers that
+// case (it aborts the launch).
 
 static_assert(offsetof(TaskDev, ntiles) == 96, "word 24 of a descriptor");
 static_assert(offsetof(TaskDev, tile_first) == 120, "words 30-31 of a descriptor");
@@ -1708,7 +1715,6 @@ __device__ __forceinline__ void serve_work(const ServeArgs &a)
             const uint64_t c = __hip_atomic_fetch_add(&a.dev->claim, 1ull, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
             uint64_t got = kNone;
-            const uint64_t wait0 = wall_clock64();
             uint32_t backoff = 1;
             for (;;) {
                 const uint64_t w = ld_agent(&a.dev->tiles_pub);
@@ -1718,7 +1724,7 @@ __device__ __forceinline__ void serve_work(const ServeArgs &a)
                     got = c;
                     break;
                 }
-                if ((w & kServeStopBit) || wall_clock64() - wait0 > 4 * a.idle_ticks)
+                if (w & kServeStopBit)
                     break;
                 // s_sleep takes an immediate: a few fixed steps of backoff
                 if (backoff == 1)

@@ -72,8 +72,15 @@ int Server::create(sparkcl_ctx *ctx, std::unique_ptr<Server> *out)
     return SPARKCL_OK;
 }
 
+void Server::set_tuning(const sparkcl_tuning &t)
+{
+    std::lock_guard<std::mutex> g(mu_);
+    tuning_ = t;
+}
+
 int Server::init()
 {
+    tuning_ = ctx_->tuning;
     cap_ = ctx_->config.ring_capacity;
     tile_cap_ = kTileCap;
     per_task_launch_ = (ctx_->config.flags & SPARKCL_FLAG_SERVE_PER_TASK) != 0;
@@ -154,7 +161,8 @@ int Server::submit(const sparkcl_task &task, uint64_t *ticket)
     if (declined(ctx_, task))
         return fail(SPARKCL_EDECLINED, "offload cost " + std::to_string(offload_cost(task)) +
                                            " bytes is below the offload threshold");
-    const uint32_t tile = tile_for(ctx_->tuning, TM_SERVE, task.kernel_id, task.n);
+    std::lock_guard<std::mutex> g(mu_);
+    const uint32_t tile = tile_for(tuning_, TM_SERVE, task.kernel_id, task.n);
     const uint64_t nt64 = std::max<uint64_t>(1, (task.n + tile - 1) / tile);
     if (nt64 > tile_cap_)
         return fail(SPARKCL_ETOOBIG, "task needs more tiles than the tile map holds");
@@ -163,7 +171,6 @@ int Server::submit(const sparkcl_task &task, uint64_t *ticket)
     if (!adm_.fits_at_all(bytes, ntiles))
         return fail(SPARKCL_ETOOBIG, "task needs " + std::to_string(bytes) +
                                          " bytes, budget is " + std::to_string(adm_.budget()));
-    std::lock_guard<std::mutex> g(mu_);
     if (quit_ || poisoned_)
         return fail(SPARKCL_ESTOPPED, poisoned_ ? "serving executor could not be stopped"
                                                 : "serving is shutting down");
@@ -250,6 +257,7 @@ void Server::admit_some(std::vector<Flight> *out)
         f.a = a;
         f.task = w.task;
         f.variant = w.variant;
+        f.tile = w.tile;
         f.part_off = off;
         f.t_admit = host_ns();
         flight_.push_back(f);
@@ -278,7 +286,7 @@ int Server::publish(const std::vector<Flight> &fl)
         d.variant = f.variant;
         std::memcpy(d.coef, t.coef, sizeof(d.coef));
         d.c = t.c;
-        d.tile_elems = tile_for(ctx_->tuning, TM_SERVE, t.kernel_id, t.n);
+        d.tile_elems = f.tile;
         d.ntiles = f.a.p.ntiles;
         d.index = f.a.slot;
         d.partials = static_cast<Partial *>(ctx_->dev(f.part_off));

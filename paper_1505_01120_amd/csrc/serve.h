@@ -26,6 +26,11 @@ class Server {
     void stats(sparkcl_serve_stats *s);
     int drain(uint32_t timeout_ms);
     int shutdown();
+    // The serving tile sizes come from this copy of the tuning table, taken
+    // under the server's own lock: a table change (sparkcl_set_tuning, the
+    // end of sparkcl_autotune) applies to tasks submitted after it, and a
+    // task keeps the tile chosen at submit until it completes.
+    void set_tuning(const sparkcl_tuning &t);
 
   private:
     explicit Server(sparkcl_ctx *ctx);
@@ -50,6 +55,7 @@ class Server {
         Admitted a;
         sparkcl_task task;
         uint32_t variant = 0;
+        uint32_t tile = 0;     // tile size fixed at submit
         uint64_t part_off = 0; // arena block for the partials
         uint64_t t_admit = 0;
     };
@@ -82,7 +88,8 @@ class Server {
     bool exec_launched_ = false;
     uint64_t tiles_pub_host_ = 0; // tiles handed out so far (global index)
 
-    std::mutex mu_; // queue, tables, counters below
+    std::mutex mu_; // queue, tables, counters below, tuning_
+    sparkcl_tuning tuning_{};
     std::condition_variable cv_work_, cv_done_;
     Admission adm_;
     std::unordered_map<uint64_t, Waiting> waiting_;     // ticket -> task (queued)

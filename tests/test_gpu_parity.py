@@ -266,20 +266,32 @@ def test_fmul_rdd_full_size(ctx):
     check_all(per, tot, "host input")
 
 
+def oracle_parallel(fn, items, threads: int = 16):
+    """Runs the single-threaded oracle on independent partitions side by side
+    (each call releases the GIL inside the C oracle)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(fn, items))
+
+
 def test_monte_carlo_full_size(ctx):
-    # 256 partitions x 2^24 samples: 8 partitions against the oracle, all
-    # against pi/4 within 5 sigma, and the RDD count equal to the sum
+    # 256 partitions x 2^24 samples in the batched and graph launches: every
+    # partition's count bit-exact against the oracle (run partition-parallel
+    # on the host), every count within 5 sigma of pi/4, and the RDD total
+    # against the oracle's combine of the partition results
     parts = datagen.monte_carlo()
-    d = DevParts(parts)
-    per, tot = ctx.reduce(d.tasks, sc.BATCHED)
     n = 1 << 24
+    want = oracle_parallel(oracle_result, parts)
+    d = DevParts(parts)
     p4 = math.pi / 4
     sigma = math.sqrt(p4 * (1 - p4) / n)
-    for r in per:
-        assert r.n == n and abs(r.count / n - p4) < 5 * sigma
-    assert tot.count == sum(r.count for r in per) and tot.n == 256 * n
-    for pid in (0, 1, 77, 128, 200, 255):
-        assert per[pid].count == oracle.mc_count(0, pid, n), f"pid {pid}"
+    for mode in (sc.BATCHED, sc.GRAPH):
+        per, tot = ctx.reduce(d.tasks, mode)
+        for p, g, o in zip(parts, per, want):
+            check_result(g, o, p.kid, p.ops, f"pid={p.pid} mode={mode}")
+            assert abs(g.count / n - p4) < 5 * sigma
+        check_total(tot, want, datagen.COUNT)
+        assert tot.n == 256 * n
 
 
 def test_beyond_32_bit_element_counts(ctx):
@@ -341,41 +353,37 @@ def test_uneven_batch_reduced(ctx):
 def test_uneven_batch_full_size(ctx):
     # The benchmark's 4096-partition log-normal batch (mixed kernels; one
     # device pool per input, each partition's slice 256-byte aligned) at full
-    # size, in its batched launch (the mixed-batch tiles and occupancy).
-    # Every partition's n and status; 64 sampled partitions (the 8 smallest,
-    # the 8 largest and 48 seeded picks) against the oracle.
+    # size, in its batched launch (the mixed-batch tiles and occupancy) and
+    # replayed from its graph: every partition and the RDD total against the
+    # oracle (run partition-parallel on the host).
     sizes, kids = datagen.uneven_sizes()
+    parts = [datagen.make_part(int(k), int(n), p) for p, (n, k) in enumerate(zip(sizes, kids))]
 
     def up(v):
         return (v + 63) // 64 * 64
-    nx = sum(up(int(n)) for n, k in zip(sizes, kids) if k != datagen.MC_PI)
-    ny = sum(up(int(n)) for n, k in zip(sizes, kids) if k == datagen.FMUL)
+    nx = sum(up(p.n) for p in parts if p.kid != datagen.MC_PI)
+    ny = sum(up(p.n) for p in parts if p.kid == datagen.FMUL)
     x = torch.empty(nx, dtype=torch.float32, device="cuda")
     y = torch.empty(max(ny, 1), dtype=torch.float32, device="cuda")
     tasks, ox, oy = [], 0, 0
-    for p, (n, k) in enumerate(zip(map(int, sizes), map(int, kids))):
-        if k == datagen.MC_PI:
-            tasks.append(sc.task(k, n, pid=p))
+    for p in parts:
+        if p.kid == datagen.MC_PI:
+            tasks.append(sc.task(p.kid, p.n, pid=p.pid, seed=p.seed))
             continue
-        xs = x[ox:ox + n]
-        xs.copy_(torch.from_numpy(datagen.x_for(k, n, 0, p)))
-        ox += up(n)
+        xs = x[ox:ox + p.n]
+        xs.copy_(torch.from_numpy(p.x))
+        ox += up(p.n)
         ys = None
-        if k == datagen.FMUL:
-            ys = y[oy:oy + n]
-            ys.copy_(torch.from_numpy(datagen.y_for(k, n, 0, p)))
-            oy += up(n)
-        tasks.append(sc.task(k, n, xs, ys, coef=datagen.POLY_COEF if k == 1 else (),
-                             c=datagen.FMUL_C))
-    per, tot = ctx.reduce(tasks, sc.BATCHED)
-    for i, r in enumerate(per):
-        assert r.status == 0 and r.n == int(sizes[i]), (i, r.status, r.n, int(sizes[i]))
-    order = np.argsort(sizes, kind="stable")
-    rng = np.random.default_rng(7)
-    pick = sorted(set(order[:8].tolist()) | set(order[-8:].tolist()) |
-                  set(rng.choice(len(sizes), 48, replace=False).tolist()))
-    for i in pick:
-        p = datagen.make_part(int(kids[i]), int(sizes[i]), i)
-        check_result(per[i], oracle_result(p), p.kid, p.ops, f"pid={i} kid={p.kid} n={p.n}")
-    assert tot.n == int(sizes.sum())
-    assert tot.count == sum(r.count for r in per)
+        if p.kid == datagen.FMUL:
+            ys = y[oy:oy + p.n]
+            ys.copy_(torch.from_numpy(p.y))
+            oy += up(p.n)
+        tasks.append(sc.task(p.kid, p.n, xs, ys, ops=p.ops, coef=p.coef, c=p.c))
+    want = oracle_parallel(oracle_result, parts)
+    ops = datagen.SUM | datagen.MAX | datagen.COUNT
+    for mode in (sc.BATCHED, sc.GRAPH):
+        per, tot = ctx.reduce(tasks, mode)
+        for p, g, o in zip(parts, per, want):
+            check_result(g, o, p.kid, p.ops, f"pid={p.pid} kid={p.kid} n={p.n} mode={mode}")
+        check_total(tot, want, ops)
+        assert tot.n == int(sizes.sum())

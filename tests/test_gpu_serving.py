@@ -219,3 +219,58 @@ def test_native_load_generator_replays_a_trace(ctx):
     bad = sched[::-1].copy()
     assert run(ctx._h, ctypes.addressof(tasks), bad.ctypes.data, count, 0, 1000,
                ctypes.byref(t0), done.ctypes.data, status.ctypes.data) == sc.EINVAL
+
+
+def test_serve_light_load_keeps_claimed_tickets():
+    # Regression: one single-tile task every ~5 ms for ~0.5 s with a 20 ms
+    # idle period.  The dispatcher stays alive (arrivals come faster than its
+    # idle exit), while the workers holding the highest tickets wait for
+    # ~100 tasks, far past any multiple of the idle period.  A worker that
+    # gave up its claimed ticket would strand that tile: its task would never
+    # complete and the 2 s watchdog would fail it with ETIMEDOUT.
+    c = sc.Context(device=0, arena_bytes=256 << 20, idle_exit_ms=20, watchdog_ms=2000)
+    try:
+        parts = [datagen.make_part(datagen.POLY if i % 2 else datagen.FMUL, 1000 + i, i)
+                 for i in range(100)]
+        d = DevParts(parts)
+        tickets = []
+        for t in d.tasks:
+            tickets.append(c.submit(t))
+            time.sleep(0.005)
+        res = wait_all(c, tickets, timeout=30)
+        for p, r in zip(parts, res):
+            check_result(r, oracle_result(p), p.kid, p.ops, f"kid={p.kid} n={p.n}")
+        assert c.serve_stats()["failed"] == 0
+    finally:
+        c.destroy()
+
+
+def test_serve_tuning_change_while_tasks_wait():
+    # A task keeps the tile size chosen when it was submitted: tasks still
+    # waiting for a ring slot when the serving tile table changes must cover
+    # exactly their n elements (samples) and match the oracle; tasks submitted
+    # after the change use the new table and match the oracle too.  Per-task
+    # launches over a two-slot ring keep most of the tasks waiting.
+    c = sc.Context(device=0, arena_bytes=256 << 20, ring_capacity=2,
+                   flags=sc.FLAG_SERVE_PER_TASK)
+    try:
+        parts = [datagen.make_part(datagen.MC_PI, (1 << 26) + 3 * i, i, with_data=False)
+                 for i in range(24)]
+        parts += [datagen.make_part(datagen.FMUL, (1 << 20) + 5 * i, 100 + i)
+                  for i in range(8)]
+        d = DevParts(parts)
+        first = [c.submit(t) for t in d.tasks]
+        before = c.serve_stats()
+        t = c.get_tuning()
+        for k in range(3):
+            for b in range(len(t.tile[2][k])):
+                t.tile[2][k][b] = 1 << 12
+        c.set_tuning(t)
+        later = [c.submit(t) for t in d.tasks]
+        res = wait_all(c, first + later, timeout=60)
+        for i, r in enumerate(res):
+            p = parts[i % len(parts)]
+            check_result(r, oracle_result(p), p.kid, p.ops, f"#{i} kid={p.kid} n={p.n}")
+        assert before["pending"] + before["in_flight"] > 0
+    finally:
+        c.destroy()

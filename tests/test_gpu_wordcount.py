@@ -99,3 +99,53 @@ def test_full_size_1gib(ctx):
     assert nw == rep * on, (nw, rep * on)
     assert np.array_equal(k[order], ok)
     assert np.array_equal(c[order], oc * np.uint64(rep))
+
+
+# An 8-byte word whose FNV-1a 64 key is 0, the GPU table's empty-slot value
+# (the oracle's pins derive the key from the definition).  The GPU counts it
+# in a counter of its own and emits it at compaction; these texts put it at
+# span (16-byte), chunk (4096) and look-ahead (256) edges, at the text's end,
+# repeated, among a skewed vocabulary and at unaligned text addresses.
+ZERO_KEY_WORD = bytes.fromhex("d56bb95342870836")
+
+
+def filler(n: int, seed: int) -> bytearray:
+    rng = np.random.default_rng(seed)
+    t = rng.choice(np.frombuffer(b"abcdefgh  \n", dtype=np.uint8), n)
+    return bytearray(t.tobytes())
+
+
+def put_zero_word(t: bytearray, pos: int) -> None:
+    if pos > 0:
+        t[pos - 1] = 0x20
+    t[pos:pos + 8] = ZERO_KEY_WORD
+    if pos + 8 < len(t):
+        t[pos + 8] = 0x0A
+
+
+@pytest.mark.parametrize("pos", [0, 5, 8, 12, 15, 16, 4088, 4090, 4095, 4096, 4096 + 248,
+                                 4096 + 250, 8191, 8192 + 4096 - 3])
+def test_zero_key_word_positions(ctx, pos):
+    t = filler(pos + 300, pos)
+    put_zero_word(t, pos)
+    check(ctx, bytes(t))
+
+
+@pytest.mark.parametrize("offset", [0, 1, 7])
+def test_zero_key_word_at_text_end_and_alone(ctx, offset):
+    check(ctx, ZERO_KEY_WORD, offset)
+    t = filler(5000, 1)
+    t[-9] = 0x20
+    t[-8:] = ZERO_KEY_WORD
+    check(ctx, bytes(t), offset)
+
+
+def test_zero_key_word_repeated_in_corpus(ctx):
+    # many copies, each block of the grid sees some; the key-0 count is the
+    # sum over blocks
+    base = bytearray(datagen.corpus(4 << 20, vocab=20_000, seed=5).tobytes())
+    rng = np.random.default_rng(9)
+    for pos in sorted(rng.choice(len(base) - 16, 3000, replace=False)):
+        put_zero_word(base, int(pos) + 1)
+    check(ctx, bytes(base))
+    check(ctx, (ZERO_KEY_WORD + b" ") * 10_000)

@@ -45,3 +45,23 @@ def test_random_bytes(oracle):
 def test_synthetic_corpus(oracle, datagen):
     text = datagen.corpus(1 << 20, vocab=20_000)
     check(oracle, text.tobytes())
+
+
+# An 8-byte word, with no whitespace byte, whose 64-bit FNV-1a key is 0 (the
+# value the GPU's counting table uses for an empty slot, so the GPU counts it
+# apart).  Its key is derived here from the FNV-1a definition by hand: 64-bit
+# offset basis, then for each byte xor it in and multiply by the prime mod 2^64.
+ZERO_KEY_WORD = bytes.fromhex("d56bb95342870836")
+
+
+def test_zero_key_word(oracle):
+    h = 0xCBF29CE484222325
+    for b in ZERO_KEY_WORD:
+        h = ((h ^ b) * 0x100000001B3) % (1 << 64)
+    assert h == 0
+    assert not any(b in b" \t\n\x0b\x0c\r" for b in ZERO_KEY_WORD)
+    assert oracle.fnv1a64(ZERO_KEY_WORD) == 0
+    text = b"ab " + ZERO_KEY_WORD + b"\n" + ZERO_KEY_WORD + b" cd ab " + ZERO_KEY_WORD
+    check(oracle, text)
+    keys, counts, nw = oracle.wordcount(text)
+    assert keys[0] == 0 and counts[0] == 3 and nw == 6
