@@ -386,6 +386,40 @@ SPARKCL_API int sparkcl_wordcount(sparkcl_ctx *ctx, const uint8_t *text, uint64_
 SPARKCL_API int sparkcl_offload_breakeven(sparkcl_ctx *ctx, double host_bytes_per_s,
                                           uint64_t *bytes);
 
+/* ---- allocation-free ReduceCL ------------------------------------------ */
+/* For callers that cannot allocate device memory when they call (tight
+   serving loops, harnesses that forbid allocation): the batched ReduceCL of
+   sparkcl_reduce_async(..., SPARKCL_BATCHED, ...) -- cut into the same tiles
+   under ctx's tuning table and occupancy, so its results are bit-identical
+   to that call's -- with every workspace it needs (task table, tile queue,
+   partials, arrival tickets, queue counters, internal results) in one fixed
+   array of SPARKCL_NOALLOC_SCRATCH_BYTES of device memory that the library
+   holds on each GPU it runs on until the process ends, instead of blocks of
+   the context's arena.  The call allocates nothing (no hipMalloc, no arena
+   block, no heap memory when it succeeds); ctx supplies the device, the
+   tuning table, the occupancy and the offload threshold only.
+   tasks (host memory) and the inputs they name are as for sparkcl_reduce;
+   results go to dev_per_task[ntasks] and *dev_total (device memory,
+   caller-owned, either may be NULL; with dev_per_task set and dev_total NULL
+   the RDD total is not computed) in the order of `stream`.
+   Limits: at most SPARKCL_NOALLOC_MAX_TASKS tasks and, after decomposition,
+   SPARKCL_NOALLOC_MAX_TILES tiles (ETOOBIG beyond); device-resident inputs
+   only (EINVAL for host-input tasks); not on a stream under capture (EINVAL);
+   devices 0..63.
+   Every call on one GPU shares that GPU's array, which keeps the last call's
+   contents; each call clears what must start at zero.  Calls that overlapped
+   on one GPU would race on it, so calls are serialised: a process-wide lock,
+   and before the array is rewritten a host wait until the previous
+   allocation-free call's kernels (on any stream) have finished.  A call
+   therefore blocks while the previous one still runs; it does not wait for
+   its own kernels. */
+#define SPARKCL_NOALLOC_MAX_TASKS 8192u
+#define SPARKCL_NOALLOC_MAX_TILES 262144u
+#define SPARKCL_NOALLOC_SCRATCH_BYTES 12190208u /* 11.6 MiB per GPU */
+SPARKCL_API int sparkcl_reduce_noalloc(sparkcl_ctx *ctx, const sparkcl_task *tasks,
+                                       uint32_t ntasks, sparkcl_result *dev_per_task,
+                                       sparkcl_result *dev_total, void *stream);
+
 /* Library version string. */
 SPARKCL_API const char *sparkcl_version(void);
 

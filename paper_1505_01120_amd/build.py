@@ -44,7 +44,7 @@ KERNELS = ("k_task", "k_batch", "k_serve", "k_map", "k_chain", "k_tree", "k_tree
            "k_wc_compact")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["kernels.hip", "api.cpp", "arrays.cpp", "chain.cpp", "wordcount.cpp", "serve.cpp",
+HIP_SOURCES = ["kernels.hip", "noalloc.hip", "api.cpp", "arrays.cpp", "chain.cpp", "wordcount.cpp", "serve.cpp",
                "autotune.cpp", "tuning.cpp"]
 HOST_SOURCES = ["tuning.cpp", "hostlogic_capi.cpp"]
 

@@ -205,6 +205,140 @@ uint32_t sparkcl::exec_grid(const sparkcl_ctx *ctx, uint32_t kid_mask, uint64_t 
     return std::max(1u, std::min(per_cu, occ)) * (uint32_t)ctx->cus;
 }
 
+sparkcl::Cut sparkcl::plan_cut(const sparkcl_ctx *ctx, int mode, const sparkcl_task *tasks,
+                                uint32_t ntasks, bool host_in, uint32_t per_cu)
+{
+    // Tile table: the batched one, unless the batch would then give the
+    // executor's blocks fewer than two tiles each (a batch of one or a few
+    // partitions, where the batched table's large tiles would leave most of
+    // the GPU idle, or about one large tile per block, where the time is set
+    // by how unevenly the blocks land on the CUs); such a batch is cut with
+    // the per-launch table instead.  The choice is a function of the call,
+    // so a repeated call is cut the same way.
+    Cut c;
+    c.tm = mode != SPARKCL_PER_LAUNCH && !host_in ? TM_BATCHED : TM_PER_LAUNCH;
+    // A batch of many tasks of widely spread sizes takes the tuned mixed-batch
+    // tile sizes instead of the per-bucket table (tuned on batches of one
+    // size).  On the 4096-task uneven batch, one 2^16 tile size for the
+    // streaming kernels ran it in 515 us against 553 us with the table: small
+    // tasks then run whole and large ones in mid-sized interleaved tiles.
+    if (c.tm == TM_BATCHED && ntasks >= kMixedMinTasks) {
+        uint32_t lo = SPARKCL_TUNE_BUCKETS, hi = 0;
+        for (uint32_t i = 0; i < ntasks; ++i) {
+            const uint32_t b = size_bucket(tasks[i].n);
+            lo = std::min(lo, b);
+            hi = std::max(hi, b);
+        }
+        c.mixed = hi >= lo + kMixedMinSpan;
+    }
+    if (c.tm == TM_BATCHED) {
+        uint64_t tiles = 0;
+        uint32_t mask = 0;
+        for (uint32_t i = 0; i < ntasks; ++i) {
+            if (tasks[i].kernel_id < SPARKCL_POLY || tasks[i].kernel_id > SPARKCL_MC_PI)
+                continue; // rejected by check_task
+            const uint32_t T = cut_tile(ctx, c, tasks[i]);
+            tiles += std::max<uint64_t>(1, (tasks[i].n + T - 1) / T);
+            mask |= 1u << (tasks[i].kernel_id - 1);
+        }
+        const uint64_t grid =
+            per_cu ? per_cu * (uint32_t)ctx->cus : exec_grid(ctx, mask, tiles, ntasks);
+        if (tiles < 2 * grid)
+            c.tm = TM_PER_LAUNCH;
+    }
+    return c;
+}
+
+uint32_t sparkcl::cut_tile(const sparkcl_ctx *ctx, const Cut &c, const sparkcl_task &t)
+{
+    if (c.tm == TM_BATCHED && c.mixed && t.kernel_id >= SPARKCL_POLY &&
+        t.kernel_id <= SPARKCL_MC_PI && ctx->tuning.tile_many[t.kernel_id - 1])
+        return ctx->tuning.tile_many[t.kernel_id - 1];
+    return tile_for(ctx->tuning, c.tm, t.kernel_id, t.n);
+}
+
+void sparkcl::fill_taskdev(const sparkcl_task &t, uint32_t variant, uint32_t tile,
+                           uint32_t ntiles, uint32_t index, Partial *partials, TaskDev *d)
+{
+    std::memset(d, 0, sizeof(*d));
+    d->kid = t.kernel_id;
+    d->ops = t.reduce_ops;
+    d->n = t.n;
+    d->in0 = t.in0;
+    d->in1 = t.in1;
+    d->out = t.out;
+    d->seed = t.seed;
+    d->pid = t.partition_id;
+    d->variant = variant;
+    std::memcpy(d->coef, t.coef, sizeof(d->coef));
+    d->c = t.c;
+    d->tile_elems = tile;
+    d->ntiles = ntiles;
+    d->index = index;
+    d->partials = partials;
+}
+
+void sparkcl::queue_tiles(const sparkcl_task *tasks, uint32_t ntasks, const TaskDev *dev,
+                          uint32_t *order, uint32_t *mem, uint32_t *alu, TileRef *tiles)
+{
+    // Tile queue, longest tiles first (a longest-processing-time list
+    // schedule: the batch then ends on short tiles instead of leaving a few
+    // blocks streaming large tiles while the rest idle).  A tile's cost is
+    // its element count times the kernel's cost per element (bytes streamed;
+    // a Monte-Carlo sample counts like ~5 bytes of HBM time).  Ties keep task
+    // order and each task's tiles together and in order, so the tiles of a
+    // task still run side by side.  The order only changes when tiles run:
+    // every partial and every combine order is fixed by the decomposition,
+    // so results are unaffected.
+    auto per_elem = [&](uint32_t i) -> uint64_t {
+        const uint32_t kid = tasks[i].kernel_id;
+        return kid == SPARKCL_POLY ? 4 : kid == SPARKCL_FMUL ? 8 : 5;
+    };
+    auto cost = [&](uint32_t i) -> uint64_t {
+        return dev[i].variant == V_DECLINED
+                   ? 0
+                   : std::min<uint64_t>(dev[i].tile_elems, tasks[i].n) * per_elem(i);
+    };
+    for (uint32_t i = 0; i < ntasks; ++i)
+        order[i] = i;
+    // (an index tie-break makes the unstable in-place sort stable)
+    std::sort(order, order + ntasks, [&](uint32_t a, uint32_t b) {
+        const uint64_t ca = cost(a), cb = cost(b);
+        return ca > cb || (ca == cb && a < b);
+    });
+    // Memory-bound (POLY, FMUL) and VALU-bound (MC_PI) tasks use different
+    // units, so the two longest-first lists are merged to advance through the
+    // same fraction of their work: at every point of the queue, tiles of both
+    // kinds run side by side and overlap.  (Sorted by cost alone, the large
+    // streaming tiles all came first and the Monte-Carlo tiles bunched later;
+    // on the 4096-task uneven batch the mix took 651 us against 498 us for
+    // its streaming part alone.)
+    auto work = [&](uint32_t i) { return (double)tasks[i].n * (double)per_elem(i); };
+    uint32_t nm = 0, na = 0;
+    double tot_mem = 0, tot_alu = 0;
+    for (uint32_t k = 0; k < ntasks; ++k) {
+        const uint32_t i = order[k];
+        if (tasks[i].kernel_id == SPARKCL_MC_PI) {
+            alu[na++] = i;
+            tot_alu += work(i);
+        } else {
+            mem[nm++] = i;
+            tot_mem += work(i);
+        }
+    }
+    uint64_t at = 0;
+    uint32_t im = 0, ia = 0;
+    double done_mem = 0, done_alu = 0;
+    while (im < nm || ia < na) {
+        const bool take_mem =
+            ia == na || (im < nm && done_mem * tot_alu <= done_alu * tot_mem);
+        const uint32_t i = take_mem ? mem[im++] : alu[ia++];
+        (take_mem ? done_mem : done_alu) += work(i);
+        for (uint32_t j = 0; j < dev[i].ntiles; ++j)
+            tiles[at++] = TileRef{i, j};
+    }
+}
+
 int sparkcl::build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
                         uint32_t ntasks, sparkcl_result *ures, sparkcl_result *utot,
                         hipStream_t stream, Plan **out, uint32_t per_cu)
@@ -227,54 +361,11 @@ int sparkcl::build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task
             return fail(SPARKCL_EINVAL, kind == 0 ? "a call's tasks must be all host-input or all device-input"
                                                   : "maps take device arrays");
     p->host = host_in;
-
-    // Tile table: the batched one, unless the batch would then give the
-    // executor's blocks fewer than two tiles each (a batch of one or a few
-    // partitions, where the batched table's large tiles would leave most of
-    // the GPU idle, or about one large tile per block, where the time is set
-    // by how unevenly the blocks land on the CUs); such a batch is cut with
-    // the per-launch table instead.  The choice is a function of the call,
-    // so a repeated call is cut the same way.
     if (host_in && mode == SPARKCL_GRAPH)
         return fail(SPARKCL_EINVAL, "host-input tasks run in PER_LAUNCH or BATCHED mode");
-    int tm = mode != SPARKCL_PER_LAUNCH && !host_in ? TM_BATCHED : TM_PER_LAUNCH;
-    // A batch of many tasks of widely spread sizes takes the tuned mixed-batch
-    // tile sizes instead of the per-bucket table (tuned on batches of one
-    // size).  On the 4096-task uneven batch, one 2^16 tile size for the
-    // streaming kernels ran it in 515 us against 553 us with the table: small
-    // tasks then run whole and large ones in mid-sized interleaved tiles.
-    bool mixed = false;
-    if (tm == TM_BATCHED && ntasks >= kMixedMinTasks) {
-        uint32_t lo = SPARKCL_TUNE_BUCKETS, hi = 0;
-        for (uint32_t i = 0; i < ntasks; ++i) {
-            const uint32_t b = size_bucket(tasks[i].n);
-            lo = std::min(lo, b);
-            hi = std::max(hi, b);
-        }
-        mixed = hi >= lo + kMixedMinSpan;
-    }
-    auto tile_of = [&](int mode_table, const sparkcl_task &t) -> uint32_t {
-        if (mode_table == TM_BATCHED && mixed && t.kernel_id >= SPARKCL_POLY &&
-            t.kernel_id <= SPARKCL_MC_PI && ctx->tuning.tile_many[t.kernel_id - 1])
-            return ctx->tuning.tile_many[t.kernel_id - 1];
-        return tile_for(ctx->tuning, mode_table, t.kernel_id, t.n);
-    };
-    if (tm == TM_BATCHED) {
-        uint64_t tiles = 0;
-        uint32_t mask = 0;
-        for (uint32_t i = 0; i < ntasks; ++i) {
-            if (tasks[i].kernel_id < SPARKCL_POLY || tasks[i].kernel_id > SPARKCL_MC_PI)
-                continue; // rejected below
-            const uint32_t T = tile_of(TM_BATCHED, tasks[i]);
-            tiles += std::max<uint64_t>(1, (tasks[i].n + T - 1) / T);
-            mask |= 1u << (tasks[i].kernel_id - 1);
-        }
-        const uint64_t grid =
-            per_cu ? per_cu * (uint32_t)ctx->cus : exec_grid(ctx, mask, tiles, ntasks);
-        if (tiles < 2 * grid)
-            tm = TM_PER_LAUNCH;
-    }
+    const Cut cut = plan_cut(ctx, mode, tasks, ntasks, host_in, per_cu);
     std::vector<uint64_t> first(ntasks);
+    std::vector<uint32_t> tile(ntasks);
     uint64_t total_tiles = 0;
     uint32_t kid_mask = 0;
     for (uint32_t i = 0; i < ntasks; ++i) {
@@ -288,7 +379,8 @@ int sparkcl::build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task
         if (skip)
             v = V_DECLINED;
         p->variants[i] = v;
-        const uint32_t T = tile_of(tm, tasks[i]);
+        const uint32_t T = cut_tile(ctx, cut, tasks[i]);
+        tile[i] = T;
         const uint64_t nt = skip ? 1 : std::max<uint64_t>(1, (tasks[i].n + T - 1) / T);
         if (nt > 0xFFFFFFFFull)
             return fail(SPARKCL_ETOOBIG, "too many tiles in task " + std::to_string(i));
@@ -344,22 +436,8 @@ int sparkcl::build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task
     for (uint32_t i = 0; i < ntasks; ++i) {
         const sparkcl_task &t = tasks[i];
         TaskDev &d = host[i];
-        std::memset(&d, 0, sizeof(d));
-        d.kid = t.kernel_id;
-        d.ops = t.reduce_ops;
-        d.n = t.n;
-        d.in0 = t.in0;
-        d.in1 = t.in1;
-        d.out = t.out;
-        d.seed = t.seed;
-        d.pid = t.partition_id;
-        d.variant = p->variants[i];
-        std::memcpy(d.coef, t.coef, sizeof(d.coef));
-        d.c = t.c;
-        d.tile_elems = tile_of(tm, t);
-        d.ntiles = p->ntiles[i];
-        d.index = i;
-        d.partials = p->dparts ? p->dparts + first[i] : nullptr;
+        fill_taskdev(t, p->variants[i], tile[i], p->ntiles[i], i,
+                     p->dparts ? p->dparts + first[i] : nullptr, &d);
         if (host_in) {
             char *base = p->staging + (uint64_t)(i % p->nslots) * p->slot_bytes;
             d.in0 = reinterpret_cast<const float *>(base + ((uintptr_t)t.in0 & 15u));
@@ -373,61 +451,10 @@ int sparkcl::build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task
                                   hipMemcpyHostToDevice, stream);
     std::vector<TileRef> tiles;
     if (e == hipSuccess && p->dtiles) {
-        // Tile queue, longest tiles first (a longest-processing-time list
-        // schedule: the batch then ends on short tiles instead of leaving a
-        // few blocks streaming large tiles while the rest idle).  A tile's
-        // cost is its element count times the kernel's cost per element
-        // (bytes streamed; a Monte-Carlo sample counts like ~5 bytes of HBM
-        // time).  Ties keep task order and each task's tiles together and in
-        // order, so the tiles of a task still run side by side.  The order
-        // only changes when tiles run: every partial and every combine order
-        // is fixed by the decomposition, so results are unaffected.
-        std::vector<uint32_t> order(ntasks);
-        std::vector<uint64_t> cost(ntasks);
-        for (uint32_t i = 0; i < ntasks; ++i) {
-            order[i] = i;
-            const uint32_t kid = tasks[i].kernel_id;
-            const uint64_t w = kid == SPARKCL_POLY ? 4 : kid == SPARKCL_FMUL ? 8 : 5;
-            cost[i] = p->variants[i] == V_DECLINED
-                          ? 0
-                          : std::min<uint64_t>(host[i].tile_elems, tasks[i].n) * w;
-        }
-        std::stable_sort(order.begin(), order.end(),
-                         [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
-        // Memory-bound (POLY, FMUL) and VALU-bound (MC_PI) tasks use
-        // different units, so the two longest-first lists are merged to
-        // advance through the same fraction of their work: at every point of
-        // the queue, tiles of both kinds run side by side and overlap.
-        // (Sorted by cost alone, the large streaming tiles all came first and
-        // the Monte-Carlo tiles bunched later; on the 4096-task uneven batch
-        // the mix took 651 us against 498 us for its streaming part alone.)
-        auto work = [&](uint32_t i) {
-            const uint32_t kid = tasks[i].kernel_id;
-            return (double)tasks[i].n * (kid == SPARKCL_POLY ? 4 : kid == SPARKCL_FMUL ? 8 : 5);
-        };
-        std::vector<uint32_t> mem, alu;
-        double tot_mem = 0, tot_alu = 0;
-        for (uint32_t i : order) {
-            if (tasks[i].kernel_id == SPARKCL_MC_PI) {
-                alu.push_back(i);
-                tot_alu += work(i);
-            } else {
-                mem.push_back(i);
-                tot_mem += work(i);
-            }
-        }
-        tiles.reserve(total_tiles);
-        size_t im = 0, ia = 0;
-        double done_mem = 0, done_alu = 0;
-        while (im < mem.size() || ia < alu.size()) {
-            const bool take_mem =
-                ia == alu.size() ||
-                (im < mem.size() && done_mem * tot_alu <= done_alu * tot_mem);
-            const uint32_t i = take_mem ? mem[im++] : alu[ia++];
-            (take_mem ? done_mem : done_alu) += work(i);
-            for (uint32_t j = 0; j < p->ntiles[i]; ++j)
-                tiles.push_back(TileRef{i, j});
-        }
+        tiles.resize(total_tiles);
+        std::vector<uint32_t> order(ntasks), mem(ntasks), alu(ntasks);
+        queue_tiles(tasks, ntasks, host.data(), order.data(), mem.data(), alu.data(),
+                    tiles.data());
         e = hipMemcpyAsync(p->dtiles, tiles.data(), sizeof(TileRef) * total_tiles,
                            hipMemcpyHostToDevice, stream);
     }
@@ -839,6 +866,8 @@ int sparkcl_init(const sparkcl_config *config, sparkcl_ctx **out)
     SPARKCL_HIP(hipStreamCreateWithFlags(&ctx->copy_stream2, hipStreamNonBlocking));
     SPARKCL_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
     if ((rc = ensure_pinned(ctx.get(), 1024)) != SPARKCL_OK)
+        return rc;
+    if ((rc = noalloc_setup(ctx->device)) != SPARKCL_OK)
         return rc;
     rc = Server::create(ctx.get(), &ctx->server);
     if (rc != SPARKCL_OK)

@@ -113,6 +113,25 @@ void free_plan(sparkcl_ctx *ctx, Plan *p);
 bool evict_one(sparkcl_ctx *ctx);
 // Arena block for plan p, evicting older plans while the arena is full.
 int arena_alloc(sparkcl_ctx *ctx, Plan *p, uint64_t bytes, void **out);
+// How a reduce-kind call is cut into tiles: the tuning table's row (batched
+// or per-launch) and whether the mixed-batch tile sizes apply.  A function of
+// the call, the tuning table and the executor occupancy; allocates nothing.
+struct Cut {
+    int tm = TM_PER_LAUNCH;
+    bool mixed = false;
+};
+Cut plan_cut(const sparkcl_ctx *ctx, int mode, const sparkcl_task *tasks, uint32_t ntasks,
+             bool host_in, uint32_t per_cu = 0);
+// The tile size of one task under a cut.
+uint32_t cut_tile(const sparkcl_ctx *ctx, const Cut &c, const sparkcl_task &t);
+// The device descriptor of one task.
+void fill_taskdev(const sparkcl_task &t, uint32_t variant, uint32_t tile, uint32_t ntiles,
+                  uint32_t index, Partial *partials, TaskDev *d);
+// The batched tile queue (longest first, streaming and Monte-Carlo tiles
+// interleaved) into tiles[sum of dev[i].ntiles]; order, mem and alu are
+// caller-provided arrays of ntasks entries.  Allocates nothing.
+void queue_tiles(const sparkcl_task *tasks, uint32_t ntasks, const TaskDev *dev,
+                 uint32_t *order, uint32_t *mem, uint32_t *alu, TileRef *tiles);
 // A reduce-kind plan (kind 0) for the call; per_cu: executor blocks per CU
 // (0: the tuned choice).
 int build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
@@ -135,6 +154,9 @@ int get_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task *tasks,
 bool capturing(hipStream_t stream);
 int enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream, bool timed);
 void drop_plans(sparkcl_ctx *ctx);
+// Allocation-free workspace (noalloc.hip): looks up this device's address of
+// the fixed device array once per device; `device` must be current.
+int noalloc_setup(int device);
 // Persistent-executor grid for a batch holding the kernels in kid_mask
 // (bit k-1 for kernel id k) and `ntiles` tiles over `ntasks` tasks.
 uint32_t exec_grid(const sparkcl_ctx *ctx, uint32_t kid_mask, uint64_t ntiles = 0,

@@ -104,7 +104,7 @@ EXPORTS = ("sparkcl_init", "sparkcl_destroy", "sparkcl_map", "sparkcl_map_partit
            "sparkcl_serve_stats_get", "sparkcl_serve_drain", "sparkcl_get_tuning",
            "sparkcl_set_tuning", "sparkcl_autotune", "sparkcl_strerror",
            "sparkcl_last_error", "sparkcl_last_kernel_ms", "sparkcl_version",
-           "sparkcl_offload_breakeven", "sparkcl_wordcount")
+           "sparkcl_offload_breakeven", "sparkcl_wordcount", "sparkcl_reduce_noalloc")
 
 
 class SparkclError(RuntimeError):
@@ -137,6 +137,7 @@ def load() -> ctypes.CDLL:
             "sparkcl_map_partition": ([P, TP, U32, I32, RP, P], I32),
             "sparkcl_reduce": ([P, TP, U32, I32, RP, RP, P], I32),
             "sparkcl_reduce_async": ([P, TP, U32, I32, P, P, P], I32),
+            "sparkcl_reduce_noalloc": ([P, TP, U32, P, P, P], I32),
             "sparkcl_reduce_arrays": ([P, U32, ctypes.POINTER(P), U32, U64, P, P], I32),
             "sparkcl_reduce_rows": ([P, U32, P, U64, U32, U64, P, P], I32),
             "sparkcl_reduce_chain": ([P, TP, U32, ctypes.POINTER(Stage), U32, RP, RP, P], I32),
@@ -292,6 +293,14 @@ class Context:
         _check(load().sparkcl_reduce_async(self._h, arr, n, mode, _ptr(dev_results),
                                            _ptr(dev_total), _stream(stream, self.device)),
                "sparkcl_reduce_async")
+
+    def reduce_noalloc(self, tasks, dev_results=None, dev_total=None, stream=None) -> None:
+        """The batched reduce_async with its workspaces in the library's fixed
+        device array instead of the arena (results: 64 B per result)."""
+        arr, n = _array(tasks)
+        _check(load().sparkcl_reduce_noalloc(self._h, arr, n, _ptr(dev_results),
+                                             _ptr(dev_total), _stream(stream, self.device)),
+               "sparkcl_reduce_noalloc")
 
     def reduce_chain(self, tasks: Iterable[Task], stages: Sequence[Stage],
                      stream=None) -> tuple[list[Result], Result]:
