@@ -185,7 +185,12 @@ typedef struct sparkcl_result {
 
 /* Create a context on config->device.  Validates the config, loads tuning,
    allocates the host-coherent serving ring (pinned host memory) and carves
-   its workspaces out of config->arena.  *out is NULL on error. */
+   its workspaces out of config->arena.  *out is NULL on error.  The paper
+   leaves memory allocation to the framework rather than to the user's
+   algorithm (sec. 3, design issue 3): every workspace of every later call is
+   sub-allocated from the arena handed over here, so no call allocates device
+   memory.  The kernels themselves are compiled into the library and loaded
+   once per context, the paper's kernel caching per worker (sec. 3.1.1.2). */
 SPARKCL_API int sparkcl_init(const sparkcl_config *config, sparkcl_ctx **out);
 
 /* Stop serving (waits up to 10 s for the resident executor to drain), release
@@ -284,13 +289,22 @@ SPARKCL_API int sparkcl_reduce_rows(sparkcl_ctx *ctx, uint32_t combiner,
    Non-blocking.  The task is admitted to the resident executor once a slot is
    free and its bytes fit the budget; tasks admitted while others run share
    the GPU with them.  *ticket identifies it for sparkcl_poll.  ETOOBIG if the
-   task alone exceeds the budget; EAGAIN if the pending queue is full. */
+   task alone exceeds the budget; EAGAIN if the pending queue is full.
+   The paper's workers take one accelerated task at a time so that tasks do
+   not contend for the device (sec. 3.1.5, Fig 4, `--cores 1`), and note that
+   the framework has its own provisions against contention; here that
+   provision is admission control: a task is admitted only against a free
+   slot and the memory budget (sec. 3, design issue 3), and admitted tasks
+   share the GPU's compute units through one resident executor. */
 SPARKCL_API int sparkcl_submit(sparkcl_ctx *ctx, const sparkcl_task *task,
                    uint64_t *ticket);
 
 /* Serving: SPARKCL_OK and *result when the task is done (the ticket is then
    retired), SPARKCL_EAGAIN while pending, ENOTFOUND for an unknown ticket.
-   A failed task returns OK with result->status holding its error. */
+   A failed task returns OK with result->status holding its error.  This is
+   the serving form of mapReturnValue (Fig 2, sec. 3.1.1.3): the partition's
+   value, or EDECLINED when the task was not offloaded and the caller's
+   alternative must compute it. */
 SPARKCL_API int sparkcl_poll(sparkcl_ctx *ctx, uint64_t ticket, sparkcl_result *result);
 
 typedef struct sparkcl_serve_stats {
