@@ -94,6 +94,17 @@ class Resident:
             self.y[p * n:(p + 1) * n].copy_(hy)
         torch.cuda.synchronize()
 
+    def pinned(self):
+        """Pinned host copies of x and y (made once): the host-resident form
+        of the same RDD."""
+        import torch
+        if getattr(self, "hx", None) is None:
+            self.hx = torch.empty(self.parts * self.n, dtype=torch.float32).pin_memory()
+            self.hy = torch.empty(self.parts * self.n, dtype=torch.float32).pin_memory()
+            self.hx.copy_(self.x)
+            self.hy.copy_(self.y)
+        return self.hx, self.hy
+
     def tasks(self, sc, kid=None):
         import datagen
         out = []
@@ -106,8 +117,12 @@ class Resident:
 
 
 def time_async(ctx, sc, tasks, mode, steps, warmup, dres, dtot):
-    """(wall ms per step, event ms per step) of back-to-back async reduces."""
+    """(wall ms per step, event ms per step) of back-to-back async reduces.
+    The batch is converted to a task array once, as a caller replaying it
+    would keep it."""
     import torch
+    if not isinstance(tasks, sc.TaskArray):
+        tasks = sc.task_array(tasks)
     s = torch.cuda.current_stream()
     for _ in range(warmup):
         ctx.reduce_async(tasks, mode, dres, dtot, stream=s)
@@ -189,8 +204,7 @@ def read_ceiling(sc, res: Resident, reps: int = 20) -> dict:
     the RDD's x and y (nontemporal float4 loads, grid-stride), timed with HIP
     events at 1, 2 and 4 blocks per CU; the best rate is the ceiling."""
     import torch
-    lib = ctypes.CDLL(os.path.join(os.path.dirname(os.path.abspath(sc.__file__)),
-                                   "libsparkcl_probe.so"))
+    lib = probe_lib(sc)
     fn = lib.sparkcl_probe_read2
     fn.restype = ctypes.c_int
     fn.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
@@ -248,6 +262,75 @@ def bench_single_partition(ctx, sc, reps=50) -> dict:
     return out
 
 
+def probe_lib(sc):
+    return ctypes.CDLL(os.path.join(os.path.dirname(os.path.abspath(sc.__file__)),
+                                    "libsparkcl_probe.so"))
+
+
+def valu_ceiling(sc, pairs: int, reps: int = 3) -> dict:
+    """The measured VALU ceiling of the Monte-Carlo loop: the probe kernel
+    that runs the same Philox4x32-10 + quarter-disc loop body from registers
+    only (no tiles, no queue, no memory), 8 blocks per CU, over the same
+    number of Philox blocks.  Its clock marks give the shader clock the loop
+    ran at."""
+    import torch
+    lib = probe_lib(sc)
+    fn = lib.sparkcl_probe_valu
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                   ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    rates = lib.sparkcl_probe_clock_rates
+    rates.restype = ctypes.c_int
+    peak_khz, wall_khz = ctypes.c_uint32(), ctypes.c_uint32()
+    if rates(0, ctypes.byref(peak_khz), ctypes.byref(wall_khz)) != 0:
+        raise RuntimeError("sparkcl_probe_clock_rates failed")
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    per_cu = 8
+    grid = per_cu * cus
+    iters = max(1, pairs // (grid * 256))
+    sink = torch.empty(grid * 256, dtype=torch.int32, device="cuda")
+    clk = torch.zeros(4, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def launch():
+        if fn(0, grid, iters, 0, 0, sink.data_ptr(), clk.data_ptr(), stream.cuda_stream) != 0:
+            raise RuntimeError("sparkcl_probe_valu failed")
+    launch()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        launch()
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    c = clk.cpu().tolist()
+    sclk_ghz = (c[2] - c[0]) / (c[3] - c[1]) * wall_khz.value / 1e6 if c[3] > c[1] else None
+    blocks = grid * 256 * iters
+    return {"kernel": "k_valu (Philox loop, registers only)", "blocks_per_cu": per_cu,
+            "ms": ms, "philox_blocks_per_s": blocks / (ms / 1e3),
+            "shader_clock_GHz": sclk_ghz, "peak_clock_GHz": peak_khz.value / 1e6}
+
+
+def alu_issue_peak(isa: dict) -> dict:
+    """The Philox loop's VALU issue bound from the chip's unit counts and
+    clock.  Each of a CU's 4 SIMDs issues one wave64 VALU instruction per 4
+    clocks, or two when both can pair.  Measured on MI355X with the probe
+    kernels: v_mad_u64_u32 never pairs, v_bitop3_b32 pairs with a simple
+    32-bit instruction but not with another v_bitop3_b32, simple 32-bit
+    instructions pair with each other.  Taking every other instruction as
+    pairable gives an upper bound on the loop's rate: per 64 Philox blocks
+    (one wave iteration) a SIMD needs at least
+    mad + max(bitop3, (valu - mad) / 2) issue slots of 4 clocks."""
+    lp = isa["philox_loop"]
+    valu, mad, x3 = lp["valu"], lp["mad_u64_u32"], lp["xor3"]
+    slots = mad + max(x3, (valu - mad) / 2)
+    blocks_per_s = CUS * 4 * 64 * CLOCK_GHZ * 1e9 / (4 * slots)
+    return {"valu_per_block": valu, "mad_u64_u32": mad, "bitop3": x3,
+            "issue_slots_per_wave_iteration": slots, "philox_blocks_per_s": blocks_per_s,
+            "lane_instr_per_s_T": blocks_per_s * valu / 1e12,
+            "single_issue_lane_instr_per_s_T": ALU_PEAK_TOPS}
+
+
 def bench_monte_carlo(ctx, sc, steps=5) -> dict:
     import torch
 
@@ -262,14 +345,23 @@ def bench_monte_carlo(ctx, sc, steps=5) -> dict:
            "philox_blocks_per_s": blocks / (ev / 1e3), "samples": samples}
     # ALU roofline: VALU instructions per Philox block (one block = two
     # samples per lane) counted in this build's own gfx950 assembly, times
-    # blocks/s, against 256 CUs x 64 lanes x 2.4 GHz.
+    # blocks/s, against the loop's issue bound at 256 CUs x 4 SIMDs x 2.4 GHz
+    # (dual issue where the instructions can pair), and against the measured
+    # ceiling of the same loop run from registers alone.
     isa = load_isa()
+    ceil = valu_ceiling(sc, blocks)
+    out["valu_ceiling"] = ceil
     if isa and "philox_loop" in isa:
+        model = alu_issue_peak(isa)
         valu = isa["philox_loop"]["valu"]
         achieved = blocks * valu / (ev / 1e3) / 1e12
-        out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS,
-                           "unit": "T VALU lane-instr/s", "frac": achieved / ALU_PEAK_TOPS,
-                           "valu_per_philox_block": valu}
+        measured = ceil["philox_blocks_per_s"] * valu / 1e12
+        out["roofline"] = {"bound": "alu", "achieved": achieved,
+                           "peak": model["lane_instr_per_s_T"],
+                           "unit": "T VALU lane-instr/s", "frac": achieved / model["lane_instr_per_s_T"],
+                           "measured_ceiling": measured,
+                           "frac_of_measured_ceiling": achieved / measured,
+                           "issue_model": model}
     return out
 
 
@@ -307,10 +399,7 @@ def bench_host_input(ctx, sc, res, reps=3) -> dict:
     host-to-device copy of the same 2 GiB (the PCIe ceiling)."""
     import torch
     n, parts = res.n, res.parts
-    hx = torch.empty(parts * n, dtype=torch.float32).pin_memory()
-    hy = torch.empty(parts * n, dtype=torch.float32).pin_memory()
-    hx.copy_(res.x)
-    hy.copy_(res.y)
+    hx, hy = res.pinned()
     tasks = [sc.task(sc.FMUL, n, hx[p * n:(p + 1) * n], hy[p * n:(p + 1) * n],
                      ops=sc.SUM | sc.MAX, c=0.1, host=True) for p in range(parts)]
     s = torch.cuda.current_stream()
@@ -478,12 +567,12 @@ def bench_uneven(ctx, sc, steps=20, ceiling_gbps: float | None = None) -> dict:
                      "elements_per_s": int(sizes.sum()) / (ev / 1e3)}
     out["batched_speedup"] = out["per_launch"]["ms"] / out["batched"]["ms"]
     # lower bound: the larger of the HBM time of the POLY/FMUL bytes and the
-    # VALU time of the Monte-Carlo samples (Philox blocks x VALU per block)
+    # VALU time of the Monte-Carlo samples (Philox blocks at the loop's issue
+    # bound)
     t_hbm = bytes_ / (HBM_PEAK_GBS * 1e9) * 1e3
     isa = load_isa()
-    valu = isa["philox_loop"]["valu"] if isa and "philox_loop" in isa else None
-    if valu:
-        t_valu = (mc / 2) * valu / (ALU_PEAK_TOPS * 1e12) * 1e3
+    if isa and "philox_loop" in isa:
+        t_valu = (mc / 2) / alu_issue_peak(isa)["philox_blocks_per_s"] * 1e3
         bound = max(t_hbm, t_valu)
         out["lower_bound"] = {"hbm_ms": t_hbm, "mc_valu_ms": t_valu, "ms": bound,
                               "hbm_frac": t_hbm / out["batched"]["ms"],
@@ -498,9 +587,11 @@ def bench_uneven(ctx, sc, steps=20, ceiling_gbps: float | None = None) -> dict:
     return out
 
 
-def trace_tasks(sc, tr, xp: int, yp: int):
+def trace_tasks(sc, tr, xp: int, yp: int, host: bool = False):
     """The serving trace as a contiguous array of sparkcl_task (filled column
-    by column; a numpy record type with the C struct's layout)."""
+    by column; a numpy record type with the C struct's layout).  host: x and
+    y are pinned host arrays, and the POLY / FMUL tasks read them from there
+    (SPARKCL_TASK_HOST_INPUT)."""
     import numpy as np
 
     import datagen
@@ -523,22 +614,30 @@ def trace_tasks(sc, tr, xp: int, yp: int):
     a["degree"] = np.where(po, len(datagen.POLY_COEF) - 1, 0)
     a["coef"][po, :len(datagen.POLY_COEF)] = datagen.POLY_COEF
     a["c"] = datagen.FMUL_C
+    if host:
+        a["flags"] = np.where(mc, 0, sc.TASK_HOST_INPUT)
     return a
 
 
 def serve_run(sc, res: Resident, seconds: float, warm: float, per_task: bool,
-              rate: float = 20000.0) -> dict:
+              rate: float = 20000.0, host: bool = False, budget: int = 64 << 30) -> dict:
     """Open-loop Poisson stream, replayed by the native load generator
     (submit at the scheduled arrival times, poll for completions); latency =
     the server's completion stamp - scheduled arrival (no coordinated
-    omission: a late submit counts against the server)."""
+    omission: a late submit counts against the server).  host: the tasks'
+    inputs are in pinned host memory, so each latency includes its PCIe
+    transfer.  budget: the admission budget in bytes."""
     import numpy as np
 
     import datagen
     count = int((seconds + warm) * rate)
     pool = res.parts * res.n
     tr = datagen.serving_trace(count, rate=rate, pool=pool)
-    tasks = trace_tasks(sc, tr, res.x.data_ptr(), res.y.data_ptr())
+    if host:
+        hx, hy = res.pinned()
+        tasks = trace_tasks(sc, tr, hx.data_ptr(), hy.data_ptr(), host=True)
+    else:
+        tasks = trace_tasks(sc, tr, res.x.data_ptr(), res.y.data_ptr())
     sched = np.ascontiguousarray((tr.t_arrive * 1e9).astype(np.int64))
     done = np.zeros(count, np.int64)
     status = np.zeros(count, np.int32)
@@ -549,8 +648,8 @@ def serve_run(sc, res: Resident, seconds: float, warm: float, per_task: bool,
     run.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                     ctypes.c_int64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int64),
                     ctypes.c_void_p, ctypes.c_void_p]
-    ctx = sc.Context(device=0, arena_bytes=1 << 30, budget_bytes=64 << 30,
-                     flags=sc.FLAG_SERVE_PER_TASK if per_task else 0)
+    ctx = sc.Context(device=0, arena_bytes=(4 << 30) if host else (1 << 30),
+                     budget_bytes=budget, flags=sc.FLAG_SERVE_PER_TASK if per_task else 0)
     t0 = ctypes.c_int64()
     rc = run(ctx._h, tasks.ctypes.data, sched.ctypes.data, count, 20_000_000, 10_000,
              ctypes.byref(t0), done.ctypes.data, status.ctypes.data)
@@ -566,7 +665,9 @@ def serve_run(sc, res: Resident, seconds: float, warm: float, per_task: bool,
 
     def pct(p):
         return float(lat[min(len(lat) - 1, int(math.ceil(p / 100 * len(lat))) - 1)])
+    in_bytes = np.where(tr.kids == datagen.POLY, 4, np.where(tr.kids == datagen.FMUL, 8, 0))
     return {"offered_per_s": rate, "tasks": count - first, "failed": failed,
+            "input_GBps": float((tr.sizes[first:] * in_bytes[first:]).sum()) / span / 1e9,
             "p50_us": pct(50), "p99_us": pct(99), "p999_us": pct(99.9),
             "mean_us": float(lat.mean()), "tasks_per_s": (count - first) / span,
             "elements_per_s": elems / span,
@@ -576,14 +677,16 @@ def serve_run(sc, res: Resident, seconds: float, warm: float, per_task: bool,
 
 
 def serve_sweep(sc, res: Resident, rates=(20e3, 50e3, 100e3, 200e3, 400e3, 800e3, 1.6e6),
-                seconds: float = 1.0, warm: float = 0.25) -> list:
-    """The resident server at rising offered rates, up to saturation (where
+                seconds: float = 1.0, warm: float = 0.25, per_task: bool = False,
+                host: bool = False, budget: int = 64 << 30) -> list:
+    """A serving form at rising offered rates, up to saturation (where
     completions fall behind arrivals and the latency grows with the queue)."""
     out = []
     for r in rates:
-        row = serve_run(sc, res, seconds, warm, False, r)
+        row = serve_run(sc, res, seconds, warm, per_task, r, host=host, budget=budget)
         out.append({k: row[k] for k in ("offered_per_s", "tasks_per_s", "p50_us", "p99_us",
-                                        "p999_us", "failed", "admission_waits")})
+                                        "p999_us", "failed", "admission_waits",
+                                        "budget_peak_bytes", "input_GBps")})
     return out
 
 
@@ -731,6 +834,20 @@ def main() -> int:
                     sc, res, args.serve_seconds, 1.0, per_task)
             log("extras: serving rate sweep ...")
             ex["serving"]["resident_rate_sweep"] = serve_sweep(sc, res)
+            log("extras: serving rate sweep (per-task launches) ...")
+            ex["serving"]["per_task_launch_rate_sweep"] = serve_sweep(
+                sc, res, rates=(20e3, 50e3, 100e3, 200e3, 400e3), per_task=True)
+            # a budget below the in-flight working set: 40 MiB holds the
+            # largest task (4M FMUL elements, 32 MiB + partials) but not the
+            # tasks that overlap it at these rates, so admission waits
+            log("extras: serving under a 40 MiB budget ...")
+            ex["serving"]["budget_bound_40MiB"] = serve_sweep(
+                sc, res, rates=(100e3, 200e3, 400e3), budget=40 << 20)
+            log("extras: serving host-resident inputs ...")
+            ex["serving"]["resident_host_input"] = serve_run(
+                sc, res, min(args.serve_seconds, 3.0), 1.0, False, host=True)
+            ex["serving"]["host_input_rate_sweep"] = serve_sweep(
+                sc, res, rates=(10e3, 20e3, 30e3, 40e3, 60e3), host=True)
         line["extras"] = ex
     ctx.destroy()
     print(json.dumps(line), flush=True)

@@ -5,4 +5,4 @@ built-in partition kernels, as hand-written HIP for gfx950 behind a C ABI
 (include/sparkcl.h).  This package is the ctypes binding of that library.
 """
 from .sparkcl import *  # noqa: F401,F403
-from .sparkcl import Context, Result, Task, Tuning, load, task  # noqa: F401
+from .sparkcl import Context, Result, Task, TaskArray, Tuning, load, task, task_array  # noqa: F401

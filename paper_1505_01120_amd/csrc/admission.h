@@ -20,12 +20,20 @@ struct Pending {
     uint32_t ntiles = 0; // tile-map entries while in flight
     uint64_t t_arrive = 0;
     uint32_t user = 0;   // caller's index into its own task storage
+    // A staged task (inputs in host memory) is admitted against the budget
+    // and tile map alone; it takes a ring slot (and its sequence number) only
+    // once its inputs have been copied to the device, so a copy in progress
+    // never holds up the tasks admitted after it.
+    bool staged = false;
 };
+
+constexpr uint64_t kNoSeq = ~0ull;
 
 struct Admitted {
     Pending p;
-    uint64_t seq = 0;
+    uint64_t seq = kNoSeq; // kNoSeq: a staged task that has no slot yet
     uint32_t slot = 0;
+    bool has_slot() const { return seq != kNoSeq; }
 };
 
 enum class AdmitBlock { NONE, EMPTY, SLOT, BUDGET, TILES };
@@ -52,7 +60,7 @@ class Admission {
         if (q_.empty())
             return AdmitBlock::EMPTY;
         const Pending &h = q_.front();
-        if (busy_[slot_of(next_seq_)])
+        if (!h.staged && !slot_free())
             return AdmitBlock::SLOT;
         if (in_use_ + h.bytes > budget_)
             return AdmitBlock::BUDGET;
@@ -61,15 +69,15 @@ class Admission {
         return AdmitBlock::NONE;
     }
 
-    // Admits the head (the caller checked head_block() == NONE).
+    // Admits the head (the caller checked head_block() == NONE).  A staged
+    // head is charged but gets no slot (take_slot later).
     Admitted admit_head()
     {
         Admitted a;
         a.p = q_.front();
         q_.pop_front();
-        a.seq = next_seq_++;
-        a.slot = slot_of(a.seq);
-        busy_[a.slot] = 1;
+        if (!a.p.staged)
+            take_slot(a);
         in_use_ += a.p.bytes;
         tiles_ += a.p.ntiles;
         if (in_use_ > peak_)
@@ -78,21 +86,37 @@ class Admission {
         return a;
     }
 
+    // Whether the ring slot of the next sequence number is free.
+    bool slot_free() const { return !busy_[slot_of(next_seq_)]; }
+
+    // Gives an admitted staged task the next sequence number and its ring
+    // slot (the caller checked slot_free()).
+    void take_slot(Admitted &a)
+    {
+        a.seq = next_seq_++;
+        a.slot = slot_of(a.seq);
+        busy_[a.slot] = 1;
+    }
+
     // Undo an admission whose device resources could not be obtained; the
-    // task goes back to the head of the queue with its sequence number.
+    // task goes back to the head of the queue (a slotted one must be the
+    // latest admission and returns its sequence number).
     void unadmit(const Admitted &a)
     {
-        busy_[a.slot] = 0;
+        if (a.has_slot()) {
+            busy_[a.slot] = 0;
+            --next_seq_;
+        }
         in_use_ -= a.p.bytes;
         tiles_ -= a.p.ntiles;
         --in_flight_;
-        --next_seq_;
         q_.push_front(a.p);
     }
 
     void complete(const Admitted &a)
     {
-        busy_[a.slot] = 0;
+        if (a.has_slot())
+            busy_[a.slot] = 0;
         in_use_ -= a.p.bytes;
         tiles_ -= a.p.ntiles;
         --in_flight_;

@@ -137,8 +137,9 @@ void free_plan(sparkcl_ctx *ctx, Plan *p)
             (void)hipEventDestroy(e);
     if (p->ev_start)
         (void)hipEventDestroy(p->ev_start);
-    if (p->gexec)
-        (void)hipGraphExecDestroy(p->gexec);
+    for (hipGraphExec_t &x : p->gexec)
+        if (x)
+            (void)hipGraphExecDestroy(x);
     if (p->graph)
         (void)hipGraphDestroy(p->graph);
     for (uint64_t off : p->blocks)
@@ -668,7 +669,7 @@ int sparkcl::enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream, bool timed)
         // The launches below, captured once on the library's own stream into
         // a graph kept with the plan, then replayed: one graph launch per
         // call.  Under the caller's capture they are recorded directly.
-        if (!p->gexec) {
+        if (!p->gexec[0]) {
             hipStream_t cs = ctx->capture_stream;
             SPARKCL_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
             const int rc = launch_device(ctx, p, cs);
@@ -681,16 +682,23 @@ int sparkcl::enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream, bool timed)
             }
             if (e != hipSuccess)
                 return fail_hip(e, "graph capture");
-            hipGraphExec_t x = nullptr;
-            const hipError_t ei = hipGraphInstantiateWithFlags(&x, g, 0);
-            if (ei != hipSuccess) {
-                (void)hipGraphDestroy(g);
-                return fail_hip(ei, "graph instantiate");
+            hipGraphExec_t x[2] = {nullptr, nullptr};
+            for (hipGraphExec_t &e : x) {
+                const hipError_t ei = hipGraphInstantiateWithFlags(&e, g, 0);
+                if (ei != hipSuccess) {
+                    if (x[0])
+                        (void)hipGraphExecDestroy(x[0]);
+                    (void)hipGraphDestroy(g);
+                    return fail_hip(ei, "graph instantiate");
+                }
             }
             p->graph = g;
-            p->gexec = x;
+            p->gexec[0] = x[0];
+            p->gexec[1] = x[1];
         }
-        SPARKCL_HIP(hipGraphLaunch(p->gexec, stream));
+        // the two instances take turns (a launch waits for its instance's
+        // previous launch; the other instance's is then one call back)
+        SPARKCL_HIP(hipGraphLaunch(p->gexec[p->glaunches++ & 1u], stream));
     } else {
         const int rc = launch_device(ctx, p, stream);
         if (rc != SPARKCL_OK)

@@ -15,7 +15,8 @@ using namespace sparkcl;
 namespace {
 struct AdmBox {
     Admission adm;
-    std::map<uint64_t, Admitted> live; // seq -> admission record
+    std::map<uint64_t, Admitted> live;   // seq -> admission record
+    std::map<uint64_t, Admitted> staged; // ticket -> admitted staged task without a slot
     AdmBox(uint64_t b, uint32_t s, uint64_t t) : adm(b, s, t) {}
 };
 } // namespace
@@ -57,6 +58,17 @@ void hl_adm_push(void *b, uint64_t ticket, uint64_t bytes, uint32_t ntiles, uint
     p.t_arrive = t_arrive;
     static_cast<AdmBox *>(b)->adm.push(p);
 }
+void hl_adm_push_staged(void *b, uint64_t ticket, uint64_t bytes, uint32_t ntiles,
+                        uint64_t t_arrive)
+{
+    Pending p;
+    p.ticket = ticket;
+    p.bytes = bytes;
+    p.ntiles = ntiles;
+    p.t_arrive = t_arrive;
+    p.staged = true;
+    static_cast<AdmBox *>(b)->adm.push(p);
+}
 // 0 admissible, 1 empty, 2 slot busy, 3 over budget, 4 tile map full
 int hl_adm_head_block(void *b) { return (int)static_cast<AdmBox *>(b)->adm.head_block(); }
 int hl_adm_admit(void *b, uint64_t *seq, uint32_t *slot, uint64_t *ticket)
@@ -65,8 +77,11 @@ int hl_adm_admit(void *b, uint64_t *seq, uint32_t *slot, uint64_t *ticket)
     if (x->adm.head_block() != AdmitBlock::NONE)
         return 0;
     Admitted a = x->adm.admit_head();
-    x->live[a.seq] = a;
-    *seq = a.seq;
+    if (a.has_slot())
+        x->live[a.seq] = a;
+    else
+        x->staged[a.p.ticket] = a;
+    *seq = a.seq; // ~0 for a staged task (no slot yet)
     *slot = a.slot;
     *ticket = a.p.ticket;
     return 1;
@@ -79,6 +94,43 @@ int hl_adm_unadmit(void *b, uint64_t seq)
         return 0;
     x->adm.unadmit(it->second);
     x->live.erase(it);
+    return 1;
+}
+// A staged task (by ticket) takes the next slot: 1 and its seq/slot, or 0
+// when that slot is busy or the ticket is not a staged admission.
+int hl_adm_take_slot(void *b, uint64_t ticket, uint64_t *seq, uint32_t *slot)
+{
+    AdmBox *x = static_cast<AdmBox *>(b);
+    auto it = x->staged.find(ticket);
+    if (it == x->staged.end() || !x->adm.slot_free())
+        return 0;
+    Admitted a = it->second;
+    x->staged.erase(it);
+    x->adm.take_slot(a);
+    x->live[a.seq] = a;
+    *seq = a.seq;
+    *slot = a.slot;
+    return 1;
+}
+// Undo or complete a staged admission that never took a slot.
+int hl_adm_unadmit_staged(void *b, uint64_t ticket)
+{
+    AdmBox *x = static_cast<AdmBox *>(b);
+    auto it = x->staged.find(ticket);
+    if (it == x->staged.end())
+        return 0;
+    x->adm.unadmit(it->second);
+    x->staged.erase(it);
+    return 1;
+}
+int hl_adm_complete_staged(void *b, uint64_t ticket)
+{
+    AdmBox *x = static_cast<AdmBox *>(b);
+    auto it = x->staged.find(ticket);
+    if (it == x->staged.end())
+        return 0;
+    x->adm.complete(it->second);
+    x->staged.erase(it);
     return 1;
 }
 int hl_adm_complete(void *b, uint64_t seq)

@@ -90,9 +90,14 @@ struct Plan {
     hipEvent_t ev_start = nullptr;
     std::vector<hipEvent_t> ev_copied, ev_copied2, ev_done; // x copied, y copied, slot free
 
-    // SPARKCL_GRAPH: the plan's launches captured once, replayed per call
+    // SPARKCL_GRAPH: the plan's launches captured once, replayed per call.
+    // Two executable instances of the graph take turns: the runtime makes a
+    // launch of an instance wait until that instance's previous launch has
+    // finished, so with one instance a replayed call could not be queued
+    // behind the one still running, and the GPU idled between them.
     hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    uint32_t glaunches = 0;
 };
 
 // Plan cache and launch helpers (api.cpp); the caller holds ctx->mu.

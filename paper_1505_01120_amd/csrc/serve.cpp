@@ -12,6 +12,14 @@
 // result until sparkcl_poll collects it.  An idle executor exits on its own
 // and is relaunched when work arrives.
 //
+// A task whose inputs live in host memory (SPARKCL_TASK_HOST_INPUT, pinned
+// arrays) is admitted against the budget with its staging block, its inputs
+// are copied into the arena on the server's copy streams while earlier tasks
+// run, and it takes a ring slot only once the copy is done, so the tasks
+// admitted after it are never held up by its transfer.  Its latency includes
+// the PCIe time, the main cost of offload that the paper names (sec. 3,
+// design issue 1).
+//
 // The same machinery also runs the baseline the paper's workers use: one
 // kernel launch per task (SPARKCL_FLAG_SERVE_PER_TASK), spread over a pool of
 // streams, with the same admission, descriptors and completion words.
@@ -25,6 +33,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <unordered_set>
 
 namespace sparkcl {
 
@@ -44,6 +53,32 @@ uint64_t task_bytes(const sparkcl_task &t, uint32_t ntiles)
         in = 8 * t.n;
     const uint64_t out = (t.out && t.kernel_id != SPARKCL_MC_PI) ? 4 * t.n : 0;
     return in + out + sizeof(Partial) * (uint64_t)ntiles;
+}
+
+// Arena bytes that stage a host-input task: each input at its host address
+// modulo 16 (so the kernel cuts the same quads and tiles, and the result is
+// bit-identical to the same data in device memory), in 256-byte units.
+uint64_t staging_stride(const sparkcl_task &t)
+{
+    return (4 * t.n + 16 + 255) / 256 * 256;
+}
+
+uint64_t staging_bytes(const sparkcl_task &t)
+{
+    return staging_stride(t) * (t.kernel_id == SPARKCL_FMUL ? 2 : 1);
+}
+
+// Whether p lies in page-locked host memory (hipHostMalloc or torch's
+// pin_memory), which an asynchronous copy needs: a copy from pageable memory
+// would stall the serving thread, and every task behind it.
+bool host_pinned(const void *p)
+{
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError(); // an unknown pointer: clear the error it left
+        return false;
+    }
+    return a.type == hipMemoryTypeHost;
 }
 
 sparkcl_result failed_result(int code)
@@ -124,6 +159,8 @@ int Server::init()
     sync_ = static_cast<TaskSync *>(m);
 
     SPARKCL_HIP(hipStreamCreateWithFlags(&exec_stream_, hipStreamNonBlocking));
+    for (hipStream_t &c : copy_stream_)
+        SPARKCL_HIP(hipStreamCreateWithFlags(&c, hipStreamNonBlocking));
     if ((rc = launch_zero(dev_, sizeof(ServeDev), exec_stream_)) != SPARKCL_OK ||
         (rc = launch_zero(sync_, (uint64_t)cap_ * sizeof(TaskSync), exec_stream_)) != SPARKCL_OK)
         return fail(rc, "clearing the serving tables failed");
@@ -156,8 +193,10 @@ int Server::submit(const sparkcl_task &task, uint64_t *ticket)
     int rc = check_task(task, &variant);
     if (rc != SPARKCL_OK)
         return rc;
-    if (task.flags & SPARKCL_TASK_HOST_INPUT)
-        return fail(SPARKCL_EINVAL, "serving takes device-resident inputs");
+    const bool host = (task.flags & SPARKCL_TASK_HOST_INPUT) != 0;
+    if (host && task.n > 0 &&
+        (!host_pinned(task.in0) || (task.kernel_id == SPARKCL_FMUL && !host_pinned(task.in1))))
+        return fail(SPARKCL_EINVAL, "served host-input arrays must be in pinned host memory");
     if (declined(ctx_, task))
         return fail(SPARKCL_EDECLINED, "offload cost " + std::to_string(offload_cost(task)) +
                                            " bytes is below the offload threshold");
@@ -167,10 +206,16 @@ int Server::submit(const sparkcl_task &task, uint64_t *ticket)
     if (nt64 > tile_cap_)
         return fail(SPARKCL_ETOOBIG, "task needs more tiles than the tile map holds");
     const uint32_t ntiles = (uint32_t)nt64;
-    const uint64_t bytes = task_bytes(task, ntiles);
+    // a host-input task is charged its staging block (the library's copy of
+    // its inputs) and its partials
+    const uint64_t bytes = host ? staging_bytes(task) + sizeof(Partial) * (uint64_t)ntiles
+                                : task_bytes(task, ntiles);
     if (!adm_.fits_at_all(bytes, ntiles))
         return fail(SPARKCL_ETOOBIG, "task needs " + std::to_string(bytes) +
                                          " bytes, budget is " + std::to_string(adm_.budget()));
+    // its staging block must fit the arena too, or it could never be admitted
+    if (host && staging_bytes(task) + sizeof(Partial) * (uint64_t)ntiles > ctx_->arena.size())
+        return fail(SPARKCL_ETOOBIG, "host-input task's staging exceeds the arena");
     if (quit_ || poisoned_)
         return fail(SPARKCL_ESTOPPED, poisoned_ ? "serving executor could not be stopped"
                                                 : "serving is shutting down");
@@ -181,6 +226,7 @@ int Server::submit(const sparkcl_task &task, uint64_t *ticket)
     p.bytes = bytes;
     p.ntiles = ntiles;
     p.t_arrive = host_ns();
+    p.staged = host && task.n > 0;
     adm_.push(p);
     Waiting w;
     w.task = task;
@@ -232,11 +278,22 @@ int Server::drain(uint32_t timeout_ms)
     return ok ? SPARKCL_OK : fail(SPARKCL_ETIMEDOUT, "drain timed out");
 }
 
-// Admit queued tasks while the head fits; the admitted ones are appended to
-// the in-flight list and copied to *out.
-void Server::admit_some(std::vector<Flight> *out)
+// Admit work while it fits.  First, staged tasks whose inputs are on the
+// device take ring slots, in the order they were admitted.  Then queued tasks
+// are admitted in FIFO order while the head fits: a device-input task takes
+// its slot at once (appended to the in-flight list and copied to *out), a
+// host-input one gets its staging block and copy event and goes to the
+// staging list (and *to_copy) until its copy is done.
+void Server::admit_some(std::vector<Flight> *out, std::vector<Flight> *to_copy)
 {
     std::lock_guard<std::mutex> g(mu_);
+    while (!staging_.empty() && staging_.front().ready && adm_.slot_free()) {
+        Flight f = staging_.front();
+        staging_.pop_front();
+        adm_.take_slot(f.a);
+        flight_.push_back(f);
+        out->push_back(f);
+    }
     for (;;) {
         const AdmitBlock b = adm_.head_block();
         if (b == AdmitBlock::EMPTY)
@@ -260,10 +317,136 @@ void Server::admit_some(std::vector<Flight> *out)
         f.tile = w.tile;
         f.part_off = off;
         f.t_admit = host_ns();
-        flight_.push_back(f);
-        out->push_back(f);
+        f.dx = w.task.in0;
+        f.dy = w.task.in1;
+        if (a.p.staged) {
+            const uint64_t so = ctx_->arena.alloc(staging_bytes(w.task));
+            if (so == Arena::kFail) {
+                ctx_->arena.release(off);
+                adm_.unadmit(a);
+                ++waits_;
+                break;
+            }
+            if (free_events_.empty()) {
+                hipEvent_t e = nullptr;
+                if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                    ctx_->arena.release(so);
+                    ctx_->arena.release(off);
+                    adm_.unadmit(a);
+                    ++waits_;
+                    break;
+                }
+                events_.push_back(e);
+                free_events_.push_back((int)events_.size() - 1);
+            }
+            f.ev = free_events_.back();
+            free_events_.pop_back();
+            f.cs = copy_next_++ & 1u;
+            f.stage_off = so;
+            char *base = static_cast<char *>(ctx_->dev(so));
+            f.dx = reinterpret_cast<const float *>(base + ((uintptr_t)w.task.in0 & 15u));
+            if (w.task.kernel_id == SPARKCL_FMUL)
+                f.dy = reinterpret_cast<const float *>(base + staging_stride(w.task) +
+                                                       ((uintptr_t)w.task.in1 & 15u));
+            staging_.push_back(f);
+            to_copy->push_back(f);
+        } else {
+            flight_.push_back(f);
+            out->push_back(f);
+        }
         ++admitted_;
     }
+}
+
+// Queue the host-to-device copies of newly staged tasks, each task's inputs
+// on one of the two copy streams in turn, followed by its event.
+int Server::start_copies(const std::vector<Flight> &fl)
+{
+    for (const Flight &f : fl) {
+        const hipStream_t s = copy_stream_[f.cs];
+        SPARKCL_HIP(hipMemcpyAsync(const_cast<float *>(f.dx), f.task.in0, 4 * f.task.n,
+                                   hipMemcpyHostToDevice, s));
+        if (f.task.kernel_id == SPARKCL_FMUL)
+            SPARKCL_HIP(hipMemcpyAsync(const_cast<float *>(f.dy), f.task.in1, 4 * f.task.n,
+                                       hipMemcpyHostToDevice, s));
+        SPARKCL_HIP(hipEventRecord(events_[f.ev], s));
+    }
+    return SPARKCL_OK;
+}
+
+// Mark staged tasks whose copies are done.  The copies on one stream finish
+// in the order they were queued, so each stream's tasks are queried from the
+// oldest until one is still copying.
+void Server::poll_staging()
+{
+    std::vector<std::pair<int, uint32_t>> cand; // (event, copy stream), oldest first
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        for (const Flight &f : staging_)
+            if (!f.ready)
+                cand.emplace_back(f.ev, f.cs);
+    }
+    if (cand.empty())
+        return;
+    std::unordered_set<int> done;
+    bool busy[2] = {false, false};
+    for (const auto &c : cand) {
+        if (busy[c.second])
+            continue;
+        if (hipEventQuery(events_[c.first]) == hipSuccess) {
+            done.insert(c.first);
+        } else {
+            (void)hipGetLastError(); // not ready yet: clear the status it left
+            busy[c.second] = true;
+            if (busy[0] && busy[1])
+                break;
+        }
+    }
+    if (done.empty())
+        return;
+    std::lock_guard<std::mutex> g(mu_);
+    for (Flight &f : staging_)
+        if (!f.ready && done.count(f.ev))
+            f.ready = true;
+}
+
+// A finished task's arena blocks and copy event go back (caller holds mu_).
+void Server::release_flight(const Flight &f)
+{
+    ctx_->arena.release(f.part_off);
+    if (f.stage_off != Arena::kFail)
+        ctx_->arena.release(f.stage_off);
+    if (f.ev >= 0)
+        free_events_.push_back(f.ev);
+}
+
+// Fail every staged task that has no ring slot yet, once its copies are done
+// (they write its staging block).  keep_memory: leave its blocks reserved.
+void Server::fail_staging(int code, bool keep_memory)
+{
+    std::deque<Flight> st;
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        st.swap(staging_);
+    }
+    for (const Flight &f : st)
+        (void)hipEventSynchronize(events_[f.ev]);
+    std::lock_guard<std::mutex> g(mu_);
+    for (const Flight &f : st) {
+        sparkcl_result r = failed_result(code);
+        r.n = f.task.n;
+        r.t_arrive_ns = f.a.p.t_arrive;
+        r.t_admit_ns = f.t_admit;
+        r.t_done_ns = host_ns();
+        if (!keep_memory) {
+            release_flight(f);
+            adm_.complete(f.a);
+        }
+        done_map_[f.a.p.ticket] = r;
+        waiting_.erase(f.a.p.ticket);
+        ++failed_;
+    }
+    cv_done_.notify_all();
 }
 
 // Write the descriptors of newly admitted tasks and hand them to the GPU.
@@ -278,8 +461,8 @@ int Server::publish(const std::vector<Flight> &fl)
         d.kid = t.kernel_id;
         d.ops = t.reduce_ops;
         d.n = t.n;
-        d.in0 = t.in0;
-        d.in1 = t.in1;
+        d.in0 = f.dx; // a host-input task reads its staged copies
+        d.in1 = f.dy;
         d.out = t.out;
         d.seed = t.seed;
         d.pid = t.partition_id;
@@ -395,7 +578,7 @@ bool Server::reap()
         r.t_arrive_ns = f.a.p.t_arrive;
         r.t_admit_ns = f.t_admit;
         r.t_done_ns = host_ns();
-        ctx_->arena.release(f.part_off);
+        release_flight(f);
         adm_.complete(f.a);
         done_map_[f.a.p.ticket] = r;
         waiting_.erase(f.a.p.ticket);
@@ -411,6 +594,7 @@ bool Server::reap()
 
 void Server::fail_in_flight(int code)
 {
+    fail_staging(code, false);
     std::lock_guard<std::mutex> g(mu_);
     for (Flight &f : flight_) {
         sparkcl_result r = failed_result(code);
@@ -418,7 +602,7 @@ void Server::fail_in_flight(int code)
         r.t_arrive_ns = f.a.p.t_arrive;
         r.t_admit_ns = f.t_admit;
         r.t_done_ns = host_ns();
-        ctx_->arena.release(f.part_off);
+        release_flight(f);
         adm_.complete(f.a);
         done_map_[f.a.p.ticket] = r;
         waiting_.erase(f.a.p.ticket);
@@ -456,16 +640,17 @@ void Server::loop()
             std::unique_lock<std::mutex> lk(mu_);
             if (quit_)
                 break;
-            if (flight_.empty() && adm_.pending() == 0 &&
+            if (flight_.empty() && staging_.empty() && adm_.pending() == 0 &&
                 host_ns() - last_activity > kSpinNs) {
                 cv_work_.wait_for(lk, std::chrono::milliseconds(20));
                 continue;
             }
         }
-        std::vector<Flight> adm;
-        admit_some(&adm);
-        bool progress = !adm.empty();
-        if (publish(adm) != SPARKCL_OK) {
+        poll_staging();
+        std::vector<Flight> adm, to_copy;
+        admit_some(&adm, &to_copy);
+        bool progress = !adm.empty() || !to_copy.empty();
+        if (start_copies(to_copy) != SPARKCL_OK || publish(adm) != SPARKCL_OK) {
             fail_in_flight(SPARKCL_EHIP);
             continue;
         }
@@ -507,7 +692,10 @@ void Server::loop()
         else
             std::this_thread::yield();
     }
-    // Shutdown: let in-flight work finish (bounded), then stop the executor.
+    // Shutdown: staged tasks without a slot fail; let in-flight work finish
+    // (bounded), then stop the executor.
+    if (!poisoned_)
+        fail_staging(SPARKCL_ESTOPPED, false);
     const uint64_t t0 = host_ns();
     for (;;) {
         reap();
@@ -536,6 +724,7 @@ void Server::loop()
 // partials and slot reserved, and refuse further work.
 void Server::poison(int code)
 {
+    fail_staging(code, true);
     std::lock_guard<std::mutex> g(mu_);
     poisoned_ = true;
     for (Flight &f : flight_) {
@@ -579,6 +768,17 @@ int Server::shutdown()
         if (exec_stream_)
             (void)hipStreamDestroy(exec_stream_);
         exec_stream_ = nullptr;
+        for (hipStream_t &c : copy_stream_) {
+            if (c) {
+                (void)hipStreamSynchronize(c);
+                (void)hipStreamDestroy(c);
+            }
+            c = nullptr;
+        }
+        for (hipEvent_t e : events_)
+            (void)hipEventDestroy(e);
+        events_.clear();
+        free_events_.clear();
         for (uint64_t off : blocks_)
             ctx_->arena.release(off);
         blocks_.clear();

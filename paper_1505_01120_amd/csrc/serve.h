@@ -39,7 +39,11 @@ class Server {
     int start_thread_locked();
     // serving-thread helpers (called without mu_ held unless noted)
     struct Flight;
-    void admit_some(std::vector<Flight> *out);
+    void admit_some(std::vector<Flight> *out, std::vector<Flight> *to_copy);
+    int start_copies(const std::vector<Flight> &fl);
+    void poll_staging();
+    void release_flight(const Flight &f);
+    void fail_staging(int code, bool keep_memory);
     int publish(const std::vector<Flight> &fl);
     bool reap();
     bool executor_running();
@@ -58,6 +62,13 @@ class Server {
         uint32_t tile = 0;     // tile size fixed at submit
         uint64_t part_off = 0; // arena block for the partials
         uint64_t t_admit = 0;
+        // host-input task: its staging block in the arena, the device copies
+        // of its inputs there, and the event that marks the copies done
+        uint64_t stage_off = Arena::kFail;
+        const float *dx = nullptr, *dy = nullptr;
+        int ev = -1;
+        uint32_t cs = 0; // copy stream
+        bool ready = false;
     };
     struct Waiting {
         sparkcl_task task;
@@ -83,6 +94,10 @@ class Server {
     TaskSync *sync_ = nullptr;
 
     hipStream_t exec_stream_ = nullptr;
+    hipStream_t copy_stream_[2] = {nullptr, nullptr}; // host-input staging copies
+    uint32_t copy_next_ = 0;
+    std::vector<hipEvent_t> events_;  // copy-done events, by index
+    std::vector<int> free_events_;
     std::vector<hipStream_t> pool_; // per-task launch mode
     uint32_t pool_next_ = 0;
     bool exec_launched_ = false;
@@ -95,6 +110,9 @@ class Server {
     std::unordered_map<uint64_t, Waiting> waiting_;     // ticket -> task (queued)
     std::unordered_map<uint64_t, sparkcl_result> done_map_;
     std::vector<Flight> flight_; // admitted, not complete (serving thread)
+    // admitted host-input tasks whose inputs are being copied to the device,
+    // in admission order; they move to flight_ when they take a ring slot
+    std::deque<Flight> staging_;
     uint64_t next_ticket_ = 1;
     uint64_t submitted_ = 0, admitted_ = 0, completed_ = 0, failed_ = 0, waits_ = 0;
     uint64_t launches_ = 0;

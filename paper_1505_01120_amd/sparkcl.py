@@ -202,7 +202,28 @@ def task(kernel_id: int, n: int, x=None, y=None, out=None, ops: int | None = Non
     return t
 
 
-def _array(tasks: Iterable[Task]):
+class TaskArray:
+    """A contiguous sparkcl_task array built once from a task list, for calls
+    that replay the same batch: passing it instead of the list skips the
+    per-call conversion of every task (on a 4096-task batch that conversion
+    costs the host about as long as the GPU takes to run the batch)."""
+
+    def __init__(self, tasks: Iterable[Task]):
+        tasks = list(tasks)
+        self.n = len(tasks)
+        self.arr = (Task * max(self.n, 1))(*tasks)
+
+    def __len__(self) -> int:
+        return self.n
+
+
+def task_array(tasks: Iterable[Task]) -> TaskArray:
+    return TaskArray(tasks)
+
+
+def _array(tasks):
+    if isinstance(tasks, TaskArray):
+        return tasks.arr, tasks.n
     tasks = list(tasks)
     arr = (Task * max(len(tasks), 1))(*tasks)
     return arr, len(tasks)

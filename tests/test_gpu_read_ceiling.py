@@ -1,6 +1,8 @@
-"""The bench's read-ceiling kernel (libsparkcl_probe.so): it reads every
-element of both arrays exactly once, so the per-block sums add up to the sum
-of x + y; bad shapes are refused and launch nothing."""
+"""The bench's probe kernels (libsparkcl_probe.so).  The read-ceiling kernel
+reads every element of both arrays exactly once, so the per-block sums add up
+to the sum of x + y; bad shapes are refused and launch nothing.  The VALU
+ceiling's Philox loop draws the same pairs as a Monte-Carlo partition, so its
+hit counts add up to the oracle's count for that partition."""
 import ctypes
 import os
 
@@ -48,3 +50,30 @@ def test_bad_shapes_launch_nothing(probe):
     assert probe(x.data_ptr() + 4, x.data_ptr(), 4096, 1, sink.data_ptr(), s) == sc.EINVAL
     torch.cuda.synchronize()
     assert torch.equal(sink, torch.full((4,), 7.0, device="cuda"))
+
+
+@pytest.mark.parametrize("mix,grid,iters,seed,pid", [(0, 4, 8, 0, 0), (0, 3, 5, 0x1234567890ABCDEF, 77),
+                                                    (1, 2, 6, 42, 3)])
+def test_valu_probe_draws_the_partition_pairs(oracle, mix, grid, iters, seed, pid):
+    fn = ctypes.CDLL(libbuild.PROBE_LIB).sparkcl_probe_valu
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                   ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    sink = torch.full((grid * 256,), -1, dtype=torch.int32, device="cuda")
+    clk = torch.zeros(4, dtype=torch.int64, device="cuda")
+    assert fn(mix, grid, iters, seed, pid, sink.data_ptr(), clk.data_ptr(),
+              torch.cuda.current_stream().cuda_stream) == 0
+    torch.cuda.synchronize()
+    pairs = grid * 256 * iters * (2 if mix == 1 else 1)
+    want = oracle.mc_count(seed, pid, 2 * pairs)
+    assert int(sink.long().sum()) == want
+    c = clk.cpu().tolist()
+    assert c[2] > c[0] and c[3] > c[1]          # block 0's clock marks advanced
+
+
+def test_clock_rates():
+    fn = ctypes.CDLL(libbuild.PROBE_LIB).sparkcl_probe_clock_rates
+    a, b = ctypes.c_uint32(), ctypes.c_uint32()
+    assert fn(0, ctypes.byref(a), ctypes.byref(b)) == 0
+    assert 1_000_000 < a.value < 5_000_000      # peak shader clock in kHz
+    assert 0 < b.value < a.value                # the wall clock is slower

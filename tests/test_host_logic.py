@@ -46,6 +46,10 @@ def host():
         ("hl_adm_unadmit", [P, U64], ctypes.c_int), ("hl_adm_complete", [P, U64], ctypes.c_int),
         ("hl_adm_in_use", [P], U64), ("hl_adm_peak", [P], U64), ("hl_adm_pending", [P], U64),
         ("hl_adm_in_flight", [P], U64), ("hl_adm_tiles", [P], U64),
+        ("hl_adm_push_staged", [P, U64, U64, U32, U64], None),
+        ("hl_adm_take_slot", [P, U64, ctypes.POINTER(U64), ctypes.POINTER(U32)], ctypes.c_int),
+        ("hl_adm_unadmit_staged", [P, U64], ctypes.c_int),
+        ("hl_adm_complete_staged", [P, U64], ctypes.c_int),
         ("hl_tuning_defaults", [ctypes.POINTER(sc.Tuning)], None),
         ("hl_tuning_validate", [ctypes.POINTER(sc.Tuning)], ctypes.c_int),
         ("hl_tile_for", [ctypes.POINTER(sc.Tuning), ctypes.c_int, U32, U64], U32),
@@ -241,6 +245,48 @@ def test_admission_tiles_and_unadmit(host):
         host.hl_adm_free(b)
 
 
+def take_slot(host, b, ticket):
+    seq, slot = ctypes.c_uint64(), ctypes.c_uint32()
+    if not host.hl_adm_take_slot(b, ticket, ctypes.byref(seq), ctypes.byref(slot)):
+        return None
+    return seq.value, slot.value
+
+
+NO_SEQ = (1 << 64) - 1
+
+
+def test_admission_staged_tasks_take_slots_when_ready(host):
+    """A staged (host-input) task is admitted against the budget without a
+    ring slot; it takes the next slot only once its inputs are on the device,
+    so tasks admitted after it are not held up while it copies."""
+    b = host.hl_adm_new(1000, 2, 1 << 20)
+    try:
+        host.hl_adm_push_staged(b, 1, 300, 1, 0)
+        host.hl_adm_push(b, 2, 300, 1, 0)
+        host.hl_adm_push(b, 3, 300, 1, 0)
+        host.hl_adm_push_staged(b, 4, 200, 1, 0)
+        assert admit(host, b) == (NO_SEQ, 0, 1)    # staged: charged, no slot
+        assert admit(host, b) == (0, 0, 2)         # the device task goes first in the ring
+        assert admit(host, b) == (1, 1, 3)
+        assert host.hl_adm_in_use(b) == 900 and host.hl_adm_head_block(b) == 3  # budget
+        assert take_slot(host, b, 1) is None       # ring full: both slots busy
+        assert host.hl_adm_complete(b, 0) == 1
+        assert take_slot(host, b, 1) == (2, 0)     # copied: takes the next slot
+        assert take_slot(host, b, 1) is None       # not staged any more
+        assert admit(host, b) == (NO_SEQ, 0, 4)    # a staged head ignores busy slots
+        assert host.hl_adm_in_use(b) == 800
+        assert host.hl_adm_unadmit_staged(b, 4) == 1   # no staging room: back to the queue
+        assert host.hl_adm_pending(b) == 1 and host.hl_adm_in_use(b) == 600
+        assert admit(host, b) == (NO_SEQ, 0, 4)
+        assert host.hl_adm_complete_staged(b, 4) == 1  # failed before it took a slot
+        assert host.hl_adm_complete_staged(b, 4) == 0
+        assert host.hl_adm_in_flight(b) == 2 and host.hl_adm_in_use(b) == 600
+        assert host.hl_adm_complete(b, 1) == 1 and host.hl_adm_complete(b, 2) == 1
+        assert host.hl_adm_in_use(b) == 0 and host.hl_adm_in_flight(b) == 0
+    finally:
+        host.hl_adm_free(b)
+
+
 # ---- tuning table ---------------------------------------------------------------
 
 def test_tuning_defaults_valid_and_lookup(host):
@@ -358,14 +404,28 @@ def test_load_generator_library_exports_one_entry(lib):
                                   ctypes.c_uint32(0), ctypes.byref(t0), None, None) == sc.EINVAL
 
 
-def test_read_ceiling_library_exports_one_entry(lib):
-    """The read-ceiling kernel is a library of its own, outside the API: one
-    exported entry point, refusing bad arguments before any HIP call."""
+def test_probe_library_exports_and_refuses(lib):
+    """The measurement probes are a library of their own, outside the API:
+    the read ceiling, the VALU ceiling and the clock rates, each refusing bad
+    arguments before any HIP call."""
     if not os.path.exists(libbuild.PROBE_LIB):
         libbuild.build()
     out = subprocess.run(["nm", "-D", "--defined-only", libbuild.PROBE_LIB],
                          capture_output=True, text=True, check=True).stdout
-    assert sorted(set(re.findall(r" T (\w+)", out))) == ["sparkcl_probe_read2"]
+    assert sorted(set(re.findall(r" T (\w+)", out))) == [
+        "sparkcl_probe_clock_rates", "sparkcl_probe_read2", "sparkcl_probe_valu"]
+    pv = ctypes.CDLL(libbuild.PROBE_LIB).sparkcl_probe_valu
+    pv.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                   ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    assert pv(0, 1, 1, 0, 0, None, 64, None) == sc.EINVAL       # no sink
+    assert pv(0, 1, 1, 0, 0, 64, None, None) == sc.EINVAL       # no clock words
+    assert pv(0, 0, 1, 0, 0, 64, 64, None) == sc.EINVAL         # empty grid
+    assert pv(0, 1, 0, 0, 0, 64, 64, None) == sc.EINVAL         # no iterations
+    assert pv(6, 1, 1, 0, 0, 64, 64, None) == sc.EINVAL         # unknown mix
+    assert pv(0, 1, 1, 0, 0, 66, 64, None) == sc.EINVAL         # sink misaligned
+    assert pv(0, 1, 1, 0, 0, 64, 68, None) == sc.EINVAL         # clock words misaligned
+    cr = ctypes.CDLL(libbuild.PROBE_LIB).sparkcl_probe_clock_rates
+    assert cr(0, None, None) == sc.EINVAL
     pr = ctypes.CDLL(libbuild.PROBE_LIB)
     fn = pr.sparkcl_probe_read2
     fn.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
