@@ -704,6 +704,9 @@ def main() -> int:
                          "and print its line: the short program that VALU counters profile")
     ap.add_argument("--wc-only", action="store_true",
                     help="only run WordCount over 1 GiB of text and print its line")
+    ap.add_argument("--uneven-only", action="store_true",
+                    help="only run the 4096-partition uneven batch (batched, graph replay, "
+                         "per-partition launches) and print its line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (3 times): the "
                          "reference kernel that scales the HBM byte counters")
@@ -735,6 +738,13 @@ def main() -> int:
         ctx = sc.Context(device=0, arena_bytes=1 << 30)
         line = {"workload": "WordCount, 1 GiB of Zipf text (vocabulary 10^5)",
                 **bench_wordcount(ctx, sc)}
+        ctx.destroy()
+        print(json.dumps(line), flush=True)
+        return 0
+    if args.uneven_only:
+        ctx = sc.Context(device=0, arena_bytes=1 << 30)
+        line = {"workload": "uneven batch: 4096 log-normal partitions, mixed kernels",
+                **bench_uneven(ctx, sc)}
         ctx.destroy()
         print(json.dumps(line), flush=True)
         return 0

@@ -165,8 +165,15 @@ typedef struct sparkcl_task {
    memory (hipHostMalloc) overlaps, pageable memory works but copies
    synchronously.  Each partition's input bytes must fit one staging slot
    (ETOOBIG beyond 1 GiB).  Results are bit-identical to the same data
-   reduced from device memory in SPARKCL_PER_LAUNCH mode.  Serving takes
-   device inputs only (EINVAL). */
+   reduced from device memory in SPARKCL_PER_LAUNCH mode.
+   Served (sparkcl_submit) host-input tasks must use pinned host memory
+   (EINVAL otherwise): the server charges the task's staging block (its
+   inputs, each at its host address modulo 16, in 256-byte units) and
+   partials against the budget, copies the inputs into the arena on its own
+   copy streams while other tasks run, and hands the task to the executor
+   once the copy is done; its latency includes the transfer.  Its result is
+   bit-identical to the same data served from device memory at the same
+   16-byte alignment.  ETOOBIG if the staging block exceeds the arena. */
 #define SPARKCL_TASK_HOST_INPUT 1u
 
 /* What mapReturnValue hands back for one partition (or the RDD total). */
