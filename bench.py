@@ -311,6 +311,57 @@ def valu_ceiling(sc, pairs: int, reps: int = 3) -> dict:
             "shader_clock_GHz": sclk_ghz, "peak_clock_GHz": peak_khz.value / 1e6}
 
 
+VALU_MIXES = {0: "philox loop", 1: "two philox blocks per iteration", 2: "v_bitop3_b32",
+              3: "v_mad_u64_u32", 4: "v_add_u32", 5: "v_mul_hi_u32",
+              6: "v_bitop3_b32 + v_add_u32", 7: "v_mad_u64_u32 + v_add_u32"}
+
+
+def valu_probe_sweep(sc, target_ms: float = 3.0) -> list:
+    """Every VALU probe mix at 1, 2, 4 and 8 blocks per CU: wave-instructions
+    issued per CU per shader clock (VALU instructions per loop iteration from
+    the probe library's own assembly, in probe_isa.json; the clock from the
+    probe's clock marks)."""
+    import torch
+    lib = probe_lib(sc)
+    fn = lib.sparkcl_probe_valu
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                   ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    rates = lib.sparkcl_probe_clock_rates
+    peak_khz, wall_khz = ctypes.c_uint32(), ctypes.c_uint32()
+    if rates(0, ctypes.byref(peak_khz), ctypes.byref(wall_khz)) != 0:
+        raise RuntimeError("sparkcl_probe_clock_rates failed")
+    with open(os.path.join(os.path.dirname(os.path.abspath(sc.__file__)), "probe_isa.json")) as f:
+        loop_valu = {int(k): v for k, v in json.load(f)["valu_per_iteration"].items()}
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    sink = torch.empty(8 * cus * 256, dtype=torch.int32, device="cuda")
+    clk = torch.zeros(4, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+    out = []
+    for mix, name in VALU_MIXES.items():
+        for per_cu in (1, 2, 4, 8):
+            grid = per_cu * cus
+            waves = grid * 4
+            iters = max(1, int(target_ms * 1e-3 * 2.4e9 * cus / (waves * loop_valu[mix])))
+            ms = []
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                if fn(mix, grid, iters, 0, 0, sink.data_ptr(), clk.data_ptr(), stream.cuda_stream):
+                    raise RuntimeError("sparkcl_probe_valu failed")
+                e1.record(stream)
+                e1.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            c = clk.cpu().tolist()
+            ghz = (c[2] - c[0]) / (c[3] - c[1]) * wall_khz.value / 1e6
+            t = sorted(ms)[1] / 1e3
+            winstr = loop_valu[mix] * iters * waves
+            out.append({"mix": mix, "instructions": name, "blocks_per_cu": per_cu, "ms": t * 1e3,
+                        "shader_clock_GHz": ghz,
+                        "wave_instr_per_cu_per_clock": winstr / cus / (t * ghz * 1e9)})
+    return out
+
+
 def alu_issue_peak(isa: dict) -> dict:
     """The Philox loop's VALU issue bound from the chip's unit counts and
     clock.  Each of a CU's 4 SIMDs issues one wave64 VALU instruction per 4
@@ -486,12 +537,16 @@ def bench_wordcount(ctx, sc, reps=5) -> dict:
     cap = 1 << 20
     keys = torch.empty(cap, dtype=torch.int64, device="cuda")
     counts = torch.empty(cap, dtype=torch.int64, device="cuda")
-    ctx.wordcount(text, cap, keys, counts)           # warm-up
+    # a context of its own: its arena holds the counting table and the
+    # spill regions (about 0.7 bytes per text byte)
+    wctx = sc.Context(device=0, arena_bytes=2 << 30)
+    wctx.wordcount(text, cap, keys, counts)          # warm-up
     times = []
     for _ in range(reps):
         t0 = time.perf_counter()
-        _, _, nd, nw = ctx.wordcount(text, cap, keys, counts)
+        _, _, nd, nw = wctx.wordcount(text, cap, keys, counts)
         times.append(time.perf_counter() - t0)
+    wctx.destroy()
     sec = sorted(times)[len(times) // 2]
     t0 = time.perf_counter()
     ok, oc, on = oracle.wordcount(base)
@@ -704,6 +759,10 @@ def main() -> int:
                          "and print its line: the short program that VALU counters profile")
     ap.add_argument("--wc-only", action="store_true",
                     help="only run WordCount over 1 GiB of text and print its line")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="only run the VALU probe kernels (the Philox loop and single-instruction "
+                         "loops) at 1, 2, 4 and 8 blocks per CU and print their issue rates: the "
+                         "short program that the dual-issue counters profile")
     ap.add_argument("--uneven-only", action="store_true",
                     help="only run the 4096-partition uneven batch (batched, graph replay, "
                          "per-partition launches) and print its line")
@@ -740,6 +799,9 @@ def main() -> int:
                 **bench_wordcount(ctx, sc)}
         ctx.destroy()
         print(json.dumps(line), flush=True)
+        return 0
+    if args.valu_probe:
+        print(json.dumps({"valu_probe": valu_probe_sweep(sc)}), flush=True)
         return 0
     if args.uneven_only:
         ctx = sc.Context(device=0, arena_bytes=1 << 30)

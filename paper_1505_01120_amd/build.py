@@ -8,8 +8,12 @@ Produces, next to this file:
   libsparkcl_loadgen.so -- an open-loop serving load generator over the public
                          C ABI (submit / poll at scheduled arrival times), for
                          the serving benchmark;
-  libsparkcl_probe.so -- a plain read-only streaming kernel, the bench's
-                         measured HBM read ceiling;
+  libsparkcl_probe.so -- the bench's measurement probes: a plain read-only
+                         streaming kernel (the measured HBM read ceiling) and
+                         register-only VALU loops (the Monte-Carlo loop's
+                         measured issue ceiling);
+  probe_isa.json      -- VALU instructions per loop iteration of each VALU
+                         probe, read from the probe library's own assembly;
   isa.json            -- resource figures of the kernels' own gfx950 code
                          (registers, private segment, VALU instructions per
                          Philox block), read from the device assembly of this
@@ -39,6 +43,7 @@ LIB = os.path.join(HERE, "libsparkcl.so")
 HOST_LIB = os.path.join(HERE, "libsparkcl_host.so")
 LOADGEN_LIB = os.path.join(HERE, "libsparkcl_loadgen.so")
 PROBE_LIB = os.path.join(HERE, "libsparkcl_probe.so")
+PROBE_ISA_JSON = os.path.join(HERE, "probe_isa.json")
 ISA_JSON = os.path.join(HERE, "isa.json")
 KERNELS = ("k_task", "k_batch", "k_serve", "k_map", "k_chain", "k_tree", "k_tree_wide", "k_wordcount",
            "k_wc_compact")
@@ -113,6 +118,30 @@ def isa_report(asm: str) -> dict:
     return out
 
 
+def probe_isa_report(asm: str) -> dict:
+    """VALU instructions per loop iteration of each k_valu<mix> probe kernel:
+    the v_ instructions of the kernel's loop block (the basic block that
+    branches back to its own label)."""
+    out = {}
+    for m in re.finditer(r"^(_ZN12_GLOBAL__N_16k_valuILj(\d+)EEEv\S*):(.*?)\.end_amdhsa_kernel",
+                         asm, re.S | re.M):
+        mix, body = m.group(2), m.group(3)
+        label, cur = None, []
+        for line in body.splitlines():
+            t = line.strip()
+            lm = re.match(r"^(\.LBB\d+_\d+):", t)
+            if lm:
+                label, cur = lm.group(1), []
+                continue
+            if not t or t.startswith(";") or t.startswith("."):
+                continue
+            op = t.split()[0]
+            cur.append(op)
+            if op.startswith("s_cbranch") and label and t.split()[-1] == label:
+                out[mix] = sum(1 for o in cur if o.startswith("v_"))
+    return {"valu_per_iteration": out}
+
+
 def build(verbose: bool = False) -> str:
     """Compile every source and link both libraries (always rebuilds)."""
     out_dir = os.path.join(HERE, "_build")
@@ -132,11 +161,20 @@ def build(verbose: bool = False) -> str:
         return asm
 
     def probe_lib() -> None:
-        # the read-ceiling kernel: a library of its own, outside the API
+        # the measurement probes: a library of their own, outside the API,
+        # and the VALU count of each VALU probe's loop from its assembly
         tmp = PROBE_LIB + ".tmp"
         _run([cc, *COMMON, *HIP_FLAGS, "-shared", "-x", "hip", os.path.join(CSRC, "probe.hip"),
               "-o", tmp])
         os.replace(tmp, PROBE_LIB)
+        pasm = os.path.join(out_dir, "probe.s")
+        _run([cc, *COMMON, *HIP_FLAGS, "-x", "hip", "--cuda-device-only", "-S",
+              os.path.join(CSRC, "probe.hip"), "-o", pasm])
+        with open(pasm) as f:
+            rep = probe_isa_report(f.read())
+        with open(PROBE_ISA_JSON + ".tmp", "w") as f:
+            json.dump(rep, f, indent=1)
+        os.replace(PROBE_ISA_JSON + ".tmp", PROBE_ISA_JSON)
 
     with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
         asm_job = ex.submit(device_asm)

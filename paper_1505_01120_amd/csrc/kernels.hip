@@ -1202,10 +1202,16 @@ __global__ __launch_bounds__(kBlock) void k_zero(uint32_t *p, uint64_t words)
 // the 64-bit FNV prime).  Blocks stage 4 KiB chunks of text (plus a 256-byte
 // look-ahead) in LDS; the thread owning a word's first byte hashes it and
 // counts it in the block's LDS hash table (the paper's "local data"), which
-// absorbs the frequent words of a skewed vocabulary; words that find no LDS
-// slot within a few probes, and the LDS table at the end, go to one global
-// open-addressing table with device-scope atomics.  Counts are integers, so
-// the result does not depend on which block counts which word.
+// absorbs the frequent words of a skewed vocabulary.  Words that find no
+// LDS slot within a few probes are appended to the block's spill region of
+// their key's partition (a plain store at an LDS-counted position); a merge
+// kernel then counts each partition's spilled keys in LDS and adds each
+// distinct key once to the global open-addressing table.  (Adding every such word to the global table
+// with a device-scope atomic, as a first version did, cost more than the
+// scan: those atomics are carried out at the memory side, one round trip
+// each.)  The LDS tables themselves, and the words that overflow a spill
+// region, go to the table with atomics.  Counts are integers, so the result
+// does not depend on which block counts which word.
 constexpr uint32_t kWcChunk = 4096;   // bytes per chunk: 16 per thread
 constexpr uint32_t kWcLook = 256;     // look-ahead bytes staged after a chunk
 constexpr uint32_t kWcSlots = 1024;   // LDS hash slots per block
@@ -1263,8 +1269,25 @@ __device__ void wc_global_add(const WcArgs &a, uint64_t h, uint64_t c)
 // of the text it scans, and a block scans either one 4 KiB chunk or at most
 // 1/256 of the text (a grid of at least one block per CU), which is limited
 // to 2^40 bytes.
-__device__ __forceinline__ void wc_local_add(uint64_t *sk, uint32_t *sc, const WcArgs &a,
-                                             uint64_t h)
+// A word that found no LDS slot: appended to this block's spill region of
+// its partition, or, when the region is full (or there are none, or its key
+// is 0), added to the table directly.  scnt: the block's per-partition
+// append counters in LDS.
+__device__ __forceinline__ void wc_spill(uint32_t *scnt, const WcArgs &a, uint64_t h)
+{
+    if (a.spill_cap != 0 && h != 0) {
+        const uint32_t p = (uint32_t)(h >> (64 - kWcPartBits));
+        const uint32_t pos = atomicAdd(&scnt[p], 1u);
+        if (pos < a.spill_cap) {
+            a.spill[((uint64_t)blockIdx.x << kWcPartBits | p) * a.spill_cap + pos] = h;
+            return;
+        }
+    }
+    wc_global_add(a, h, 1);
+}
+
+__device__ __forceinline__ void wc_local_add(uint64_t *sk, uint32_t *sc, uint32_t *scnt,
+                                             const WcArgs &a, uint64_t h)
 {
     if (h != 0) {
         uint32_t s = (uint32_t)h & (kWcSlots - 1);
@@ -1285,7 +1308,7 @@ __device__ __forceinline__ void wc_local_add(uint64_t *sk, uint32_t *sc, const W
             s = (s + 1) & (kWcSlots - 1);
         }
     }
-    wc_global_add(a, h, 1);
+    wc_spill(scnt, a, h);
 }
 
 // 16 bytes of text at byte `pos` (a thread's span), bytes at or past n read
@@ -1305,8 +1328,6 @@ __device__ __forceinline__ uint4 wc_span(const uint8_t *text, uint64_t n, uint64
     return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-// Byte k (0..15) of a span held in registers: a 64-bit select and a shift
-// (no indexed register array, which the compiler would put in scratch).
 // Bit i of the result is set when byte i of w (little-endian) is whitespace
 // (wc_space), for the four bytes at once: with each byte's top bit forced to
 // 1, the per-byte subtractions below cannot borrow across bytes, so the top
@@ -1323,12 +1344,6 @@ __device__ __forceinline__ uint32_t space_bits4(uint32_t w)
     return ((ws >> 7) & 1u) | ((ws >> 14) & 2u) | ((ws >> 21) & 4u) | ((ws >> 28) & 8u);
 }
 
-__device__ __forceinline__ uint32_t span_byte(uint64_t lo, uint64_t hi, uint32_t k)
-{
-    const uint64_t half = k < 8 ? lo : hi;
-    return (uint32_t)(half >> (8 * (k & 7))) & 0xFFu;
-}
-
 // Block barrier for LDS traffic only: waits for this wave's LDS operations,
 // not for its global loads in flight (the next chunk's prefetch).
 __device__ __forceinline__ void lds_barrier()
@@ -1339,25 +1354,39 @@ __device__ __forceinline__ void lds_barrier()
     __asm__ __volatile__("" ::: "memory");
 }
 
+// The scan.  Per staged chunk: each thread marks the whitespace bytes of its
+// 16-byte span in a bitmap (one 16-bit word per span, chunk and look-ahead)
+// and the word starts in its span; a wave prefix sum places the starts in a
+// per-wave list; then each lane takes whole words from the list, reads the
+// word's length off the bitmap, hashes its bytes from the staged chunk and
+// counts the key in the block's LDS table.  A word that runs past the
+// look-ahead continues from the text in global memory, one byte at a time.
 __global__ __launch_bounds__(kBlock) void k_wordcount(WcArgs a)
 {
+    constexpr uint32_t kLookSpans = kWcLook / 16;
+    constexpr uint32_t kSpans = kBlock + kLookSpans;
     __shared__ uint64_t sk[kWcSlots];
     __shared__ uint32_t sc[kWcSlots];
-    __shared__ uint4 st4[(kWcChunk + kWcLook) / 16];
-    __shared__ uint64_t emit[kWaves][64 * 8]; // a 16-byte span holds <= 8 word starts
+    __shared__ uint4 st4[kSpans + 1];               // (+ 16 bytes read past the end)
+    __shared__ uint32_t sepm[kSpans];               // whitespace bits of each span
+    __shared__ uint16_t starts16[kWaves][64 * 8];   // a 16-byte span holds <= 8 word starts
+    __shared__ uint32_t scnt[1u << kWcPartBits];    // spill appends per partition
     __shared__ uint32_t sh_prev;
     const uint8_t *st = reinterpret_cast<const uint8_t *>(st4);
     for (uint32_t i = threadIdx.x; i < kWcSlots; i += kBlock) {
         sk[i] = 0;
         sc[i] = 0;
     }
+    for (uint32_t i = threadIdx.x; i < (1u << kWcPartBits); i += kBlock)
+        scnt[i] = 0;
+    if (threadIdx.x == 0)
+        st4[kSpans] = make_uint4(0x20202020u, 0x20202020u, 0x20202020u, 0x20202020u);
     const uint8_t *text = a.text;
     const uint64_t n = a.n;
     const bool vec = ((uintptr_t)text & 15u) == 0;
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-    uint64_t *buf = emit[wave];
+    uint16_t *wl = starts16[wave];
     const uint64_t nchunks = (n + kWcChunk - 1) / kWcChunk;
-    constexpr uint32_t kLookSpans = kWcLook / 16;
     constexpr uint64_t kBasis = 14695981039346656037ull;
     // this thread's span of the first chunk, its look-ahead span and (thread
     // 0) the byte before the chunk, loaded ahead of use
@@ -1370,11 +1399,17 @@ __global__ __launch_bounds__(kBlock) void k_wordcount(WcArgs a)
     uint64_t words = 0;
     for (; c < nchunks; c += gridDim.x) {
         const uint64_t c0 = c * kWcChunk;
-        lds_barrier(); // the previous chunk's scan is done with the staging
+        lds_barrier(); // the previous chunk's words are done with the staging
         const uint4 mine = cur;
         st4[tid] = mine;
-        if (tid < kLookSpans)
+        const uint32_t sep = space_bits4(mine.x) | (space_bits4(mine.y) << 4) |
+                             (space_bits4(mine.z) << 8) | (space_bits4(mine.w) << 12);
+        sepm[tid] = sep;
+        if (tid < kLookSpans) {
             st4[kBlock + tid] = look;
+            sepm[kBlock + tid] = space_bits4(look.x) | (space_bits4(look.y) << 4) |
+                                 (space_bits4(look.z) << 8) | (space_bits4(look.w) << 12);
+        }
         if (tid == 0)
             sh_prev = prevb;
         const uint64_t cn = c + gridDim.x;
@@ -1387,15 +1422,7 @@ __global__ __launch_bounds__(kBlock) void k_wordcount(WcArgs a)
         }
         lds_barrier(); // staged
         const uint32_t prev = tid ? st[16 * tid - 1] : sh_prev;
-        const uint4 nxt = st4[tid + 1]; // the following span (or look-ahead)
-        const uint64_t lo = ((uint64_t)mine.y << 32) | mine.x;
-        const uint64_t hi = ((uint64_t)mine.w << 32) | mine.z;
-        const uint64_t lo2 = ((uint64_t)nxt.y << 32) | nxt.x;
-        // whitespace bits of the 16 bytes and of the first 8 of the next span
-        const uint32_t sep = space_bits4(mine.x) | (space_bits4(mine.y) << 4) |
-                             (space_bits4(mine.z) << 8) | (space_bits4(mine.w) << 12);
-        const uint32_t sep24 = sep | (space_bits4(nxt.x) << 16) | (space_bits4(nxt.y) << 20);
-        const uint32_t starts = ~sep & ((sep << 1) | (uint32_t)wc_space(prev)) & 0xFFFFu;
+        uint32_t starts = ~sep & ((sep << 1) | (uint32_t)wc_space(prev)) & 0xFFFFu;
         const uint32_t mycount = __builtin_popcount(starts);
         // exclusive prefix sum of the word counts over the wave's lanes
         uint32_t incl = mycount;
@@ -1407,61 +1434,137 @@ __global__ __launch_bounds__(kBlock) void k_wordcount(WcArgs a)
         }
         const uint32_t total = __shfl(incl, 63);
         uint32_t slot = incl - mycount;
-        // All lanes walk their 16 bytes and the first 8 of the next span in
-        // step: a word that starts in this span is hashed byte by byte and
-        // written to the wave's buffer when its separator comes.
-        // The steps are branch-free selects on 0/1 integers, except the
-        // store of a finished key.
-        uint64_t h = kBasis;
-        uint32_t inw = 0;
-#pragma unroll
-        for (uint32_t k = 0; k < 24; ++k) {
-            const uint32_t byte = k < 16 ? span_byte(lo, hi, k) : span_byte(lo2, 0, k - 16);
-            const uint32_t sp = (sep24 >> k) & 1u;
-            if (k < 16) {
-                const uint32_t st = (starts >> k) & 1u;
-                h = st ? kBasis : h;
-                inw |= st;
-            }
-            const uint64_t hn = fnv_step(h, byte);
-            const uint32_t emit = inw & sp;
-            h = (inw & (sp ^ 1u)) ? hn : h;
-            if (emit)
-                buf[slot] = h;
-            slot += emit;
-            inw &= sp ^ 1u;
-        }
-        if (inw) {
-            // a word longer than what is left of the 24 bytes: the rest comes
-            // from the staging (then the text), one byte at a time
-            for (uint64_t j = 16 * tid + 24;; ++j) {
-                uint32_t byte;
-                if (j < kWcChunk + kWcLook)
-                    byte = st[j];
-                else if (c0 + j < n)
-                    byte = text[c0 + j];
-                else
-                    break;
-                if (wc_space(byte))
-                    break;
-                h = fnv_step(h, byte);
-            }
-            buf[slot++] = h;
+        while (starts) {
+            const uint32_t b = __builtin_ctz(starts);
+            wl[slot++] = (uint16_t)(16 * tid + b);
+            starts &= starts - 1;
         }
         words += mycount;
-        // the wave's words, 64 at a time, into the block's LDS table
-        for (uint32_t i = lane; i < total; i += 64)
-            wc_local_add(sk, sc, a, buf[i]);
+        // the wave's words: one per lane at a time
+        for (uint32_t i = lane; i < total; i += 64) {
+            const uint32_t s0 = wl[i];
+            // length: the distance to the next whitespace bit at or after s0
+            uint32_t span = s0 >> 4;
+            uint32_t m = sepm[span] >> (s0 & 15u);
+            uint32_t len = 0;
+            bool ends = m != 0;
+            if (ends) {
+                len = __builtin_ctz(m);
+            } else {
+                len = 16u - (s0 & 15u);
+                for (++span; span < kSpans; ++span) {
+                    m = sepm[span];
+                    if (m) {
+                        len += __builtin_ctz(m);
+                        ends = true;
+                        break;
+                    }
+                    len += 16u;
+                }
+            }
+            // the staged bytes of the word, four at a time
+            uint64_t h = kBasis;
+            for (uint32_t k = 0; k < len; k += 4) {
+                const uint32_t b0 = st[s0 + k], b1 = st[s0 + k + 1];
+                const uint32_t b2 = st[s0 + k + 2], b3 = st[s0 + k + 3];
+                h = fnv_step(h, b0);
+                if (k + 1 < len)
+                    h = fnv_step(h, b1);
+                if (k + 2 < len)
+                    h = fnv_step(h, b2);
+                if (k + 3 < len)
+                    h = fnv_step(h, b3);
+            }
+            if (!ends) {
+                // past the look-ahead: the rest from the text
+                for (uint64_t j = c0 + s0 + len; j < n; ++j) {
+                    const uint32_t byte = text[j];
+                    if (wc_space(byte))
+                        break;
+                    h = fnv_step(h, byte);
+                }
+            }
+            wc_local_add(sk, sc, scnt, a, h);
+        }
     }
     __syncthreads();
     for (uint32_t i = tid; i < kWcSlots; i += kBlock)
         if (sk[i])
             wc_global_add(a, sk[i], sc[i]);
+    if (a.spill_cap != 0)
+        for (uint32_t p = tid; p < (1u << kWcPartBits); p += kBlock)
+            a.spill_cnt[((uint64_t)blockIdx.x << kWcPartBits) | p] = min(scnt[p], a.spill_cap);
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1)
         words += __shfl_xor(words, o);
     if (lane == 0 && words)
         atomicAdd((unsigned long long *)&a.ctl[0], (unsigned long long)words);
+}
+
+// Merge of the spill regions: block b counts partition b / per_part's keys
+// from the regions of the scan blocks congruent to b modulo per_part in an
+// LDS table, then adds each distinct key it holds to the global table once.
+// Each thread walks one region at a time (a few hundred bytes), sixteen
+// keys in flight, so the block has many regions' loads outstanding at once.
+// Keys that find no LDS slot go to the table directly.
+constexpr uint32_t kWcMergeSlots = 2048;
+constexpr uint32_t kWcMergeProbes = 8;
+
+__device__ __forceinline__ void wc_merge_add(uint64_t *mk, uint32_t *mc, const WcArgs &a,
+                                             uint64_t h)
+{
+    uint32_t s = (uint32_t)h & (kWcMergeSlots - 1);
+    for (uint32_t q = 0; q < kWcMergeProbes; ++q) {
+        const uint64_t key = mk[s];
+        if (key == h) {
+            atomicAdd(&mc[s], 1u);
+            return;
+        }
+        if (key == 0) {
+            const uint64_t old =
+                atomicCAS((unsigned long long *)&mk[s], 0ull, (unsigned long long)h);
+            if (old == 0 || old == h) {
+                atomicAdd(&mc[s], 1u);
+                return;
+            }
+        }
+        s = (s + 1) & (kWcMergeSlots - 1);
+    }
+    wc_global_add(a, h, 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_wc_merge(WcArgs a, uint32_t scan_grid,
+                                                    uint32_t per_part)
+{
+    __shared__ uint64_t mk[kWcMergeSlots];
+    __shared__ uint32_t mc[kWcMergeSlots];
+    for (uint32_t i = threadIdx.x; i < kWcMergeSlots; i += kBlock) {
+        mk[i] = 0;
+        mc[i] = 0;
+    }
+    __syncthreads();
+    const uint32_t p = blockIdx.x / per_part, k = blockIdx.x % per_part;
+    constexpr uint32_t kInFlight = 16;
+    for (uint64_t b = k + (uint64_t)per_part * threadIdx.x; b < scan_grid;
+         b += (uint64_t)per_part * kBlock) {
+        const uint64_t r = (b << kWcPartBits) | p;
+        const uint32_t cnt = a.spill_cnt[r];
+        const uint64_t *src = a.spill + r * a.spill_cap;
+        for (uint32_t i = 0; i < cnt; i += kInFlight) {
+            uint64_t h[kInFlight];
+#pragma unroll
+            for (uint32_t u = 0; u < kInFlight; ++u)
+                h[u] = i + u < cnt ? src[i + u] : 0;
+#pragma unroll
+            for (uint32_t u = 0; u < kInFlight; ++u)
+                if (h[u]) // spilled keys are never 0
+                    wc_merge_add(mk, mc, a, h[u]);
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kWcMergeSlots; i += kBlock)
+        if (mk[i])
+            wc_global_add(a, mk[i], mc[i]);
 }
 
 // Compaction of the global table into the caller's key/count arrays
@@ -1789,9 +1892,20 @@ int launch_map(const TaskDev *dtask, uint64_t n, uint32_t variant, uint32_t grid
 
 int launch_wordcount(const WcArgs &a, uint32_t grid, void *stream)
 {
-    if (grid == 0 || !a.keys || !a.counts || !a.ctl || ((a.mask + 1) & a.mask))
+    if (grid == 0 || !a.keys || !a.counts || !a.ctl || ((a.mask + 1) & a.mask) ||
+        (a.spill_cap != 0 && (!a.spill || !a.spill_cnt)))
         return SPARKCL_EINVAL;
     hipLaunchKernelGGL(k_wordcount, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, a);
+    return hip_status(hipGetLastError());
+}
+
+int launch_wc_merge(const WcArgs &a, uint32_t scan_grid, uint32_t per_part, void *stream)
+{
+    if (a.spill_cap == 0 || scan_grid == 0 || per_part == 0)
+        return SPARKCL_EINVAL;
+    const uint32_t grid = per_part << kWcPartBits;
+    hipLaunchKernelGGL(k_wc_merge, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, a,
+                       scan_grid, per_part);
     return hip_status(hipGetLastError());
 }
 

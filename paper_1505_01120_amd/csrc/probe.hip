@@ -76,7 +76,9 @@ enum ValuMix : uint32_t {
     MIX_MAD64 = 3,   // v_mad_u64_u32 32x32+64 -> 64, 8 independent chains
     MIX_ADD = 4,     // v_add_u32, 8 independent chains
     MIX_MULHI = 5,   // v_mul_hi_u32, 8 independent chains
-    MIX_COUNT = 6
+    MIX_BITOP3_ADD = 6, // v_bitop3_b32 and v_add_u32 in turn, 8 chains of each
+    MIX_MAD64_ADD = 7,  // v_mad_u64_u32 and v_add_u32 in turn, 8 chains of each
+    MIX_COUNT = 8
 };
 
 __device__ __forceinline__ void clock_mark(uint64_t *clk, int at)
@@ -149,6 +151,13 @@ __global__ __launch_bounds__(kThreads) void k_valu(uint64_t seed, uint32_t pid, 
                         a[j] = b[j] + b[(j + 1) & 7];
                     else if constexpr (MIX == MIX_MULHI)
                         a[j] = __umulhi(b[j], b[(j + 1) & 7]);
+                    else if constexpr (MIX == MIX_BITOP3_ADD) {
+                        a[j] = sparkcl::xor3(b[j], b[(j + 1) & 7], s0);
+                        w[j] = (uint32_t)v[j] + (uint32_t)v[(j + 1) & 7];
+                    } else if constexpr (MIX == MIX_MAD64_ADD) {
+                        w[j] = (uint64_t)(uint32_t)v[(j + 1) & 7] * s0 + v[j];
+                        a[j] = b[j] + b[(j + 1) & 7];
+                    }
                 }
             }
         }
@@ -183,7 +192,8 @@ sparkcl_probe_valu(uint32_t mix, uint32_t grid, uint32_t iters, uint64_t seed, u
                    uint32_t *sink, uint64_t *clk, void *stream)
 {
     // One launch of the VALU probe `mix` (0 Philox loop, 1 two Philox blocks
-    // per iteration, 2 xor3, 3 mad_u64_u32, 4 add_u32, 5 mul_hi_u32) with
+    // per iteration, 2 xor3, 3 mad_u64_u32, 4 add_u32, 5 mul_hi_u32, 6 xor3
+    // and add_u32, 7 mad_u64_u32 and add_u32) with
     // `grid` blocks of 256 threads, `iters` iterations per thread, on
     // `stream`.  sink: grid * 256 words (device); clk: 4 words (device),
     // receiving block 0's (shader clock, wall clock) at its start and its end.
@@ -212,8 +222,14 @@ sparkcl_probe_valu(uint32_t mix, uint32_t grid, uint32_t iters, uint64_t seed, u
     case MIX_ADD:
         hipLaunchKernelGGL(k_valu<MIX_ADD>, dim3(grid), dim3(kThreads), 0, s, seed, pid, iters, sink, clk);
         break;
-    default:
+    case MIX_MULHI:
         hipLaunchKernelGGL(k_valu<MIX_MULHI>, dim3(grid), dim3(kThreads), 0, s, seed, pid, iters, sink, clk);
+        break;
+    case MIX_BITOP3_ADD:
+        hipLaunchKernelGGL(k_valu<MIX_BITOP3_ADD>, dim3(grid), dim3(kThreads), 0, s, seed, pid, iters, sink, clk);
+        break;
+    default:
+        hipLaunchKernelGGL(k_valu<MIX_MAD64_ADD>, dim3(grid), dim3(kThreads), 0, s, seed, pid, iters, sink, clk);
         break;
     }
     return hipGetLastError() == hipSuccess ? SPARKCL_OK : SPARKCL_EHIP;

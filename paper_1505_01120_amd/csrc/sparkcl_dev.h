@@ -172,15 +172,30 @@ int launch_tree(const TreeArgs &a, uint32_t combiner, bool vec4, void *stream);
 // keys/counts of mask + 1 slots (a power of two, cleared beforehand); ctl[0]
 // words, ctl[1] count of the key 0, ctl[2] table-full flag, ctl[3] distinct
 // keys written by the compaction.
+// Words that miss a block's LDS table are appended to the block's spill
+// region of their key's partition (the top kWcPartBits bits of the key),
+// spill_cap keys per region, counts in spill_cnt, instead of being added to
+// the global table one atomic at a time; the merge kernel then counts each
+// partition's spilled keys in LDS and adds each distinct key to the table
+// once per merge block.  spill_cap 0: no spill regions (every miss goes to
+// the table directly).
+constexpr uint32_t kWcPartBits = 8;
 struct WcArgs {
     const uint8_t *text;
     uint64_t n;
     uint64_t *keys;
     uint64_t *counts;
-    uint64_t mask;
-    uint64_t *ctl;
+    uint64_t mask;       // table slots - 1 (a power of two minus one)
+    uint64_t *ctl;       // words, zero-key count, table full, distinct keys
+    uint32_t spill_cap;  // keys per spill region (0: no spill regions)
+    uint32_t pad;
+    uint64_t *spill;     // [scan block][partition][spill_cap]
+    uint32_t *spill_cnt; // [scan block][partition] keys written
 };
 int launch_wordcount(const WcArgs &a, uint32_t grid, void *stream);
+// Merge of the spill regions of `scan_grid` scan blocks into the table, with
+// `per_part` blocks per partition.
+int launch_wc_merge(const WcArgs &a, uint32_t scan_grid, uint32_t per_part, void *stream);
 int launch_wc_compact(const WcArgs &a, uint64_t *keys, uint64_t *counts, uint64_t cap,
                       uint32_t grid, void *stream);
 int wordcount_blocks_per_cu(int *out);

@@ -1,6 +1,8 @@
 // WordCount (sec. 3.2.3): words of a device-resident byte stream counted under
-// their 64-bit FNV-1a key, in per-block LDS tables that spill to one global
-// open-addressing table, then compacted into the caller's arrays.
+// their 64-bit FNV-1a key, in per-block LDS tables whose misses go to
+// per-partition spill regions; a merge pass counts each partition's spilled
+// keys and adds them to one global open-addressing table, which is then
+// compacted into the caller's arrays.
 #include <algorithm>
 #include <cstring>
 #include <string>
@@ -35,8 +37,31 @@ int sparkcl_wordcount(sparkcl_ctx *ctx, const uint8_t *text, uint64_t nbytes, ui
     uint64_t slots = 1024;
     while (slots < 2 * need)
         slots *= 2;
-    const uint64_t bytes = slots * 16 + 64;
-    const uint64_t off = ctx->arena.alloc(bytes);
+    if (!ctx->occ_wordcount) {
+        int occ = 0;
+        if (wordcount_blocks_per_cu(&occ) != SPARKCL_OK || occ < 1)
+            occ = 1;
+        ctx->occ_wordcount = occ;
+    }
+    const uint64_t nchunks = (nbytes + 4095) / 4096;
+    const uint32_t grid =
+        (uint32_t)std::min<uint64_t>(nchunks, (uint64_t)ctx->occ_wordcount * ctx->cus);
+    const uint64_t table_bytes = slots * 16 + 64;
+    // Spill regions: room for one spilled word per 16 bytes of each scan
+    // block's share of the text (a quarter more for the spread between
+    // partitions); words past a full region go to the table directly.  Left
+    // out when the arena cannot hold them.
+    const uint64_t parts = 1ull << kWcPartBits;
+    uint64_t cap = nbytes / ((uint64_t)grid * parts * 16);
+    cap = cap + cap / 4 + 16;
+    const uint64_t spill_bytes = (uint64_t)grid * parts * (cap * 8 + 4);
+    uint64_t bytes = table_bytes + spill_bytes;
+    uint64_t off = ctx->arena.alloc(bytes);
+    if (off == Arena::kFail) {
+        cap = 0;
+        bytes = table_bytes;
+        off = ctx->arena.alloc(bytes);
+    }
     if (off == Arena::kFail)
         return fail(SPARKCL_ENOMEM, "word-count table of " + std::to_string(bytes) +
                                         " bytes does not fit the arena");
@@ -48,20 +73,24 @@ int sparkcl_wordcount(sparkcl_ctx *ctx, const uint8_t *text, uint64_t nbytes, ui
     a.counts = reinterpret_cast<uint64_t *>(base + slots * 8);
     a.ctl = reinterpret_cast<uint64_t *>(base + slots * 16);
     a.mask = slots - 1;
-    if (!ctx->occ_wordcount) {
-        int occ = 0;
-        if (wordcount_blocks_per_cu(&occ) != SPARKCL_OK || occ < 1)
-            occ = 1;
-        ctx->occ_wordcount = occ;
+    a.spill_cap = (uint32_t)cap;
+    if (cap) {
+        a.spill = reinterpret_cast<uint64_t *>(base + table_bytes);
+        a.spill_cnt = reinterpret_cast<uint32_t *>(base + table_bytes +
+                                                   (uint64_t)grid * parts * cap * 8);
     }
-    const uint64_t nchunks = (nbytes + 4095) / 4096;
-    const uint32_t grid =
-        (uint32_t)std::min<uint64_t>(nchunks, (uint64_t)ctx->occ_wordcount * ctx->cus);
+    // merge: eight blocks per partition (each merge block's loads are a
+    // few hundred bytes per region, so it takes many blocks to keep enough
+    // of them in flight), at least one per CU in all
+    const uint32_t per_part = (uint32_t)std::max<uint64_t>(8, (uint64_t)ctx->cus / parts);
     const uint32_t cgrid =
         (uint32_t)std::min<uint64_t>((slots + kBlock - 1) / kBlock, 4ull * ctx->cus);
+    // (only the table and the counters need clearing: every spill slot read
+    // by the merge was written by the scan)
     if ((rc = ensure_pinned(ctx, 1)) == SPARKCL_OK &&
-        (rc = launch_zero(base, bytes, s)) == SPARKCL_OK &&
+        (rc = launch_zero(base, table_bytes, s)) == SPARKCL_OK &&
         (rc = launch_wordcount(a, grid, s)) == SPARKCL_OK &&
+        (!cap || (rc = launch_wc_merge(a, grid, per_part, s)) == SPARKCL_OK) &&
         (rc = launch_wc_compact(a, keys, counts, capacity, cgrid, s)) == SPARKCL_OK) {
         hipError_t e = hipMemcpyAsync(ctx->pinned, a.ctl, 32, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess)

@@ -149,3 +149,39 @@ def test_zero_key_word_repeated_in_corpus(ctx):
         put_zero_word(base, int(pos) + 1)
     check(ctx, bytes(base))
     check(ctx, (ZERO_KEY_WORD + b" ") * 10_000)
+
+
+def _one_partition_words(count: int, length: int = 8, seed: int = 5) -> np.ndarray:
+    """`count` distinct lowercase words of `length` letters whose 64-bit FNV-1a
+    keys all have a top byte of 0 (the oracle's hash, computed here with
+    numpy's wrapping uint64 arithmetic and checked against the oracle), as
+    rows of a uint8 array."""
+    rng = np.random.default_rng(seed)
+    out = []
+    with np.errstate(over="ignore"):
+        while sum(len(o) for o in out) < count:
+            w = rng.integers(ord("a"), ord("z") + 1, (1 << 20, length), dtype=np.uint8)
+            h = np.full(w.shape[0], 14695981039346656037, dtype=np.uint64)
+            for j in range(length):
+                h = (h ^ w[:, j].astype(np.uint64)) * np.uint64(1099511628211)
+            out.append(w[(h >> np.uint64(56)) == 0])
+    w = np.unique(np.concatenate(out), axis=0)[:count]
+    ok, _, _ = oracle.wordcount(np.concatenate([np.append(r, 32) for r in w[:4]]).astype(np.uint8))
+    assert np.all((ok >> np.uint64(56)) == 0)
+    return w
+
+
+def test_spill_regions_of_one_partition_overflow(ctx):
+    # 1500 distinct words whose keys share their top byte, so every word that
+    # misses a block's LDS table (1024 slots; each block scans 16 chunks)
+    # spills into the same partition's region, which overflows: the excess
+    # goes to the table directly, the rest through the merge.
+    w = _one_partition_words(1500)
+    rng = np.random.default_rng(11)
+    line = np.concatenate([np.append(w[i], 32) for i in rng.integers(0, len(w), 1 << 16)])
+    reps = (64 << 20) // line.size + 1
+    text = np.tile(line.astype(np.uint8), reps)[:64 << 20]
+    gk, gc, gn = gpu_count(ctx, text, capacity=1 << 14)
+    ok, oc, on = oracle.wordcount(text)
+    assert gn == on, (gn, on)
+    assert np.array_equal(gk, ok) and np.array_equal(gc, oc)

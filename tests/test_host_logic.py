@@ -421,7 +421,7 @@ def test_probe_library_exports_and_refuses(lib):
     assert pv(0, 1, 1, 0, 0, 64, None, None) == sc.EINVAL       # no clock words
     assert pv(0, 0, 1, 0, 0, 64, 64, None) == sc.EINVAL         # empty grid
     assert pv(0, 1, 0, 0, 0, 64, 64, None) == sc.EINVAL         # no iterations
-    assert pv(6, 1, 1, 0, 0, 64, 64, None) == sc.EINVAL         # unknown mix
+    assert pv(8, 1, 1, 0, 0, 64, 64, None) == sc.EINVAL         # unknown mix
     assert pv(0, 1, 1, 0, 0, 66, 64, None) == sc.EINVAL         # sink misaligned
     assert pv(0, 1, 1, 0, 0, 64, 68, None) == sc.EINVAL         # clock words misaligned
     cr = ctypes.CDLL(libbuild.PROBE_LIB).sparkcl_probe_clock_rates
