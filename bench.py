@@ -619,7 +619,14 @@ def bench_uneven(ctx, sc, steps=20, ceiling_gbps: float | None = None) -> dict:
                        ("per_launch", sc.PER_LAUNCH)):
         wall, ev = time_async(ctx, sc, tasks, mode, steps, 3, dres, None)
         out[name] = {"ms": ev, "wall_ms": wall,
-                     "elements_per_s": int(sizes.sum()) / (ev / 1e3)}
+                     "elements_per_s": int(sizes.sum()) / (ev / 1e3),
+                     "launch": ctx.last_launch_shape()}
+    # the tuned entries this batch is cut and launched with (a mixed batch:
+    # the mixed-batch tiles, occupancy and block size)
+    t = ctx.get_tuning()
+    out["tuning"] = {"tile_many": list(t.tile_many), "blocks_per_cu_many": t.blocks_per_cu_many,
+                     "block_many": t.block_many, "blocks_per_cu": list(t.blocks_per_cu),
+                     "unroll": list(t.unroll)}
     out["batched_speedup"] = out["per_launch"]["ms"] / out["batched"]["ms"]
     # lower bound: the larger of the HBM time of the POLY/FMUL bytes and the
     # VALU time of the Monte-Carlo samples (Philox blocks at the loop's issue

@@ -352,6 +352,20 @@ typedef struct sparkcl_tuning {
                                     best whole and large ones in mid-sized
                                     tiles; 0 = use the table, else a power of
                                     two from 2^10 to 2^22                     */
+    uint32_t block[3];           /* threads per block of the batch executor and
+                                    the per-partition kernel for each registry
+                                    kernel (a batch of one kernel takes its
+                                    kernel's; serving, map chains and maps use
+                                    256): 256, 512 or 1024; 0 = 256          */
+    uint32_t block_many;         /* the executor's block size for a batch that
+                                    mixes kernels; 0 = 256                    */
+    uint32_t unroll[3];          /* float4 loads in flight per thread and
+                                    input in the POLY / FMUL streaming loops
+                                    (index kernel id - 1; MC_PI has none):
+                                    2, 4 or 8; 0 = 4.  Block size and unroll
+                                    fix which thread sums which elements, so
+                                    sums are identical across calls that
+                                    share them and the tile size.             */
     /* tile size in elements (samples for MC_PI) for [mode][kernel-1][log2 n];
        powers of two from 2^10 to 2^22.  A batched call whose executor blocks
        would get fewer than two of the batched row's tiles each is cut with
@@ -380,6 +394,27 @@ SPARKCL_API const char *sparkcl_last_error(void);
    sequence on this context, measured with HIP events on the launch stream
    (asynchronous calls are not timed, so they add no event packets). */
 SPARKCL_API int sparkcl_last_kernel_ms(sparkcl_ctx *ctx, float *ms);
+
+/* How the last reduce/map_partition call on this context (blocking or
+   asynchronous) was cut and launched: the scheduling decisions of sec. 3.1.5
+   (how an RDD's partitions are spread over the device) as this library takes
+   them from the tuning table.  Written into *out; SPARKCL_EAGAIN before the
+   first such call. */
+typedef struct sparkcl_launch_shape {
+    uint32_t grid;        /* persistent-executor blocks; 0 for PER_LAUNCH
+                             (one launch per task) and host-input calls     */
+    uint32_t block;       /* threads per executor block; 0 for per-task
+                             launches of several kernels (each takes its
+                             own tuned size)                                */
+    uint32_t ntiles;      /* tiles the call was cut into                    */
+    uint32_t ntasks;
+    uint32_t tile_table;  /* 0: the per-launch tile table, 1: the batched one */
+    uint32_t mixed;       /* 1: cut with the mixed-batch tiles (tile_many)  */
+    uint32_t mode;        /* SPARKCL_PER_LAUNCH, _BATCHED or _GRAPH         */
+    uint32_t reserved;
+} sparkcl_launch_shape;
+
+SPARKCL_API int sparkcl_last_launch_shape(sparkcl_ctx *ctx, sparkcl_launch_shape *out);
 
 /* WordCount (sec. 3.2.3, the Spark word-count demo as a SparkCL kernel) over
    `nbytes` bytes of device text: a word is a maximal run of bytes that are

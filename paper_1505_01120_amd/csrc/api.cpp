@@ -178,8 +178,23 @@ int arena_alloc(sparkcl_ctx *ctx, Plan *p, uint64_t bytes, void **out)
 
 } // namespace sparkcl
 
+uint32_t sparkcl::exec_block(const sparkcl_ctx *ctx, uint32_t kid_mask)
+{
+    uint32_t b = ctx->tuning.block_many;
+    for (uint32_t k = 0; k < 3; ++k)
+        if (kid_mask == (1u << k))
+            b = ctx->tuning.block[k];
+    return b ? b : (uint32_t)kBlock;
+}
+
+uint32_t sparkcl::kernel_unroll(const sparkcl_tuning &t, uint32_t kid)
+{
+    const uint32_t u = kid >= SPARKCL_POLY && kid <= SPARKCL_MC_PI ? t.unroll[kid - 1] : 0;
+    return u ? u : (uint32_t)kUnroll;
+}
+
 uint32_t sparkcl::exec_grid(const sparkcl_ctx *ctx, uint32_t kid_mask, uint64_t ntiles,
-                            uint64_t ntasks)
+                            uint64_t ntasks, uint32_t block)
 {
     const uint32_t occ = (uint32_t)ctx->occ_batch;
     uint32_t per_cu = 0;
@@ -203,7 +218,12 @@ uint32_t sparkcl::exec_grid(const sparkcl_ctx *ctx, uint32_t kid_mask, uint64_t 
             per_cu = std::max(per_cu, v ? v : occ);
         }
     }
-    return std::max(1u, std::min(per_cu, occ)) * (uint32_t)ctx->cus;
+    // per_cu counts 256-thread blocks (waves per SIMD); larger blocks take
+    // their share of them
+    const uint32_t waves = std::max(1u, std::min(per_cu, occ));
+    if (block == 0)
+        block = exec_block(ctx, kid_mask);
+    return std::max(1u, waves * (uint32_t)kBlock / block) * (uint32_t)ctx->cus;
 }
 
 sparkcl::Cut sparkcl::plan_cut(const sparkcl_ctx *ctx, int mode, const sparkcl_task *tasks,
@@ -259,10 +279,12 @@ uint32_t sparkcl::cut_tile(const sparkcl_ctx *ctx, const Cut &c, const sparkcl_t
 }
 
 void sparkcl::fill_taskdev(const sparkcl_task &t, uint32_t variant, uint32_t tile,
-                           uint32_t ntiles, uint32_t index, Partial *partials, TaskDev *d)
+                           uint32_t ntiles, uint32_t index, Partial *partials, uint32_t unroll,
+                           TaskDev *d)
 {
     std::memset(d, 0, sizeof(*d));
-    d->kid = t.kernel_id;
+    d->kid = (uint16_t)t.kernel_id;
+    d->unroll = (uint16_t)unroll;
     d->ops = t.reduce_ops;
     d->n = t.n;
     d->in0 = t.in0;
@@ -365,6 +387,7 @@ int sparkcl::build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task
     if (host_in && mode == SPARKCL_GRAPH)
         return fail(SPARKCL_EINVAL, "host-input tasks run in PER_LAUNCH or BATCHED mode");
     const Cut cut = plan_cut(ctx, mode, tasks, ntasks, host_in, per_cu);
+    p->cut = cut;
     std::vector<uint64_t> first(ntasks);
     std::vector<uint32_t> tile(ntasks);
     uint64_t total_tiles = 0;
@@ -438,7 +461,8 @@ int sparkcl::build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task
         const sparkcl_task &t = tasks[i];
         TaskDev &d = host[i];
         fill_taskdev(t, p->variants[i], tile[i], p->ntiles[i], i,
-                     p->dparts ? p->dparts + first[i] : nullptr, &d);
+                     p->dparts ? p->dparts + first[i] : nullptr,
+                     kernel_unroll(ctx->tuning, t.kernel_id), &d);
         if (host_in) {
             char *base = p->staging + (uint64_t)(i % p->nslots) * p->slot_bytes;
             d.in0 = reinterpret_cast<const float *>(base + ((uintptr_t)t.in0 & 15u));
@@ -483,8 +507,10 @@ int sparkcl::build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task
         // it.  Blocking calls (ures == NULL) always return the total.
         p->out.ntasks = (ures && !utot) ? 0 : ntasks;
         p->out.ns_per_tick = ctx->ns_per_tick;
+        // map chains run 256-thread blocks; a given per_cu (chains) counts them
+        p->block = kind == 4 ? (uint32_t)kBlock : exec_block(ctx, kid_mask);
         p->grid = std::min(per_cu ? per_cu * (uint32_t)ctx->cus
-                                  : exec_grid(ctx, kid_mask, p->ntiles_total, ntasks),
+                                  : exec_grid(ctx, kid_mask, p->ntiles_total, ntasks, p->block),
                            p->ntiles_total);
     }
     if (host_in) {
@@ -588,16 +614,18 @@ int launch_device(sparkcl_ctx *ctx, Plan *p, hipStream_t stream)
         // One dispatch of the persistent executor: the cached plan holds the
         // uploaded task table and tile queue, and the kernel leaves its queue
         // head and tickets at zero, so nothing is cleared between launches.
-        int rc = launch_batch(p->dtasks, p->dtiles, p->ntiles_total, p->grid, p->out, stream);
+        int rc = launch_batch(p->dtasks, p->dtiles, p->ntiles_total, p->grid, p->out, stream,
+                              p->block);
         if (rc != SPARKCL_OK)
             return fail(rc, "executor launch failed: " +
                                 std::string(hipGetErrorString(hipGetLastError())));
         return SPARKCL_OK;
     }
     for (uint32_t i = 0; i < p->ntasks; ++i) {
-        const uint32_t cap = exec_grid(ctx, 1u << (p->tasks[i].kernel_id - 1));
+        const uint32_t kmask = 1u << (p->tasks[i].kernel_id - 1);
+        const uint32_t cap = exec_grid(ctx, kmask);
         int rc = launch_task(p->dtasks + i, p->ntiles[i], std::min(cap, p->ntiles[i]),
-                             p->out, stream);
+                             p->out, stream, exec_block(ctx, kmask));
         if (rc != SPARKCL_OK)
             return fail(rc, "kernel launch failed: " +
                                 std::string(hipGetErrorString(hipGetLastError())));
@@ -657,9 +685,10 @@ int sparkcl::enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream, bool timed)
                 SPARKCL_HIP(hipEventRecord(ev, cs[a]));
                 SPARKCL_HIP(hipStreamWaitEvent(stream, ev, 0));
             }
-            const uint32_t cap = exec_grid(ctx, 1u << (t.kernel_id - 1));
+            const uint32_t kmask = 1u << (t.kernel_id - 1);
+            const uint32_t cap = exec_grid(ctx, kmask);
             int rc = launch_task(p->dtasks + i, p->ntiles[i], std::min(cap, p->ntiles[i]),
-                                 p->out, stream);
+                                 p->out, stream, exec_block(ctx, kmask));
             if (rc != SPARKCL_OK)
                 return fail(rc, "kernel launch failed: " +
                                     std::string(hipGetErrorString(hipGetLastError())));
@@ -707,6 +736,23 @@ int sparkcl::enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream, bool timed)
     if (timed) {
         SPARKCL_HIP(hipEventRecord(ctx->ev1, stream));
         ctx->have_ms = true;
+    }
+    if (p->kind == 0) {
+        sparkcl_launch_shape &s = ctx->shape;
+        s = sparkcl_launch_shape{};
+        const bool per_task = p->mode == SPARKCL_PER_LAUNCH || p->host;
+        uint32_t kmask = 0;
+        for (const sparkcl_task &t : p->tasks)
+            kmask |= 1u << (t.kernel_id - 1);
+        s.grid = per_task ? 0 : p->grid;
+        // per-task launches take each kernel's own block size
+        s.block = per_task && (kmask & (kmask - 1)) ? 0 : p->block;
+        s.ntiles = p->ntiles_total;
+        s.ntasks = p->ntasks;
+        s.tile_table = p->cut.tm == TM_BATCHED ? 1 : 0;
+        s.mixed = p->cut.mixed ? 1 : 0;
+        s.mode = (uint32_t)p->mode;
+        ctx->have_shape = true;
     }
     return SPARKCL_OK;
 }
@@ -1136,6 +1182,17 @@ int sparkcl_set_tuning(sparkcl_ctx *ctx, const sparkcl_tuning *in)
     ctx->tuning = *in;
     if (ctx->server)
         ctx->server->set_tuning(*in);
+    return SPARKCL_OK;
+}
+
+int sparkcl_last_launch_shape(sparkcl_ctx *ctx, sparkcl_launch_shape *out)
+{
+    if (!ctx || !out)
+        return fail(SPARKCL_EINVAL, "null argument");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    if (!ctx->have_shape)
+        return fail(SPARKCL_EAGAIN, "no reduce-kind call yet");
+    *out = ctx->shape;
     return SPARKCL_OK;
 }
 

@@ -1,8 +1,11 @@
 // Autotuner: picks, by the lowest median HIP-event time on synthetic device
 // data, first each registry kernel's persistent-executor blocks per CU
-// jointly with its tile for large (2^22-element) partitions, then the tile
-// size per execution mode, kernel and log2(n) bucket, then the occupancy for
-// batches of many small tasks.  The result is a tuning table
+// jointly with its tile for large (2^22-element) partitions, then its block
+// size (256, 512, 1024 threads) and, for the streaming kernels, its float4
+// loads in flight per thread (2, 4, 8), then the tile size per execution
+// mode, kernel and log2(n) bucket, then the tiles, occupancy and block size
+// for batches of many small tasks of mixed kernels (tuned on a batch drawn
+// from a distribution of its own, not the benchmark's).  The result is a tuning table
 // that is written to a JSON cache keyed by the device's gfx arch, so a given
 // machine always decomposes a task the same way (results stay run-to-run
 // identical).  The paper leaves optimisation open (sec. 6); this is ours.
@@ -93,21 +96,22 @@ sparkcl_task make_task(const Bench &b, uint32_t kid, uint64_t n, uint64_t i)
     return t;
 }
 
-// Many tasks of mixed kernels, shaped like an uneven RDD: 4096 tasks with
-// log-normal sizes (median 2^16, log-sd ln 4, clipped to [2^10, 2^23]) and
-// kernel ids uniform over the registry.
+// Many tasks of mixed kernels, shaped like an uneven RDD but not like any
+// one benchmark: 3000 tasks with log-normal sizes (median 2^15, log-sd ln 5,
+// clipped to [2^9, 2^22]) and kernel ids 2 : 2 : 1 (POLY : FMUL : MC_PI).
 std::vector<sparkcl_task> make_mixed(const Bench &b)
 {
     std::vector<sparkcl_task> v;
     uint64_t off = 0;
-    for (uint64_t i = 0; i < 4096; ++i) {
-        const uint64_t h1 = mix64(0x5eed0000 + 2 * i), h2 = mix64(0x5eed0001 + 2 * i);
+    for (uint64_t i = 0; i < 3000; ++i) {
+        const uint64_t h1 = mix64(0x7a11e000 + 2 * i), h2 = mix64(0x7a11e001 + 2 * i);
         const double u1 = ((double)(h1 >> 11) + 0.5) * 0x1p-53;
         const double u2 = (double)(h2 >> 11) * 0x1p-53;
         const double z = std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
-        const double e = std::log(65536.0) + std::log(4.0) * z;
-        const uint64_t n = (uint64_t)std::min(8388608.0, std::max(1024.0, std::rint(std::exp(e))));
-        const uint32_t kid = 1 + (uint32_t)((mix64(h1 ^ h2) >> 32) % 3);
+        const double e = std::log(32768.0) + std::log(5.0) * z;
+        const uint64_t n = (uint64_t)std::min(4194304.0, std::max(512.0, std::rint(std::exp(e))));
+        const uint32_t r5 = (uint32_t)((mix64(h1 ^ h2) >> 32) % 5);
+        const uint32_t kid = r5 < 2 ? SPARKCL_POLY : r5 < 4 ? SPARKCL_FMUL : SPARKCL_MC_PI;
         sparkcl_task t = make_task(b, kid, n, 0);
         if (kid != SPARKCL_MC_PI) {
             if (off + n > kPoolElems)
@@ -234,6 +238,49 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
             }
         best.blocks_per_cu[kid - 1] = best_bpc;
         best.tile[TM_BATCHED][kid - 1][kRefLog2] = best_tile;
+
+        // 1b. Block size and loads in flight at that tile, then the blocks
+        //     per CU again at the chosen shape (blocks per CU count 256-thread
+        //     blocks: a 512-thread block takes two).  Ties (within 2%) go to
+        //     the defaults (256 threads, 4 loads), which come first.
+        {
+            const sparkcl_tuning base = best;
+            float shape_ms = 1e30f;
+            for (uint32_t blk : {256u, 512u, 1024u})
+                for (uint32_t u : {4u, 2u, 8u}) {
+                    if (kid == SPARKCL_MC_PI && u != 4)
+                        continue; // no streaming loop
+                    sparkcl_tuning t = base;
+                    t.block[kid - 1] = blk;
+                    t.unroll[kid - 1] = u;
+                    if (!batched_takes(t, kid, tasks, best_tile))
+                        continue;
+                    float ms = 0;
+                    if (!measure(t, SPARKCL_BATCHED, tasks, &ms))
+                        return abort_with(rc);
+                    if (verbose)
+                        std::fprintf(stderr, "shape kid %u block %u unroll %u: %.1f us\n", kid,
+                                     blk, u, ms * 1e3f);
+                    if (ms < shape_ms * 0.98f) {
+                        shape_ms = ms;
+                        best.block[kid - 1] = blk;
+                        best.unroll[kid - 1] = u;
+                    }
+                }
+            for (uint32_t bpc = 1; bpc <= occ; ++bpc) {
+                sparkcl_tuning t = best;
+                t.blocks_per_cu[kid - 1] = bpc;
+                if (bpc == best_bpc || !batched_takes(t, kid, tasks, best_tile))
+                    continue;
+                float ms = 0;
+                if (!measure(t, SPARKCL_BATCHED, tasks, &ms))
+                    return abort_with(rc);
+                if (ms < shape_ms * 0.98f) {
+                    shape_ms = ms;
+                    best.blocks_per_cu[kid - 1] = bpc;
+                }
+            }
+        }
     }
 
     // 2. Tile size per (mode, kernel, log2-size bucket) at those occupancies.
@@ -327,6 +374,22 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
             }
         }
         best.blocks_per_cu_many = best_bpc;
+
+        // 5. The executor's block size for batches that mix kernels.
+        float shape_ms = 1e30f;
+        for (uint32_t blk : {256u, 512u, 1024u}) {
+            sparkcl_tuning t = best;
+            t.block_many = blk;
+            float ms = 0;
+            if (!measure(t, SPARKCL_BATCHED, tasks, &ms))
+                return abort_with(rc);
+            if (verbose)
+                std::fprintf(stderr, "many block %u: %.1f us\n", blk, ms * 1e3f);
+            if (ms < shape_ms * 0.98f) {
+                shape_ms = ms;
+                best.block_many = blk;
+            }
+        }
     }
 
     ctx->tuning = best;

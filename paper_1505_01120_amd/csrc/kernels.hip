@@ -3,8 +3,8 @@
 // A partition task (a MapCL / MapCLPartition / ReduceCL application, paper
 // sec. 3.1.3) is cut into tiles of `tile_elems` elements.  One 256-thread
 // block turns one tile into one partial:
-//   1. streaming loop: coalesced 128-bit loads (float4), kUnroll quads per
-//      input in flight per thread, the registry kernel's map applied per
+//   1. streaming loop: coalesced 128-bit loads (float4), U quads per input
+//      in flight per thread (2, 4 or 8, from the tuning table), the registry kernel's map applied per
 //      element, each value added to a per-thread FP64 sum, a running max, or
 //      a hit counter;
 //   2. the per-thread values are combined across the wave with cross-lane
@@ -15,12 +15,13 @@
 //      sec. 3.1.3 and 3.2.2); a task of one tile is finished by its block
 //      directly.  The block that finishes the last task of a launch folds
 //      the partition results into the RDD-level total.
-// Tiles of at least one chunk (kBlock x kUnroll quads) deal a task's chunks
+// Tiles of at least one chunk (B threads x U quads, B the block size and U
+// the quads each thread has in flight per input) deal a task's chunks
 // round-robin to its tiles, so the tiles that run together read one sliding
 // window of the task; smaller tiles are contiguous ranges.  Every element's
 // owner thread and every combine order depend only on the tile size, the
-// block size and x's 16-byte alignment, so results are identical run to run
-// and across execution modes with the same tiles.
+// block size, U and x's 16-byte alignment, so results are identical run to
+// run and across execution modes with the same tiles, block size and U.
 //
 // Compiled with -ffp-contract=off: the maps are the binary32 definition
 // operation by operation.  No MFMA: nothing on this path is a contraction.
@@ -211,8 +212,8 @@ __device__ __forceinline__ void map_quad(const M &f, const float4 &xv,
     a.add(v.w);
 }
 
-// Stream `ng` groups of the calling thread.  Group g is the kUnroll quads
-// base(g) + u * kBlock (u = 0..kUnroll-1), in quads from x4/y4/o4: all the
+// Stream `ng` groups of the calling thread.  Group g is the U quads
+// base(g) + u * B (u = 0..U-1, B the block size), in quads from x4/y4/o4: all the
 // group's loads are issued, then the group is folded in order.  (Measured on
 // MI355X: keeping a second group in flight while folding -- a register double
 // buffer -- streams slower than this at every tile size and occupancy; the
@@ -220,22 +221,22 @@ __device__ __forceinline__ void map_quad(const M &f, const float4 &xv,
 //
 // A map with run-time steps (kGroup: a fused chain) maps the whole group at
 // once, so each step's uniform test and coefficient is paid once per group
-// of 4 kUnroll elements per thread rather than once per element.
-template <class M, bool W, class Base>
+// of 4 U elements per thread rather than once per element.
+template <class M, bool W, int U, class Base>
 __device__ __forceinline__ void stream_groups(const M &f, const float *x4,
                                               const float *y4, float *o4,
                                               uint64_t ng, Base base, Acc &a)
 {
-    constexpr int U = kUnroll;
+    const uint32_t B = blockDim.x;
     constexpr int NY = M::kTwo ? U : 1; // one-input maps carry no y buffer
     for (uint64_t g = 0; g < ng; ++g) {
         const uint64_t q0 = base(g);
         float4 xv[U], yv[NY];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            xv[u] = ld4(x4 + 4 * (q0 + u * kBlock));
+            xv[u] = ld4(x4 + 4 * (q0 + u * B));
             if (M::kTwo)
-                yv[u] = ld4u(y4 + 4 * (q0 + u * kBlock));
+                yv[u] = ld4u(y4 + 4 * (q0 + u * B));
         }
         if constexpr (M::kGroup) {
             float v[4 * U];
@@ -243,7 +244,7 @@ __device__ __forceinline__ void stream_groups(const M &f, const float *x4,
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (W)
-                    st4u(o4 + 4 * (q0 + u * kBlock),
+                    st4u(o4 + 4 * (q0 + u * B),
                          make_float4(v[4 * u], v[4 * u + 1], v[4 * u + 2], v[4 * u + 3]));
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
@@ -253,7 +254,7 @@ __device__ __forceinline__ void stream_groups(const M &f, const float *x4,
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 map_quad<M, W>(f, xv[u], M::kTwo ? yv[u] : xv[u],
-                               W ? o4 + 4 * (q0 + u * kBlock) : nullptr, a);
+                               W ? o4 + 4 * (q0 + u * B) : nullptr, a);
         }
     }
 }
@@ -264,7 +265,7 @@ __device__ __forceinline__ void map_scalar(const M &f, const float *x,
                                            const float *y, float *out,
                                            uint64_t i0, uint64_t i1, Acc &a)
 {
-    for (uint64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
+    for (uint64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
         float v = f(ld1(x + i), M::kTwo ? ld1(y + i) : 0.0f);
         if (W)
             st1(out + i, v);
@@ -284,7 +285,7 @@ __device__ __forceinline__ uint32_t quad_head(const float *x, uint64_t n)
 // Contiguous tile [begin, end): the middle in float4 quads (thread t owns
 // quads t, t+B, t+2B, ...), the head before x's first 16-byte boundary and
 // the ragged tail as single elements owned by threads 0..2.
-template <class M, bool W>
+template <class M, bool W, int U>
 __device__ __forceinline__ void tile_contiguous(const M &f,
                                                 const float *__restrict__ x,
                                                 const float *__restrict__ y,
@@ -300,35 +301,33 @@ __device__ __forceinline__ void tile_contiguous(const M &f,
     const uint32_t head = quad_head(xb, len);
     map_scalar<M, W>(f, xb, yb, ob, 0, head, a);
 
-    constexpr uint32_t kStep = kUnroll * kBlock;
+    const uint32_t B = blockDim.x;
+    const uint32_t kStep = U * B;
     const uint32_t nq = (len - head) >> 2;
     const float *x4 = xb + head;
     const float *y4 = M::kTwo ? yb + head : nullptr;
     float *o4 = W ? ob + head : nullptr;
-    // full groups of kUnroll quads owned by this thread
-    const uint32_t full = (tid + (kUnroll - 1) * kBlock < nq)
-                              ? (nq - tid - (kUnroll - 1) * kBlock + kStep - 1) / kStep
+    // full groups of U quads owned by this thread
+    const uint32_t full = (tid + (U - 1) * B < nq)
+                              ? (nq - tid - (U - 1) * B + kStep - 1) / kStep
                               : 0u;
-    stream_groups<M, W>(f, x4, y4, o4, full,
-                        [&](uint64_t g) { return (uint64_t)tid + g * kStep; }, a);
-    for (uint32_t q = tid + full * kStep; q < nq; q += kBlock)
+    stream_groups<M, W, U>(f, x4, y4, o4, full,
+                           [&](uint64_t g) { return (uint64_t)tid + g * kStep; }, a);
+    for (uint32_t q = tid + full * kStep; q < nq; q += B)
         map_quad<M, W>(f, ld4(x4 + 4u * q), M::kTwo ? ld4u(y4 + 4u * q) : float4{},
                        W ? o4 + 4u * q : nullptr, a);
     map_scalar<M, W>(f, xb, yb, ob, head + 4u * nq, len, a);
 }
 
-// Interleaved layout of a whole task (tiles of at least kChunkElems
+// Interleaved layout of a whole task (tiles of at least one chunk, 4 U B
 // elements): the task's quad-aligned
-// middle is cut into chunks of kBlock * kUnroll quads, and tile j of nt owns
+// middle is cut into chunks of U * B quads, and tile j of nt owns
 // chunks j, j + nt, j + 2 nt, ...; tile 0 also owns the unaligned head and
 // the ragged tail.  Tiles that run at the same time (the queue hands out a
 // task's tiles in order) then read neighbouring chunks, one sliding window
 // per task instead of one stream per tile, which HBM serves at a higher rate.
 // Returns the number of elements the tile covers.
-constexpr uint32_t kChunkQuads = kUnroll * kBlock;
-constexpr uint32_t kChunkElems = 4 * kChunkQuads;
-
-template <class M, bool W>
+template <class M, bool W, int U>
 __device__ __forceinline__ uint64_t tile_interleaved(const M &f,
                                                      const float *__restrict__ x,
                                                      const float *__restrict__ y,
@@ -338,6 +337,8 @@ __device__ __forceinline__ uint64_t tile_interleaved(const M &f,
                                                      Acc &a)
 {
     const uint32_t tid = threadIdx.x;
+    const uint32_t B = blockDim.x;
+    const uint32_t kChunkQuads = U * B;
     const uint64_t nq = (n - head) >> 2;
     const uint64_t nfull = nq / kChunkQuads;
     const uint32_t rem = (uint32_t)(nq % kChunkQuads);
@@ -345,12 +346,12 @@ __device__ __forceinline__ uint64_t tile_interleaved(const M &f,
     const float *y4 = M::kTwo ? y + head : nullptr;
     float *o4 = W ? out + head : nullptr;
     const uint64_t ng = nfull > j ? (nfull - j + nt - 1) / nt : 0;
-    stream_groups<M, W>(f, x4, y4, o4, ng,
-                        [&](uint64_t g) { return (j + g * nt) * kChunkQuads + tid; }, a);
+    stream_groups<M, W, U>(f, x4, y4, o4, ng,
+                           [&](uint64_t g) { return (j + g * nt) * kChunkQuads + tid; }, a);
     uint64_t count = 4 * ng * kChunkQuads;
     if (rem != 0 && nfull % nt == j) {
         const uint64_t q0 = nfull * kChunkQuads;
-        for (uint32_t q = tid; q < rem; q += kBlock)
+        for (uint32_t q = tid; q < rem; q += B)
             map_quad<M, W>(f, ld4(x4 + 4 * (q0 + q)),
                            M::kTwo ? ld4u(y4 + 4 * (q0 + q)) : float4{},
                            W ? o4 + 4 * (q0 + q) : nullptr, a);
@@ -367,18 +368,18 @@ __device__ __forceinline__ uint64_t tile_interleaved(const M &f,
 // Tile j of an elementwise task: interleaved when the tile size allows,
 // else the contiguous range [jT, jT + T).  Returns the number of elements
 // covered.
-template <class M, bool W>
+template <class M, bool W, int U>
 __device__ __forceinline__ uint64_t tile_map(const M &f, const float *x,
                                              const float *y, float *out,
                                              uint64_t n, uint32_t T, uint32_t nt,
                                              uint32_t j, Acc &a)
 {
-    if (T >= kChunkElems)
-        return tile_interleaved<M, W>(f, x, y, out, n, quad_head(x, n), nt, j, a);
+    if (T >= 4u * U * blockDim.x)
+        return tile_interleaved<M, W, U>(f, x, y, out, n, quad_head(x, n), nt, j, a);
     const uint64_t begin = (uint64_t)j * T;
     const uint64_t end = min(n, begin + T);
     if (begin < end)
-        tile_contiguous<M, W>(f, x, y, out, begin, end, a);
+        tile_contiguous<M, W, U>(f, x, y, out, begin, end, a);
     return begin < end ? end - begin : 0;
 }
 
@@ -393,7 +394,7 @@ __device__ __forceinline__ void tile_mc(uint64_t seed, uint32_t pid,
     const bool odd_tail = (end & 1u) != 0;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     uint32_t hits = 0;
-    for (uint32_t i = threadIdx.x; i < npairs; i += kBlock) {
+    for (uint32_t i = threadIdx.x; i < npairs; i += blockDim.x) {
         const uint64_t p = p0 + i;
         const U4 r = philox10(U4{(uint32_t)p, (uint32_t)(p >> 32), pid, 0u}, k0, k1);
         const uint32_t second = (odd_tail && i == npairs - 1) ? 0u : 1u;
@@ -421,12 +422,14 @@ __device__ __forceinline__ void wave_reduce(Red &r)
 }
 
 // Block-wide combine; the result is valid in thread 0.  Waves are combined
-// as a fixed pairwise tree ((w0 + w1) + (w2 + w3)).
+// as a fixed pairwise tree ((w0 + w1) + (w2 + w3)) + ... over the block's
+// B / 64 waves (4, 8 or 16).
 __device__ __forceinline__ Red block_reduce(Red r)
 {
-    __shared__ double sh_s[kWaves];
-    __shared__ float sh_m[kWaves];
-    __shared__ uint64_t sh_h[kWaves], sh_n[kWaves];
+    __shared__ double sh_s[kMaxWaves];
+    __shared__ float sh_m[kMaxWaves];
+    __shared__ uint64_t sh_h[kMaxWaves], sh_n[kMaxWaves];
+    const uint32_t nw = blockDim.x >> 6;
     wave_reduce(r);
     const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
     if (lane == 0) {
@@ -438,26 +441,15 @@ __device__ __forceinline__ Red block_reduce(Red r)
     __syncthreads();
     Red out = r;
     if (threadIdx.x == 0) {
-        double s[kWaves];
-        float m[kWaves];
-        uint64_t h[kWaves], n[kWaves];
-#pragma unroll
-        for (int i = 0; i < kWaves; ++i) {
-            s[i] = sh_s[i];
-            m[i] = sh_m[i];
-            h[i] = sh_h[i];
-            n[i] = sh_n[i];
-        }
-#pragma unroll
-        for (int step = 1; step < kWaves; step <<= 1)
-#pragma unroll
-            for (int i = 0; i + step < kWaves; i += 2 * step) {
-                s[i] = s[i] + s[i + step];
-                m[i] = fmaxf(m[i], m[i + step]);
-                h[i] += h[i + step];
-                n[i] += n[i + step];
+        // in place in LDS (thread 0 alone): the pairwise tree over nw waves
+        for (uint32_t step = 1; step < nw; step <<= 1)
+            for (uint32_t i = 0; i + step < nw; i += 2 * step) {
+                sh_s[i] = sh_s[i] + sh_s[i + step];
+                sh_m[i] = fmaxf(sh_m[i], sh_m[i + step]);
+                sh_h[i] += sh_h[i + step];
+                sh_n[i] += sh_n[i + step];
             }
-        out = Red{s[0], m[0], h[0], n[0]};
+        out = Red{sh_s[0], sh_m[0], sh_h[0], sh_n[0]};
     }
     __syncthreads();
     return out;
@@ -469,7 +461,7 @@ template <class Load>
 __device__ __forceinline__ Red combine_ordered(uint32_t count, Load load)
 {
     Red r{0.0, kNegInf, 0, 0};
-    for (uint32_t k = threadIdx.x; k < count; k += kBlock) {
+    for (uint32_t k = threadIdx.x; k < count; k += blockDim.x) {
         double s;
         float m;
         uint64_t h, n;
@@ -621,6 +613,12 @@ __device__ __forceinline__ bool run_tile(const TaskDev *__restrict__ tp, uint32_
         const float *x = tp->in0;
         const float *y = tp->in1;
         float *o = tp->out;
+        const uint32_t U = uni(tp->unroll);
+        // the tile loop for map f with U quads in flight per thread
+#define SPARKCL_TILE_U(MAP, WR, f)                                             \
+    (U == 2   ? tile_map<MAP, WR, 2>(f, x, y, o, n, T, ntiles, j, a)               \
+     : U == 8 ? tile_map<MAP, WR, 8>(f, x, y, o, n, T, ntiles, j, a)               \
+              : tile_map<MAP, WR, 4>(f, x, y, o, n, T, ntiles, j, a))
         if (variant < V_FMUL) {
             const bool w = variant >= V_POLYW;
             const uint32_t d = variant & 7u;
@@ -633,8 +631,8 @@ __device__ __forceinline__ bool run_tile(const TaskDev *__restrict__ tp, uint32_
             PolyMap<D> f;                                                          \
             for (int i = 0; i < 8; ++i)                                            \
                 f.k[i] = k[i];                                                     \
-            count = w ? tile_map<PolyMap<D>, true>(f, x, y, o, n, T, ntiles, j, a)  \
-                      : tile_map<PolyMap<D>, false>(f, x, y, o, n, T, ntiles, j, a); \
+            count = w ? SPARKCL_TILE_U(PolyMap<D>, true, f)                        \
+                      : SPARKCL_TILE_U(PolyMap<D>, false, f);                      \
         } break;
             switch (d) {
                 SPARKCL_POLY_CASE(0)
@@ -649,8 +647,8 @@ __device__ __forceinline__ bool run_tile(const TaskDev *__restrict__ tp, uint32_
 #undef SPARKCL_POLY_CASE
         } else if (variant == V_FMUL || variant == V_FMULW) {
             FmulMap f{tp->c};
-            count = variant == V_FMULW ? tile_map<FmulMap, true>(f, x, y, o, n, T, ntiles, j, a)
-                                       : tile_map<FmulMap, false>(f, x, y, o, n, T, ntiles, j, a);
+            count = variant == V_FMULW ? SPARKCL_TILE_U(FmulMap, true, f)
+                                       : SPARKCL_TILE_U(FmulMap, false, f);
         } else if (variant == V_MC) {
             const uint64_t begin = (uint64_t)j * T;
             const uint64_t end = min(n, begin + T);
@@ -659,6 +657,7 @@ __device__ __forceinline__ bool run_tile(const TaskDev *__restrict__ tp, uint32_
                 count = end - begin;
             }
         } // V_DECLINED: nothing to do; the empty partial leaves the total as is
+#undef SPARKCL_TILE_U
         return count;
     });
 }
@@ -828,19 +827,19 @@ __device__ __forceinline__ bool chain_tile(const TaskDev *__restrict__ tp,
         const bool w = variant == V_FMULW || (variant >= V_POLYW && variant < V_FMUL);
         if (two) {
             const ChainMap<true> f = chain_map<true>(tp, chain);
-            return w ? tile_map<ChainMap<true>, true>(f, x, y, o, n, T, nt, j, a)
-                     : tile_map<ChainMap<true>, false>(f, x, y, o, n, T, nt, j, a);
+            return w ? tile_map<ChainMap<true>, true, kUnroll>(f, x, y, o, n, T, nt, j, a)
+                     : tile_map<ChainMap<true>, false, kUnroll>(f, x, y, o, n, T, nt, j, a);
         }
         const ChainMap<false> f = chain_map<false>(tp, chain);
-        return w ? tile_map<ChainMap<false>, true>(f, x, y, o, n, T, nt, j, a)
-                 : tile_map<ChainMap<false>, false>(f, x, y, o, n, T, nt, j, a);
+        return w ? tile_map<ChainMap<false>, true, kUnroll>(f, x, y, o, n, T, nt, j, a)
+                 : tile_map<ChainMap<false>, false, kUnroll>(f, x, y, o, n, T, nt, j, a);
     });
 }
 
 // ---- kernels --------------------------------------------------------------
 
 // One partition per launch: blocks stride over the task's tiles.
-__global__ __launch_bounds__(kBlock) void k_task(const TaskDev *__restrict__ task,
+__global__ __launch_bounds__(kMaxBlock) void k_task(const TaskDev *__restrict__ task,
                                                  LaunchOut L)
 {
     const uint32_t ntiles = uni(task->ntiles);
@@ -905,7 +904,7 @@ __device__ __forceinline__ void executor(const TaskDev *__restrict__ tasks,
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_batch(const TaskDev *__restrict__ tasks,
+__global__ __launch_bounds__(kMaxBlock) void k_batch(const TaskDev *__restrict__ tasks,
                                                   const TileRef *__restrict__ tiles,
                                                   uint32_t ntiles, LaunchOut L)
 {
@@ -1214,8 +1213,8 @@ __global__ __launch_bounds__(kBlock) void k_zero(uint32_t *p, uint64_t words)
 // does not depend on which block counts which word.
 constexpr uint32_t kWcChunk = 4096;   // bytes per chunk: 16 per thread
 constexpr uint32_t kWcLook = 256;     // look-ahead bytes staged after a chunk
-constexpr uint32_t kWcSlots = 1024;   // LDS hash slots per block
-constexpr uint32_t kWcProbes = 4;     // LDS probes before a word spills
+constexpr uint32_t kWcSlots = 2048;   // LDS hash slots per block
+constexpr uint32_t kWcProbes = 2;     // LDS probes before a word spills
 static_assert(kWcChunk == 16 * kBlock, "one 16-byte span per thread");
 
 __device__ __forceinline__ bool wc_space(uint32_t b)
@@ -1850,12 +1849,14 @@ int hip_status(hipError_t e)
 } // namespace
 
 int launch_task(const TaskDev *dtask, uint32_t ntiles, uint32_t grid,
-                const LaunchOut &out, void *stream)
+                const LaunchOut &out, void *stream, uint32_t block)
 {
+    if (block != 256 && block != 512 && block != 1024)
+        return SPARKCL_EINVAL;
     if (ntiles == 0 || grid == 0)
         return SPARKCL_EINVAL;
     grid = grid < ntiles ? grid : ntiles;
-    hipLaunchKernelGGL(k_task, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
+    hipLaunchKernelGGL(k_task, dim3(grid), dim3(block), 0, (hipStream_t)stream,
                        dtask, out);
     return hip_status(hipGetLastError());
 }
@@ -1871,11 +1872,11 @@ int launch_chain(const TaskDev *dtasks, const TileRef *tiles, uint32_t ntiles,
 }
 
 int launch_batch(const TaskDev *dtasks, const TileRef *tiles, uint32_t ntiles,
-                 uint32_t grid, const LaunchOut &out, void *stream)
+                 uint32_t grid, const LaunchOut &out, void *stream, uint32_t block)
 {
-    if (ntiles == 0 || grid == 0)
+    if (ntiles == 0 || grid == 0 || (block != 256 && block != 512 && block != 1024))
         return SPARKCL_EINVAL;
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(block), 0, (hipStream_t)stream,
                        dtasks, tiles, ntiles, out);
     return hip_status(hipGetLastError());
 }

@@ -119,7 +119,7 @@ extern "C" int sparkcl_reduce_noalloc(sparkcl_ctx *ctx, const sparkcl_task *task
     // Decompose exactly as the batched sparkcl_reduce_async does.
     Cut cut;
     uint64_t total_tiles = 0;
-    uint32_t kid_mask = 0, grid = 0;
+    uint32_t kid_mask = 0, grid = 0, block = 256;
     {
         std::lock_guard<std::mutex> gc(ctx->mu); // tuning table, threshold
         for (uint32_t i = 0; i < ntasks; ++i) {
@@ -141,6 +141,7 @@ extern "C" int sparkcl_reduce_noalloc(sparkcl_ctx *ctx, const sparkcl_task *task
                                              std::to_string(kMaxTiles) + " tiles, the call needs " +
                                              std::to_string(total_tiles));
         grid = std::min<uint64_t>(exec_grid(ctx, kid_mask, total_tiles, ntasks), total_tiles);
+        block = exec_block(ctx, kid_mask);
 
         Partial *parts = reinterpret_cast<Partial *>(base + kOffParts);
         uint64_t first = 0;
@@ -153,7 +154,8 @@ extern "C" int sparkcl_reduce_noalloc(sparkcl_ctx *ctx, const sparkcl_task *task
             const uint32_t T = cut_tile(ctx, cut, tasks[i]);
             const uint32_t nt =
                 skip ? 1u : (uint32_t)std::max<uint64_t>(1, (tasks[i].n + T - 1) / T);
-            fill_taskdev(tasks[i], v, T, nt, i, parts + first, &h_tasks[i]);
+            fill_taskdev(tasks[i], v, T, nt, i, parts + first,
+                         kernel_unroll(ctx->tuning, tasks[i].kernel_id), &h_tasks[i]);
             first += nt;
         }
     }
@@ -181,7 +183,7 @@ extern "C" int sparkcl_reduce_noalloc(sparkcl_ctx *ctx, const sparkcl_task *task
     // as sparkcl_reduce_async: per-task results and no total skip the fold
     L.ntasks = (dev_per_task && !dev_total) ? 0 : ntasks;
     L.ns_per_tick = ctx->ns_per_tick;
-    if ((rc = launch_batch(dtasks, dtiles, (uint32_t)total_tiles, grid, L, s)) != SPARKCL_OK)
+    if ((rc = launch_batch(dtasks, dtiles, (uint32_t)total_tiles, grid, L, s, block)) != SPARKCL_OK)
         return fail(rc, "executor launch failed: " +
                             std::string(hipGetErrorString(hipGetLastError())));
     SPARKCL_HIP(hipEventRecord(dv.done, s));

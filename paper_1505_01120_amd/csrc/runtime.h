@@ -41,6 +41,13 @@ uint64_t host_ns();
 
 class Server;
 
+// How a reduce-kind call is cut into tiles: the tuning table's row (batched
+// or per-launch) and whether the mixed-batch tile sizes apply.
+struct Cut {
+    int tm = TM_PER_LAUNCH;
+    bool mixed = false;
+};
+
 // A cached, uploaded launch: device task table, tile queue, partials, sync
 // words and results.
 struct Plan {
@@ -64,6 +71,8 @@ struct Plan {
     std::vector<uint32_t> ntiles;
     std::vector<uint32_t> variants;
     uint32_t grid = 0;
+    uint32_t block = 256; // executor threads per block
+    Cut cut{};            // kind 0: the tile table the call was cut with
     LaunchOut out{};
 
     // kinds 2 and 3, array-valued ReduceCL: the leaves (a pointer table, or
@@ -118,20 +127,15 @@ void free_plan(sparkcl_ctx *ctx, Plan *p);
 bool evict_one(sparkcl_ctx *ctx);
 // Arena block for plan p, evicting older plans while the arena is full.
 int arena_alloc(sparkcl_ctx *ctx, Plan *p, uint64_t bytes, void **out);
-// How a reduce-kind call is cut into tiles: the tuning table's row (batched
-// or per-launch) and whether the mixed-batch tile sizes apply.  A function of
-// the call, the tuning table and the executor occupancy; allocates nothing.
-struct Cut {
-    int tm = TM_PER_LAUNCH;
-    bool mixed = false;
-};
+// The cut of a call: a function of the call, the tuning table and the
+// executor occupancy; allocates nothing.
 Cut plan_cut(const sparkcl_ctx *ctx, int mode, const sparkcl_task *tasks, uint32_t ntasks,
              bool host_in, uint32_t per_cu = 0);
 // The tile size of one task under a cut.
 uint32_t cut_tile(const sparkcl_ctx *ctx, const Cut &c, const sparkcl_task &t);
 // The device descriptor of one task.
 void fill_taskdev(const sparkcl_task &t, uint32_t variant, uint32_t tile, uint32_t ntiles,
-                  uint32_t index, Partial *partials, TaskDev *d);
+                  uint32_t index, Partial *partials, uint32_t unroll, TaskDev *d);
 // The batched tile queue (longest first, streaming and Monte-Carlo tiles
 // interleaved) into tiles[sum of dev[i].ntiles]; order, mem and alu are
 // caller-provided arrays of ntasks entries.  Allocates nothing.
@@ -165,7 +169,12 @@ int noalloc_setup(int device);
 // Persistent-executor grid for a batch holding the kernels in kid_mask
 // (bit k-1 for kernel id k) and `ntiles` tiles over `ntasks` tasks.
 uint32_t exec_grid(const sparkcl_ctx *ctx, uint32_t kid_mask, uint64_t ntiles = 0,
-                   uint64_t ntasks = 0);
+                   uint64_t ntasks = 0, uint32_t block = 0);
+// The executor's threads per block for a batch holding the kernels in
+// kid_mask (one kernel: its tuned size; several: the mixed-batch size), and
+// the float4 loads in flight per thread for a kernel's streaming loop.
+uint32_t exec_block(const sparkcl_ctx *ctx, uint32_t kid_mask);
+uint32_t kernel_unroll(const sparkcl_tuning &t, uint32_t kid);
 
 } // namespace sparkcl
 
@@ -192,6 +201,8 @@ struct sparkcl_ctx {
     hipStream_t copy_stream2 = nullptr; // and of y
     hipStream_t capture_stream = nullptr; // builds SPARKCL_GRAPH plans' graphs
     bool have_ms = false;
+    bool have_shape = false;
+    sparkcl_launch_shape shape{}; // of the last reduce-kind call
     double offload_fixed_s = 0.0;   // selective execution: measured fixed
     double offload_gpu_bps = 0.0;   // cost and streaming rate (0: not yet)
     sparkcl_result *pinned = nullptr;

@@ -232,6 +232,7 @@ int Server::submit(const sparkcl_task &task, uint64_t *ticket)
     w.task = task;
     w.ntiles = ntiles;
     w.tile = tile;
+    w.unroll = kernel_unroll(tuning_, task.kernel_id);
     w.variant = variant;
     waiting_[p.ticket] = w;
     ++submitted_;
@@ -315,6 +316,7 @@ void Server::admit_some(std::vector<Flight> *out, std::vector<Flight> *to_copy)
         f.task = w.task;
         f.variant = w.variant;
         f.tile = w.tile;
+        f.unroll = w.unroll;
         f.part_off = off;
         f.t_admit = host_ns();
         f.dx = w.task.in0;
@@ -458,7 +460,8 @@ int Server::publish(const std::vector<Flight> &fl)
         const sparkcl_task &t = f.task;
         TaskDev d;
         std::memset(&d, 0, sizeof(d));
-        d.kid = t.kernel_id;
+        d.kid = (uint16_t)t.kernel_id;
+        d.unroll = (uint16_t)f.unroll;
         d.ops = t.reduce_ops;
         d.n = t.n;
         d.in0 = f.dx; // a host-input task reads its staged copies

@@ -60,6 +60,7 @@ class Server {
         sparkcl_task task;
         uint32_t variant = 0;
         uint32_t tile = 0;     // tile size fixed at submit
+        uint32_t unroll = 4;   // loads in flight per thread, fixed at submit
         uint64_t part_off = 0; // arena block for the partials
         uint64_t t_admit = 0;
         // host-input task: its staging block in the arena, the device copies
@@ -72,7 +73,7 @@ class Server {
     };
     struct Waiting {
         sparkcl_task task;
-        uint32_t ntiles = 0, tile = 0, variant = 0;
+        uint32_t ntiles = 0, tile = 0, variant = 0, unroll = 4;
     };
 
     sparkcl_ctx *ctx_;

@@ -8,12 +8,18 @@
 
 namespace sparkcl {
 
-// Threads per block of every tile kernel.  The per-thread element order inside
-// a tile, and so the rounding of its sum, depends on this constant and on the
-// tile size only.
+// Threads per block of the tile kernels (the default, and the only size of
+// the serving, chain, map, tree and word-count kernels).  The batch executor
+// and the per-partition kernel also run 512- and 1024-thread blocks, as the
+// tuning table says.  The per-thread element order inside a tile, and so
+// the rounding of its sum, depends on the block size, the quads in flight
+// per thread and the tile size only.
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-// Loads in flight per thread in the streaming loops (float4 per input).
+constexpr int kMaxBlock = 1024;
+constexpr int kMaxWaves = kMaxBlock / 64;
+// Loads in flight per thread in the streaming loops (float4 per input): the
+// default; the tuning table picks 2, 4 or 8 per kernel.
 constexpr int kUnroll = 4;
 
 // Kernel body selector, derived on the host from (kernel id, degree, output).
@@ -39,7 +45,8 @@ static_assert(sizeof(Partial) == 32, "Partial layout");
 
 // A partition task as the kernels read it (128 B, one cache line pair).
 struct TaskDev {
-    uint32_t kid;
+    uint16_t kid;
+    uint16_t unroll;     // quads in flight per thread and input: 2, 4 or 8
     uint32_t ops;
     uint64_t n;
     const float *in0;
@@ -131,9 +138,9 @@ struct ServeArgs {
 
 // ---- launchers (kernels.hip) ---------------------------------------------
 int launch_task(const TaskDev *dtask, uint32_t ntiles, uint32_t grid,
-                const LaunchOut &out, void *stream);
+                const LaunchOut &out, void *stream, uint32_t block = kBlock);
 int launch_batch(const TaskDev *dtasks, const TileRef *tiles, uint32_t ntiles,
-                 uint32_t grid, const LaunchOut &out, void *stream);
+                 uint32_t grid, const LaunchOut &out, void *stream, uint32_t block = kBlock);
 int launch_map(const TaskDev *dtask, uint64_t n, uint32_t variant,
                uint32_t grid, void *stream);
 int launch_zero(void *p, uint64_t bytes, void *stream);

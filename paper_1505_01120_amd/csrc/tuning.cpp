@@ -173,6 +173,11 @@ struct Parser {
 void tuning_defaults(sparkcl_tuning *t)
 {
     std::memset(t, 0, sizeof(*t));
+    for (int k = 0; k < 3; ++k) {
+        t->block[k] = 256;
+        t->unroll[k] = 4;
+    }
+    t->block_many = 256;
     // blocks_per_cu 0: as many as fit (occupancy)
     for (uint32_t b = 0; b < SPARKCL_TUNE_BUCKETS; ++b) {
         // One launch per partition: aim at ~2048 tiles so the grid fills the
@@ -214,6 +219,23 @@ int tuning_validate(const sparkcl_tuning *t, std::string *why)
                 *why = "blocks_per_cu above 32";
             return SPARKCL_EINVAL;
         }
+    auto block_ok = [](uint32_t b) { return b == 0 || b == 256 || b == 512 || b == 1024; };
+    auto unroll_ok = [](uint32_t u) { return u == 0 || u == 2 || u == 4 || u == 8; };
+    for (int k = 0; k < 3; ++k)
+        if (!block_ok(t->block[k]) || !unroll_ok(t->unroll[k])) {
+            if (why)
+                *why = std::string("block[") + kKernelNames[k] + "] = " +
+                       std::to_string(t->block[k]) + " or unroll = " +
+                       std::to_string(t->unroll[k]) +
+                       " not in {0, 256, 512, 1024} / {0, 2, 4, 8}";
+            return SPARKCL_EINVAL;
+        }
+    if (!block_ok(t->block_many)) {
+        if (why)
+            *why = "block_many = " + std::to_string(t->block_many) +
+                   " not in {0, 256, 512, 1024}";
+        return SPARKCL_EINVAL;
+    }
     for (int k = 0; k < 3; ++k) {
         const uint32_t v = t->tile_many[k];
         if (v != 0 && (v < (1u << kMinTileLog2) || v > (1u << kMaxTileLog2) || (v & (v - 1)))) {
@@ -283,6 +305,20 @@ bool tuning_parse_json(const std::string &text,
         }
         if (const Json *b = e.get("blocks_per_cu_many"))
             t.blocks_per_cu_many = (uint32_t)b->num;
+        for (const char *name : {"block", "unroll"}) {
+            const Json *b = e.get(name);
+            if (!b)
+                continue;
+            if (b->kind != Json::ARR || b->arr.size() != 3) {
+                if (err)
+                    *err = std::string(name) + " must be an array of 3";
+                return false;
+            }
+            for (int k = 0; k < 3; ++k)
+                (name[0] == 'b' ? t.block : t.unroll)[k] = (uint32_t)b->arr[k].num;
+        }
+        if (const Json *b = e.get("block_many"))
+            t.block_many = (uint32_t)b->num;
         if (const Json *b = e.get("tile_many")) {
             if (b->kind != Json::ARR || b->arr.size() != 3) {
                 if (err)
@@ -334,7 +370,9 @@ std::string tuning_to_json(const std::map<std::string, sparkcl_tuning> &all)
           << ", " << t.blocks_per_cu[1] << ", " << t.blocks_per_cu[2]
           << "],\n  \"blocks_per_cu_many\": " << t.blocks_per_cu_many
           << ",\n  \"tile_many\": [" << t.tile_many[0] << ", " << t.tile_many[1] << ", "
-          << t.tile_many[2] << "],\n  \"tile\": {\n";
+          << t.tile_many[2] << "],\n  \"block\": [" << t.block[0] << ", " << t.block[1] << ", "
+          << t.block[2] << "],\n  \"block_many\": " << t.block_many << ",\n  \"unroll\": ["
+          << t.unroll[0] << ", " << t.unroll[1] << ", " << t.unroll[2] << "],\n  \"tile\": {\n";
         for (int m = 0; m < SPARKCL_TUNE_MODES; ++m) {
             o << "   \"" << kModeNames[m] << "\": {\n";
             for (int k = 0; k < 3; ++k) {

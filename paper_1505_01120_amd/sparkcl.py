@@ -66,7 +66,8 @@ class Result(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_uint32 * 3), ("blocks_per_cu_many", ctypes.c_uint32),
-                ("tile_many", ctypes.c_uint32 * 3),
+                ("tile_many", ctypes.c_uint32 * 3), ("block", ctypes.c_uint32 * 3),
+                ("block_many", ctypes.c_uint32), ("unroll", ctypes.c_uint32 * 3),
                 ("tile", ((ctypes.c_uint32 * TUNE_BUCKETS) * 3) * TUNE_MODES)]
 
 
@@ -94,6 +95,14 @@ class ServeStats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class LaunchShape(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint32) for f in (
+        "grid", "block", "ntiles", "ntasks", "tile_table", "mixed", "mode", "reserved")]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
 assert ctypes.sizeof(Task) == 96 and ctypes.sizeof(Result) == 64
 
 # Every symbol declared in include/sparkcl.h.
@@ -104,7 +113,8 @@ EXPORTS = ("sparkcl_init", "sparkcl_destroy", "sparkcl_map", "sparkcl_map_partit
            "sparkcl_serve_stats_get", "sparkcl_serve_drain", "sparkcl_get_tuning",
            "sparkcl_set_tuning", "sparkcl_autotune", "sparkcl_strerror",
            "sparkcl_last_error", "sparkcl_last_kernel_ms", "sparkcl_version",
-           "sparkcl_offload_breakeven", "sparkcl_wordcount", "sparkcl_reduce_noalloc")
+           "sparkcl_offload_breakeven", "sparkcl_wordcount", "sparkcl_reduce_noalloc",
+           "sparkcl_last_launch_shape")
 
 
 class SparkclError(RuntimeError):
@@ -151,6 +161,7 @@ def load() -> ctypes.CDLL:
             "sparkcl_strerror": ([I32], ctypes.c_char_p),
             "sparkcl_last_error": ([], ctypes.c_char_p),
             "sparkcl_last_kernel_ms": ([P, ctypes.POINTER(ctypes.c_float)], I32),
+            "sparkcl_last_launch_shape": ([P, ctypes.POINTER(LaunchShape)], I32),
             "sparkcl_version": ([], ctypes.c_char_p),
             "sparkcl_offload_breakeven": ([P, ctypes.c_double, ctypes.POINTER(U64)], I32),
             "sparkcl_wordcount": ([P, P, U64, P, P, U64, ctypes.POINTER(U64),
@@ -422,6 +433,13 @@ class Context:
         v = ctypes.c_float()
         _check(load().sparkcl_last_kernel_ms(self._h, ctypes.byref(v)), "last_kernel_ms")
         return v.value
+
+    def last_launch_shape(self) -> dict:
+        """Grid, block size, tile count and tile table of the last
+        reduce/map_partition call."""
+        v = LaunchShape()
+        _check(load().sparkcl_last_launch_shape(self._h, ctypes.byref(v)), "last_launch_shape")
+        return v.as_dict()
 
 
 def version() -> str:

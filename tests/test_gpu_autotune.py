@@ -4,11 +4,12 @@ to the JSON cache, a new context reads back the identical table from that
 cache (the tuned choice is fixed per architecture key, not re-drawn per run),
 and reductions under the tuned table still match the oracle."""
 import ctypes
+import math
 
 import pytest
 
 import datagen
-from gpu_helpers import DevParts, check_result, oracle_result
+from gpu_helpers import DevParts, check_result, check_total, oracle_result
 import paper_1505_01120_amd as sc
 
 pytestmark = pytest.mark.gpu
@@ -33,6 +34,11 @@ def test_autotune_table_cache_and_parity(tmp_path):
 
     for b in list(tuned.blocks_per_cu) + [tuned.blocks_per_cu_many]:
         assert 1 <= b <= 16, b
+    for b in list(tuned.block) + [tuned.block_many]:
+        assert b in (256, 512, 1024), b
+    for u in tuned.unroll:
+        assert u in (2, 4, 8), u
+    assert tuned.unroll[2] == 4  # the Monte-Carlo kernel has no streaming loop
     for v in tuned.tile_many:
         assert v == 0 or (MIN_TILE <= v <= MAX_TILE and v & (v - 1) == 0), v
     for m in range(sc.TUNE_MODES):
@@ -50,10 +56,22 @@ def test_autotune_table_cache_and_parity(tmp_path):
         parts = [datagen.make_part(k, n, i) for i, (k, n) in enumerate(
             [(datagen.POLY, 5000), (datagen.FMUL, 8192 + 3), (datagen.MC_PI, 70_000),
              (datagen.FMUL, 1 << 18)])]
-        d = DevParts(parts)
-        for mode in (sc.PER_LAUNCH, sc.BATCHED):
+        d = DevParts(parts, 1, 2)
+        for mode in (sc.PER_LAUNCH, sc.BATCHED, sc.GRAPH):
             per, _ = c2.reduce(d.tasks, mode)
             for p, g in zip(parts, per):
                 check_result(g, oracle_result(p), p.kid, p.ops, f"mode {mode} kid {p.kid} n {p.n}")
+        # a mixed batch of many tasks: the tuned mixed-batch tiles, occupancy
+        # and block size
+        sizes = datagen.lognormal_sizes(700, 11, 3, 8192, math.log(4.0), 16, 300_000)
+        kids = datagen.uniform_kernel_ids(700, 11, 4)
+        parts = [datagen.make_part(int(k), int(n), i) for i, (n, k) in enumerate(zip(sizes, kids))]
+        d = DevParts(parts, 3, 1)
+        want = [oracle_result(p) for p in parts]
+        for mode in (sc.BATCHED, sc.GRAPH):
+            per, tot = c2.reduce(d.tasks, mode)
+            for p, g, o in zip(parts, per, want):
+                check_result(g, o, p.kid, p.ops, f"mixed mode {mode} kid {p.kid} n {p.n}")
+            check_total(tot, want, datagen.SUM | datagen.MAX | datagen.COUNT)
     finally:
         c2.destroy()

@@ -103,8 +103,11 @@ def test_host_input_errors(ctx):
         with pytest.raises(sc.SparkclError) as e:
             ctx.reduce(bad)
         assert e.value.code == sc.EINVAL
+    # served host-input tasks must sit in pinned memory (the serving thread
+    # copies them asynchronously); pageable memory is refused at submit
+    pageable = torch.from_numpy(p.x.copy())
     with pytest.raises(sc.SparkclError) as e:
-        ctx.submit(h)
+        ctx.submit(sc.task(p.kid, p.n, pageable, coef=p.coef, host=True))
     assert e.value.code == sc.EINVAL
     t = sc.task(p.kid, p.n, hx, coef=p.coef, host=True)
     t.flags = 2

@@ -181,6 +181,80 @@ def test_forced_tile_sizes(ctx, forced_tiles, mode, tile_log2, off):
     check_total(tot, want, ops)
 
 
+SHAPES = [(256, 2), (256, 8), (512, 4), (512, 8), (1024, 2), (1024, 4)]
+
+
+@pytest.mark.parametrize("block,unroll", SHAPES)
+@pytest.mark.parametrize("off", [0, 3])
+def test_forced_block_and_unroll(ctx, block, unroll, off):
+    # every kernel's executor block size and streaming loads in flight forced
+    # to one shape (sparkcl_tuning.block, .unroll, .block_many), with small
+    # tiles so that each task spans many tiles and takes the interleaved,
+    # contiguous and ragged paths; per-launch, batched and graph, single-kernel
+    # and mixed batches, materialised outputs, and the RDD total
+    saved = ctx.get_tuning()
+    t = sc.Tuning.from_buffer_copy(saved)
+    for k in range(3):
+        t.block[k] = block
+        t.unroll[k] = unroll
+        for m in range(len(t.tile)):
+            for b in range(len(t.tile[m][k])):
+                t.tile[m][k][b] = min(t.tile[m][k][b], 1 << 14)
+    t.block_many = block
+    ctx.set_tuning(t)
+    try:
+        sizes = [1, 4095, 4097, 3 * 16384 + 5, 100_003, 262_147, 1 << 20]
+        mixed = [datagen.make_part(kid, n, 8 * i + kid, with_data=kid != datagen.MC_PI)
+                 for i, n in enumerate(sizes)
+                 for kid in (datagen.POLY, datagen.FMUL, datagen.MC_PI)]
+        single = [p for p in mixed if p.kid == datagen.FMUL]
+        for parts in (mixed, single):
+            d = DevParts(parts, off, off, out=True)
+            want = [oracle_result(p) for p in parts]
+            ops = 0
+            for p in parts:
+                ops |= p.ops
+            for mode in MODES:
+                per, tot = ctx.reduce(d.tasks, mode)
+                torch.cuda.synchronize()
+                shape = ctx.last_launch_shape()
+                assert shape["mode"] == mode and shape["ntasks"] == len(parts), shape
+                if mode == sc.PER_LAUNCH:
+                    assert shape["grid"] == 0 and shape["tile_table"] == 0, shape
+                    assert shape["block"] == (0 if parts is mixed else block), shape
+                else:
+                    assert shape["block"] == block and 0 < shape["grid"] <= shape["ntiles"], shape
+                for p, g, o, buf in zip(parts, per, want, d.outs):
+                    where = f"kid={p.kid} n={p.n} B={block} U={unroll} off={off} mode={mode}"
+                    check_result(g, o, p.kid, p.ops, where)
+                    if buf is not None:
+                        m = oracle.poly_map(p.x, p.coef) if p.kid == datagen.POLY else \
+                            oracle.fmul_map(p.x, p.y)
+                        assert np.array_equal(buf.cpu().numpy().view(np.uint32),
+                                              m.view(np.uint32)), where
+                check_total(tot, want, ops)
+    finally:
+        ctx.set_tuning(saved)
+
+
+def test_block_and_unroll_refused_out_of_range(ctx):
+    saved = ctx.get_tuning()
+    for field, value in (("block_many", 128), ("block_many", 768)):
+        t = sc.Tuning.from_buffer_copy(saved)
+        setattr(t, field, value)
+        with pytest.raises(sc.SparkclError):
+            ctx.set_tuning(t)
+    t = sc.Tuning.from_buffer_copy(saved)
+    t.unroll[1] = 3
+    with pytest.raises(sc.SparkclError):
+        ctx.set_tuning(t)
+    t = sc.Tuning.from_buffer_copy(saved)
+    t.block[0] = 2048
+    with pytest.raises(sc.SparkclError):
+        ctx.set_tuning(t)
+    assert bytes(ctx.get_tuning()) == bytes(saved)
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_repeat_is_bit_identical_and_async_matches(ctx, mode):
     parts = [datagen.make_part(k, 200_000 + 17 * i, i)

@@ -87,9 +87,9 @@ def test_every_declared_symbol_is_exported(lib):
 def test_struct_layouts_match_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text('#include "sparkcl.h"\n#include <stdio.h>\n#include <stddef.h>\n'
-                   "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\","
+                   "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\","
                    "sizeof(sparkcl_task), sizeof(sparkcl_result), sizeof(sparkcl_config),"
-                   "sizeof(sparkcl_tuning), sizeof(sparkcl_serve_stats),"
+                   "sizeof(sparkcl_tuning), sizeof(sparkcl_serve_stats), sizeof(sparkcl_launch_shape),"
                    "offsetof(sparkcl_task, coef), offsetof(sparkcl_result, t_done_ns),"
                    "offsetof(sparkcl_config, tune_cache));return 0;}\n")
     exe = tmp_path / "layout"
@@ -97,7 +97,8 @@ def test_struct_layouts_match_header(tmp_path):
                            "-o", str(exe)])
     got = list(map(int, subprocess.check_output([str(exe)]).split()))
     want = [ctypes.sizeof(sc.Task), ctypes.sizeof(sc.Result), ctypes.sizeof(sc.Config),
-            ctypes.sizeof(sc.Tuning), ctypes.sizeof(sc.ServeStats), sc.Task.coef.offset,
+            ctypes.sizeof(sc.Tuning), ctypes.sizeof(sc.ServeStats),
+            ctypes.sizeof(sc.LaunchShape), sc.Task.coef.offset,
             sc.Result.t_done_ns.offset, sc.Config.tune_cache.offset]
     assert got == want
 
@@ -335,6 +336,21 @@ def test_tuning_json_roundtrip(host, tmp_path):
     assert host.hl_tuning_parse(b'{"gfx950": {"tile_many": [0, 65536]}}', err, 256) == -1
     assert host.hl_tuning_parse(b'{"gfx950": {"tile_many": [0, 3000, 0]}}', err, 256) == -1
     assert b"tile_many" in err.value
+    # block sizes (0 = default, 256, 512, 1024) and loads in flight (0, 2, 4, 8)
+    assert host.hl_tuning_parse(b'{"gfx950": {"block": [512, 0, 1024], "block_many": 256,'
+                                b' "unroll": [2, 8, 0]}}', err, 256) == 1
+    for bad in (b'{"gfx950": {"block": [384, 0, 0]}}', b'{"gfx950": {"block": [256, 256]}}',
+                b'{"gfx950": {"block_many": 2048}}', b'{"gfx950": {"unroll": [3, 4, 4]}}',
+                b'{"gfx950": {"unroll": [16, 4, 4]}}'):
+        assert host.hl_tuning_parse(bad, err, 256) == -1, bad
+    t.block[0], t.block[2], t.block_many = 512, 1024, 1024
+    t.unroll[0], t.unroll[1] = 8, 2
+    assert host.hl_tuning_validate(ctypes.byref(t)) == 0
+    assert host.hl_tuning_save(path, b"gfx950:sramecc+:xnack-", ctypes.byref(t)) == 1
+    assert host.hl_tuning_load(path, b"gfx950:sramecc+:xnack-", ctypes.byref(back)) == 1
+    assert bytes(back) == bytes(t)
+    t.unroll[2] = 5
+    assert host.hl_tuning_validate(ctypes.byref(t)) == sc.EINVAL
 
 
 def test_committed_tuning_cache_is_valid(host):
