@@ -625,6 +625,7 @@ def bench_uneven(ctx, sc, steps=20, ceiling_gbps: float | None = None) -> dict:
     # the mixed-batch tiles, occupancy and block size)
     t = ctx.get_tuning()
     out["tuning"] = {"tile_many": list(t.tile_many), "blocks_per_cu_many": t.blocks_per_cu_many,
+                     "many_tiles_per_cu": list(t.many_tiles_per_cu),
                      "block_many": t.block_many, "blocks_per_cu": list(t.blocks_per_cu),
                      "unroll": list(t.unroll)}
     out["batched_speedup"] = out["per_launch"]["ms"] / out["batched"]["ms"]

@@ -366,6 +366,17 @@ typedef struct sparkcl_tuning {
                                     fix which thread sums which elements, so
                                     sums are identical across calls that
                                     share them and the tile size.             */
+    uint32_t many_tiles_per_cu[2]; /* for such a batch of many spread tasks,
+                                    when tile_many leaves a kernel at 0: the
+                                    number of tiles per CU to cut the batch's
+                                    streaming (POLY, FMUL) elements [0] or
+                                    Monte-Carlo samples [1] into; the tile is
+                                    the batch's total over (CUs x this value),
+                                    rounded to the nearest power of two in
+                                    [2^10, 2^22].  A work share, unlike a tile
+                                    size, carries over between batches of
+                                    different totals.  0 = use the per-bucket
+                                    table; else 1 to 4096                     */
     /* tile size in elements (samples for MC_PI) for [mode][kernel-1][log2 n];
        powers of two from 2^10 to 2^22.  A batched call whose executor blocks
        would get fewer than two of the batched row's tiles each is cut with
@@ -409,9 +420,12 @@ typedef struct sparkcl_launch_shape {
     uint32_t ntiles;      /* tiles the call was cut into                    */
     uint32_t ntasks;
     uint32_t tile_table;  /* 0: the per-launch tile table, 1: the batched one */
-    uint32_t mixed;       /* 1: cut with the mixed-batch tiles (tile_many)  */
+    uint32_t mixed;       /* 1: cut with the mixed-batch tiles (tile_many or
+                             many_tiles_per_cu)                            */
     uint32_t mode;        /* SPARKCL_PER_LAUNCH, _BATCHED or _GRAPH         */
-    uint32_t reserved;
+    uint32_t mixed_tile[3]; /* when mixed: each kernel's tile size (index
+                             kernel id - 1), 0 where it took the per-bucket
+                             table                                          */
 } sparkcl_launch_shape;
 
 SPARKCL_API int sparkcl_last_launch_shape(sparkcl_ctx *ctx, sparkcl_launch_shape *out);

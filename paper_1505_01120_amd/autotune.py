@@ -1,9 +1,10 @@
 """Run the library's autotuner on GPU 0 and write the tuning cache.
 
-The autotuner (sparkcl_autotune) times candidate tile sizes for every
-execution mode, registry kernel and log2(n) bucket on synthetic device data,
-then the persistent executor's blocks per CU, and stores the table in a JSON
-file keyed by the device's gfx arch.  Contexts load that file by default
+The autotuner (sparkcl_autotune) times, on synthetic device data, each
+registry kernel's blocks per CU with its tile, its block size and loads in
+flight, then candidate tile sizes for every execution mode, kernel and log2(n)
+bucket, then the tiles, occupancy and block size for mixed batches of many
+tasks, and stores the table in a JSON file keyed by the device's gfx arch.  Contexts load that file by default
 (paper_1505_01120_amd/tuning.json), so one machine always cuts a task into the
 same tiles and results stay run-to-run identical.
 
@@ -36,6 +37,9 @@ def main(argv=None) -> int:
     summary = {"blocks_per_cu": list(t.blocks_per_cu),
                "blocks_per_cu_many": t.blocks_per_cu_many,
                "tile_many": list(t.tile_many),
+               "many_tiles_per_cu": list(t.many_tiles_per_cu),
+               "block": list(t.block), "block_many": t.block_many,
+               "unroll": list(t.unroll),
                "tiles": {m: {k: list(t.tile[i][j][args.lo:args.hi + 1])
                              for j, k in enumerate(kern)} for i, m in enumerate(names[:2])}}
     print(json.dumps(summary), flush=True)

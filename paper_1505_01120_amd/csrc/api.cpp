@@ -238,19 +238,36 @@ sparkcl::Cut sparkcl::plan_cut(const sparkcl_ctx *ctx, int mode, const sparkcl_t
     // so a repeated call is cut the same way.
     Cut c;
     c.tm = mode != SPARKCL_PER_LAUNCH && !host_in ? TM_BATCHED : TM_PER_LAUNCH;
-    // A batch of many tasks of widely spread sizes takes the tuned mixed-batch
+    // A batch of many tasks of widely spread sizes takes the mixed-batch
     // tile sizes instead of the per-bucket table (tuned on batches of one
-    // size).  On the 4096-task uneven batch, one 2^16 tile size for the
-    // streaming kernels ran it in 515 us against 553 us with the table: small
-    // tasks then run whole and large ones in mid-sized interleaved tiles.
+    // size): one tile size per kernel class, so small tasks run whole and
+    // large ones in mid-sized interleaved tiles.  On the 4096-task uneven
+    // batch one 2^16 tile for the streaming kernels ran it in 515 us against
+    // 553 us with the table.  The size is either given (tile_many) or derived
+    // from the batch's own total work, cut into a tuned number of tiles per
+    // CU: the share, not the size, is what carries over between batches.
     if (c.tm == TM_BATCHED && ntasks >= kMixedMinTasks) {
         uint32_t lo = SPARKCL_TUNE_BUCKETS, hi = 0;
+        uint64_t total[2] = {0, 0}; // streaming elements, Monte-Carlo samples
         for (uint32_t i = 0; i < ntasks; ++i) {
             const uint32_t b = size_bucket(tasks[i].n);
             lo = std::min(lo, b);
             hi = std::max(hi, b);
+            if (tasks[i].kernel_id == SPARKCL_MC_PI)
+                total[1] += tasks[i].n;
+            else if (tasks[i].kernel_id == SPARKCL_POLY || tasks[i].kernel_id == SPARKCL_FMUL)
+                total[0] += tasks[i].n;
         }
         c.mixed = hi >= lo + kMixedMinSpan;
+        for (int k = 0; k < 2 && c.mixed; ++k) {
+            const uint32_t q = ctx->tuning.many_tiles_per_cu[k];
+            if (q == 0 || total[k] == 0)
+                continue;
+            const double want = (double)total[k] / ((double)ctx->cus * q);
+            const double l2 = std::rint(std::log2(std::max(want, 1.0)));
+            const int e = (int)std::min<double>(kMaxTileLog2, std::max<double>(kMinTileLog2, l2));
+            c.share_tile[k] = 1u << e;
+        }
     }
     if (c.tm == TM_BATCHED) {
         uint64_t tiles = 0;
@@ -264,8 +281,11 @@ sparkcl::Cut sparkcl::plan_cut(const sparkcl_ctx *ctx, int mode, const sparkcl_t
         }
         const uint64_t grid =
             per_cu ? per_cu * (uint32_t)ctx->cus : exec_grid(ctx, mask, tiles, ntasks);
-        if (tiles < 2 * grid)
+        if (tiles < 2 * grid) {
             c.tm = TM_PER_LAUNCH;
+            c.mixed = false;
+            c.share_tile[0] = c.share_tile[1] = 0;
+        }
     }
     return c;
 }
@@ -273,8 +293,13 @@ sparkcl::Cut sparkcl::plan_cut(const sparkcl_ctx *ctx, int mode, const sparkcl_t
 uint32_t sparkcl::cut_tile(const sparkcl_ctx *ctx, const Cut &c, const sparkcl_task &t)
 {
     if (c.tm == TM_BATCHED && c.mixed && t.kernel_id >= SPARKCL_POLY &&
-        t.kernel_id <= SPARKCL_MC_PI && ctx->tuning.tile_many[t.kernel_id - 1])
-        return ctx->tuning.tile_many[t.kernel_id - 1];
+        t.kernel_id <= SPARKCL_MC_PI) {
+        if (ctx->tuning.tile_many[t.kernel_id - 1])
+            return ctx->tuning.tile_many[t.kernel_id - 1];
+        const uint32_t s = c.share_tile[t.kernel_id == SPARKCL_MC_PI ? 1 : 0];
+        if (s)
+            return s;
+    }
     return tile_for(ctx->tuning, c.tm, t.kernel_id, t.n);
 }
 
@@ -752,6 +777,10 @@ int sparkcl::enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream, bool timed)
         s.tile_table = p->cut.tm == TM_BATCHED ? 1 : 0;
         s.mixed = p->cut.mixed ? 1 : 0;
         s.mode = (uint32_t)p->mode;
+        for (uint32_t k = 0; k < 3 && p->cut.mixed; ++k)
+            s.mixed_tile[k] = ctx->tuning.tile_many[k]
+                                  ? ctx->tuning.tile_many[k]
+                                  : p->cut.share_tile[k + 1 == SPARKCL_MC_PI ? 1 : 0];
         ctx->have_shape = true;
     }
     return SPARKCL_OK;

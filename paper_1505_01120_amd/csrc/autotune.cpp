@@ -321,37 +321,33 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
         }
     }
 
-    // 3. Tile sizes for batches of many tasks of spread sizes (the mixed
-    //    batch), against the per-bucket table (0): one size shared by the
-    //    two streaming kernels, whose tiles run side by side in HBM, then the
-    //    Monte-Carlo kernel's.
+    // 3. Work shares for batches of many tasks of spread sizes (the mixed
+    //    batch): the tiles per CU that the batch's streaming elements (both
+    //    streaming kernels, whose tiles run side by side in HBM), then its
+    //    Monte-Carlo samples, are cut into, against the per-bucket table (0).
+    //    Explicit mixed-batch tile sizes are left unset: a size tuned on one
+    //    batch does not carry over to a batch of another total, a share does.
     {
         const std::vector<sparkcl_task> tasks = make_mixed(b);
+        best.tile_many[0] = best.tile_many[1] = best.tile_many[2] = 0;
         for (int group = 0; group < 2; ++group) {
             float best_ms = 1e30f;
-            uint32_t best_T = 0;
-            for (uint32_t tl = 13; tl <= 19; ++tl) {
-                const uint32_t T = tl == 13 ? 0u : 1u << tl; // 0 first: the table
+            uint32_t best_q = 0;
+            for (uint32_t q : {0u, 4u, 8u, 16u, 32u, 64u, 128u, 256u}) { // 0 first: the table
                 sparkcl_tuning t = best;
-                if (group == 0)
-                    t.tile_many[SPARKCL_POLY - 1] = t.tile_many[SPARKCL_FMUL - 1] = T;
-                else
-                    t.tile_many[SPARKCL_MC_PI - 1] = T;
+                t.many_tiles_per_cu[group] = q;
                 float ms = 0;
                 if (!measure(t, SPARKCL_BATCHED, tasks, &ms))
                     return abort_with(rc);
                 if (verbose)
-                    std::fprintf(stderr, "mixed %s tile %u: %.1f us\n",
-                                 group == 0 ? "streaming" : "mc_pi", T, ms * 1e3f);
+                    std::fprintf(stderr, "mixed %s tiles per CU %u: %.1f us\n",
+                                 group == 0 ? "streaming" : "mc_pi", q, ms * 1e3f);
                 if (ms < best_ms * 0.98f) {
                     best_ms = ms;
-                    best_T = T;
+                    best_q = q;
                 }
             }
-            if (group == 0)
-                best.tile_many[SPARKCL_POLY - 1] = best.tile_many[SPARKCL_FMUL - 1] = best_T;
-            else
-                best.tile_many[SPARKCL_MC_PI - 1] = best_T;
+            best.many_tiles_per_cu[group] = best_q;
         }
     }
 

@@ -46,6 +46,10 @@ class Server;
 struct Cut {
     int tm = TM_PER_LAUNCH;
     bool mixed = false;
+    // mixed batches: tiles derived from the batch's totals and the tuned
+    // tiles per CU, for the streaming kernels and the Monte-Carlo kernel
+    // (0: none derived)
+    uint32_t share_tile[2] = {0, 0};
 };
 
 // A cached, uploaded launch: device task table, tile queue, partials, sync

@@ -236,6 +236,13 @@ int tuning_validate(const sparkcl_tuning *t, std::string *why)
                    " not in {0, 256, 512, 1024}";
         return SPARKCL_EINVAL;
     }
+    for (int k = 0; k < 2; ++k)
+        if (t->many_tiles_per_cu[k] > 4096) {
+            if (why)
+                *why = "many_tiles_per_cu[" + std::to_string(k) + "] = " +
+                       std::to_string(t->many_tiles_per_cu[k]) + " is above 4096";
+            return SPARKCL_EINVAL;
+        }
     for (int k = 0; k < 3; ++k) {
         const uint32_t v = t->tile_many[k];
         if (v != 0 && (v < (1u << kMinTileLog2) || v > (1u << kMaxTileLog2) || (v & (v - 1)))) {
@@ -319,6 +326,15 @@ bool tuning_parse_json(const std::string &text,
         }
         if (const Json *b = e.get("block_many"))
             t.block_many = (uint32_t)b->num;
+        if (const Json *b = e.get("many_tiles_per_cu")) {
+            if (b->kind != Json::ARR || b->arr.size() != 2) {
+                if (err)
+                    *err = "many_tiles_per_cu must be an array of 2";
+                return false;
+            }
+            for (int k = 0; k < 2; ++k)
+                t.many_tiles_per_cu[k] = (uint32_t)b->arr[k].num;
+        }
         if (const Json *b = e.get("tile_many")) {
             if (b->kind != Json::ARR || b->arr.size() != 3) {
                 if (err)
@@ -372,7 +388,9 @@ std::string tuning_to_json(const std::map<std::string, sparkcl_tuning> &all)
           << ",\n  \"tile_many\": [" << t.tile_many[0] << ", " << t.tile_many[1] << ", "
           << t.tile_many[2] << "],\n  \"block\": [" << t.block[0] << ", " << t.block[1] << ", "
           << t.block[2] << "],\n  \"block_many\": " << t.block_many << ",\n  \"unroll\": ["
-          << t.unroll[0] << ", " << t.unroll[1] << ", " << t.unroll[2] << "],\n  \"tile\": {\n";
+          << t.unroll[0] << ", " << t.unroll[1] << ", " << t.unroll[2]
+          << "],\n  \"many_tiles_per_cu\": [" << t.many_tiles_per_cu[0] << ", "
+          << t.many_tiles_per_cu[1] << "],\n  \"tile\": {\n";
         for (int m = 0; m < SPARKCL_TUNE_MODES; ++m) {
             o << "   \"" << kModeNames[m] << "\": {\n";
             for (int k = 0; k < 3; ++k) {

@@ -68,6 +68,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_uint32 * 3), ("blocks_per_cu_many", ctypes.c_uint32),
                 ("tile_many", ctypes.c_uint32 * 3), ("block", ctypes.c_uint32 * 3),
                 ("block_many", ctypes.c_uint32), ("unroll", ctypes.c_uint32 * 3),
+                ("many_tiles_per_cu", ctypes.c_uint32 * 2),
                 ("tile", ((ctypes.c_uint32 * TUNE_BUCKETS) * 3) * TUNE_MODES)]
 
 
@@ -97,10 +98,13 @@ class ServeStats(ctypes.Structure):
 
 class LaunchShape(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint32) for f in (
-        "grid", "block", "ntiles", "ntasks", "tile_table", "mixed", "mode", "reserved")]
+        "grid", "block", "ntiles", "ntasks", "tile_table", "mixed", "mode")] + \
+        [("mixed_tile", ctypes.c_uint32 * 3)]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["mixed_tile"] = list(self.mixed_tile)
+        return d
 
 
 assert ctypes.sizeof(Task) == 96 and ctypes.sizeof(Result) == 64

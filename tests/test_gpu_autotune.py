@@ -19,6 +19,7 @@ MIN_TILE, MAX_TILE = 1 << 10, 1 << 22
 
 def entries(t: sc.Tuning):
     return (list(t.blocks_per_cu) + [t.blocks_per_cu_many] + list(t.tile_many) +
+            list(t.block) + [t.block_many] + list(t.unroll) + list(t.many_tiles_per_cu) +
             [t.tile[m][k][b] for m in range(sc.TUNE_MODES) for k in range(3)
              for b in range(sc.TUNE_BUCKETS)])
 
@@ -39,6 +40,8 @@ def test_autotune_table_cache_and_parity(tmp_path):
     for u in tuned.unroll:
         assert u in (2, 4, 8), u
     assert tuned.unroll[2] == 4  # the Monte-Carlo kernel has no streaming loop
+    for q in tuned.many_tiles_per_cu:
+        assert q in (0, 4, 8, 16, 32, 64, 128, 256), q
     for v in tuned.tile_many:
         assert v == 0 or (MIN_TILE <= v <= MAX_TILE and v & (v - 1) == 0), v
     for m in range(sc.TUNE_MODES):

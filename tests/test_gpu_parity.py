@@ -396,10 +396,26 @@ def test_beyond_32_bit_element_counts(ctx):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("many", [(4096, 8192, 2048), (1 << 16, 1 << 16, 1 << 15), (0, 1024, 0)])
-def test_mixed_batch_tile_sizes(ctx, many):
-    # 600 tasks spanning many size buckets take the mixed-batch tile sizes
-    # (sparkcl_tuning.tile_many, 0 = the per-bucket table) in batched modes
+def share_tile(total: int, cus: int, q: int) -> int:
+    """The mixed-batch tile a work share gives: total / (CUs x q) rounded to
+    the nearest power of two (log2 rounded half to even), clamped to
+    [2^10, 2^22]."""
+    if q == 0 or total == 0:
+        return 0
+    e = int(np.rint(math.log2(max(total / (cus * q), 1.0))))
+    return 1 << min(22, max(10, e))
+
+
+@pytest.mark.parametrize("many,share", [((4096, 8192, 2048), (0, 0)),
+                                        ((1 << 16, 1 << 16, 1 << 15), (0, 0)),
+                                        ((0, 1024, 0), (0, 0)),
+                                        ((0, 0, 0), (16, 8)),
+                                        ((0, 4096, 0), (64, 2))])
+def test_mixed_batch_tile_sizes(ctx, many, share):
+    # 600 tasks spanning many size buckets take the mixed-batch tile sizes in
+    # batched modes: given per kernel (sparkcl_tuning.tile_many), else derived
+    # from the batch's totals and a number of tiles per CU
+    # (many_tiles_per_cu), else the per-bucket table
     sizes = datagen.lognormal_sizes(600, 9, 3, 8192, math.log(4.0), 16, 300_000)
     kids = datagen.uniform_kernel_ids(600, 9, 4)
     parts = [datagen.make_part(int(k), int(n), i) for i, (n, k) in enumerate(zip(sizes, kids))]
@@ -407,10 +423,26 @@ def test_mixed_batch_tile_sizes(ctx, many):
     t = sc.Tuning.from_buffer_copy(saved)
     for k in range(3):
         t.tile_many[k] = many[k]
+    t.many_tiles_per_cu[0], t.many_tiles_per_cu[1] = share
     ctx.set_tuning(t)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    stream = sum(p.n for p in parts if p.kid != datagen.MC_PI)
+    mc = sum(p.n for p in parts if p.kid == datagen.MC_PI)
+    want = [many[0] or share_tile(stream, cus, share[0]),
+            many[1] or share_tile(stream, cus, share[0]),
+            many[2] or share_tile(mc, cus, share[1])]
     try:
         for mode in (sc.BATCHED, sc.GRAPH):
             run_and_check(ctx, parts, mode)
+            shape = ctx.last_launch_shape()
+            if many[0] == 1 << 16:
+                # 2^16 tiles leave the executor's blocks under two tiles each:
+                # the batch is cut with the per-launch table instead
+                assert shape["tile_table"] == 0 and shape["mixed"] == 0, shape
+                assert shape["mixed_tile"] == [0, 0, 0], shape
+            else:
+                assert shape["mixed"] == 1 and shape["tile_table"] == 1, shape
+                assert shape["mixed_tile"] == want, (shape, want)
     finally:
         ctx.set_tuning(saved)
 
