@@ -560,6 +560,13 @@ def bench_wordcount(ctx, sc, reps=5) -> dict:
     return {"ms": sec * 1e3, "GBps": nbytes / sec / 1e9, "words_per_s": nw / sec,
             "hbm_frac": nbytes / sec / 1e9 / HBM_PEAK_GBS, "words": nw, "distinct": nd,
             "matches_oracle": exact, "timing": "host-observed blocking call, median of 5",
+            # the scan kernel issues about 0.5 VALU, 0.5 SALU and 0.06 LDS
+            # wave-instructions per text byte and inserts into an LDS hash
+            # table: it is bound by instruction issue and LDS latency, not
+            # by HBM (counters in the WordCount profile summary)
+            "bound": {"kind": "issue (VALU, SALU, LDS table inserts)",
+                      "hbm_frac": nbytes / sec / 1e9 / HBM_PEAK_GBS,
+                      "summary": "profiles/k_wordcount_1gib_counters.md"},
             "cpu_baseline": {"GBps": base_n / cpu_sec / 1e9, "cores": 1, "kind": "oracle",
                              "sample": "the 64 MiB base corpus, one thread"}}
 
