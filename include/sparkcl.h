@@ -369,10 +369,12 @@ typedef struct sparkcl_tuning {
     uint32_t many_tiles_per_cu[2]; /* for such a batch of many spread tasks,
                                     when tile_many leaves a kernel at 0: the
                                     number of tiles per CU to cut the batch's
-                                    streaming (POLY, FMUL) elements [0] or
-                                    Monte-Carlo samples [1] into; the tile is
-                                    the batch's total over (CUs x this value),
-                                    rounded to the nearest power of two in
+                                    streaming input bytes [0] (4 per POLY
+                                    element, 8 per FMUL element) or its
+                                    Monte-Carlo samples [1] into; a kernel's
+                                    tile is the batch's total over (CUs x
+                                    this value), in its own elements, rounded
+                                    to the nearest power of two in
                                     [2^10, 2^22].  A work share, unlike a tile
                                     size, carries over between batches of
                                     different totals.  0 = use the per-bucket

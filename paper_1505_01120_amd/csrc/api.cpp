@@ -86,9 +86,14 @@ int check_task(const sparkcl_task &t, uint32_t *variant)
     return SPARKCL_OK;
 }
 
+uint64_t input_bytes(uint32_t kernel_id)
+{
+    return kernel_id == SPARKCL_FMUL ? 8ull : 4ull;
+}
+
 uint64_t offload_cost(const sparkcl_task &t)
 {
-    return t.n * (t.kernel_id == SPARKCL_FMUL ? 8ull : 4ull);
+    return t.n * input_bytes(t.kernel_id);
 }
 
 bool declined(const sparkcl_ctx *ctx, const sparkcl_task &t)
@@ -240,15 +245,20 @@ sparkcl::Cut sparkcl::plan_cut(const sparkcl_ctx *ctx, int mode, const sparkcl_t
     c.tm = mode != SPARKCL_PER_LAUNCH && !host_in ? TM_BATCHED : TM_PER_LAUNCH;
     // A batch of many tasks of widely spread sizes takes the mixed-batch
     // tile sizes instead of the per-bucket table (tuned on batches of one
-    // size): one tile size per kernel class, so small tasks run whole and
-    // large ones in mid-sized interleaved tiles.  On the 4096-task uneven
-    // batch one 2^16 tile for the streaming kernels ran it in 515 us against
-    // 553 us with the table.  The size is either given (tile_many) or derived
-    // from the batch's own total work, cut into a tuned number of tiles per
-    // CU: the share, not the size, is what carries over between batches.
+    // size): one tile size per kernel, so small tasks run whole and large
+    // ones in mid-sized interleaved tiles.  On the 4096-task uneven batch one
+    // 2^16 tile for the streaming kernels ran it in 515 us against 553 us
+    // with the table.  The size is either given (tile_many) or derived from
+    // the batch's own total work, cut into a tuned number of tiles per CU:
+    // the share, not the size, is what carries over between batches.
+    // Streaming work is counted in input bytes, so a POLY tile (4 bytes per
+    // element) holds twice the elements of an FMUL tile (8): tiles of equal
+    // bytes stream for equal times and carry equal shares of the per-tile
+    // set-up (on the uneven batch, 2^16 POLY with 2^15 FMUL elements ran in
+    // 461 us against 471 us with 2^16 for both).
     if (c.tm == TM_BATCHED && ntasks >= kMixedMinTasks) {
         uint32_t lo = SPARKCL_TUNE_BUCKETS, hi = 0;
-        uint64_t total[2] = {0, 0}; // streaming elements, Monte-Carlo samples
+        uint64_t total[2] = {0, 0}; // streaming input bytes, Monte-Carlo samples
         for (uint32_t i = 0; i < ntasks; ++i) {
             const uint32_t b = size_bucket(tasks[i].n);
             lo = std::min(lo, b);
@@ -256,17 +266,19 @@ sparkcl::Cut sparkcl::plan_cut(const sparkcl_ctx *ctx, int mode, const sparkcl_t
             if (tasks[i].kernel_id == SPARKCL_MC_PI)
                 total[1] += tasks[i].n;
             else if (tasks[i].kernel_id == SPARKCL_POLY || tasks[i].kernel_id == SPARKCL_FMUL)
-                total[0] += tasks[i].n;
+                total[0] += tasks[i].n * input_bytes(tasks[i].kernel_id);
         }
         c.mixed = hi >= lo + kMixedMinSpan;
-        for (int k = 0; k < 2 && c.mixed; ++k) {
+        for (uint32_t kid = SPARKCL_POLY; kid <= SPARKCL_MC_PI && c.mixed; ++kid) {
+            const int k = kid == SPARKCL_MC_PI ? 1 : 0;
             const uint32_t q = ctx->tuning.many_tiles_per_cu[k];
             if (q == 0 || total[k] == 0)
                 continue;
-            const double want = (double)total[k] / ((double)ctx->cus * q);
+            const double per_elem = k == 1 ? 1.0 : (double)input_bytes(kid);
+            const double want = (double)total[k] / ((double)ctx->cus * q) / per_elem;
             const double l2 = std::rint(std::log2(std::max(want, 1.0)));
             const int e = (int)std::min<double>(kMaxTileLog2, std::max<double>(kMinTileLog2, l2));
-            c.share_tile[k] = 1u << e;
+            c.share_tile[kid - 1] = 1u << e;
         }
     }
     if (c.tm == TM_BATCHED) {
@@ -284,7 +296,7 @@ sparkcl::Cut sparkcl::plan_cut(const sparkcl_ctx *ctx, int mode, const sparkcl_t
         if (tiles < 2 * grid) {
             c.tm = TM_PER_LAUNCH;
             c.mixed = false;
-            c.share_tile[0] = c.share_tile[1] = 0;
+            c.share_tile[0] = c.share_tile[1] = c.share_tile[2] = 0;
         }
     }
     return c;
@@ -296,7 +308,7 @@ uint32_t sparkcl::cut_tile(const sparkcl_ctx *ctx, const Cut &c, const sparkcl_t
         t.kernel_id <= SPARKCL_MC_PI) {
         if (ctx->tuning.tile_many[t.kernel_id - 1])
             return ctx->tuning.tile_many[t.kernel_id - 1];
-        const uint32_t s = c.share_tile[t.kernel_id == SPARKCL_MC_PI ? 1 : 0];
+        const uint32_t s = c.share_tile[t.kernel_id - 1];
         if (s)
             return s;
     }
@@ -780,7 +792,7 @@ int sparkcl::enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream, bool timed)
         for (uint32_t k = 0; k < 3 && p->cut.mixed; ++k)
             s.mixed_tile[k] = ctx->tuning.tile_many[k]
                                   ? ctx->tuning.tile_many[k]
-                                  : p->cut.share_tile[k + 1 == SPARKCL_MC_PI ? 1 : 0];
+                                  : p->cut.share_tile[k];
         ctx->have_shape = true;
     }
     return SPARKCL_OK;

@@ -239,45 +239,58 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
         best.blocks_per_cu[kid - 1] = best_bpc;
         best.tile[TM_BATCHED][kid - 1][kRefLog2] = best_tile;
 
-        // 1b. Block size and loads in flight at that tile, then the blocks
-        //     per CU again at the chosen shape (blocks per CU count 256-thread
-        //     blocks: a 512-thread block takes two).  Ties (within 2%) go to
-        //     the defaults (256 threads, 4 loads), which come first.
+        // 1b. Blocks per CU, block size and loads in flight jointly at that
+        //     tile, against the step-1 choice (256 threads, 4 loads), which a
+        //     candidate must beat by 2%; then the tile again at the chosen
+        //     shape.  Blocks per CU count 256-thread blocks (a 512-thread
+        //     block takes two), so a bigger block needs as many of them.
+        //     On MI355X the joint search matters: POLY streamed 2^22-element
+        //     partitions fastest at 1 block per CU with 8 loads in flight, a
+        //     point that neither one-dimensional search visits.
         {
+            float shape_ms = best_ms;
             const sparkcl_tuning base = best;
-            float shape_ms = 1e30f;
             for (uint32_t blk : {256u, 512u, 1024u})
-                for (uint32_t u : {4u, 2u, 8u}) {
-                    if (kid == SPARKCL_MC_PI && u != 4)
-                        continue; // no streaming loop
-                    sparkcl_tuning t = base;
-                    t.block[kid - 1] = blk;
-                    t.unroll[kid - 1] = u;
-                    if (!batched_takes(t, kid, tasks, best_tile))
-                        continue;
-                    float ms = 0;
-                    if (!measure(t, SPARKCL_BATCHED, tasks, &ms))
-                        return abort_with(rc);
-                    if (verbose)
-                        std::fprintf(stderr, "shape kid %u block %u unroll %u: %.1f us\n", kid,
-                                     blk, u, ms * 1e3f);
-                    if (ms < shape_ms * 0.98f) {
-                        shape_ms = ms;
-                        best.block[kid - 1] = blk;
-                        best.unroll[kid - 1] = u;
+                for (uint32_t bpc = blk / 256; bpc <= occ; ++bpc)
+                    for (uint32_t u : {4u, 2u, 8u}) {
+                        if (kid == SPARKCL_MC_PI && u != 4)
+                            continue; // no streaming loop
+                        if (blk == 256 && u == 4 && bpc == best_bpc)
+                            continue; // the step-1 choice
+                        sparkcl_tuning t = base;
+                        t.blocks_per_cu[kid - 1] = bpc;
+                        t.block[kid - 1] = blk;
+                        t.unroll[kid - 1] = u;
+                        if (!batched_takes(t, kid, tasks, best_tile))
+                            continue;
+                        float ms = 0;
+                        if (!measure(t, SPARKCL_BATCHED, tasks, &ms))
+                            return abort_with(rc);
+                        if (verbose)
+                            std::fprintf(stderr,
+                                         "shape kid %u block %u bpc %u unroll %u: %.1f us\n",
+                                         kid, blk, bpc, u, ms * 1e3f);
+                        if (ms < shape_ms * 0.98f) {
+                            shape_ms = ms;
+                            best.blocks_per_cu[kid - 1] = bpc;
+                            best.block[kid - 1] = blk;
+                            best.unroll[kid - 1] = u;
+                        }
                     }
-                }
-            for (uint32_t bpc = 1; bpc <= occ; ++bpc) {
+            for (uint32_t tl = 14; tl <= 20; ++tl) {
                 sparkcl_tuning t = best;
-                t.blocks_per_cu[kid - 1] = bpc;
-                if (bpc == best_bpc || !batched_takes(t, kid, tasks, best_tile))
+                t.tile[TM_BATCHED][kid - 1][kRefLog2] = 1u << tl;
+                if ((1u << tl) == best_tile || !batched_takes(t, kid, tasks, 1u << tl))
                     continue;
                 float ms = 0;
                 if (!measure(t, SPARKCL_BATCHED, tasks, &ms))
                     return abort_with(rc);
+                if (verbose)
+                    std::fprintf(stderr, "retile kid %u tile 2^%u: %.1f us\n", kid, tl,
+                                 ms * 1e3f);
                 if (ms < shape_ms * 0.98f) {
                     shape_ms = ms;
-                    best.blocks_per_cu[kid - 1] = bpc;
+                    best.tile[TM_BATCHED][kid - 1][kRefLog2] = 1u << tl;
                 }
             }
         }
@@ -322,9 +335,10 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
     }
 
     // 3. Work shares for batches of many tasks of spread sizes (the mixed
-    //    batch): the tiles per CU that the batch's streaming elements (both
-    //    streaming kernels, whose tiles run side by side in HBM), then its
-    //    Monte-Carlo samples, are cut into, against the per-bucket table (0).
+    //    batch): the tiles per CU that the batch's streaming input bytes
+    //    (both streaming kernels, whose tiles run side by side in HBM), then
+    //    its Monte-Carlo samples, are cut into, against the per-bucket table
+    //    (0).
     //    Explicit mixed-batch tile sizes are left unset: a size tuned on one
     //    batch does not carry over to a batch of another total, a share does.
     {
@@ -333,7 +347,7 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
         for (int group = 0; group < 2; ++group) {
             float best_ms = 1e30f;
             uint32_t best_q = 0;
-            for (uint32_t q : {0u, 4u, 8u, 16u, 32u, 64u, 128u, 256u}) { // 0 first: the table
+            for (uint32_t q : {0u, 4u, 8u, 12u, 16u, 24u, 32u, 48u, 64u, 128u}) { // 0: the table
                 sparkcl_tuning t = best;
                 t.many_tiles_per_cu[group] = q;
                 float ms = 0;

@@ -507,10 +507,13 @@ __device__ __forceinline__ void read_result(const sparkcl_result *p, double &s,
 
 // ---- one tile, start to finish ------------------------------------------
 // Thread 0 of the block that completes a task: write its result and, when
-// serving, publish the completion word.
+// serving, publish the completion word.  With `wait` false the result stores
+// are left to complete while the block goes on: the persistent executor waits
+// for all of a block's stores once, before the block counts itself out, and
+// only then is any result read on the device (the RDD total).
 __device__ __forceinline__ void finish_task(const TaskDev *__restrict__ tp, const LaunchOut &L,
                                             const Red &t, uint64_t t_start, uint32_t variant,
-                                            uint32_t idx)
+                                            uint32_t idx, bool wait = true)
 {
     write_result(L.results + idx, uni(tp->ops), t, t_start, device_ns(L.ns_per_tick),
                  variant == V_DECLINED ? SPARKCL_EDECLINED : SPARKCL_OK);
@@ -520,14 +523,15 @@ __device__ __forceinline__ void finish_task(const TaskDev *__restrict__ tp, cons
         __threadfence_system();
         __hip_atomic_store(L.done + idx, uni64(tp->seq) + 1, __ATOMIC_RELEASE,
                            __HIP_MEMORY_SCOPE_SYSTEM);
-    } else {
+    } else if (wait) {
         own_stores_complete();
     }
 }
 
 // Returns true in the block that completed the task (after writing its
-// result); callers use it only for the RDD-level step.
-template <class Body>
+// result); callers use it only for the RDD-level step.  kExec: called by the
+// persistent executor, which waits for the result stores at its exit.
+template <bool kExec = false, class Body>
 __device__ __forceinline__ bool run_tile_with(const TaskDev *__restrict__ tp, uint32_t j,
                                               const LaunchOut &L, Body body)
 {
@@ -552,7 +556,7 @@ __device__ __forceinline__ bool run_tile_with(const TaskDev *__restrict__ tp, ui
         // combine of a single partial is the partial itself, except that its
         // FP64 sum starts from +0.0, which the + 0.0 below reproduces.
         if (threadIdx.x == 0)
-            finish_task(tp, L, Red{r.s + 0.0, r.m, r.h, count}, t0, variant, idx);
+            finish_task(tp, L, Red{r.s + 0.0, r.m, r.h, count}, t0, variant, idx, !kExec);
         __syncthreads();
         return true;
     }
@@ -590,7 +594,7 @@ __device__ __forceinline__ bool run_tile_with(const TaskDev *__restrict__ tp, ui
                            __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&sync[idx].ticket, 0u, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-        finish_task(tp, L, t, t_start, variant, idx);
+        finish_task(tp, L, t, t_start, variant, idx, !kExec);
     }
     // A barrier closes every thread-0 region that ends a loop iteration of the
     // callers: without it the compiler may sink the region past the loop
@@ -601,10 +605,11 @@ __device__ __forceinline__ bool run_tile_with(const TaskDev *__restrict__ tp, ui
 
 // The registry kernels' tile body (maps fused with their reductions, or the
 // Monte-Carlo count) run through the common tile epilogue.
+template <bool kExec = false>
 __device__ __forceinline__ bool run_tile(const TaskDev *__restrict__ tp, uint32_t j,
                                          const LaunchOut &L)
 {
-    return run_tile_with(tp, j, L, [&](Acc &a) -> uint64_t {
+    return run_tile_with<kExec>(tp, j, L, [&](Acc &a) -> uint64_t {
         const uint32_t variant = uni(tp->variant);
         const uint32_t T = uni(tp->tile_elems);
         const uint32_t ntiles = uni(tp->ntiles);
@@ -813,7 +818,7 @@ __device__ __forceinline__ bool chain_tile(const TaskDev *__restrict__ tp,
                                            const ChainDev *__restrict__ chain, uint32_t j,
                                            const LaunchOut &L)
 {
-    return run_tile_with(tp, j, L, [&](Acc &a) -> uint64_t {
+    return run_tile_with<true>(tp, j, L, [&](Acc &a) -> uint64_t {
         const uint32_t variant = uni(tp->variant);
         if (variant == V_DECLINED)
             return 0;
@@ -909,7 +914,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(const TaskDev *__restrict__
                                                   uint32_t ntiles, LaunchOut L)
 {
     executor(tasks, tiles, ntiles, L,
-             [&](const TaskDev *tp, uint32_t j) { return run_tile(tp, j, L); });
+             [&](const TaskDev *tp, uint32_t j) { return run_tile<true>(tp, j, L); });
 }
 
 // The persistent executor over tasks that share one map chain.

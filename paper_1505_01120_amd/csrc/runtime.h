@@ -34,6 +34,8 @@ int check_task(const sparkcl_task &t, uint32_t *variant);
 // Selective execution: a task's offload cost in bytes, and whether the
 // context's threshold declines it.
 uint64_t offload_cost(const sparkcl_task &t);
+// Input bytes a streaming kernel reads per element (x, and y for FMUL).
+uint64_t input_bytes(uint32_t kernel_id);
 bool declined(const sparkcl_ctx *ctx, const sparkcl_task &t);
 
 // Host steady-clock time in ns.
@@ -46,10 +48,9 @@ class Server;
 struct Cut {
     int tm = TM_PER_LAUNCH;
     bool mixed = false;
-    // mixed batches: tiles derived from the batch's totals and the tuned
-    // tiles per CU, for the streaming kernels and the Monte-Carlo kernel
-    // (0: none derived)
-    uint32_t share_tile[2] = {0, 0};
+    // mixed batches: each kernel's tile derived from the batch's totals and
+    // the tuned tiles per CU (index kernel id - 1; 0: none derived)
+    uint32_t share_tile[3] = {0, 0, 0};
 };
 
 // A cached, uploaded launch: device task table, tile queue, partials, sync

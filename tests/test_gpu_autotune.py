@@ -41,7 +41,7 @@ def test_autotune_table_cache_and_parity(tmp_path):
         assert u in (2, 4, 8), u
     assert tuned.unroll[2] == 4  # the Monte-Carlo kernel has no streaming loop
     for q in tuned.many_tiles_per_cu:
-        assert q in (0, 4, 8, 16, 32, 64, 128, 256), q
+        assert q in (0, 4, 8, 12, 16, 24, 32, 48, 64, 128), q
     for v in tuned.tile_many:
         assert v == 0 or (MIN_TILE <= v <= MAX_TILE and v & (v - 1) == 0), v
     for m in range(sc.TUNE_MODES):

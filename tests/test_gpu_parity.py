@@ -396,7 +396,7 @@ def test_beyond_32_bit_element_counts(ctx):
     torch.cuda.empty_cache()
 
 
-def share_tile(total: int, cus: int, q: int) -> int:
+def share_tile(total: float, cus: int, q: int) -> int:
     """The mixed-batch tile a work share gives: total / (CUs x q) rounded to
     the nearest power of two (log2 rounded half to even), clamped to
     [2^10, 2^22]."""
@@ -426,10 +426,12 @@ def test_mixed_batch_tile_sizes(ctx, many, share):
     t.many_tiles_per_cu[0], t.many_tiles_per_cu[1] = share
     ctx.set_tuning(t)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    stream = sum(p.n for p in parts if p.kid != datagen.MC_PI)
+    # streaming work in input bytes (4 per POLY element, 8 per FMUL element)
+    stream = sum(p.n * (8 if p.kid == datagen.FMUL else 4) for p in parts
+                 if p.kid != datagen.MC_PI)
     mc = sum(p.n for p in parts if p.kid == datagen.MC_PI)
-    want = [many[0] or share_tile(stream, cus, share[0]),
-            many[1] or share_tile(stream, cus, share[0]),
+    want = [many[0] or share_tile(stream / 4, cus, share[0]),
+            many[1] or share_tile(stream / 8, cus, share[0]),
             many[2] or share_tile(mc, cus, share[1])]
     try:
         for mode in (sc.BATCHED, sc.GRAPH):
