@@ -546,7 +546,14 @@ def bench_wordcount(ctx, sc, reps=5) -> dict:
         t0 = time.perf_counter()
         _, _, nd, nw = wctx.wordcount(text, cap, keys, counts)
         times.append(time.perf_counter() - t0)
+    # the first occurrence of every distinct key (sparkcl_wordcount_locate)
+    loc_times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        offs = wctx.wordcount_locate(text, keys, nd)
+        loc_times.append(time.perf_counter() - t0)
     wctx.destroy()
+    loc_sec = sorted(loc_times)[len(loc_times) // 2]
     sec = sorted(times)[len(times) // 2]
     t0 = time.perf_counter()
     ok, oc, on = oracle.wordcount(base)
@@ -556,10 +563,16 @@ def bench_wordcount(ctx, sc, reps=5) -> dict:
     order = np.argsort(k)
     exact = bool(nw == rep * on and np.array_equal(k[order], ok) and
                  np.array_equal(c[order], oc * np.uint64(rep)))
+    # every key's first word lies in the first copy of the base
+    o = offs[:nd].cpu().numpy().view(np.uint64)
+    loc_exact = bool(np.array_equal(o, oracle.wordcount_first(base, k)))
     nbytes = base_n * rep
     return {"ms": sec * 1e3, "GBps": nbytes / sec / 1e9, "words_per_s": nw / sec,
             "hbm_frac": nbytes / sec / 1e9 / HBM_PEAK_GBS, "words": nw, "distinct": nd,
             "matches_oracle": exact, "timing": "host-observed blocking call, median of 5",
+            "locate": {"ms": loc_sec * 1e3, "GBps": nbytes / loc_sec / 1e9, "keys": nd,
+                       "matches_oracle": loc_exact,
+                       "what": "first byte offset of each distinct key's word"},
             # the scan kernel issues about 0.5 VALU, 0.5 SALU and 0.06 LDS
             # wave-instructions per text byte and inserts into an LDS hash
             # table: it is bound by instruction issue and LDS latency, not

@@ -447,6 +447,21 @@ SPARKCL_API int sparkcl_wordcount(sparkcl_ctx *ctx, const uint8_t *text, uint64_
                                   uint64_t *keys, uint64_t *counts, uint64_t capacity,
                                   uint64_t *ndistinct, uint64_t *nwords, void *stream);
 
+/* WordCount's words (sec. 3.2.3 counts words, which sparkcl_wordcount names
+   by their keys): for each of the `nkeys` distinct keys in keys[] (device
+   memory, e.g. the first *ndistinct entries sparkcl_wordcount wrote), the
+   byte offset in the same `nbytes` of device text of the first word whose
+   key it is, written to offsets[] (device, nkeys entries, caller-owned);
+   UINT64_MAX for a key that no word of the text has.  The word is the run
+   of non-whitespace bytes starting there.  One pass over the text plus a
+   lookup table from the arena (12 B per slot, two slots per key, at least
+   1024): ENOMEM if it does not fit; EINVAL if a key appears twice (offsets
+   are then unspecified); ETOOBIG if nkeys exceeds 2^32 - 1 or nbytes
+   exceeds 2^40.  Blocking. */
+SPARKCL_API int sparkcl_wordcount_locate(sparkcl_ctx *ctx, const uint8_t *text,
+                                         uint64_t nbytes, const uint64_t *keys,
+                                         uint64_t nkeys, uint64_t *offsets, void *stream);
+
 /* Selective execution helper: the smallest offload cost (bytes, as defined
    at sparkcl_config.offload_min_bytes) at which running a task on this GPU
    beats a host path that processes `host_bytes_per_s`.  The GPU side is

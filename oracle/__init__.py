@@ -88,6 +88,8 @@ def lib() -> ctypes.CDLL:
             L.oracle_wordcount.argtypes = [P, U64, P, P, U64, ctypes.POINTER(U64),
                                            ctypes.POINTER(U64)]
             L.oracle_wordcount.restype = ctypes.c_int
+            L.oracle_wordcount_first.argtypes = [P, U64, P, U64, P]
+            L.oracle_wordcount_first.restype = ctypes.c_int
             L.oracle_rdd_total.argtypes = [ctypes.POINTER(Result), U64, U32,
                                            ctypes.POINTER(Result)]
             _lib = L
@@ -235,6 +237,20 @@ def wordcount(text) -> tuple[np.ndarray, np.ndarray, int]:
     if rc != 0:
         raise MemoryError("oracle_wordcount failed")
     return keys[:nd.value].copy(), counts[:nd.value].copy(), nw.value
+
+
+def wordcount_first(text, keys) -> np.ndarray:
+    """O10 words: for each query key (uint64), the byte offset of the first
+    word of `text` with that key, UINT64_MAX when none has it."""
+    t = np.frombuffer(text, dtype=np.uint8) if isinstance(text, (bytes, bytearray)) \
+        else np.ascontiguousarray(text, dtype=np.uint8)
+    q = np.ascontiguousarray(keys, dtype=np.uint64)
+    out = np.empty(max(q.size, 1), dtype=np.uint64)
+    rc = lib().oracle_wordcount_first(_ptr(t) if t.size else None, t.size,
+                                      _ptr(q) if q.size else None, q.size, _ptr(out))
+    if rc != 0:
+        raise MemoryError("oracle_wordcount_first failed")
+    return out[:q.size].copy()
 
 
 def chain_map(x, y, kid: int, coef=(), c=np.float32(0.1), stages=()) -> np.ndarray:

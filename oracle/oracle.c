@@ -342,3 +342,66 @@ int oracle_wordcount(const uint8_t *text, uint64_t nbytes, uint64_t *keys,
     *nwords = nw;
     return nd <= cap ? 0 : -1;
 }
+
+/* O10 WordCount's words: the first occurrence of each key.  Tokenise in byte
+ * order as above, pair every word's key with the offset of its first byte,
+ * sort the pairs by key and then offset, and answer each query key with the
+ * offset of its first pair (UINT64_MAX when no word has the key).            */
+struct key_off {
+    uint64_t key, off;
+};
+
+static int cmp_key_off(const void *a, const void *b)
+{
+    const struct key_off *x = a, *y = b;
+    if (x->key != y->key)
+        return x->key < y->key ? -1 : 1;
+    return x->off < y->off ? -1 : x->off > y->off ? 1 : 0;
+}
+
+int oracle_wordcount_first(const uint8_t *text, uint64_t nbytes, const uint64_t *keys,
+                           uint64_t nkeys, uint64_t *offsets)
+{
+    uint64_t nw = 0, room = 1024;
+    struct key_off *all = malloc(room * sizeof(*all));
+    if (!all)
+        return -1;
+    uint64_t i = 0;
+    while (i < nbytes) {
+        if (is_space(text[i])) {
+            ++i;
+            continue;
+        }
+        uint64_t j = i;
+        while (j < nbytes && !is_space(text[j]))
+            ++j;
+        if (nw == room) {
+            room *= 2;
+            struct key_off *grown = realloc(all, room * sizeof(*all));
+            if (!grown) {
+                free(all);
+                return -1;
+            }
+            all = grown;
+        }
+        all[nw].key = oracle_fnv1a64(text + i, j - i);
+        all[nw].off = i;
+        ++nw;
+        i = j;
+    }
+    qsort(all, nw, sizeof(*all), cmp_key_off);
+    for (uint64_t q = 0; q < nkeys; ++q) {
+        /* the first pair whose key is not below the query */
+        uint64_t lo = 0, hi = nw;
+        while (lo < hi) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if (all[mid].key < keys[q])
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        offsets[q] = (lo < nw && all[lo].key == keys[q]) ? all[lo].off : UINT64_MAX;
+    }
+    free(all);
+    return 0;
+}

@@ -109,6 +109,11 @@ uint64_t oracle_fnv1a64(const uint8_t *bytes, uint64_t len);
 int oracle_wordcount(const uint8_t *text, uint64_t nbytes, uint64_t *keys,
                      uint64_t *counts, uint64_t cap, uint64_t *ndistinct,
                      uint64_t *nwords);
+/*     For each of the nkeys query keys, the byte offset of the first word
+ *     whose key it is, or UINT64_MAX when no word has it.  Returns 0, or -1
+ *     if memory runs out. */
+int oracle_wordcount_first(const uint8_t *text, uint64_t nbytes, const uint64_t *keys,
+                           uint64_t nkeys, uint64_t *offsets);
 
 #ifdef __cplusplus
 }

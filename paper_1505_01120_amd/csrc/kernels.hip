@@ -1365,28 +1365,22 @@ __device__ __forceinline__ void lds_barrier()
 // word's length off the bitmap, hashes its bytes from the staged chunk and
 // counts the key in the block's LDS table.  A word that runs past the
 // look-ahead continues from the text in global memory, one byte at a time.
-__global__ __launch_bounds__(kBlock) void k_wordcount(WcArgs a)
+// The scan front end shared by counting and locating: the block's chunks of
+// the text are staged in LDS, each wave lists its words' starts and hashes
+// one word per lane; word(h, off) is called with the word's key and the byte
+// offset of its first byte.  Returns the number of words this thread listed.
+template <class Word>
+__device__ __forceinline__ uint64_t wc_scan(const uint8_t *text, uint64_t n, Word word)
 {
     constexpr uint32_t kLookSpans = kWcLook / 16;
     constexpr uint32_t kSpans = kBlock + kLookSpans;
-    __shared__ uint64_t sk[kWcSlots];
-    __shared__ uint32_t sc[kWcSlots];
     __shared__ uint4 st4[kSpans + 1];               // (+ 16 bytes read past the end)
     __shared__ uint32_t sepm[kSpans];               // whitespace bits of each span
     __shared__ uint16_t starts16[kWaves][64 * 8];   // a 16-byte span holds <= 8 word starts
-    __shared__ uint32_t scnt[1u << kWcPartBits];    // spill appends per partition
     __shared__ uint32_t sh_prev;
     const uint8_t *st = reinterpret_cast<const uint8_t *>(st4);
-    for (uint32_t i = threadIdx.x; i < kWcSlots; i += kBlock) {
-        sk[i] = 0;
-        sc[i] = 0;
-    }
-    for (uint32_t i = threadIdx.x; i < (1u << kWcPartBits); i += kBlock)
-        scnt[i] = 0;
     if (threadIdx.x == 0)
         st4[kSpans] = make_uint4(0x20202020u, 0x20202020u, 0x20202020u, 0x20202020u);
-    const uint8_t *text = a.text;
-    const uint64_t n = a.n;
     const bool vec = ((uintptr_t)text & 15u) == 0;
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
     uint16_t *wl = starts16[wave];
@@ -1488,9 +1482,27 @@ __global__ __launch_bounds__(kBlock) void k_wordcount(WcArgs a)
                     h = fnv_step(h, byte);
                 }
             }
-            wc_local_add(sk, sc, scnt, a, h);
+            word(h, c0 + s0);
         }
     }
+    return words;
+}
+
+__global__ __launch_bounds__(kBlock) void k_wordcount(WcArgs a)
+{
+    __shared__ uint64_t sk[kWcSlots];
+    __shared__ uint32_t sc[kWcSlots];
+    __shared__ uint32_t scnt[1u << kWcPartBits];    // spill appends per partition
+    for (uint32_t i = threadIdx.x; i < kWcSlots; i += kBlock) {
+        sk[i] = 0;
+        sc[i] = 0;
+    }
+    for (uint32_t i = threadIdx.x; i < (1u << kWcPartBits); i += kBlock)
+        scnt[i] = 0;
+    uint64_t words = wc_scan(a.text, a.n, [&](uint64_t h, uint64_t) {
+        wc_local_add(sk, sc, scnt, a, h);
+    });
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
     __syncthreads();
     for (uint32_t i = tid; i < kWcSlots; i += kBlock)
         if (sk[i])
@@ -1503,6 +1515,68 @@ __global__ __launch_bounds__(kBlock) void k_wordcount(WcArgs a)
         words += __shfl_xor(words, o);
     if (lane == 0 && words)
         atomicAdd((unsigned long long *)&a.ctl[0], (unsigned long long)words);
+}
+
+// ---- WordCount's words: the first occurrence of each key --------------------
+// A lookup table from key to the key's index in the caller's array (open
+// addressing at load <= 1/2, key 0 = empty; the key 0 itself is kept in
+// ctl[0] as index + 1), then one pass of the scan front end in which every
+// word whose key is in the table lowers that key's offset to its own with an
+// atomic minimum.  A word reads the key's current offset first and skips the
+// atomic when that is already lower, so after a key's first few words its
+// later ones cost one load.
+__global__ __launch_bounds__(kBlock) void k_wl_build(WlArgs l)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= l.nkeys)
+        return;
+    l.offsets[i] = ~0ull;
+    const uint64_t h = l.keys[i];
+    if (h == 0) {
+        if (atomicCAS((unsigned long long *)&l.ctl[0], 0ull, (unsigned long long)(i + 1)) != 0)
+            atomicOr((unsigned long long *)&l.ctl[1], 1ull); // the key 0 twice
+        return;
+    }
+    uint64_t s = h & l.mask;
+    for (uint64_t probe = 0; probe <= l.mask; ++probe) {
+        const uint64_t old =
+            atomicCAS((unsigned long long *)&l.tkeys[s], 0ull, (unsigned long long)h);
+        if (old == 0) {
+            l.tidx[s] = (uint32_t)i;
+            return;
+        }
+        if (old == h) {
+            atomicOr((unsigned long long *)&l.ctl[1], 1ull); // a key twice
+            return;
+        }
+        s = (s + 1) & l.mask;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_wl_scan(WlArgs l)
+{
+    (void)wc_scan(l.text, l.n, [&](uint64_t h, uint64_t off) {
+        uint64_t idx = ~0ull;
+        if (h == 0) {
+            const uint64_t z = l.ctl[0];
+            if (z)
+                idx = z - 1;
+        } else {
+            // the table is at most half full, so a probe run ends at an
+            // empty slot
+            for (uint64_t s = h & l.mask;; s = (s + 1) & l.mask) {
+                const uint64_t k = l.tkeys[s];
+                if (k == h) {
+                    idx = l.tidx[s];
+                    break;
+                }
+                if (k == 0)
+                    break;
+            }
+        }
+        if (idx != ~0ull && l.offsets[idx] > off)
+            atomicMin((unsigned long long *)&l.offsets[idx], (unsigned long long)off);
+    });
 }
 
 // Merge of the spill regions: block b counts partition b / per_part's keys
@@ -1922,6 +1996,25 @@ int launch_wc_compact(const WcArgs &a, uint64_t *keys, uint64_t *counts, uint64_
         return SPARKCL_EINVAL;
     hipLaunchKernelGGL(k_wc_compact, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, a,
                        keys, counts, cap);
+    return hip_status(hipGetLastError());
+}
+
+int launch_wordcount_locate(const WlArgs &l, uint32_t scan_grid, void *stream)
+{
+    if (scan_grid == 0 || !l.offsets || !l.tkeys || !l.tidx || !l.ctl ||
+        ((l.mask + 1) & l.mask) || (l.nkeys && !l.keys) || l.nkeys > 0xFFFFFFFFull ||
+        2 * l.nkeys > l.mask + 1)
+        return SPARKCL_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (l.nkeys) {
+        const uint64_t bgrid = (l.nkeys + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL(k_wl_build, dim3((uint32_t)bgrid), dim3(kBlock), 0, s, l);
+        const int rc = hip_status(hipGetLastError());
+        if (rc != SPARKCL_OK)
+            return rc;
+    }
+    if (l.n)
+        hipLaunchKernelGGL(k_wl_scan, dim3(scan_grid), dim3(kBlock), 0, s, l);
     return hip_status(hipGetLastError());
 }
 

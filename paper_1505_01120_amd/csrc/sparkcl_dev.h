@@ -206,6 +206,22 @@ int launch_wc_merge(const WcArgs &a, uint32_t scan_grid, uint32_t per_part, void
 int launch_wc_compact(const WcArgs &a, uint64_t *keys, uint64_t *counts, uint64_t cap,
                       uint32_t grid, void *stream);
 int wordcount_blocks_per_cu(int *out);
+// WordCount's words: for each of nkeys distinct keys, the byte offset of the
+// first word with that key (UINT64_MAX if none), through a lookup table of
+// mask + 1 slots (tkeys cleared to 0 and ctl[0..1] to 0 beforehand).  ctl[0]:
+// index + 1 of the key 0; ctl[1]: set when a key repeats.
+struct WlArgs {
+    const uint8_t *text;
+    uint64_t n;
+    const uint64_t *keys;
+    uint64_t nkeys;
+    uint64_t *offsets;
+    uint64_t *tkeys;     // lookup table keys (0: empty)
+    uint32_t *tidx;      // the index of each table key in keys
+    uint64_t mask;       // table slots - 1 (a power of two minus one)
+    uint64_t *ctl;
+};
+int launch_wordcount_locate(const WlArgs &l, uint32_t scan_grid, void *stream);
 // Resident serving executor: block 0 dispatches, the rest run tiles.  Each
 // launch first discards tickets left unpublished by the previous launch.
 int launch_serve(const ServeArgs &a, uint32_t workers, void *stream);

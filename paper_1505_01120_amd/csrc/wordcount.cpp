@@ -114,4 +114,74 @@ int sparkcl_wordcount(sparkcl_ctx *ctx, const uint8_t *text, uint64_t nbytes, ui
     return SPARKCL_OK;
 }
 
+int sparkcl_wordcount_locate(sparkcl_ctx *ctx, const uint8_t *text, uint64_t nbytes,
+                             const uint64_t *keys, uint64_t nkeys, uint64_t *offsets,
+                             void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc != SPARKCL_OK)
+        return rc;
+    if ((nbytes && !text) || (nkeys && (!keys || !offsets)))
+        return fail(SPARKCL_EINVAL, "NULL argument");
+    if (nkeys == 0)
+        return SPARKCL_OK;
+    if (nbytes > kMaxN)
+        return fail(SPARKCL_ETOOBIG, "text of " + std::to_string(nbytes) +
+                                         " bytes exceeds 2^40");
+    if (nkeys > 0xFFFFFFFFull)
+        return fail(SPARKCL_ETOOBIG, "more than 2^32 - 1 keys");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint64_t slots = 1024;
+    while (slots < 2 * nkeys)
+        slots *= 2;
+    if (!ctx->occ_wordcount) {
+        int occ = 0;
+        if (wordcount_blocks_per_cu(&occ) != SPARKCL_OK || occ < 1)
+            occ = 1;
+        ctx->occ_wordcount = occ;
+    }
+    const uint64_t nchunks = std::max<uint64_t>(1, (nbytes + 4095) / 4096);
+    const uint32_t grid =
+        (uint32_t)std::min<uint64_t>(nchunks, (uint64_t)ctx->occ_wordcount * ctx->cus);
+    // table keys, then control words, then the key indices
+    const uint64_t zero_bytes = slots * 8 + 64;
+    const uint64_t bytes = zero_bytes + slots * 4;
+    const uint64_t off = ctx->arena.alloc(bytes);
+    if (off == Arena::kFail)
+        return fail(SPARKCL_ENOMEM, "word lookup table of " + std::to_string(bytes) +
+                                        " bytes does not fit the arena");
+    char *base = static_cast<char *>(ctx->dev(off));
+    WlArgs l{};
+    l.text = text;
+    l.n = nbytes;
+    l.keys = keys;
+    l.nkeys = nkeys;
+    l.offsets = offsets;
+    l.tkeys = reinterpret_cast<uint64_t *>(base);
+    l.ctl = reinterpret_cast<uint64_t *>(base + slots * 8);
+    l.tidx = reinterpret_cast<uint32_t *>(base + zero_bytes);
+    l.mask = slots - 1;
+    if ((rc = ensure_pinned(ctx, 1)) == SPARKCL_OK &&
+        (rc = launch_zero(base, zero_bytes, s)) == SPARKCL_OK &&
+        (rc = launch_wordcount_locate(l, grid, s)) == SPARKCL_OK) {
+        hipError_t e = hipMemcpyAsync(ctx->pinned, l.ctl, 16, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess)
+            rc = fail_hip(e, "word locate");
+    } else if (rc != SPARKCL_OK) {
+        (void)hipStreamSynchronize(s);
+        rc = fail(rc, "word-locate launch failed");
+    }
+    ctx->arena.release(off);
+    if (rc != SPARKCL_OK)
+        return rc;
+    uint64_t ctl[2];
+    std::memcpy(ctl, ctx->pinned, sizeof(ctl));
+    if (ctl[1])
+        return fail(SPARKCL_EINVAL, "a key appears twice in keys");
+    return SPARKCL_OK;
+}
+
 } // extern "C"

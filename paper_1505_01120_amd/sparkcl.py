@@ -117,7 +117,8 @@ EXPORTS = ("sparkcl_init", "sparkcl_destroy", "sparkcl_map", "sparkcl_map_partit
            "sparkcl_serve_stats_get", "sparkcl_serve_drain", "sparkcl_get_tuning",
            "sparkcl_set_tuning", "sparkcl_autotune", "sparkcl_strerror",
            "sparkcl_last_error", "sparkcl_last_kernel_ms", "sparkcl_version",
-           "sparkcl_offload_breakeven", "sparkcl_wordcount", "sparkcl_reduce_noalloc",
+           "sparkcl_offload_breakeven", "sparkcl_wordcount", "sparkcl_wordcount_locate",
+           "sparkcl_reduce_noalloc",
            "sparkcl_last_launch_shape")
 
 
@@ -170,6 +171,7 @@ def load() -> ctypes.CDLL:
             "sparkcl_offload_breakeven": ([P, ctypes.c_double, ctypes.POINTER(U64)], I32),
             "sparkcl_wordcount": ([P, P, U64, P, P, U64, ctypes.POINTER(U64),
                                    ctypes.POINTER(U64), P], I32),
+            "sparkcl_wordcount_locate": ([P, P, U64, P, U64, P, P], I32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -424,6 +426,19 @@ class Context:
                                         ctypes.byref(nw), _stream(stream, self.device)),
                "sparkcl_wordcount")
         return keys, counts, nd.value, nw.value
+
+    def wordcount_locate(self, text, keys, nkeys: int | None = None, offsets=None, stream=None):
+        """First byte offset in `text` (device uint8 tensor) of each of the
+        first `nkeys` keys of `keys` (device int64 tensor, distinct), as an
+        int64 device tensor; -1 (UINT64_MAX) for a key no word has."""
+        import torch
+        n = keys.numel() if nkeys is None else nkeys
+        if offsets is None:
+            offsets = torch.empty(max(n, 1), dtype=torch.int64, device=text.device)
+        _check(load().sparkcl_wordcount_locate(self._h, _ptr(text), text.numel(), _ptr(keys),
+                                               n, _ptr(offsets), _stream(stream, self.device)),
+               "sparkcl_wordcount_locate")
+        return offsets
 
     def offload_breakeven(self, host_bytes_per_s: float) -> int:
         """Smallest offload cost (bytes) at which this GPU beats a host path of

@@ -185,3 +185,92 @@ def test_spill_regions_of_one_partition_overflow(ctx):
     ok, oc, on = oracle.wordcount(text)
     assert gn == on, (gn, on)
     assert np.array_equal(gk, ok) and np.array_equal(gc, oc)
+
+
+# ---- the first occurrence of each key (sparkcl_wordcount_locate) -------------
+
+def check_locate(ctx, text, offset=0, extra_keys=()):
+    """Count on the GPU, then locate every key it returned (and `extra_keys`,
+    which the text need not hold): each offset equal to the oracle's first
+    occurrence, UINT64_MAX for absent keys."""
+    text = np.frombuffer(text, dtype=np.uint8) if isinstance(text, bytes) else text
+    buf = torch.zeros(text.size + offset + 16, dtype=torch.uint8, device="cuda")
+    view = buf[offset:offset + text.size]
+    view.copy_(torch.from_numpy(text))
+    keys, counts, nd, nw = ctx.wordcount(view, text.size // 2 + 1)
+    q = np.concatenate([keys[:nd].cpu().numpy().view(np.uint64),
+                        np.array(extra_keys, dtype=np.uint64)])
+    qd = torch.from_numpy(q.view(np.int64).copy()).cuda()
+    off = ctx.wordcount_locate(view, qd, q.size).cpu().numpy()[:q.size].view(np.uint64)
+    want = oracle.wordcount_first(text, q)
+    assert np.array_equal(off, want), np.nonzero(off != want)[0][:10]
+    return q, off
+
+
+@pytest.mark.parametrize("i", range(len(EDGE)))
+def test_locate_edge_texts(ctx, i):
+    check_locate(ctx, EDGE[i])
+
+
+@pytest.mark.parametrize("n", [4095, 4097, 4353, 8192 + 7])
+def test_locate_across_chunk_and_lookahead_edges(ctx, n):
+    parts, rng = [], np.random.default_rng(n)
+    while sum(map(len, parts)) < n:
+        parts.append(b"q" * int(rng.integers(1, 600)) + b" ")
+    check_locate(ctx, b"".join(parts)[:n])
+
+
+@pytest.mark.parametrize("offset", [0, 3])
+def test_locate_random_bytes_and_absent_keys(ctx, offset):
+    rng = np.random.default_rng(offset + 40)
+    text = rng.integers(0, 256, (1 << 20) + 13, dtype=np.uint8)
+    absent = [oracle.fnv1a64(b"\x20"), 1, 2**64 - 1]   # no word hashes to these here
+    q, off = check_locate(ctx, text, offset, absent)
+    assert off[-2:].tolist() == [2**64 - 1, 2**64 - 1]
+
+
+@pytest.mark.parametrize("vocab,nbytes", [(10, 1 << 20), (20_000, 8 << 20), (1_000_000, 16 << 20)])
+def test_locate_zipf_corpus(ctx, vocab, nbytes):
+    check_locate(ctx, datagen.corpus(nbytes, vocab=vocab, seed=vocab + 1))
+
+
+@pytest.mark.parametrize("pos", [0, 15, 4095, 4096 + 250])
+def test_locate_zero_key_word(ctx, pos):
+    t = filler(pos + 300, pos + 1)
+    put_zero_word(t, pos)
+    put_zero_word(t, pos + 100)   # a second copy: the first one counts
+    q, off = check_locate(ctx, bytes(t))
+    assert off[q.tolist().index(0)] == pos
+
+
+def test_locate_errors_and_empty(ctx):
+    text = torch.from_numpy(np.frombuffer(b"ab cd ab", dtype=np.uint8).copy()).cuda()
+    k = oracle.fnv1a64(b"ab")
+    dup = torch.from_numpy(np.array([k, k], dtype=np.uint64).view(np.int64)).cuda()
+    with pytest.raises(sc.SparkclError) as e:
+        ctx.wordcount_locate(text, dup, 2)
+    assert e.value.code == sc.EINVAL
+    zero = torch.zeros(2, dtype=torch.int64, device="cuda")
+    with pytest.raises(sc.SparkclError) as e:
+        ctx.wordcount_locate(text, zero, 2)       # the key 0 twice
+    assert e.value.code == sc.EINVAL
+    one = torch.from_numpy(np.array([k], dtype=np.uint64).view(np.int64)).cuda()
+    assert ctx.wordcount_locate(text, one, 1).cpu().tolist() == [0]
+    empty = torch.zeros(0, dtype=torch.uint8, device="cuda")
+    assert ctx.wordcount_locate(empty, one, 1).cpu().numpy().view(np.uint64).tolist() == \
+        [2**64 - 1]
+    ctx.wordcount_locate(text, one, 0)            # no keys: nothing to do
+
+
+def test_locate_full_size_1gib(ctx):
+    # The benchmark's 1 GiB text (the 64 MiB base repeated 16 times): every
+    # key's first word lies in the first copy, at the oracle's offset on the
+    # base.
+    base_n, rep = 64 << 20, 16
+    base = datagen.corpus(base_n - 1, vocab=100_000)
+    base = np.concatenate([base, np.frombuffer(b"\n", dtype=np.uint8)])
+    text = torch.from_numpy(base).cuda().repeat(rep)
+    keys, counts, nd, nw = ctx.wordcount(text, 1 << 20)
+    off = ctx.wordcount_locate(text, keys, nd).cpu().numpy()[:nd].view(np.uint64)
+    k = keys[:nd].cpu().numpy().view(np.uint64)
+    assert np.array_equal(off, oracle.wordcount_first(base, k))

@@ -65,3 +65,51 @@ def test_zero_key_word(oracle):
     check(oracle, text)
     keys, counts, nw = oracle.wordcount(text)
     assert keys[0] == 0 and counts[0] == 3 and nw == 6
+
+
+# ---- the first occurrence of each key ----------------------------------------
+
+def first_by_regex(oracle, text: bytes) -> dict:
+    """key -> byte offset of the first word with that key, from Python's
+    regular-expression tokenisation (runs of bytes outside the six whitespace
+    bytes) and a plain dictionary that keeps each word's first start."""
+    import re
+    first = {}
+    for m in re.finditer(rb"[^ \t\n\x0b\x0c\r]+", text):
+        first.setdefault(m.group(0), m.start())
+    return {oracle.fnv1a64(w): off for w, off in first.items()}
+
+
+def check_first(oracle, text: bytes):
+    want = first_by_regex(oracle, text)
+    keys = np.array(sorted(want), dtype=np.uint64)
+    got = oracle.wordcount_first(text, keys)
+    assert got.tolist() == [want[int(k)] for k in keys]
+    # every word's offset names a word with that key
+    for k, off in zip(keys.tolist(), got.tolist()):
+        end = off
+        while end < len(text) and text[end] not in b" \t\n\x0b\x0c\r":
+            end += 1
+        assert oracle.fnv1a64(text[off:end]) == k
+        assert off == 0 or text[off - 1] in b" \t\n\x0b\x0c\r"
+
+
+def test_first_occurrence_edge_texts(oracle):
+    for t in [b"a", b"  a  ", b"a b\tc\nd\re\x0bf\x0cg", b"ab ab  ab\n\nab", b"b a b a c",
+              b"x" * 5000, b"\x00\x01 \x7f\xff \x00\x01"]:
+        check_first(oracle, t)
+    text = b"ab " + ZERO_KEY_WORD + b"\n" + ZERO_KEY_WORD + b" cd"
+    got = oracle.wordcount_first(text, np.array([0], dtype=np.uint64))
+    assert got.tolist() == [3]
+
+
+def test_first_occurrence_absent_and_empty(oracle):
+    absent = np.array([oracle.fnv1a64(b"zz"), 12345], dtype=np.uint64)
+    assert oracle.wordcount_first(b"a b c", absent).tolist() == [2**64 - 1] * 2
+    assert oracle.wordcount_first(b"", absent).tolist() == [2**64 - 1] * 2
+    assert oracle.wordcount_first(b"a", np.array([], dtype=np.uint64)).size == 0
+
+
+def test_first_occurrence_corpus(oracle, datagen):
+    text = datagen.corpus(1 << 18, vocab=5_000).tobytes()
+    check_first(oracle, text)
