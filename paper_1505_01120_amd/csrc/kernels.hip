@@ -1633,10 +1633,18 @@ __global__ __launch_bounds__(kBlock) void k_wc_merge(WcArgs a, uint32_t scan_gri
 #pragma unroll
             for (uint32_t u = 0; u < kInFlight; ++u)
                 h[u] = i + u < cnt ? src[i + u] : 0;
+            // one copy of the insert, the keys rotated through h[0] (sixteen
+            // inlined copies of it left the compiler spilling hundreds of
+            // scalar registers)
+#pragma unroll 1
+            for (uint32_t u = 0; u < kInFlight; ++u) {
+                const uint64_t key = h[0];
 #pragma unroll
-            for (uint32_t u = 0; u < kInFlight; ++u)
-                if (h[u]) // spilled keys are never 0
-                    wc_merge_add(mk, mc, a, h[u]);
+                for (uint32_t v = 0; v + 1 < kInFlight; ++v)
+                    h[v] = h[v + 1];
+                if (key) // spilled keys are never 0
+                    wc_merge_add(mk, mc, a, key);
+            }
         }
     }
     __syncthreads();
