@@ -685,6 +685,7 @@ int sparkcl::enqueue(sparkcl_ctx *ctx, Plan *p, hipStream_t stream, bool timed)
         // map chains: the persistent executor over the plan's batched tile
         // queue, with the plan's stage table
         int rc = launch_chain(p->dtasks, p->dtiles, p->ntiles_total, p->dchain, p->grid, p->out,
+                              p->chain_unroll,
                               stream);
         if (rc != SPARKCL_OK)
             return fail(rc, "chain launch failed: " +

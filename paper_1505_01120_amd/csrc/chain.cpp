@@ -58,26 +58,30 @@ int sparkcl_reduce_chain(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t n
         while (ctx->plans.size() >= kMaxPlans)
             evict_one(ctx);
         // The chain's Horner steps add dependent VALU work per element, whose
-        // latency more waves per CU hide.  Measured on MI355X (64 x 2^22 FMUL
-        // partitions): no steps streams best at the map's tuned occupancy
-        // (1 block per CU, 316 us), 3 steps at 2 blocks per CU (347-353 us;
-        // 356-358 at 3, 407 at 1), 28 steps (four degree-7 stages) at 4
-        // (393-414 us; 425-438 at 3, 505-565 at 2, 791 at 1).  A grid that
+        // latency either more waves per CU or more loads in flight per wave
+        // hide.  Measured on MI355X (64 x 2^22 FMUL partitions): no steps
+        // streams best at the map's tuned occupancy (1 block per CU, 316 us);
+        // 3 steps with 8 float4 loads in flight per thread and input at 1
+        // block per CU (324 us; with 4 loads: 346-351 at 2 blocks per CU,
+        // 354-359 at 3, 397-408 at 1); 28 steps (four degree-7 stages) with
+        // 4 loads at 4 blocks per CU (407-411 us; with 8 loads 526-558 at 3,
+        // where the deeper stream's registers cap the waves).  A grid that
         // would get fewer than two of the batched table's tiles per block
         // takes the per-launch table's smaller tiles, so blocks keep pulling
         // tiles from the queue (with one large tile per block, blocks placed
         // unevenly on the CUs decide the time: 440-490 us at 2 per CU).
+        uint32_t steps = 0;
+        for (uint32_t s = 0; s < nstages; ++s)
+            steps += chain.deg[s];
+        uint32_t base = 0;
+        for (uint32_t i = 0; i < ntasks; ++i)
+            if (tasks[i].kernel_id == SPARKCL_POLY)
+                base = std::max(base, tasks[i].degree);
+        steps += base;
+        const bool deep = steps >= 1 && steps <= 4;
         uint32_t per_cu = 0;
         if (!ctx->config.exec_blocks_per_cu) {
-            uint32_t steps = 0;
-            for (uint32_t s = 0; s < nstages; ++s)
-                steps += chain.deg[s];
-            uint32_t base = 0;
-            for (uint32_t i = 0; i < ntasks; ++i)
-                if (tasks[i].kernel_id == SPARKCL_POLY)
-                    base = std::max(base, tasks[i].degree);
-            steps += base;
-            const uint32_t want = steps == 0 ? 0 : steps <= 4 ? 2 : steps <= 12 ? 3 : 4;
+            const uint32_t want = steps == 0 ? 0 : deep ? 1 : steps <= 12 ? 3 : 4;
             per_cu = std::min(want, (uint32_t)ctx->occ_chain);
         }
         if ((rc = build_plan(ctx, 0, SPARKCL_BATCHED, tasks, ntasks, nullptr, nullptr, st,
@@ -85,6 +89,7 @@ int sparkcl_reduce_chain(sparkcl_ctx *ctx, const sparkcl_task *tasks, uint32_t n
             return rc;
         p->kind = 4;
         p->chain = chain;
+        p->chain_unroll = deep ? 8 : 4;
         p->hash = h;
         void *d = nullptr;
         if ((rc = arena_alloc(ctx, p, sizeof(ChainDev), &d)) != SPARKCL_OK) {

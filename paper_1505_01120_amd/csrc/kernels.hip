@@ -814,6 +814,7 @@ __device__ __forceinline__ ChainMap<TWO> chain_map(const TaskDev *tp, const Chai
 }
 
 // Tile j of a task with a map chain, through the common tile epilogue.
+template <int UC>
 __device__ __forceinline__ bool chain_tile(const TaskDev *__restrict__ tp,
                                            const ChainDev *__restrict__ chain, uint32_t j,
                                            const LaunchOut &L)
@@ -832,12 +833,12 @@ __device__ __forceinline__ bool chain_tile(const TaskDev *__restrict__ tp,
         const bool w = variant == V_FMULW || (variant >= V_POLYW && variant < V_FMUL);
         if (two) {
             const ChainMap<true> f = chain_map<true>(tp, chain);
-            return w ? tile_map<ChainMap<true>, true, kUnroll>(f, x, y, o, n, T, nt, j, a)
-                     : tile_map<ChainMap<true>, false, kUnroll>(f, x, y, o, n, T, nt, j, a);
+            return w ? tile_map<ChainMap<true>, true, UC>(f, x, y, o, n, T, nt, j, a)
+                     : tile_map<ChainMap<true>, false, UC>(f, x, y, o, n, T, nt, j, a);
         }
         const ChainMap<false> f = chain_map<false>(tp, chain);
-        return w ? tile_map<ChainMap<false>, true, kUnroll>(f, x, y, o, n, T, nt, j, a)
-                 : tile_map<ChainMap<false>, false, kUnroll>(f, x, y, o, n, T, nt, j, a);
+        return w ? tile_map<ChainMap<false>, true, UC>(f, x, y, o, n, T, nt, j, a)
+                 : tile_map<ChainMap<false>, false, UC>(f, x, y, o, n, T, nt, j, a);
     });
 }
 
@@ -917,7 +918,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(const TaskDev *__restrict__
              [&](const TaskDev *tp, uint32_t j) { return run_tile<true>(tp, j, L); });
 }
 
-// The persistent executor over tasks that share one map chain.
+// The persistent executor over tasks that share one map chain, with UC float4
+// loads in flight per thread and input (4, or 8 for short chains run at one
+// block per CU, where the deeper stream hides the Horner steps' latency that
+// more blocks would otherwise have to).
+template <int UC>
 __global__ __launch_bounds__(kBlock) void k_chain(const TaskDev *__restrict__ tasks,
                                                   const TileRef *__restrict__ tiles,
                                                   uint32_t ntiles,
@@ -925,7 +930,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(const TaskDev *__restrict__ ta
                                                   LaunchOut L)
 {
     executor(tasks, tiles, ntiles, L,
-             [&](const TaskDev *tp, uint32_t j) { return chain_tile(tp, chain, j, L); });
+             [&](const TaskDev *tp, uint32_t j) { return chain_tile<UC>(tp, chain, j, L); });
 }
 
 // MapCL materialisation only (no reduction): out[i] = map(x[i] [, y[i]]),
@@ -1949,12 +1954,17 @@ int launch_task(const TaskDev *dtask, uint32_t ntiles, uint32_t grid,
 }
 
 int launch_chain(const TaskDev *dtasks, const TileRef *tiles, uint32_t ntiles,
-                 const ChainDev *chain, uint32_t grid, const LaunchOut &out, void *stream)
+                 const ChainDev *chain, uint32_t grid, const LaunchOut &out, uint32_t unroll,
+                 void *stream)
 {
-    if (ntiles == 0 || grid == 0 || !chain)
+    if (ntiles == 0 || grid == 0 || !chain || (unroll != 4 && unroll != 8))
         return SPARKCL_EINVAL;
-    hipLaunchKernelGGL(k_chain, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, dtasks,
-                       tiles, ntiles, chain, out);
+    if (unroll == 8)
+        hipLaunchKernelGGL(k_chain<8>, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
+                           dtasks, tiles, ntiles, chain, out);
+    else
+        hipLaunchKernelGGL(k_chain<4>, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
+                           dtasks, tiles, ntiles, chain, out);
     return hip_status(hipGetLastError());
 }
 
@@ -2142,7 +2152,7 @@ int batch_blocks_per_cu(int *out)
 int chain_blocks_per_cu(int *out)
 {
     return hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        out, reinterpret_cast<const void *>(k_chain), kBlock, 0));
+        out, reinterpret_cast<const void *>(k_chain<4>), kBlock, 0));
 }
 
 } // namespace sparkcl

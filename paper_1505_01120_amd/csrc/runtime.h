@@ -92,9 +92,10 @@ struct Plan {
     std::vector<const float *> leaves;
     std::vector<TreeArgs> passes;
 
-    // kind 4, map chains: the stage table
+    // kind 4, map chains: the stage table and the loads in flight
     ChainDev chain{};
     ChainDev *dchain = nullptr;
+    uint32_t chain_unroll = 4;
 
     // host-input partitions: the staging ring and its events
     bool host = false;

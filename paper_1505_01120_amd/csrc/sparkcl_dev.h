@@ -152,9 +152,11 @@ struct ChainDev {
     float coef[kMaxPost][8];
 };
 // One persistent-executor launch over a batched tile queue whose tasks all
-// run the chain `chain` after their own map.
+// run the chain `chain` after their own map; `unroll` float4 loads (4 or 8)
+// in flight per thread and input.
 int launch_chain(const TaskDev *dtasks, const TileRef *tiles, uint32_t ntiles,
-                 const ChainDev *chain, uint32_t grid, const LaunchOut &out, void *stream);
+                 const ChainDev *chain, uint32_t grid, const LaunchOut &out, uint32_t unroll,
+                 void *stream);
 // Array-valued ReduceCL, one pass: reduces `count` leaves of `len` floats
 // (from the device pointer table `ptrs`, or, when ptrs is null, the rows
 // base + i * stride) in chunks of `chunk` leaves; chunk c's tree goes to

@@ -385,8 +385,10 @@ def test_hot_kernels_keep_registers_and_no_scratch():
         with open(libbuild.ISA_JSON) as f:
             isa = json.load(f)
     # the wide array reduce holds a 7-level counter for 4 float4 columns per
-    # thread and runs at three waves per SIMD (at most 168 VGPRs)
-    limit = {"k_tree_wide": 168}
+    # thread and runs at three waves per SIMD (at most 168 VGPRs); so may the
+    # chain executor's 8-loads instance, which short chains run at one block
+    # (one wave per SIMD) per CU
+    limit = {"k_tree_wide": 168, "k_chain": 168}
     for k in libbuild.KERNELS:
         assert isa[k]["private_segment_bytes"] == 0, (k, isa[k])
         assert isa[k]["vgpr_spills"] == 0, (k, isa[k])
