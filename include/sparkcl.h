@@ -338,7 +338,9 @@ typedef struct sparkcl_tuning {
     uint32_t blocks_per_cu[3];   /* persistent-executor blocks per CU for each
                                     registry kernel (index kernel id - 1); a
                                     batch uses the largest among the kernels
-                                    it holds; 0 = as many as fit              */
+                                    it holds (a batch of Monte-Carlo tasks
+                                    alone: blocks_per_cu_mc_only); 0 = as
+                                    many as fit                               */
     uint32_t blocks_per_cu_many; /* the executor's blocks per CU for a batch of
                                     many small tasks (under 4 tiles per task
                                     on average), where per-tile latency
@@ -379,6 +381,11 @@ typedef struct sparkcl_tuning {
                                     size, carries over between batches of
                                     different totals.  0 = use the per-bucket
                                     table; else 1 to 4096                     */
+    uint32_t blocks_per_cu_mc_only; /* blocks per CU for a batch of Monte-Carlo
+                                    tasks alone, which runs an executor
+                                    instance holding only the Philox body
+                                    (fewer registers, so more blocks fit);
+                                    0 = as many as fit, else 1 to 32          */
     /* tile size in elements (samples for MC_PI) for [mode][kernel-1][log2 n];
        powers of two from 2^10 to 2^22.  A batched call whose executor blocks
        would get fewer than two of the batched row's tiles each is cut with

@@ -38,6 +38,7 @@ def main(argv=None) -> int:
                "blocks_per_cu_many": t.blocks_per_cu_many,
                "tile_many": list(t.tile_many),
                "many_tiles_per_cu": list(t.many_tiles_per_cu),
+               "blocks_per_cu_mc_only": t.blocks_per_cu_mc_only,
                "block": list(t.block), "block_many": t.block_many,
                "unroll": list(t.unroll),
                "tiles": {m: {k: list(t.tile[i][j][args.lo:args.hi + 1])

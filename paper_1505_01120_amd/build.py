@@ -46,7 +46,7 @@ PROBE_LIB = os.path.join(HERE, "libsparkcl_probe.so")
 PROBE_ISA_JSON = os.path.join(HERE, "probe_isa.json")
 ISA_JSON = os.path.join(HERE, "isa.json")
 KERNELS = ("k_task", "k_batch", "k_serve", "k_map", "k_chain", "k_tree", "k_tree_wide", "k_wordcount",
-           "k_wc_merge", "k_wc_compact", "k_wl_scan")
+           "k_wc_merge", "k_wc_compact", "k_wl_scan", "k_batch_mc")
 ARCH = "gfx950"
 
 HIP_SOURCES = ["kernels.hip", "noalloc.hip", "api.cpp", "arrays.cpp", "chain.cpp", "wordcount.cpp", "serve.cpp",

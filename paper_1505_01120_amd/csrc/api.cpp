@@ -198,13 +198,28 @@ uint32_t sparkcl::kernel_unroll(const sparkcl_tuning &t, uint32_t kid)
     return u ? u : (uint32_t)kUnroll;
 }
 
+uint32_t sparkcl::exec_occupancy(const sparkcl_ctx *ctx, uint32_t kid_mask)
+{
+    return (uint32_t)(mc_instance(ctx, kid_mask) ? ctx->occ_mc : ctx->occ_batch);
+}
+
+bool sparkcl::mc_instance(const sparkcl_ctx *ctx, uint32_t kid_mask)
+{
+    return kid_mask == (1u << (SPARKCL_MC_PI - 1)) && !ctx->tune_shared_mc;
+}
+
 uint32_t sparkcl::exec_grid(const sparkcl_ctx *ctx, uint32_t kid_mask, uint64_t ntiles,
                             uint64_t ntasks, uint32_t block)
 {
-    const uint32_t occ = (uint32_t)ctx->occ_batch;
+    // a batch of Monte-Carlo tasks alone runs the executor's MC instance,
+    // which fits more blocks per CU
+    const uint32_t occ = exec_occupancy(ctx, kid_mask);
     uint32_t per_cu = 0;
     if (ctx->config.exec_blocks_per_cu) {
         per_cu = ctx->config.exec_blocks_per_cu;
+    } else if (kid_mask == (1u << (SPARKCL_MC_PI - 1)) && !ctx->tune_shared_mc) {
+        // Monte-Carlo tasks alone: the executor instance of their own
+        per_cu = ctx->tuning.blocks_per_cu_mc_only ? ctx->tuning.blocks_per_cu_mc_only : occ;
     } else {
         // the largest tuned value among the kernels in the batch: a
         // compute-bound kernel needs waves to hide instruction latency, a
@@ -546,6 +561,7 @@ int sparkcl::build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task
         p->out.ns_per_tick = ctx->ns_per_tick;
         // map chains run 256-thread blocks; a given per_cu (chains) counts them
         p->block = kind == 4 ? (uint32_t)kBlock : exec_block(ctx, kid_mask);
+        p->mc_only = mc_instance(ctx, kid_mask);
         p->grid = std::min(per_cu ? per_cu * (uint32_t)ctx->cus
                                   : exec_grid(ctx, kid_mask, p->ntiles_total, ntasks, p->block),
                            p->ntiles_total);
@@ -652,7 +668,7 @@ int launch_device(sparkcl_ctx *ctx, Plan *p, hipStream_t stream)
         // uploaded task table and tile queue, and the kernel leaves its queue
         // head and tickets at zero, so nothing is cleared between launches.
         int rc = launch_batch(p->dtasks, p->dtiles, p->ntiles_total, p->grid, p->out, stream,
-                              p->block);
+                              p->block, p->mc_only);
         if (rc != SPARKCL_OK)
             return fail(rc, "executor launch failed: " +
                                 std::string(hipGetErrorString(hipGetLastError())));
@@ -935,6 +951,10 @@ int sparkcl_init(const sparkcl_config *config, sparkcl_ctx **out)
     if (rc != SPARKCL_OK)
         return fail(rc, "occupancy query failed");
     ctx->occ_batch = std::max(1, occ);
+    occ = 0;
+    if ((rc = batch_mc_blocks_per_cu(&occ)) != SPARKCL_OK)
+        return fail(rc, "occupancy query failed");
+    ctx->occ_mc = std::max(1, occ);
     occ = 0;
     if ((rc = chain_blocks_per_cu(&occ)) != SPARKCL_OK)
         return fail(rc, "occupancy query failed");

@@ -30,10 +30,11 @@ constexpr int kWarm = 3, kReps = 9;
 
 // Elements per timed batch: 2^28 for the streaming kernels (1 GiB per input
 // array; the tiles per block, not the launch, dominate, as in a large RDD)
-// and 2^27 samples for the Monte-Carlo kernel.
+// and 2^30 samples (about 1 ms) for the Monte-Carlo kernel, enough tiles for
+// the Monte-Carlo-only executor's high occupancies to show.
 uint64_t work_elems(uint32_t kid)
 {
-    return kid == SPARKCL_MC_PI ? (1ull << 27) : (1ull << 28);
+    return kid == SPARKCL_MC_PI ? (1ull << 30) : (1ull << 28);
 }
 
 uint64_t mix64(uint64_t z)
@@ -125,10 +126,11 @@ std::vector<sparkcl_task> make_mixed(const Bench &b)
     return v;
 }
 
-std::vector<sparkcl_task> make_tasks(const Bench &b, uint32_t kid, uint64_t n, int mode)
+std::vector<sparkcl_task> make_tasks(const Bench &b, uint32_t kid, uint64_t n, int mode,
+                                     uint64_t work = 0)
 {
     const uint64_t count =
-        mode == SPARKCL_BATCHED ? std::max<uint64_t>(1, work_elems(kid) / n) : 1;
+        mode == SPARKCL_BATCHED ? std::max<uint64_t>(1, (work ? work : work_elems(kid)) / n) : 1;
     std::vector<sparkcl_task> v;
     for (uint64_t i = 0; i < std::min<uint64_t>(count, 4096); ++i)
         v.push_back(make_task(b, kid, n, i));
@@ -201,6 +203,7 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
         return tiles >= 2 * grid;
     };
     auto abort_with = [&](int code) {
+        ctx->tune_shared_mc = false;
         ctx->tuning = best;
         cleanup();
         return code;
@@ -213,11 +216,19 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
     //    Ties (within 2%) go to fewer blocks and smaller tiles.
     constexpr uint32_t kRefLog2 = 22;
     for (uint32_t kid = SPARKCL_POLY; kid <= SPARKCL_MC_PI; ++kid) {
+        // Monte-Carlo tasks are first timed on the shared executor, where
+        // only mixed batches use blocks_per_cu[MC_PI], at the Monte-Carlo
+        // share such a batch carries (2^27 samples; the 4096-task uneven
+        // batch holds 2.1e8); the instance that runs them alone is tuned
+        // after (1c) on the full 2^30
         const std::vector<sparkcl_task> tasks =
-            make_tasks(b, kid, 1ull << kRefLog2, SPARKCL_BATCHED);
+            kid == SPARKCL_MC_PI ? make_tasks(b, kid, 1ull << kRefLog2, SPARKCL_BATCHED, 1ull << 27)
+                                 : make_tasks(b, kid, 1ull << kRefLog2, SPARKCL_BATCHED);
+        ctx->tune_shared_mc = kid == SPARKCL_MC_PI;
+        const uint32_t kocc = exec_occupancy(ctx, 1u << (kid - 1));
         float best_ms = 1e30f;
         uint32_t best_bpc = 1, best_tile = best.tile[TM_BATCHED][kid - 1][kRefLog2];
-        for (uint32_t bpc = 1; bpc <= occ; ++bpc)
+        for (uint32_t bpc = 1; bpc <= kocc; ++bpc)
             for (uint32_t tl = 14; tl <= 20; ++tl) {
                 sparkcl_tuning t = best;
                 t.blocks_per_cu[kid - 1] = bpc;
@@ -251,7 +262,7 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
             float shape_ms = best_ms;
             const sparkcl_tuning base = best;
             for (uint32_t blk : {256u, 512u, 1024u})
-                for (uint32_t bpc = blk / 256; bpc <= occ; ++bpc)
+                for (uint32_t bpc = blk / 256; bpc <= kocc; ++bpc)
                     for (uint32_t u : {4u, 2u, 8u}) {
                         if (kid == SPARKCL_MC_PI && u != 4)
                             continue; // no streaming loop
@@ -291,6 +302,32 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
                 if (ms < shape_ms * 0.98f) {
                     shape_ms = ms;
                     best.tile[TM_BATCHED][kid - 1][kRefLog2] = 1u << tl;
+                }
+            }
+        }
+
+        // 1c. Monte-Carlo tasks alone: the blocks per CU of the executor
+        //     instance that holds only the Philox body, at the tile above.
+        ctx->tune_shared_mc = false;
+        if (kid == SPARKCL_MC_PI) {
+            const std::vector<sparkcl_task> alone =
+                make_tasks(b, kid, 1ull << kRefLog2, SPARKCL_BATCHED);
+            const uint32_t mocc = exec_occupancy(ctx, 1u << (kid - 1));
+            const uint32_t T = best.tile[TM_BATCHED][kid - 1][kRefLog2];
+            float mc_ms = 1e30f;
+            for (uint32_t bpc = 1; bpc <= mocc; ++bpc) {
+                sparkcl_tuning t = best;
+                t.blocks_per_cu_mc_only = bpc;
+                if (!batched_takes(t, kid, alone, T))
+                    continue;
+                float ms = 0;
+                if (!measure(t, SPARKCL_BATCHED, alone, &ms))
+                    return abort_with(rc);
+                if (verbose)
+                    std::fprintf(stderr, "mc alone bpc %u: %.1f us\n", bpc, ms * 1e3f);
+                if (ms < mc_ms * 0.98f) {
+                    mc_ms = ms;
+                    best.blocks_per_cu_mc_only = bpc;
                 }
             }
         }
@@ -334,16 +371,39 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
         }
     }
 
-    // 3. Work shares for batches of many tasks of spread sizes (the mixed
-    //    batch): the tiles per CU that the batch's streaming input bytes
-    //    (both streaming kernels, whose tiles run side by side in HBM), then
-    //    its Monte-Carlo samples, are cut into, against the per-bucket table
-    //    (0).
-    //    Explicit mixed-batch tile sizes are left unset: a size tuned on one
-    //    batch does not carry over to a batch of another total, a share does.
+    // 3-5. The mixed batch (many tasks of spread sizes and mixed kernels,
+    //    drawn from a distribution of its own): its occupancy, which a batch
+    //    that mixes kernels takes alone; the work shares (tiles per CU) that
+    //    its streaming input bytes (both streaming kernels, whose tiles run
+    //    side by side in HBM), then its Monte-Carlo samples, are cut into,
+    //    against the per-bucket table (0); the occupancy again at those
+    //    shares; then the executor's block size.  Explicit mixed-batch tile
+    //    sizes are left unset: a size tuned on one batch does not carry over
+    //    to a batch of another total, a share does.
     {
         const std::vector<sparkcl_task> tasks = make_mixed(b);
         best.tile_many[0] = best.tile_many[1] = best.tile_many[2] = 0;
+        auto tune_many_bpc = [&]() -> bool {
+            float best_ms = 1e30f;
+            uint32_t best_bpc = best.blocks_per_cu_many;
+            for (uint32_t bpc = 1; bpc <= occ; ++bpc) {
+                sparkcl_tuning t = best;
+                t.blocks_per_cu_many = bpc;
+                float ms = 0;
+                if (!measure(t, SPARKCL_BATCHED, tasks, &ms))
+                    return false;
+                if (verbose)
+                    std::fprintf(stderr, "many bpc %u: %.1f us\n", bpc, ms * 1e3f);
+                if (ms < best_ms * 0.98f) {
+                    best_ms = ms;
+                    best_bpc = bpc;
+                }
+            }
+            best.blocks_per_cu_many = best_bpc;
+            return true;
+        };
+        if (!tune_many_bpc())
+            return abort_with(rc);
         for (int group = 0; group < 2; ++group) {
             float best_ms = 1e30f;
             uint32_t best_q = 0;
@@ -363,29 +423,9 @@ extern "C" int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_
             }
             best.many_tiles_per_cu[group] = best_q;
         }
-    }
+        if (!tune_many_bpc())
+            return abort_with(rc);
 
-    // 4. Occupancy for batches of many small tasks.
-    {
-        const std::vector<sparkcl_task> tasks = make_mixed(b);
-        float best_ms = 1e30f;
-        uint32_t best_bpc = best.blocks_per_cu_many;
-        for (uint32_t bpc = 1; bpc <= occ; ++bpc) {
-            sparkcl_tuning t = best;
-            t.blocks_per_cu_many = bpc;
-            float ms = 0;
-            if (!measure(t, SPARKCL_BATCHED, tasks, &ms))
-                return abort_with(rc);
-            if (verbose)
-                std::fprintf(stderr, "many bpc %u: %.1f us\n", bpc, ms * 1e3f);
-            if (ms < best_ms * 0.98f) {
-                best_ms = ms;
-                best_bpc = bpc;
-            }
-        }
-        best.blocks_per_cu_many = best_bpc;
-
-        // 5. The executor's block size for batches that mix kernels.
         float shape_ms = 1e30f;
         for (uint32_t blk : {256u, 512u, 1024u}) {
             sparkcl_tuning t = best;

@@ -918,6 +918,33 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(const TaskDev *__restrict__
              [&](const TaskDev *tp, uint32_t j) { return run_tile<true>(tp, j, L); });
 }
 
+// The persistent executor for batches whose tasks are all Monte-Carlo ones:
+// the same queue and tile epilogue around the Philox tile body alone.  The
+// streaming bodies set k_batch's register count (and so its waves per CU);
+// without them this kernel holds half the registers and fits twice the
+// waves, which the VALU-bound loop needs to issue near its rate (measured on
+// MI355X: 0.95 wave-instructions per CU per clock at 3 blocks per CU, 1.04
+// at 8).  A declined task (empty partial) runs no body.
+__global__ __launch_bounds__(kMaxBlock) void k_batch_mc(const TaskDev *__restrict__ tasks,
+                                                     const TileRef *__restrict__ tiles,
+                                                     uint32_t ntiles, LaunchOut L)
+{
+    executor(tasks, tiles, ntiles, L, [&](const TaskDev *tp, uint32_t j) {
+        return run_tile_with<true>(tp, j, L, [&](Acc &a) -> uint64_t {
+            if (uni(tp->variant) != V_MC)
+                return 0;
+            const uint32_t T = uni(tp->tile_elems);
+            const uint64_t n = uni64(tp->n);
+            const uint64_t begin = (uint64_t)j * T;
+            const uint64_t end = min(n, begin + T);
+            if (begin >= end)
+                return 0;
+            tile_mc(uni64(tp->seed), uni(tp->pid), begin, end, a);
+            return end - begin;
+        });
+    });
+}
+
 // The persistent executor over tasks that share one map chain, with UC float4
 // loads in flight per thread and input (4, or 8 for short chains run at one
 // block per CU, where the deeper stream hides the Horner steps' latency that
@@ -1969,12 +1996,17 @@ int launch_chain(const TaskDev *dtasks, const TileRef *tiles, uint32_t ntiles,
 }
 
 int launch_batch(const TaskDev *dtasks, const TileRef *tiles, uint32_t ntiles,
-                 uint32_t grid, const LaunchOut &out, void *stream, uint32_t block)
+                 uint32_t grid, const LaunchOut &out, void *stream, uint32_t block,
+                 bool mc_only)
 {
     if (ntiles == 0 || grid == 0 || (block != 256 && block != 512 && block != 1024))
         return SPARKCL_EINVAL;
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(block), 0, (hipStream_t)stream,
-                       dtasks, tiles, ntiles, out);
+    if (mc_only)
+        hipLaunchKernelGGL(k_batch_mc, dim3(grid), dim3(block), 0, (hipStream_t)stream,
+                           dtasks, tiles, ntiles, out);
+    else
+        hipLaunchKernelGGL(k_batch, dim3(grid), dim3(block), 0, (hipStream_t)stream,
+                           dtasks, tiles, ntiles, out);
     return hip_status(hipGetLastError());
 }
 
@@ -2147,6 +2179,12 @@ int batch_blocks_per_cu(int *out)
 {
     return hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(
         out, reinterpret_cast<const void *>(k_batch), kBlock, 0));
+}
+
+int batch_mc_blocks_per_cu(int *out)
+{
+    return hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        out, reinterpret_cast<const void *>(k_batch_mc), kBlock, 0));
 }
 
 int chain_blocks_per_cu(int *out)

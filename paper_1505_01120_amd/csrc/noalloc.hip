@@ -183,7 +183,8 @@ extern "C" int sparkcl_reduce_noalloc(sparkcl_ctx *ctx, const sparkcl_task *task
     // as sparkcl_reduce_async: per-task results and no total skip the fold
     L.ntasks = (dev_per_task && !dev_total) ? 0 : ntasks;
     L.ns_per_tick = ctx->ns_per_tick;
-    if ((rc = launch_batch(dtasks, dtiles, (uint32_t)total_tiles, grid, L, s, block)) != SPARKCL_OK)
+    if ((rc = launch_batch(dtasks, dtiles, (uint32_t)total_tiles, grid, L, s, block,
+                           mc_instance(ctx, kid_mask))) != SPARKCL_OK)
         return fail(rc, "executor launch failed: " +
                             std::string(hipGetErrorString(hipGetLastError())));
     SPARKCL_HIP(hipEventRecord(dv.done, s));

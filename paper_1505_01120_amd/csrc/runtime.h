@@ -77,6 +77,7 @@ struct Plan {
     std::vector<uint32_t> variants;
     uint32_t grid = 0;
     uint32_t block = 256; // executor threads per block
+    bool mc_only = false; // every task Monte-Carlo: the executor's MC instance
     Cut cut{};            // kind 0: the tile table the call was cut with
     LaunchOut out{};
 
@@ -180,6 +181,12 @@ uint32_t exec_grid(const sparkcl_ctx *ctx, uint32_t kid_mask, uint64_t ntiles = 
 // kid_mask (one kernel: its tuned size; several: the mixed-batch size), and
 // the float4 loads in flight per thread for a kernel's streaming loop.
 uint32_t exec_block(const sparkcl_ctx *ctx, uint32_t kid_mask);
+// Executor blocks per CU that fit for a batch holding the kernels in
+// kid_mask (the Monte-Carlo-only instance fits more).
+uint32_t exec_occupancy(const sparkcl_ctx *ctx, uint32_t kid_mask);
+// Whether a batch holding the kernels in kid_mask runs the Monte-Carlo-only
+// executor instance (Monte-Carlo tasks alone).
+bool mc_instance(const sparkcl_ctx *ctx, uint32_t kid_mask);
 uint32_t kernel_unroll(const sparkcl_tuning &t, uint32_t kid);
 
 } // namespace sparkcl
@@ -190,6 +197,10 @@ struct sparkcl_ctx {
     int cus = 0;
     uint32_t ns_per_tick = 10;
     int occ_batch = 1; // batch-executor blocks per CU that fit
+    int occ_mc = 1;    // blocks per CU of the Monte-Carlo-only executor
+    // autotuner only: Monte-Carlo batches run the shared executor, so that
+    // blocks_per_cu[MC_PI] is measured where mixed batches use it
+    bool tune_shared_mc = false;
     int occ_chain = 1; // chain-executor blocks per CU that fit
     int occ_wordcount = 0; // word-count blocks per CU that fit (0: not yet asked)
 

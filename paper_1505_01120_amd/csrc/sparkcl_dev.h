@@ -139,8 +139,11 @@ struct ServeArgs {
 // ---- launchers (kernels.hip) ---------------------------------------------
 int launch_task(const TaskDev *dtask, uint32_t ntiles, uint32_t grid,
                 const LaunchOut &out, void *stream, uint32_t block = kBlock);
+// mc_only: every task is a Monte-Carlo one (or declined), run by the
+// executor instance that holds only the Philox body.
 int launch_batch(const TaskDev *dtasks, const TileRef *tiles, uint32_t ntiles,
-                 uint32_t grid, const LaunchOut &out, void *stream, uint32_t block = kBlock);
+                 uint32_t grid, const LaunchOut &out, void *stream, uint32_t block = kBlock,
+                 bool mc_only = false);
 int launch_map(const TaskDev *dtask, uint64_t n, uint32_t variant,
                uint32_t grid, void *stream);
 int launch_zero(void *p, uint64_t bytes, void *stream);
@@ -228,8 +231,10 @@ int launch_wordcount_locate(const WlArgs &l, uint32_t scan_grid, void *stream);
 // launch first discards tickets left unpublished by the previous launch.
 int launch_serve(const ServeArgs &a, uint32_t workers, void *stream);
 int launch_fill_pattern(float *p, uint64_t n, uint32_t salt, void *stream);
-// Blocks of the batch executor that fit on one CU at once.
+// Blocks of the batch executor (and of its Monte-Carlo-only instance) that
+// fit on one CU at once.
 int batch_blocks_per_cu(int *out);
+int batch_mc_blocks_per_cu(int *out);
 int chain_blocks_per_cu(int *out);
 
 } // namespace sparkcl

@@ -208,6 +208,11 @@ int tuning_validate(const sparkcl_tuning *t, std::string *why)
             *why = "null tuning table";
         return SPARKCL_EINVAL;
     }
+    if (t->blocks_per_cu_mc_only > 32) {
+        if (why)
+            *why = "blocks_per_cu_mc_only above 32";
+        return SPARKCL_EINVAL;
+    }
     if (t->blocks_per_cu_many > 32) {
         if (why)
             *why = "blocks_per_cu_many above 32";
@@ -312,6 +317,8 @@ bool tuning_parse_json(const std::string &text,
         }
         if (const Json *b = e.get("blocks_per_cu_many"))
             t.blocks_per_cu_many = (uint32_t)b->num;
+        if (const Json *b = e.get("blocks_per_cu_mc_only"))
+            t.blocks_per_cu_mc_only = (uint32_t)b->num;
         for (const char *name : {"block", "unroll"}) {
             const Json *b = e.get(name);
             if (!b)
@@ -385,6 +392,7 @@ std::string tuning_to_json(const std::map<std::string, sparkcl_tuning> &all)
         o << " \"" << kv.first << "\": {\n  \"blocks_per_cu\": [" << t.blocks_per_cu[0]
           << ", " << t.blocks_per_cu[1] << ", " << t.blocks_per_cu[2]
           << "],\n  \"blocks_per_cu_many\": " << t.blocks_per_cu_many
+          << ",\n  \"blocks_per_cu_mc_only\": " << t.blocks_per_cu_mc_only
           << ",\n  \"tile_many\": [" << t.tile_many[0] << ", " << t.tile_many[1] << ", "
           << t.tile_many[2] << "],\n  \"block\": [" << t.block[0] << ", " << t.block[1] << ", "
           << t.block[2] << "],\n  \"block_many\": " << t.block_many << ",\n  \"unroll\": ["

@@ -32,7 +32,7 @@ int tuning_validate(const sparkcl_tuning *t, std::string *why);
 uint32_t tile_for(const sparkcl_tuning &t, int mode, uint32_t kid, uint64_t n);
 
 // JSON cache: { "<gfx arch>": { "blocks_per_cu": [P, F, M], "blocks_per_cu_many":
-// N, "tile_many": [P, F, M], "block": [P, F, M], "block_many": N, "unroll":
+// N, "blocks_per_cu_mc_only": N, "tile_many": [P, F, M], "block": [P, F, M], "block_many": N, "unroll":
 // [P, F, M], "many_tiles_per_cu": [S, M], "tile": { "<mode>": { "<kernel>":
 // [32 tile sizes] } } }, ... }
 // with modes per_launch, batched, serve and kernels poly, fmul, mc_pi; keys

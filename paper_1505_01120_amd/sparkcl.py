@@ -69,6 +69,7 @@ class Tuning(ctypes.Structure):
                 ("tile_many", ctypes.c_uint32 * 3), ("block", ctypes.c_uint32 * 3),
                 ("block_many", ctypes.c_uint32), ("unroll", ctypes.c_uint32 * 3),
                 ("many_tiles_per_cu", ctypes.c_uint32 * 2),
+                ("blocks_per_cu_mc_only", ctypes.c_uint32),
                 ("tile", ((ctypes.c_uint32 * TUNE_BUCKETS) * 3) * TUNE_MODES)]
 
 

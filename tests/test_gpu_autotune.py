@@ -20,6 +20,7 @@ MIN_TILE, MAX_TILE = 1 << 10, 1 << 22
 def entries(t: sc.Tuning):
     return (list(t.blocks_per_cu) + [t.blocks_per_cu_many] + list(t.tile_many) +
             list(t.block) + [t.block_many] + list(t.unroll) + list(t.many_tiles_per_cu) +
+            [t.blocks_per_cu_mc_only] +
             [t.tile[m][k][b] for m in range(sc.TUNE_MODES) for k in range(3)
              for b in range(sc.TUNE_BUCKETS)])
 
@@ -33,7 +34,7 @@ def test_autotune_table_cache_and_parity(tmp_path):
     finally:
         c.destroy()
 
-    for b in list(tuned.blocks_per_cu) + [tuned.blocks_per_cu_many]:
+    for b in list(tuned.blocks_per_cu) + [tuned.blocks_per_cu_many, tuned.blocks_per_cu_mc_only]:
         assert 1 <= b <= 16, b
     for b in list(tuned.block) + [tuned.block_many]:
         assert b in (256, 512, 1024), b

@@ -350,9 +350,12 @@ def test_tuning_json_roundtrip(host, tmp_path):
     assert host.hl_tuning_load(path, b"gfx950:sramecc+:xnack-", ctypes.byref(back)) == 1
     assert bytes(back) == bytes(t)
     t.many_tiles_per_cu[0], t.many_tiles_per_cu[1] = 24, 4096
+    t.blocks_per_cu_mc_only = 6
     assert host.hl_tuning_save(path, b"gfx950:sramecc+:xnack-", ctypes.byref(t)) == 1
     assert host.hl_tuning_load(path, b"gfx950:sramecc+:xnack-", ctypes.byref(back)) == 1
     assert bytes(back) == bytes(t) and list(back.many_tiles_per_cu) == [24, 4096]
+    assert back.blocks_per_cu_mc_only == 6
+    assert host.hl_tuning_parse(b'{"gfx950": {"blocks_per_cu_mc_only": 33}}', err, 256) == -1
     assert host.hl_tuning_parse(b'{"gfx950": {"many_tiles_per_cu": [8, 0]}}', err, 256) == 1
     for bad in (b'{"gfx950": {"many_tiles_per_cu": [8]}}',
                 b'{"gfx950": {"many_tiles_per_cu": [4097, 8]}}'):
