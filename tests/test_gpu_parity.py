@@ -495,3 +495,41 @@ def test_uneven_batch_full_size(ctx):
             check_result(g, o, p.kid, p.ops, f"pid={p.pid} kid={p.kid} n={p.n} mode={mode}")
         check_total(tot, want, ops)
         assert tot.n == int(sizes.sum())
+
+
+def test_launch_shape_follows_the_occupancy_rules():
+    # A batch of Monte-Carlo tasks alone runs the executor instance of its
+    # own at blocks_per_cu_mc_only; a batch that mixes kernels takes the
+    # largest of its kernels' blocks_per_cu.  Counts against the oracle in
+    # both.  Before any reduce-kind call the shape query says EAGAIN.
+    c = sc.Context(device=0, arena_bytes=1 << 30)
+    try:
+        with pytest.raises(sc.SparkclError) as e:
+            c.last_launch_shape()
+        assert e.value.code == sc.EAGAIN
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        t = c.get_tuning()
+        t.blocks_per_cu[0], t.blocks_per_cu[1], t.blocks_per_cu[2] = 2, 1, 3
+        t.blocks_per_cu_mc_only = 5
+        t.blocks_per_cu_many = 1
+        for m in range(len(t.tile)):
+            t.tile[m][2][20] = 1 << 12   # 256 tiles per 2^20-sample task
+            t.tile[m][0][20] = 1 << 14
+        c.set_tuning(t)
+        mc = [datagen.make_part(datagen.MC_PI, 1 << 20, pid, with_data=False)
+              for pid in range(16)]
+        for mode in (sc.BATCHED, sc.GRAPH):
+            per, _ = c.reduce(DevParts(mc).tasks, mode)
+            for p, g in zip(mc, per):
+                check_result(g, oracle_result(p), p.kid, p.ops, f"mc pid={p.pid} mode={mode}")
+            shape = c.last_launch_shape()
+            assert shape["grid"] == 5 * cus and shape["ntiles"] == 16 * 256, shape
+        mixed = mc[:8] + [datagen.make_part(datagen.POLY, 1 << 20, 100 + i) for i in range(8)]
+        d = DevParts(mixed)
+        per, _ = c.reduce(d.tasks, sc.BATCHED)
+        for p, g in zip(mixed, per):
+            check_result(g, oracle_result(p), p.kid, p.ops, f"mixed kid={p.kid} pid={p.pid}")
+        shape = c.last_launch_shape()
+        assert shape["grid"] == 3 * cus, shape
+    finally:
+        c.destroy()
