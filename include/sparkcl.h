@@ -398,11 +398,17 @@ SPARKCL_API int sparkcl_get_tuning(sparkcl_ctx *ctx, sparkcl_tuning *out);
    Cached plans are dropped. */
 SPARKCL_API int sparkcl_set_tuning(sparkcl_ctx *ctx, const sparkcl_tuning *in);
 
-/* Autotuner: for each kernel and size bucket in [lo_log2, hi_log2], time the
-   candidate tile sizes on synthetic device data and keep the fastest by
-   median HIP-event time, then each kernel's executor blocks per CU; writes
-   the table into the context and, if `path` is non-NULL, into that JSON file
-   under the device's gfx arch name.  Needs 2 GiB of free arena. */
+/* Autotuner (the paper leaves such optimisation open, sec. 6): on synthetic
+   device data, by median HIP-event time, with a 2% margin a candidate must
+   beat: per kernel, the executor blocks per CU jointly with the tile for
+   2^22-element partitions, then blocks per CU, block size and loads in
+   flight jointly (and, for Monte-Carlo, the occupancy of the instance that
+   runs Monte-Carlo tasks alone); then the tile size per execution mode,
+   kernel and size bucket in [lo_log2, hi_log2]; then, on a mixed batch of
+   its own distribution, the many-task occupancy, the work shares and the
+   mixed-batch block size.  Writes the table into the context and, if
+   `path` is non-NULL, into that JSON file under the device's gfx arch name.
+   Needs 2 GiB of free arena. */
 SPARKCL_API int sparkcl_autotune(sparkcl_ctx *ctx, uint32_t lo_log2, uint32_t hi_log2,
                      const char *path);
 
