@@ -48,7 +48,7 @@ def kernel_source_hash() -> str:
 
 
 def load_isa():
-    """Resource figures of this build's device code (written by the build
+    """Resource figures of the library's compiled device code (written by the build
     next to the library), if they belong to the current kernel source."""
     p = os.path.join(ROOT, "paper_1505_01120_amd", "isa.json")
     try:
@@ -408,7 +408,7 @@ def bench_monte_carlo(ctx, sc, steps=5) -> dict:
     out = {"ms": ev, "samples_per_s": samples / (ev / 1e3),
            "philox_blocks_per_s": blocks / (ev / 1e3), "samples": samples}
     # ALU roofline: VALU instructions per Philox block (one block = two
-    # samples per lane) counted in this build's own gfx950 assembly, times
+    # samples per lane) counted in the library's compiled gfx950 assembly, times
     # blocks/s, against the loop's issue bound at 256 CUs x 4 SIMDs x 2.4 GHz
     # (dual issue where the instructions can pair), and against the measured
     # ceiling of the same loop run from registers alone.
