@@ -746,12 +746,12 @@ def serve_run(sc, res: Resident, seconds: float, warm: float, per_task: bool,
     run.restype = ctypes.c_int
     run.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                     ctypes.c_int64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int64),
-                    ctypes.c_void_p, ctypes.c_void_p]
+                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     ctx = sc.Context(device=0, arena_bytes=(4 << 30) if host else (1 << 30),
                      budget_bytes=budget, flags=sc.FLAG_SERVE_PER_TASK if per_task else 0)
     t0 = ctypes.c_int64()
     rc = run(ctx._h, tasks.ctypes.data, sched.ctypes.data, count, 20_000_000, 10_000,
-             ctypes.byref(t0), done.ctypes.data, status.ctypes.data)
+             ctypes.byref(t0), done.ctypes.data, status.ctypes.data, None)
     stats = ctx.serve_stats()
     ctx.destroy()
     if rc != 0:

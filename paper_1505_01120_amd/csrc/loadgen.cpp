@@ -28,13 +28,14 @@ int64_t now_ns()
 extern "C" __attribute__((visibility("default"))) int
 sparkcl_loadgen_run(sparkcl_ctx *ctx, const sparkcl_task *tasks, const int64_t *sched_ns,
                     uint64_t count, int64_t lead_ns, uint32_t stall_ms, int64_t *t0_ns,
-                    int64_t *done_ns, int32_t *status)
+                    int64_t *done_ns, int32_t *status, sparkcl_result *results)
 {
     // tasks[i] is submitted at t0 + sched_ns[i] (sched_ns ascending, t0 = now +
     // lead_ns); done_ns[i] receives the server's completion stamp (steady
-    // clock), status[i] the result status or the submit error.  The call fails
-    // with SPARKCL_ETIMEDOUT when nothing completes or gets submitted for
-    // stall_ms while work is outstanding.
+    // clock), status[i] the result status or the submit error, and, when
+    // `results` is not NULL, results[i] the task's result as polled.  The
+    // call fails with SPARKCL_ETIMEDOUT when nothing completes or gets
+    // submitted for stall_ms while work is outstanding.
     if (!ctx || (count && (!tasks || !sched_ns || !done_ns || !status)) || !t0_ns)
         return SPARKCL_EINVAL;
     for (uint64_t i = 1; i < count; ++i)
@@ -82,6 +83,8 @@ sparkcl_loadgen_run(sparkcl_ctx *ctx, const sparkcl_task *tasks, const int64_t *
             progress = true;
             done_ns[j] = rc == SPARKCL_OK ? (int64_t)r.t_done_ns : now_ns();
             status[j] = rc == SPARKCL_OK ? r.status : rc;
+            if (results && rc == SPARKCL_OK)
+                results[j] = r;
             open[cursor] = open.back();
             open.pop_back();
         }

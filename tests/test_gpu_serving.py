@@ -7,7 +7,9 @@ exit, the per-task-launch baseline mode, and the watchdog are covered too.
 The watchdog case ends a long task from the host (stop word); every kernel
 still exits normally.
 """
+import ctypes
 import math
+import os
 import threading
 import time
 
@@ -16,6 +18,7 @@ import pytest
 import torch
 
 import datagen
+import oracle
 import paper_1505_01120_amd as sc
 from gpu_helpers import DevParts, check_result, oracle_result
 
@@ -27,6 +30,22 @@ def mixed_parts(count, seed, median=16384, lo=1024, hi=262144):
     kids = datagen.uniform_kernel_ids(count, seed, 7)
     return [datagen.make_part(int(k), int(n), i, seed=0)
             for i, (n, k) in enumerate(zip(sizes, kids))]
+
+
+# sparkcl_loadgen_run(ctx, tasks, sched_ns, count, lead_ns, stall_ms, &t0, done_ns,
+# status, results)
+LOADGEN_ARGS = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                ctypes.c_int64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int64),
+                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+
+
+def loadgen():
+    lg = ctypes.CDLL(os.path.join(os.path.dirname(os.path.abspath(sc.__file__)),
+                                  "libsparkcl_loadgen.so"))
+    run = lg.sparkcl_loadgen_run
+    run.restype = ctypes.c_int
+    run.argtypes = LOADGEN_ARGS
+    return run
 
 
 def wait_all(ctx, tickets, timeout=60.0):
@@ -189,12 +208,9 @@ def test_serve_watchdog_fails_long_task_then_recovers():
 
 def test_native_load_generator_replays_a_trace(ctx):
     """The serving benchmark's load generator (libsparkcl_loadgen.so, over the
-    public C ABI): a short Poisson trace is submitted at its scheduled times,
-    every task completes with status OK after its scheduled arrival, and the
-    results it collects are the server's."""
-    import ctypes
-    import os
-
+    public C ABI): a short trace is submitted at its scheduled times, every
+    task completes with status OK after its scheduled arrival, and the results
+    it collects match the oracle."""
     parts = mixed_parts(64, 5)
     d = DevParts(parts)
     count = 2000
@@ -202,23 +218,74 @@ def test_native_load_generator_replays_a_trace(ctx):
     sched = (np.arange(count, dtype=np.int64) * 50_000)  # 20K tasks/s
     done = np.zeros(count, np.int64)
     status = np.full(count, -99, np.int32)
-    lg = ctypes.CDLL(os.path.join(os.path.dirname(os.path.abspath(sc.__file__)),
-                                  "libsparkcl_loadgen.so"))
-    run = lg.sparkcl_loadgen_run
-    run.restype = ctypes.c_int
-    run.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
-                    ctypes.c_int64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int64),
-                    ctypes.c_void_p, ctypes.c_void_p]
+    run = loadgen()
     t0 = ctypes.c_int64()
+    results = (sc.Result * count)()
     rc = run(ctx._h, ctypes.addressof(tasks), sched.ctypes.data, count, 5_000_000, 10_000,
-             ctypes.byref(t0), done.ctypes.data, status.ctypes.data)
+             ctypes.byref(t0), done.ctypes.data, status.ctypes.data, ctypes.addressof(results))
     assert rc == 0
     assert np.all(status == 0)
     assert np.all(done >= t0.value + sched)
+    want = [oracle_result(p) for p in parts]
+    for i in range(count):
+        p = parts[i % len(parts)]
+        check_result(results[i], want[i % len(parts)], p.kid, p.ops, f"task {i} kid={p.kid} n={p.n}")
     # unsorted arrival times are refused
     bad = sched[::-1].copy()
     assert run(ctx._h, ctypes.addressof(tasks), bad.ctypes.data, count, 0, 1000,
-               ctypes.byref(t0), done.ctypes.data, status.ctypes.data) == sc.EINVAL
+               ctypes.byref(t0), done.ctypes.data, status.ctypes.data, None) == sc.EINVAL
+
+
+@pytest.mark.parametrize("per_task", [False, True], ids=["resident", "per_task_launch"])
+def test_serving_trace_at_full_rate_matches_oracle(per_task):
+    """The serving workload as the benchmark runs it: Poisson arrivals at
+    20K tasks/s (0.5 s, 10000 tasks), log-normal sizes of 1K to 4M elements
+    (median 64K), uniform kernel ids, inputs at drawn offsets of a resident
+    pool, a 64 GiB admission budget, replayed open-loop by the native load
+    generator; every task completes with status OK and its element count, and
+    a sample of 300 tasks plus the 20 largest match the oracle one by one.
+    Both serving forms: the resident executor and one launch per task."""
+    import bench
+
+    pool = 1 << 24
+    x = datagen.x_for(datagen.FMUL, pool, 0, 0)   # N(0,1)
+    y = datagen.y_for(datagen.FMUL, pool, 0, 0)   # U[0,2)
+    dx = torch.from_numpy(x).cuda()
+    dy = torch.from_numpy(y).cuda()
+    count = 10_000
+    tr = datagen.serving_trace(count, rate=20000.0, pool=pool)
+    tasks = bench.trace_tasks(sc, tr, dx.data_ptr(), dy.data_ptr())
+    sched = np.ascontiguousarray((tr.t_arrive * 1e9).astype(np.int64))
+    done = np.zeros(count, np.int64)
+    status = np.full(count, -99, np.int32)
+    results = (sc.Result * count)()
+    c = sc.Context(device=0, arena_bytes=1 << 30, budget_bytes=64 << 30,
+                   flags=sc.FLAG_SERVE_PER_TASK if per_task else 0)
+    try:
+        t0 = ctypes.c_int64()
+        rc = loadgen()(c._h, tasks.ctypes.data, sched.ctypes.data, count, 20_000_000, 10_000,
+                       ctypes.byref(t0), done.ctypes.data, status.ctypes.data,
+                       ctypes.addressof(results))
+    finally:
+        c.destroy()
+    assert rc == 0
+    assert np.all(status == 0)
+    assert [results[i].n for i in range(count)] == [int(v) for v in tr.sizes]
+    rng = np.random.default_rng(5)
+    pick = set(rng.choice(count, 300, replace=False).tolist())
+    pick |= set(np.argsort(tr.sizes)[-20:].tolist())
+    for i in sorted(pick):
+        kid, n, off = int(tr.kids[i]), int(tr.sizes[i]), int(tr.offsets[i])
+        if kid == datagen.MC_PI:
+            o = oracle.run_task(kid, sc.COUNT, n, None, None, seed=0, pid=i)
+            ops = sc.COUNT
+        else:
+            ops = sc.SUM | sc.MAX
+            o = oracle.run_task(kid, ops, n, x[off:off + n],
+                                y[off:off + n] if kid == datagen.FMUL else None,
+                                coef=datagen.POLY_COEF if kid == datagen.POLY else (),
+                                c=datagen.FMUL_C)
+        check_result(results[i], o, kid, ops, f"task {i} kid={kid} n={n} off={off}")
 
 
 def test_serve_light_load_keeps_claimed_tickets():

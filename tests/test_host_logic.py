@@ -430,7 +430,8 @@ def test_load_generator_library_exports_one_entry(lib):
     lg = ctypes.CDLL(libbuild.LOADGEN_LIB)
     t0 = ctypes.c_int64()
     assert lg.sparkcl_loadgen_run(None, None, None, ctypes.c_uint64(0), ctypes.c_int64(0),
-                                  ctypes.c_uint32(0), ctypes.byref(t0), None, None) == sc.EINVAL
+                                  ctypes.c_uint32(0), ctypes.byref(t0), None, None,
+                                  None) == sc.EINVAL
 
 
 def test_probe_library_exports_and_refuses(lib):
