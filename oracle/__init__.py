@@ -218,6 +218,24 @@ def tree_reduce_arrays(arrays, combiner: int = VADD) -> np.ndarray:
     return out
 
 
+def tree_reduce_rows(rows: np.ndarray, combiner: int = VADD) -> np.ndarray:
+    """O9 over the rows of a 2-D float32 array (any row stride, unit column
+    stride): the same fold as tree_reduce_arrays, with the row pointers built
+    by numpy instead of one Python object per row."""
+    if rows.ndim != 2 or rows.dtype != np.float32 or rows.strides[1] != 4:
+        raise ValueError("rows must be a 2-D float32 array with contiguous rows")
+    k, n = rows.shape
+    if k == 0:
+        raise ValueError("tree reduce of an empty RDD")
+    ptrs = (np.uint64(rows.ctypes.data) +
+            np.arange(k, dtype=np.uint64) * np.uint64(rows.strides[0]))
+    out = np.empty(n, dtype=np.float32)
+    rc = lib().oracle_tree_reduce_arrays(combiner, ptrs.ctypes.data, k, n, _ptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle_tree_reduce_arrays rejected combiner {combiner}")
+    return out
+
+
 def fnv1a64(b: bytes) -> int:
     """O10's word key: 64-bit FNV-1a of the bytes."""
     buf = np.frombuffer(bytes(b), dtype=np.uint8)

@@ -105,18 +105,19 @@ def test_repeat_uses_cached_plan_and_is_identical(ctx):
 
 
 def test_full_size_64_arrays_of_2p22(ctx):
-    # the 64 x 2^22 RDD as array-valued elements; columns checked on samples
+    # the 64 x 2^22 RDD as array-valued elements; every column bit-exact
+    # against the oracle's tree
     k, length = 64, 1 << 22
+    host = [datagen.fill(length, 0, e, 1, datagen.NORMAL) for e in range(k)]
     dev = torch.empty((k, length), dtype=torch.float32, device="cuda")
     for e in range(k):
-        dev[e].copy_(torch.from_numpy(datagen.fill(length, 0, e, 1, datagen.NORMAL)))
+        dev[e].copy_(torch.from_numpy(host[e]))
     out = torch.empty(length, device="cuda")
-    ctx.reduce_arrays(list(dev), out)
-    torch.cuda.synchronize()
-    got = out.cpu().numpy()
-    for lo in (0, 1_234_564, length - 4096):
-        want = oracle.tree_reduce_arrays(dev[:, lo:lo + 4096].cpu().numpy())
-        assert np.array_equal(got[lo:lo + 4096].view(np.uint32), want.view(np.uint32)), lo
+    for comb in (sc.VADD, sc.VMAX):
+        ctx.reduce_arrays(list(dev), out, comb)
+        torch.cuda.synchronize()
+        want = oracle.tree_reduce_arrays(host, comb)
+        assert np.array_equal(out.cpu().numpy().view(np.uint32), want.view(np.uint32)), comb
 
 
 # Shapes that fill the GPU with float4 columns take the wide kernel (leaf
@@ -188,10 +189,22 @@ def test_rows_match_oracle(ctx, k, length, pad):
         assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), (k, length, pad, comb)
 
 
+def oracle_by_column_blocks(host, comb, blocks=16):
+    """The oracle's tree over the rows of `host`, run on blocks of columns in
+    parallel host threads (each column's tree is independent of the others)."""
+    from concurrent.futures import ThreadPoolExecutor
+    n = host.shape[1]
+    step = -(-n // blocks)
+    with ThreadPoolExecutor(blocks) as ex:
+        parts = list(ex.map(lambda lo: oracle.tree_reduce_rows(host[:, lo:lo + step], comb),
+                            range(0, n, step)))
+    return np.concatenate(parts)
+
+
 def test_rows_full_size_65536_of_4096(ctx):
     # The 1 GiB RDD as 65536 rows of 4096 floats (the benchmark's second
-    # array shape, three passes of the 8-leaf kernel); both combiners, with
-    # columns checked on samples against the oracle's tree over all 65536 rows
+    # array shape, three passes of the 8-leaf kernel); both combiners, every
+    # column bit-exact against the oracle's tree over all 65536 rows
     k, length = 65_536, 4096
     host = datagen.fill(k * length, 11, 0, 1, datagen.NORMAL).reshape(k, length)
     rows = torch.from_numpy(host).cuda()
@@ -199,10 +212,8 @@ def test_rows_full_size_65536_of_4096(ctx):
     for comb in (sc.VADD, sc.VMAX):
         ctx.reduce_rows(rows, out, comb)
         torch.cuda.synchronize()
-        got = out.cpu().numpy()
-        for lo in (0, 2000, length - 64):
-            want = oracle.tree_reduce_arrays(np.ascontiguousarray(host[:, lo:lo + 64]), comb)
-            assert np.array_equal(got[lo:lo + 64].view(np.uint32), want.view(np.uint32)), (comb, lo)
+        want = oracle_by_column_blocks(host, comb)
+        assert np.array_equal(out.cpu().numpy().view(np.uint32), want.view(np.uint32)), comb
 
 
 def test_rows_errors(ctx):

@@ -91,3 +91,21 @@ def test_single_element_is_copied_and_errors(oracle):
     with pytest.raises(ValueError):
         oracle.tree_reduce_arrays(a, 9)
     assert oracle.tree_reduce_arrays(np.zeros((3, 0), np.float32)).size == 0
+
+
+def test_rows_entry_is_the_same_fold(oracle):
+    # tree_reduce_rows only builds the row pointers differently: on strided
+    # column windows of a larger array it returns the per-array fold's bits
+    rng = np.random.default_rng(3)
+    big = rng.standard_normal((131, 70)).astype(np.float32)
+    for comb in (oracle.VADD, oracle.VMAX):
+        for lo, hi in ((0, 70), (5, 41), (69, 70)):
+            want = oracle.tree_reduce_arrays([r[lo:hi] for r in big], comb)
+            got = oracle.tree_reduce_rows(big[:, lo:hi], comb)
+            assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), (comb, lo, hi)
+    with pytest.raises(ValueError):
+        oracle.tree_reduce_rows(big.astype(np.float64))
+    with pytest.raises(ValueError):
+        oracle.tree_reduce_rows(big[:, ::2])
+    with pytest.raises(ValueError):
+        oracle.tree_reduce_rows(big[:0])
