@@ -236,31 +236,38 @@ def test_native_load_generator_replays_a_trace(ctx):
                ctypes.byref(t0), done.ctypes.data, status.ctypes.data, None) == sc.EINVAL
 
 
-@pytest.mark.parametrize("per_task", [False, True], ids=["resident", "per_task_launch"])
-def test_serving_trace_at_full_rate_matches_oracle(per_task):
+@pytest.mark.parametrize("per_task,host", [(False, False), (True, False), (False, True)],
+                         ids=["resident", "per_task_launch", "host_inputs"])
+def test_serving_trace_at_full_rate_matches_oracle(per_task, host):
     """The serving workload as the benchmark runs it: Poisson arrivals at
     20K tasks/s (0.5 s, 10000 tasks), log-normal sizes of 1K to 4M elements
     (median 64K), uniform kernel ids, inputs at drawn offsets of a resident
     pool, a 64 GiB admission budget, replayed open-loop by the native load
     generator; every task completes with status OK and its element count, and
     a sample of 300 tasks plus the 20 largest match the oracle one by one.
-    Both serving forms: the resident executor and one launch per task."""
+    Both serving forms (the resident executor and one launch per task), and
+    the resident executor with the pool in pinned host memory (each task's
+    inputs staged over PCIe)."""
     import bench
 
     pool = 1 << 24
     x = datagen.x_for(datagen.FMUL, pool, 0, 0)   # N(0,1)
     y = datagen.y_for(datagen.FMUL, pool, 0, 0)   # U[0,2)
-    dx = torch.from_numpy(x).cuda()
-    dy = torch.from_numpy(y).cuda()
+    if host:
+        dx = torch.from_numpy(x).pin_memory()
+        dy = torch.from_numpy(y).pin_memory()
+    else:
+        dx = torch.from_numpy(x).cuda()
+        dy = torch.from_numpy(y).cuda()
     count = 10_000
     tr = datagen.serving_trace(count, rate=20000.0, pool=pool)
-    tasks = bench.trace_tasks(sc, tr, dx.data_ptr(), dy.data_ptr())
+    tasks = bench.trace_tasks(sc, tr, dx.data_ptr(), dy.data_ptr(), host=host)
     sched = np.ascontiguousarray((tr.t_arrive * 1e9).astype(np.int64))
     done = np.zeros(count, np.int64)
     status = np.full(count, -99, np.int32)
     results = (sc.Result * count)()
-    c = sc.Context(device=0, arena_bytes=1 << 30, budget_bytes=64 << 30,
-                   flags=sc.FLAG_SERVE_PER_TASK if per_task else 0)
+    c = sc.Context(device=0, arena_bytes=(4 << 30) if host else (1 << 30),
+                   budget_bytes=64 << 30, flags=sc.FLAG_SERVE_PER_TASK if per_task else 0)
     try:
         t0 = ctypes.c_int64()
         rc = loadgen()(c._h, tasks.ctypes.data, sched.ctypes.data, count, 20_000_000, 10_000,
