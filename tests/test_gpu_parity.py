@@ -1,7 +1,8 @@
 """GPU parity: the HIP path through the C ABI against the oracle, element by
 element on the same seeded inputs (MapCL, MapCLPartition, ReduceCL; paper
 sec. 3.1.3).  Sizes span several tiles with ragged tails; the full-size
-workloads are checked on sampled partitions plus size-independent properties.
+workloads (the 64 x 2^22 RDD, 256 x 2^24 Monte-Carlo samples, the 4096-task
+uneven batch) are checked partition by partition, with the RDD totals.
 """
 import math
 
