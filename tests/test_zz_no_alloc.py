@@ -76,6 +76,16 @@ def test_two_calls_second_smaller(ctx):
     check_call(ctx, second)
 
 
+@pytest.mark.parametrize("workload", ["rdd_64x2p22", "uneven_4096"])
+def test_full_size_batches(ctx, workload):
+    # the two batched workloads at their full sizes: the 64 x 2^22 FMUL RDD
+    # (512 tiles) and the 4096-partition uneven batch of mixed kernels (the
+    # mixed-batch cut, about 14000 tiles), each bit-identical to the batched
+    # call and within the oracle's bar, with the RDD total
+    parts = datagen.fmul_rdd() if workload == "rdd_64x2p22" else datagen.uneven_rdd()
+    check_call(ctx, parts)
+
+
 def test_repeated_calls_and_per_task_only(ctx):
     parts = [datagen.make_part(k, 200_000 + 7 * i, i) for i, k in enumerate([1, 2, 3] * 5)]
     d = DevParts(parts)
