@@ -485,8 +485,10 @@ int sparkcl::build_plan(sparkcl_ctx *ctx, int kind, int mode, const sparkcl_task
         ALLOC(dparts, sizeof(Partial) * total_tiles);
         ALLOC(dsync, sizeof(TaskSync) * ntasks);
         ALLOC(dctl, sizeof(BatchCtl));
-        ALLOC(dresults, sizeof(sparkcl_result) * ntasks);
-        ALLOC(dtotal, sizeof(sparkcl_result));
+        // the RDD total right after the per-task results, so that a blocking
+        // call brings both back in one copy
+        ALLOC(dresults, sizeof(sparkcl_result) * ((uint64_t)ntasks + 1));
+        p->dtotal = p->dresults + ntasks;
         if (mode != SPARKCL_PER_LAUNCH && !host_in)
             ALLOC(dtiles, sizeof(TileRef) * total_tiles);
     }
@@ -824,9 +826,9 @@ int sparkcl::launch_and_collect(sparkcl_ctx *ctx, Plan *p, const sparkcl_task *t
         return rc;
     if ((rc = enqueue(ctx, p, stream, true)) != SPARKCL_OK)
         return rc;
-    SPARKCL_HIP(hipMemcpyAsync(ctx->pinned, p->dresults, sizeof(sparkcl_result) * ntasks,
-                               hipMemcpyDeviceToHost, stream));
-    SPARKCL_HIP(hipMemcpyAsync(ctx->pinned + ntasks, p->dtotal, sizeof(sparkcl_result),
+    // the per-task results and the RDD total behind them, in one copy
+    SPARKCL_HIP(hipMemcpyAsync(ctx->pinned, p->dresults,
+                               sizeof(sparkcl_result) * ((uint64_t)ntasks + 1),
                                hipMemcpyDeviceToHost, stream));
     SPARKCL_HIP(hipStreamSynchronize(stream));
     if (per_task)
